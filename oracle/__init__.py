@@ -1,0 +1,207 @@
+"""Reference FP64 CPU solver for the shallow water patch step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the library under
+``paper_1901_06798_amd`` never does.  The C source (``swe_oracle.c``) follows
+Sec. 2 of Qin, LeVeque & Motley (the shallow water equations, the
+wave-propagation form with limited second-order corrections, dimensional
+splitting and the CFL condition), plus a written-out reading of the augmented
+Riemann solver that the paper cites but does not state.
+
+State layout: numpy arrays ``q`` of shape ``(my + 4, mx + 4, 3)`` holding
+``(h, hu, hv)`` per cell (array of structures, two ghost layers), and ``b`` of
+shape ``(my + 4, mx + 4)``.
+
+Parity status of each function is listed in the test suite's oracle pins
+(tests/test_oracle_*.py); the unsplit (transverse) mode is pinned only by
+invariants (lake at rest, mass, symmetry, convergence), not by a closed form.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "swe_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
+EDGE_WET, EDGE_WALL_R, EDGE_WALL_L, EDGE_DRY = 0, 1, 2, 3
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O3, no fast-math, no FP contraction)."""
+    cmd = ["gcc", "-std=c11", "-O3", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("drytol", ctypes.c_double),
+                ("manning_n", ctypes.c_double), ("cfl_desired", ctypes.c_double),
+                ("cfl_max", ctypes.c_double), ("h_corr", ctypes.c_double),
+                ("method", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("transverse_order", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("mx", ctypes.c_int32), ("my", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 4)]
+
+
+class Waves(ctypes.Structure):
+    _fields_ = [("z", (ctypes.c_double * 3) * 3), ("s", ctypes.c_double * 3),
+                ("kind", ctypes.c_int32), ("clamped", ctypes.c_int32),
+                ("shallow", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P, G = ctypes.POINTER(Params), ctypes.POINTER(Grid)
+        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        L.orc_riemann.argtypes = [P] + [d] * 8 + [ctypes.POINTER(Waves)]
+        L.orc_riemann.restype = None
+        L.orc_fluctuations.argtypes = [ctypes.POINTER(Waves), _D, _D]
+        L.orc_mc_limiter.argtypes = [d]
+        L.orc_mc_limiter.restype = d
+        L.orc_ghost_fill.argtypes = [G, _D]
+        L.orc_ghost_fill_b.argtypes = [G, _D]
+        L.orc_step.argtypes = [P, G, _D, _D, d, _D, _D, ctypes.POINTER(i32)]
+        L.orc_step.restype = i64
+        L.orc_speed_scan.argtypes = [P, G, _D, _D, _D]
+        L.orc_run.argtypes = [P, G, _D, _D, i32, d, _D, _D, ctypes.POINTER(i32),
+                              ctypes.POINTER(i32)]
+        L.orc_run.restype = i64
+        L.orc_mass.argtypes = [G, _D]
+        L.orc_mass.restype = d
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_get_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def params(g=9.81, drytol=1e-3, manning_n=0.0, cfl_desired=0.9, cfl_max=1.0,
+           h_corr=0.1, method=0, order=2, transverse_order=2) -> Params:
+    return Params(g, drytol, manning_n, cfl_desired, cfl_max, h_corr, method, order,
+                  transverse_order, 0)
+
+
+def grid(mx, my, dx, dy, bc=(BC_WALL,) * 4) -> Grid:
+    return Grid(mx, my, dx, dy, (ctypes.c_int32 * 4)(*bc))
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+def mc_limiter(theta: float) -> float:
+    return float(lib().orc_mc_limiter(float(theta)))
+
+
+def riemann(left, right, p: Params | None = None):
+    """Solve one edge.  left/right = (h, normal momentum, transverse momentum, b).
+
+    Returns (Z, s, kind, clamped) with Z[p, k] the f-wave p in components
+    (mass, normal momentum, transverse momentum)."""
+    p = p or params()
+    w = Waves()
+    lib().orc_riemann(ctypes.byref(p), *[float(v) for v in left],
+                      *[float(v) for v in right], ctypes.byref(w))
+    Z = np.array([[w.z[a][k] for k in range(3)] for a in range(3)])
+    s = np.array([w.s[a] for a in range(3)])
+    return Z, s, int(w.kind), int(w.clamped)
+
+
+def fluctuations(left, right, p: Params | None = None):
+    p = p or params()
+    w = Waves()
+    lib().orc_riemann(ctypes.byref(p), *[float(v) for v in left],
+                      *[float(v) for v in right], ctypes.byref(w))
+    am = np.zeros(3)
+    ap = np.zeros(3)
+    lib().orc_fluctuations(ctypes.byref(w), _ptr(am), _ptr(ap))
+    return am, ap
+
+
+def new_state(h, hu, hv, b, bc=(BC_WALL,) * 4):
+    """Embed interior (my, mx) arrays into ghost-framed AoS arrays; fill ghosts."""
+    my, mx = np.shape(h)
+    q = np.zeros((my + 4, mx + 4, 3))
+    q[2:-2, 2:-2, 0] = h
+    q[2:-2, 2:-2, 1] = hu
+    q[2:-2, 2:-2, 2] = hv
+    bb = np.zeros((my + 4, mx + 4))
+    bb[2:-2, 2:-2] = b
+    return q, bb
+
+
+def ghost_fill(g: Grid, q: np.ndarray) -> None:
+    lib().orc_ghost_fill(ctypes.byref(g), _ptr(q))
+
+
+def ghost_fill_b(g: Grid, b: np.ndarray) -> None:
+    lib().orc_ghost_fill_b(ctypes.byref(g), _ptr(b))
+
+
+def step(p: Params, g: Grid, q: np.ndarray, b: np.ndarray, dt: float):
+    """One step from q (ghosts must be filled).  Returns (q_out, smax, clamps, nonfinite)."""
+    out = np.empty_like(q)
+    smax = np.zeros(2)
+    nf = ctypes.c_int32(0)
+    c = lib().orc_step(ctypes.byref(p), ctypes.byref(g), _ptr(q), _ptr(b), float(dt),
+                       _ptr(out), _ptr(smax), ctypes.byref(nf))
+    return out, smax, int(c), int(nf.value)
+
+
+def speed_scan(p: Params, g: Grid, q: np.ndarray, b: np.ndarray):
+    smax = np.zeros(2)
+    lib().orc_speed_scan(ctypes.byref(p), ctypes.byref(g), _ptr(q), _ptr(b), _ptr(smax))
+    return smax
+
+
+def run(p: Params, g: Grid, q: np.ndarray, b: np.ndarray, nsteps: int, dt0: float = 0.0,
+        dt_forced=None):
+    """Advance q in place.  Returns dict(dt, clamps, retakes, nonfinite)."""
+    dts = np.zeros(max(nsteps, 1))
+    rt = ctypes.c_int32(0)
+    nf = ctypes.c_int32(0)
+    forced = None
+    if dt_forced is not None:
+        forced = np.ascontiguousarray(dt_forced, dtype=np.float64)
+        assert forced.size >= nsteps
+    c = lib().orc_run(ctypes.byref(p), ctypes.byref(g), _ptr(q), _ptr(b), int(nsteps),
+                      float(dt0), _ptr(forced) if forced is not None else None,
+                      _ptr(dts), ctypes.byref(rt), ctypes.byref(nf))
+    return {"dt": dts[:nsteps], "clamps": int(c), "retakes": int(rt.value),
+            "nonfinite": int(nf.value)}
+
+
+def mass(g: Grid, q: np.ndarray) -> float:
+    return float(lib().orc_mass(ctypes.byref(g), _ptr(q)))

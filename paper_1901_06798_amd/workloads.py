@@ -1,0 +1,261 @@
+"""Seeded synthetic inputs for the shallow water patch step.
+
+This module only builds input arrays (bathymetry, initial surface, patch
+layouts, request streams).  It contains none of the solver's arithmetic, and
+both the HIP path and the reference solver used by the tests take their inputs
+from here.
+
+The paper's own runs (2011 Tohoku -> Crescent City, Seattle Fault -> Eagle
+Harbor, Sec. 5) need earthquake deformation files and coastal elevation models
+that are not available; these generators stand in for them with the shapes the
+paper's runs have: a deep abyssal plain (about 4000 m) rising over a
+continental shelf to a dry coast, a Gaussian sea-floor uplift as the source,
+patch sizes up to 128 x 128 cells and three refinement levels.
+
+Conventions: cell (i, j) with 1 <= i <= mx, 1 <= j <= my has centre
+(x0 + (i - 1/2) dx, y0 + (j - 1/2) dy); arrays are indexed [j - 1, i - 1]
+(row-major, x fastest).  b < 0 is below sea level.  Depth h = max(0, eta - b).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+G = 9.81
+DRYTOL = 1e-3
+
+BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
+
+
+@dataclass
+class Problem:
+    """Interior arrays of one patch plus its geometry."""
+    name: str
+    h: np.ndarray
+    hu: np.ndarray
+    hv: np.ndarray
+    b: np.ndarray
+    dx: float
+    dy: float
+    bc: tuple = (BC_WALL,) * 4
+    nsteps: int = 0
+    x0: float = 0.0
+    y0: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def mx(self) -> int:
+        return int(self.h.shape[1])
+
+    @property
+    def my(self) -> int:
+        return int(self.h.shape[0])
+
+
+def cell_centres(n: int, d: float, x0: float = 0.0) -> np.ndarray:
+    return x0 + (np.arange(n, dtype=np.float64) + 0.5) * d
+
+
+def shelf_profile(x: np.ndarray, x_s: float, width: float, deep: float = -4000.0,
+                  coast: float = 50.0) -> np.ndarray:
+    """Abyssal plain at `deep` rising by a tanh profile to `coast` metres."""
+    return deep + (coast - deep) * 0.5 * (1.0 + np.tanh((x - x_s) / width))
+
+
+def gaussian(xc: np.ndarray, yc: np.ndarray, amp: float, sigma: float, cx: float,
+             cy: float) -> np.ndarray:
+    X, Y = np.meshgrid(xc, yc)
+    r2 = (X - cx) ** 2 + (Y - cy) ** 2
+    return amp * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def depth_from_surface(eta: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Initial depth of a surface eta over bed b (0 where the bed is above eta)."""
+    return np.maximum(0.0, eta - b)
+
+
+def _roughen(b: np.ndarray, rough: float, rng: np.random.Generator) -> np.ndarray:
+    xi = rng.uniform(-1.0, 1.0, size=b.shape)
+    return b * (1.0 + rough * xi)
+
+
+def gaussian_hump(n: int = 200, dx: float = 1000.0, depth: float = 4000.0,
+                  amp: float = 1.0, sigma: float = 10e3, nsteps: int = 100) -> Problem:
+    """Flat bottom at -depth, Gaussian surface hump at the centre, walls."""
+    xc = cell_centres(n, dx)
+    b = np.full((n, n), -depth)
+    eta = gaussian(xc, xc, amp, sigma, 0.5 * n * dx, 0.5 * n * dx)
+    h = depth_from_surface(eta, b)
+    z = np.zeros_like(h)
+    return Problem("gaussian_hump", h, z, z.copy(), b, dx, dx, (BC_WALL,) * 4, nsteps,
+                   meta={"amp": amp, "sigma": sigma, "depth": depth})
+
+
+def lake_at_rest_flat(n: int = 200, dx: float = 1000.0, depth: float = 4000.0) -> Problem:
+    p = gaussian_hump(n, dx, depth, amp=0.0)
+    p.name = "lake_at_rest_flat"
+    return p
+
+
+def dam_break_1d(n: int = 400, length: float = 400.0, h_left: float = 2.0,
+                 h_right: float = 1.0, transpose: bool = False) -> Problem:
+    """1D dam break on x in [-L/2, L/2], flat bed at 0, extrapolation ends.
+    Embedded as an (my = 1, mx = n) patch, or (my = n, mx = 1) if transposed."""
+    dx = length / n
+    xc = cell_centres(n, dx, -0.5 * length)
+    h = np.where(xc < 0.0, h_left, h_right).astype(np.float64)
+    b = np.zeros(n)
+    z = np.zeros(n)
+    bc = (BC_EXTRAP,) * 4
+    if transpose:
+        return Problem("dam_break_y", h[:, None].copy(), z[:, None].copy(), z[:, None].copy(),
+                       b[:, None].copy(), dx, dx, bc, 0, 0.0, -0.5 * length)
+    return Problem("dam_break_x", h[None, :].copy(), z[None, :].copy(), z[None, :].copy(),
+                   b[None, :].copy(), dx, dx, bc, 0, -0.5 * length, 0.0)
+
+
+def shelf_grid(n: int, dx: float, seed: int, rough: float = 0.05, amp: float = 2.0,
+               sigma: float = 30e3, src=None, bc=(BC_EXTRAP,) * 4, width: float = 20e3,
+               x_s_frac: float = 0.75, nsteps: int = 0, name: str = "shelf") -> Problem:
+    """Square n x n grid on [0, n dx]^2 with the tanh shelf along x, seeded
+    multiplicative roughness, and a Gaussian uplift added to the surface."""
+    L = n * dx
+    x_s = x_s_frac * L
+    xc = cell_centres(n, dx)
+    b = np.broadcast_to(shelf_profile(xc, x_s, width)[None, :], (n, n)).copy()
+    rng = np.random.default_rng(seed)
+    if rough > 0.0:
+        b = _roughen(b, rough, rng)
+    if src is None:
+        src = (0.5 * L, 0.5 * L)
+    eta = gaussian(xc, xc, amp, sigma, src[0], src[1])
+    h = depth_from_surface(eta, b)
+    z = np.zeros_like(h)
+    return Problem(name, h, z, z.copy(), b, dx, dx, tuple(bc), nsteps,
+                   meta={"x_s": x_s, "width": width, "amp": amp, "sigma": sigma,
+                         "src": src, "seed": seed, "rough": rough})
+
+
+def shelf_4096(n: int = 4096, dx: float = 250.0, nsteps: int = 500) -> Problem:
+    """4096^2 grid, dx = 250 m, shelf + 5% roughness (seed 2), 2 m source of
+    sigma 30 km at the domain centre, extrapolation boundaries."""
+    return shelf_grid(n, dx, seed=2, nsteps=nsteps, name=f"shelf_{n}")
+
+
+def shelf_walls(n: int = 2048, dx: float = 500.0, seed: int = 4, nsteps: int = 2000,
+                amp: float = 2.0) -> Problem:
+    """Wall-bounded shelf (mass drift is then pure numerics), source 60 km
+    seaward of the shelf break at mid-height."""
+    L = n * dx
+    x_s = 0.75 * L
+    return shelf_grid(n, dx, seed=seed, amp=amp, src=(x_s - 60e3, 0.5 * L),
+                      bc=(BC_WALL,) * 4, nsteps=nsteps, name=f"shelf_walls_{n}")
+
+
+# --------------------------------------------------------------------------
+# Batched AMR-shaped patch sets.
+
+@dataclass
+class PatchSpec:
+    mx: int
+    my: int
+    level: int          # 1-based refinement level
+    dx: float
+    x0: float
+    y0: float
+    tref: int           # substeps per coarse step (r^(level-1))
+
+
+def amr_patch_set(npatch=(200, 800, 2000), dx1: float = 4000.0, ratio: int = 4,
+                  L: float = 1024e3, size_lo: int = 16, size_hi: int = 96, seed: int = 3,
+                  width: float = 20e3, x_s_frac: float = 0.75, amp: float = 2.0,
+                  sigma: float = 30e3, rough: float = 0.05):
+    """Patches of three refinement levels placed along the shelf.
+
+    Level 1 windows lie anywhere in the domain, level 2 within 150 km of the
+    shelf break, level 3 between 30 km seaward of the break and 20 km inland of
+    the shoreline (so most level-3 patches hold a wet/dry coastline).  Side
+    lengths are uniform in [size_lo, size_hi].  Each patch gets its own seeded
+    roughness.  Returns (specs, problems) with one Problem per patch
+    (extrapolation boundaries)."""
+    rng = np.random.default_rng(seed)
+    x_s = x_s_frac * L
+    shore = x_s + width * np.arctanh(2.0 * 4000.0 / 4050.0 - 1.0)
+    specs = []
+    for lev, cnt in enumerate(npatch, start=1):
+        dx = dx1 / ratio ** (lev - 1)
+        for _ in range(cnt):
+            mx = int(rng.integers(size_lo, size_hi + 1))
+            my = int(rng.integers(size_lo, size_hi + 1))
+            wx, wy = mx * dx, my * dx
+            if lev == 1:
+                lo, hi = 0.0, L - wx
+            elif lev == 2:
+                lo, hi = x_s - 150e3, x_s + 150e3 - wx
+            else:
+                lo, hi = x_s - 30e3, shore + 20e3 - wx
+            x0 = float(rng.uniform(lo, hi))
+            y0 = float(rng.uniform(0.0, L - wy))
+            specs.append(PatchSpec(mx, my, lev, dx, x0, y0, ratio ** (lev - 1)))
+    src = (x_s - 60e3, 0.5 * L)
+    probs = []
+    for k, s in enumerate(specs):
+        xc = cell_centres(s.mx, s.dx, s.x0)
+        yc = cell_centres(s.my, s.dx, s.y0)
+        b = np.broadcast_to(shelf_profile(xc, x_s, width)[None, :], (s.my, s.mx)).copy()
+        if rough > 0.0:
+            b = _roughen(b, rough, np.random.default_rng([seed, k]))
+        eta = gaussian(xc, yc, amp, sigma, src[0], src[1])
+        h = depth_from_surface(eta, b)
+        z = np.zeros_like(h)
+        probs.append(Problem(f"patch{k}", h, z, z.copy(), b, s.dx, s.dx, (BC_EXTRAP,) * 4, 0,
+                             s.x0, s.y0, meta={"level": s.level, "tref": s.tref}))
+    return specs, probs
+
+
+# --------------------------------------------------------------------------
+# Scenario requests for the serving loop.
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float       # seconds after the stream starts
+    problem: Problem
+    nsteps: int
+
+
+def scenario(k: int, n: int | None = None, dx: float = 500.0, nsteps: int = 1000,
+             n_lo: int = 256, n_hi: int = 2048) -> Problem:
+    """Tsunami scenario k: seeded n x n shelf (no roughness), random source."""
+    rng = np.random.default_rng(5000 + k)
+    if n is None:
+        n = int(rng.integers(n_lo, n_hi + 1))
+    else:
+        rng.integers(n_lo, n_hi + 1)
+    L = n * dx
+    x_s = float(rng.uniform(0.6, 0.85)) * L
+    width = float(rng.uniform(10e3, 30e3))
+    amp = float(rng.uniform(0.5, 5.0))
+    sigma = float(rng.uniform(10e3, 50e3))
+    cx = float(rng.uniform(0.2, 0.5)) * L
+    cy = float(rng.uniform(0.3, 0.7)) * L
+    xc = cell_centres(n, dx)
+    b = np.broadcast_to(shelf_profile(xc, x_s, width)[None, :], (n, n)).copy()
+    eta = gaussian(xc, xc, amp, sigma, cx, cy)
+    h = depth_from_surface(eta, b)
+    z = np.zeros_like(h)
+    return Problem(f"scenario{k}", h, z, z.copy(), b, dx, dx, (BC_EXTRAP,) * 4, nsteps,
+                   meta={"x_s": x_s, "width": width, "amp": amp, "sigma": sigma,
+                         "src": (cx, cy)})
+
+
+def request_stream(count: int = 1200, rate: float = 20.0, seed: int = 5, nsteps: int = 1000,
+                   n_lo: int = 256, n_hi: int = 2048, dx: float = 500.0):
+    """Poisson arrivals (exponential gaps of mean 1/rate) of scenario requests.
+    Problems are generated lazily by the caller via scenario(rid, ...)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps)
+    sizes = [int(np.random.default_rng(5000 + k).integers(n_lo, n_hi + 1)) for k in range(count)]
+    return [(k, float(t[k]), sizes[k]) for k in range(count)]
