@@ -1,0 +1,219 @@
+/*
+ * swe.h -- C ABI of the MI355X (gfx950) shallow water patch-step library.
+ *
+ * The library advances patches of the 2D shallow water equations over
+ * bathymetry (Qin, LeVeque & Motley, Sec. 2, equations swe) by one time step
+ * of the wave-propagation method: an augmented Riemann solve at every edge
+ * with wet/dry handling, the fluctuations A+-dQ and B+-dQ, limited
+ * second-order corrections (MC limiter), dimensional splitting x then y
+ * (Sec. 2, split x/y forms) or an unsplit update with transverse waves, and
+ * the largest wave speed for the CFL condition (Sec. 2, CFL condition;
+ * Sec. 4 keeps the Riemann solves, the limiter and the CFL reduction on the
+ * GPU).  A patch is a rectangle of cells with two ghost layers and its
+ * bathymetry (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer argument is a DEVICE pointer unless its comment says
+ *    "host".  The caller owns all memory and streams; the library allocates
+ *    nothing.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Every call only enqueues work on `stream`: none synchronises,
+ *    reads device data on the host or allocates, so every call can be
+ *    captured into a HIP graph.  Step sizes are read from device memory, so
+ *    a replayed graph needs no host update.
+ *  - State planes.  A patch stores (h, hu, hv) in FP64 (precision SWE_F64) or
+ *    (eta', hu, hv) in FP32 (precision SWE_F32_DEV, eta' = h + b - sea_level)
+ *    as three planes of one element type; the bathymetry b is one plane of
+ *    the same type.  Cell (i, j) of a patch, 0 <= i < mx + 4,
+ *    0 <= j < my + 4 (interior 2 <= i < mx + 2, 2 <= j < my + 2), is element
+ *        off + j * pitch + i
+ *    of each plane; the planes of q are plane_stride elements apart (h first).
+ *    b uses the same off and pitch.  SI units throughout.
+ *  - Ghost cells.  Sides with boundary code SWE_BC_WALL (mirror, normal
+ *    momentum negated) or SWE_BC_EXTRAP (copy of the nearest interior cell)
+ *    are synthesised from the interior when a step loads the patch; their
+ *    memory is neither read nor written by the step.  Sides with
+ *    SWE_BC_USER are read from memory (the caller filled them, e.g. from a
+ *    neighbouring patch).  The rule is: x-ghosts of interior rows from the
+ *    x-sides, then y-ghosts of every column from the y-sides (which fills the
+ *    corners).  swe_ghost_fill writes the same values into memory.
+ *  - Return codes: SWE_OK (0); SWE_EINVAL (-1) for a bad shape, a null
+ *    pointer, in/out aliasing or an unknown enum, detected on the host before
+ *    anything is enqueued; SWE_EHIP (-2) for a HIP launch/runtime error.  The
+ *    message of the last failure of the calling thread is returned by
+ *    swe_last_error().  No C++ exception crosses this boundary.
+ *  - Conditions found on the device are OR-ed into status[0] (a device
+ *    uint32_t pair; status[1] counts depth clamps): SWE_STATUS_NEG_DEPTH (a
+ *    negative depth was reset to 0), SWE_STATUS_NONFINITE (an updated value
+ *    is NaN/Inf), SWE_STATUS_CFL_EXCEEDED (the Courant number of the step
+ *    exceeded cfl_max; the caller retakes it with the reduced dt that
+ *    swe_cfl_reduce wrote).  The caller reads status after synchronising.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_OK 0
+#define SWE_EINVAL (-1)
+#define SWE_EHIP (-2)
+
+#define SWE_STATUS_NEG_DEPTH 1u
+#define SWE_STATUS_NONFINITE 2u
+#define SWE_STATUS_CFL_EXCEEDED 4u
+
+enum swe_method { SWE_SPLIT = 0, SWE_UNSPLIT = 1 };
+enum swe_precision { SWE_F64 = 0, SWE_F32_DEV = 1 };
+enum swe_bc { SWE_BC_WALL = 0, SWE_BC_EXTRAP = 1, SWE_BC_USER = 2 };
+
+/* Physical and numerical parameters (host struct, passed by pointer). */
+typedef struct swe_params {
+    double g;            /* gravity, 9.81 m s^-2 */
+    double drytol;       /* a cell with h <= drytol is dry (1e-3 m) */
+    double h_corr;       /* an edge with a cell at or below this depth gets no
+                            limited correction (0.1 m); keeps the swash zone
+                            first order, which keeps depths non-negative */
+    double manning_n;    /* Manning coefficient (Sec. 2 drag term); 0 = off */
+    double cfl_desired;  /* Courant number aimed at by swe_cfl_reduce (0.9) */
+    double cfl_max;      /* a step above this Courant number is flagged (1.0) */
+    double sea_level;    /* reference level of eta' in SWE_F32_DEV (0 m) */
+    double h_fp64;       /* SWE_F32_DEV: an edge with a cell at or below this
+                            depth, or a dry cell, is solved in FP64 (1 m) */
+    int32_t method;      /* swe_method */
+    int32_t order;       /* 1 = fluctuations only, 2 = with limited corrections */
+    int32_t transverse_order; /* SWE_UNSPLIT: 1 or 2 */
+    int32_t precision;   /* swe_precision */
+} swe_params;
+
+/* One patch (host struct for swe_patch_step, device array for the batched
+ * entry points).  See the layout rules above. */
+typedef struct swe_patch {
+    int64_t off;          /* element offset of cell (0, 0) in every plane */
+    int64_t plane_stride; /* elements between the h, hu and hv planes */
+    double dx, dy;        /* cell size [m] */
+    int32_t mx, my;       /* interior cells, >= 1 each */
+    int32_t pitch;        /* elements per row, >= mx + 4 */
+    int32_t group;        /* index of the patch's dt slot */
+    int32_t tref;         /* substeps of the patch per group step, >= 1 */
+    int32_t level;        /* refinement level (1-based), informational */
+    int8_t bc[4];         /* swe_bc of the sides xlo, xhi, ylo, yhi */
+    int32_t reserved;
+} swe_patch;
+
+/* Advance one patch by one step: q_out = step(q_in, dt[0]).
+ * p, patch: host.  q_in, q_out: plane sets as above, must not overlap.
+ * b: bathymetry plane.  dt: device double.  smax: device double[2]; the
+ * largest wave speeds over the x- and y-edges of interior cells are
+ * max-combined into smax[0], smax[1] (so it must hold 0 or an earlier value
+ * on entry; swe_cfl_reduce resets it).  status: device uint32_t[2].
+ * Only interior cells of q_out are written. */
+int swe_patch_step(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
+                   const void *b, const double *dt, double *smax, uint32_t *status,
+                   void *stream);
+
+/* Write the ghost cells of n patches (device array `patches`) into the
+ * planes `q` (all three) and, if fill_b != 0, into `b`, by the rule above.
+ * Sides with SWE_BC_USER are left untouched.  max_mx/max_my bound the
+ * patch sizes (host ints) and size the launch. */
+int swe_ghost_fill(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
+                   int32_t max_my, void *q, void *b, int32_t fill_b, void *stream);
+
+/* Wave speeds of n patches without updating them: max-combines the largest
+ * |s| over the x- and y-edges of each patch's interior cells into
+ * smax_patch[2 k], smax_patch[2 k + 1].  Used for the first dt. */
+int swe_speed_scan(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
+                   int32_t max_my, const void *q, const void *b, double *smax_patch,
+                   void *stream);
+
+/* CFL rule (Sec. 2).  For each group g, with rate_k = max(smax_x / dx,
+ * smax_y / dy) / tref over the patches k of g (patches: device array):
+ *   nu = dt_group[g] * max_k rate_k; nu > cfl_max sets SWE_STATUS_CFL_EXCEEDED
+ *   in status[0] and group_flags[g] (if not NULL);
+ *   dt_group[g] = cfl_desired / max_k rate_k (unchanged if that rate is 0).
+ * smax_patch entries are reset to 0 for the next step.  If
+ * initial != 0 the CFL test is skipped (first dt from swe_speed_scan).
+ * p: host.  Groups are 0 .. ngroups - 1. */
+int swe_cfl_reduce(const swe_params *p, const swe_patch *patches, int32_t n, int32_t ngroups,
+                   double *smax_patch, double *dt_group, uint32_t *status,
+                   uint32_t *group_flags, int32_t initial, void *stream);
+
+/* Water volume sum(h) dx dy over the interior of each patch, in FP64,
+ * written to mass_patch[k] (deterministic order).  In SWE_F32_DEV, h is
+ * eta' + sea_level - b accumulated in FP64. */
+int swe_mass(const swe_params *p, const swe_patch *patches, int32_t n, const void *q,
+             const void *b, double *mass_patch, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched step: many patches (e.g. the patches of an AMR hierarchy, or the
+ * grids of several scenarios) in one persistent launch (Sec. 3: patches of
+ * several levels, each level refining dx and dt by an integer ratio; Sec. 4:
+ * memory pool and many small patches, whose launch overhead the paper could
+ * not hide).
+ *
+ * A plan splits every patch into strip tasks (a strip of seg - 4 columns and
+ * a run of rows, marched by a segment of seg lanes) and groups the tasks into
+ * items; one workgroup takes one item at a time from a queue ordered longest
+ * first.  A patch with tref > 1 forms a single item, whose workgroup runs its
+ * tref substeps back to back with a barrier in between.
+ */
+typedef struct swe_schedule {
+    int32_t seg;             /* lanes per strip: 64 or 32 */
+    int32_t rows_per_task;   /* rows per task; 0 = choose from the patch size */
+    int32_t waves_per_group; /* waves per workgroup: 1, 2, 4 or 8 */
+    int32_t tasks_per_item;  /* tref == 1 patches: tasks per item; 0 = auto */
+    int32_t order;           /* 0 = longest item first, 1 = patch order */
+    int32_t groups_per_cu;   /* persistent workgroups per compute unit; 0 = occupancy */
+} swe_schedule;
+
+typedef struct swe_task {
+    int32_t patch;  /* index into the patch table */
+    int32_t strip;  /* first column of the strip is strip * (seg - 4) (ghosts included) */
+    int32_t row0;   /* first updated row (2 = first interior row) */
+    int32_t rows;   /* updated rows */
+} swe_task;
+
+typedef struct swe_item {
+    int32_t task_begin, task_end; /* tasks [begin, end) of one patch */
+    int32_t patch;
+    int32_t substeps;             /* tref of the patch if the item covers it whole, else 1 */
+} swe_item;
+
+/* Build a plan on the host.  patches: host array of n patches.  With items
+ * and tasks NULL only the counts are returned in *nitems, *ntasks; otherwise
+ * the arrays (host, sized from a previous query) are filled.  Fails with
+ * SWE_EINVAL if a patch that needs several items has tref > 1, or a
+ * SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
+ * substeps). */
+int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sched,
+                     swe_item *items, int32_t *nitems, swe_task *tasks, int32_t *ntasks);
+
+/* Advance every patch of the plan: patch k takes tref_k substeps of
+ * dt_group[group_k] / tref_k from pool_in to pool_out (pool_in is not
+ * modified; pool_work, same size as the pools, holds intermediate substeps of
+ * patches with tref > 1; NULL is allowed when every tref is 1).  The largest
+ * speeds of all substeps are max-combined into smax_patch[2 k], [2 k + 1].
+ * patches, items, tasks: device copies of the table and of the plan.
+ * queue: device uint32_t[2], zero before the first call; the launch leaves it
+ * zero again.  sched: host, the schedule the plan was built with. */
+int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_item *items,
+                     int32_t nitems, const swe_task *tasks, const void *pool_in, void *pool_out,
+                     void *pool_work, const void *pool_b, const double *dt_group,
+                     double *smax_patch, uint32_t *status, uint32_t *queue,
+                     const swe_schedule *sched, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *swe_last_error(void);
+
+/* Library version string. */
+const char *swe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

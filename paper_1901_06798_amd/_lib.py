@@ -1,0 +1,177 @@
+"""ctypes binding of the C ABI in include/swe.h (argument marshalling only).
+
+Every function has the C name and argument order; device pointers are passed
+as Python ints (e.g. ``tensor.data_ptr()``) and the stream as an int
+(``torch.cuda.current_stream().cuda_stream``) or 0.  A non-zero return code
+raises SweError with the library's message.  If the HIP library has not been
+built, importing the binding fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswe.so")
+
+SWE_OK, SWE_EINVAL, SWE_EHIP = 0, -1, -2
+STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED = 1, 2, 4
+SPLIT, UNSPLIT = 0, 1
+F64, F32_DEV = 0, 1
+BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
+
+
+class SweError(RuntimeError):
+    pass
+
+
+class swe_params(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("drytol", ctypes.c_double),
+                ("h_corr", ctypes.c_double), ("manning_n", ctypes.c_double),
+                ("cfl_desired", ctypes.c_double), ("cfl_max", ctypes.c_double),
+                ("sea_level", ctypes.c_double), ("h_fp64", ctypes.c_double),
+                ("method", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("transverse_order", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class swe_patch(ctypes.Structure):
+    _fields_ = [("off", ctypes.c_int64), ("plane_stride", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("mx", ctypes.c_int32), ("my", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("tref", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("bc", ctypes.c_int8 * 4), ("reserved", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(swe_patch) == 64
+
+
+class swe_schedule(ctypes.Structure):
+    _fields_ = [("seg", ctypes.c_int32), ("rows_per_task", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("tasks_per_item", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
+
+
+class swe_task(ctypes.Structure):
+    _fields_ = [("patch", ctypes.c_int32), ("strip", ctypes.c_int32), ("row0", ctypes.c_int32),
+                ("rows", ctypes.c_int32)]
+
+
+class swe_item(ctypes.Structure):
+    _fields_ = [("task_begin", ctypes.c_int32), ("task_end", ctypes.c_int32),
+                ("patch", ctypes.c_int32), ("substeps", ctypes.c_int32)]
+
+
+def schedule(seg=64, rows_per_task=0, waves_per_group=4, tasks_per_item=0, order=0,
+             groups_per_cu=0) -> swe_schedule:
+    return swe_schedule(seg, rows_per_task, waves_per_group, tasks_per_item, order, groups_per_cu)
+
+
+def params(g=9.81, drytol=1e-3, h_corr=0.1, manning_n=0.0, cfl_desired=0.9, cfl_max=1.0,
+           sea_level=0.0, h_fp64=1.0, method=SPLIT, order=2, transverse_order=2,
+           precision=F64) -> swe_params:
+    return swe_params(g, drytol, h_corr, manning_n, cfl_desired, cfl_max, sea_level, h_fp64,
+                      method, order, transverse_order, precision)
+
+
+def patch(mx, my, pitch, dx, dy, off=0, plane_stride=None, group=0, tref=1, level=1,
+          bc=(BC_WALL,) * 4) -> swe_patch:
+    if plane_stride is None:
+        plane_stride = pitch * (my + 4)
+    return swe_patch(off, plane_stride, dx, dy, mx, my, pitch, group, tref, level,
+                     (ctypes.c_int8 * 4)(*bc), 0)
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SweError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i32 = ctypes.c_int32
+        pp = ctypes.POINTER(swe_params)
+        L.swe_patch_step.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P, _P]
+        L.swe_ghost_fill.argtypes = [pp, _P, i32, i32, i32, _P, _P, i32, _P]
+        L.swe_speed_scan.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P]
+        L.swe_cfl_reduce.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, i32, _P]
+        L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
+        ps = ctypes.POINTER(swe_schedule)
+        pi32 = ctypes.POINTER(i32)
+        L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32]
+        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ps,
+                                       _P]
+        L.swe_last_error.restype = ctypes.c_char_p
+        L.swe_version.restype = ctypes.c_char_p
+        for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
+                     "swe_mass", "swe_batched_plan", "swe_batched_step"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != SWE_OK:
+        msg = lib().swe_last_error().decode()
+        raise SweError(f"{what} failed ({rc}): {msg}")
+
+
+def swe_version() -> str:
+    return lib().swe_version().decode()
+
+
+def swe_patch_step(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                   smax: int, status: int, stream: int = 0) -> None:
+    _check(lib().swe_patch_step(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
+                                status, stream), "swe_patch_step")
+
+
+def swe_ghost_fill(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,
+                   b: int, fill_b: int, stream: int = 0) -> None:
+    _check(lib().swe_ghost_fill(ctypes.byref(p), patches, n, max_mx, max_my, q, b, fill_b,
+                                stream), "swe_ghost_fill")
+
+
+def swe_speed_scan(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,
+                   b: int, smax_patch: int, stream: int = 0) -> None:
+    _check(lib().swe_speed_scan(ctypes.byref(p), patches, n, max_mx, max_my, q, b, smax_patch,
+                                stream), "swe_speed_scan")
+
+
+def swe_cfl_reduce(p: swe_params, patches: int, n: int, ngroups: int, smax_patch: int,
+                   dt_group: int, status: int, group_flags: int, initial: int,
+                   stream: int = 0) -> None:
+    _check(lib().swe_cfl_reduce(ctypes.byref(p), patches, n, ngroups, smax_patch, dt_group,
+                                status, group_flags, initial, stream), "swe_cfl_reduce")
+
+
+def swe_mass(p: swe_params, patches: int, n: int, q: int, b: int, mass_patch: int,
+             stream: int = 0) -> None:
+    _check(lib().swe_mass(ctypes.byref(p), patches, n, q, b, mass_patch, stream), "swe_mass")
+
+
+def swe_batched_plan(patches, sched: swe_schedule):
+    """Plan for a host list of swe_patch; returns (items, tasks) ctypes arrays."""
+    n = len(patches)
+    arr = (swe_patch * n)(*patches)
+    ni = ctypes.c_int32(0)
+    nt = ctypes.c_int32(0)
+    _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched), None,
+                                  ctypes.byref(ni), None, ctypes.byref(nt)), "swe_batched_plan")
+    items = (swe_item * max(ni.value, 1))()
+    tasks = (swe_task * max(nt.value, 1))()
+    _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched),
+                                  ctypes.addressof(items), ctypes.byref(ni),
+                                  ctypes.addressof(tasks), ctypes.byref(nt)), "swe_batched_plan")
+    return items, ni.value, tasks, nt.value
+
+
+def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
+                     pool_in: int, pool_out: int, pool_work: int, pool_b: int, dt_group: int,
+                     smax_patch: int, status: int, queue: int, sched: swe_schedule,
+                     stream: int = 0) -> None:
+    _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
+                                  pool_out, pool_work, pool_b, dt_group, smax_patch, status,
+                                  queue, ctypes.byref(sched), stream), "swe_batched_step")

@@ -1,0 +1,103 @@
+"""Schedule autotuner for the batched persistent step.
+
+Candidates are (segment width, rows per task, waves per workgroup, workgroups
+per compute unit).  Each is timed on the actual patch set with HIP events
+(warm-up, then the median of several steps); the fastest is kept.  Results
+are cached in a JSON file keyed by the precision and a histogram of patch
+sizes and substep counts, so a patch set of the same shape reuses them.
+Timing never changes results: every schedule gives bit-identical states.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+CACHE = os.environ.get("SWE_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "swe_gfx950_tune.json"))
+
+BUCKETS = (32, 64, 96, 128, 256, 1024, 1 << 30)
+
+
+def signature(solver) -> str:
+    hist = {}
+    for pb, t in zip(solver.problems, solver.trefs):
+        side = max(pb.mx, pb.my)
+        b = next(x for x in BUCKETS if side <= x)
+        key = f"{b}:{t}"
+        hist[key] = hist.get(key, 0) + 1
+    parts = ",".join(f"{k}x{hist[k]}" for k in sorted(hist))
+    return f"p{int(solver.p.precision)}|{parts}"
+
+
+def candidates():
+    out = []
+    for seg in (64, 32):
+        for rows in (0, 8, 16, 32):
+            for waves in (2, 4, 8):
+                for per_cu in (0, 1, 2):
+                    out.append(L.schedule(seg=seg, rows_per_task=rows, waves_per_group=waves,
+                                          groups_per_cu=per_cu))
+    return out
+
+
+def _sched_dict(s: L.swe_schedule) -> dict:
+    return {k: int(getattr(s, k)) for k, _ in L.swe_schedule._fields_}
+
+
+def time_schedule(solver, sched: L.swe_schedule, steps: int = 5) -> float:
+    solver.replan(sched)
+    # restore the same state for every candidate so timings compare
+    saved = [t.clone() for t in solver.pools]
+    dt = solver.dt.clone()
+    solver.enqueue_step(cfl=False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    st = torch.cuda.current_stream(solver.dev)
+    for k in range(steps):
+        ev[2 * k].record(st)
+        solver.enqueue_step(cfl=False)
+        ev[2 * k + 1].record(st)
+    torch.cuda.synchronize(solver.dev)
+    ms = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps)]
+    for t, s in zip(solver.pools, saved):
+        t.copy_(s)
+    solver.dt.copy_(dt)
+    solver.smax.zero_()
+    return float(np.median(ms))
+
+
+def tune(solver, cands=None, use_cache: bool = True, log=None) -> L.swe_schedule:
+    sig = signature(solver)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and sig in cache:
+        best = L.swe_schedule(**cache[sig]["schedule"])
+        solver.replan(best)
+        return best
+    best, best_ms = None, float("inf")
+    results = []
+    for s in cands or candidates():
+        ms = time_schedule(solver, s)
+        results.append((ms, _sched_dict(s)))
+        if log:
+            log(f"[tune] {_sched_dict(s)} {ms:.3f} ms")
+        if ms < best_ms:
+            best, best_ms = s, ms
+    solver.replan(best)
+    if use_cache:
+        cache[sig] = {"schedule": _sched_dict(best), "ms": best_ms}
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(CACHE + ".tmp", CACHE)
+    solver.tune_results = sorted(results, key=lambda r: r[0])
+    return best

@@ -1,0 +1,40 @@
+"""Build step of the HIP library (hipcc, gfx950) -- run on the host, before use."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = ["swe_step.hip", "swe_batched.hip"]
+OUT = os.path.join(HERE, "libswe.so")
+
+# -ffp-contract=off: every product and sum rounds as written, so a cell's
+# result does not depend on the tile or launch that computed it.
+# -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
+HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function"]
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = (["/opt/rocm/bin/hipcc"] + HIPFLAGS + ["-shared", "-I", os.path.join(ROOT, "include"),
+                                                 "-I", CSRC] + srcs + ["-o", OUT + ".tmp"])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    noise = "packed-fp32-ops"
+    err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
+    if verbose and err.strip():
+        print(err, file=sys.stderr)
+    os.replace(OUT + ".tmp", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,332 @@
+// swe_batched.hip -- many patches in one persistent launch (gfx950).
+//
+// Patches of an AMR hierarchy (Qin, LeVeque & Motley, Sec. 3: levels refined
+// in space and time by integer ratios) or the grids of several scenarios are
+// advanced together.  A host-side plan cuts every patch into strip tasks and
+// groups them into items; a fixed grid of workgroups pulls items from a
+// device queue ordered longest first.  A patch with tref substeps forms one
+// item: its workgroup runs the substeps back to back, with a workgroup
+// barrier between them (the patch's writes of one substep are the next
+// substep's reads, and all of them stay on one compute unit).  Ghost cells of
+// physical boundaries are synthesised on load, so each substep refreshes
+// them without a separate pass.  The arithmetic per cell is the same device
+// code as the single-patch step, so a patch's result does not depend on the
+// batch it runs in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "swe.h"
+#include "swe_common.hpp"
+#include "swe_march.hpp"
+
+namespace swe {
+
+struct BatchArgs {
+    const swe_patch* patches;
+    const swe_item* items;
+    const swe_task* tasks;
+    const void* pin;
+    void* pout;
+    void* pwork;
+    const void* pb;
+    const double* dt_group;
+    double* smax;
+    uint32_t* status;
+    uint32_t* queue;  // [0] next item, [1] finished workgroups
+    int nitems;
+    DevParams P;
+};
+
+template <bool DEV, int SEG>
+__global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
+    constexpr int kSegPerWave = kWave / SEG;
+    __shared__ int s_item;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int seg_in_wave = lane / SEG;
+    const int lane_in_seg = lane % SEG;
+    const int nseg = (blockDim.x / kWave) * kSegPerWave;
+    const int seg_id = wave * kSegPerWave + seg_in_wave;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.queue[0], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= a.nitems) break;
+        const swe_item it = a.items[item];
+        const swe_patch pt = a.patches[it.patch];
+        const double dt_sub = a.dt_group[pt.group] / (double)pt.tref;
+        double smx = 0.0, smy = 0.0;
+        uint32_t clamps = 0, flags = 0;
+        const void* src = a.pin;
+        for (int s = 0; s < it.substeps; ++s) {
+            // the last substep lands in pool_out; earlier ones alternate so that
+            // no substep reads the buffer it writes
+            void* dst = ((it.substeps - 1 - s) % 2 == 0) ? a.pout : a.pwork;
+            for (int base = it.task_begin; base < it.task_end; base += nseg) {
+                const int tid = base + seg_id;
+                const bool active = tid < it.task_end;
+                const swe_task tsk = a.tasks[active ? tid : it.task_begin];
+                Task tk;
+                tk.qin = src;
+                tk.qout = dst;
+                tk.b = a.pb;
+                tk.off = pt.off;
+                tk.ps = pt.plane_stride;
+                tk.dt = dt_sub;
+                tk.dx = pt.dx;
+                tk.dy = pt.dy;
+                tk.pitch = pt.pitch;
+                tk.mx = pt.mx;
+                tk.my = pt.my;
+                tk.c0 = tsk.strip * (SEG - 4);
+                tk.U0 = tsk.row0;
+                tk.U1 = tsk.row0 + tsk.rows - 1;
+                tk.bc[0] = pt.bc[0];
+                tk.bc[1] = pt.bc[1];
+                tk.bc[2] = pt.bc[2];
+                tk.bc[3] = pt.bc[3];
+                tk.active = active;
+                // every lane of the wave runs the same number of row iterations
+                int steps = tsk.rows + 4;
+#pragma unroll
+                for (int o = kWave / 2; o >= 1; o >>= 1) {
+                    const int other = __shfl_xor(steps, o, kWave);
+                    steps = other > steps ? other : steps;
+                }
+                const MarchOut r = march<DEV, SEG>(tk, a.P, lane_in_seg, steps);
+                smx = r.smx > smx ? r.smx : smx;
+                smy = r.smy > smy ? r.smy : smy;
+                clamps += r.clamps;
+                flags |= r.flags;
+            }
+            if (s + 1 < it.substeps) {
+                // the next substep reads what this one wrote, across the waves
+                __threadfence_block();
+                __syncthreads();
+            }
+            src = dst;
+        }
+        // NaN propagates through the bit-pattern maximum
+        const double wx = wave_max_nonneg(smx);
+        const double wy = wave_max_nonneg(smy);
+        if (lane == 0) {
+            atomic_max_nonneg(&a.smax[2 * it.patch], wx);
+            atomic_max_nonneg(&a.smax[2 * it.patch + 1], wy);
+        }
+        if (clamps) atomicAdd(&a.status[1], clamps);
+        if (flags) atomicOr(&a.status[0], flags);
+    }
+    // the last workgroup to finish rewinds the queue for the next launch
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&a.queue[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&a.queue[0], 0u);
+            atomicExch(&a.queue[1], 0u);
+        }
+    }
+}
+
+template __global__ void k_batched<false, 64>(BatchArgs);
+template __global__ void k_batched<false, 32>(BatchArgs);
+template __global__ void k_batched<true, 64>(BatchArgs);
+template __global__ void k_batched<true, 32>(BatchArgs);
+
+}  // namespace swe
+
+// ===========================================================================
+// C ABI
+
+namespace {
+
+int bfail(int code, const std::string& msg);
+
+int check_sched(const swe_schedule* s) {
+    if (!s) return bfail(SWE_EINVAL, "schedule is NULL");
+    if (s->seg != 64 && s->seg != 32) return bfail(SWE_EINVAL, "schedule: seg must be 64 or 32");
+    if (s->waves_per_group != 1 && s->waves_per_group != 2 && s->waves_per_group != 4 &&
+        s->waves_per_group != 8)
+        return bfail(SWE_EINVAL, "schedule: waves_per_group must be 1, 2, 4 or 8");
+    if (s->rows_per_task < 0 || s->tasks_per_item < 0 || s->groups_per_cu < 0 ||
+        (s->order != 0 && s->order != 1))
+        return bfail(SWE_EINVAL, "schedule: bad rows_per_task, tasks_per_item, groups_per_cu or order");
+    return SWE_OK;
+}
+
+}  // namespace
+
+// error slot shared with swe_step.hip (not part of the ABI)
+extern "C" __attribute__((visibility("hidden"))) int swe_internal_set_error(int code,
+                                                                           const char* msg);
+
+namespace {
+int bfail(int code, const std::string& msg) { return swe_internal_set_error(code, msg.c_str()); }
+}  // namespace
+
+extern "C" {
+
+int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sched,
+                     swe_item* items, int32_t* nitems, swe_task* tasks, int32_t* ntasks) {
+    int rc = check_sched(sched);
+    if (rc) return rc;
+    if (!patches || n < 0 || !nitems || !ntasks)
+        return bfail(SWE_EINVAL, "swe_batched_plan: bad arguments");
+    const int seg = sched->seg;
+    const int out_cols = seg - 4;
+    const int segs_per_group = sched->waves_per_group * (64 / seg);
+    struct PItem {
+        swe_item it;
+        double cost;
+    };
+    std::vector<PItem> its;
+    std::vector<swe_task> tks;
+    for (int k = 0; k < n; ++k) {
+        const swe_patch& p = patches[k];
+        if (p.mx < 1 || p.my < 1 || p.pitch < p.mx + 4 || p.tref < 1 || !(p.dx > 0) ||
+            !(p.dy > 0) || p.off < 0 || p.plane_stride < (int64_t)p.pitch * (p.my + 4))
+            return bfail(SWE_EINVAL, "swe_batched_plan: patch " + std::to_string(k) + " has a bad shape");
+        for (int s = 0; s < 4; ++s) {
+            if (p.bc[s] != SWE_BC_WALL && p.bc[s] != SWE_BC_EXTRAP && p.bc[s] != SWE_BC_USER)
+                return bfail(SWE_EINVAL, "swe_batched_plan: unknown boundary code");
+            if (p.bc[s] == SWE_BC_USER && p.tref > 1)
+                return bfail(SWE_EINVAL, "swe_batched_plan: a user boundary needs tref == 1");
+        }
+        if ((p.bc[0] == SWE_BC_WALL || p.bc[1] == SWE_BC_WALL) && p.mx < 2)
+            return bfail(SWE_EINVAL, "swe_batched_plan: a wall in x needs mx >= 2");
+        if ((p.bc[2] == SWE_BC_WALL || p.bc[3] == SWE_BC_WALL) && p.my < 2)
+            return bfail(SWE_EINVAL, "swe_batched_plan: a wall in y needs my >= 2");
+        const int nstrips = (p.mx + out_cols - 1) / out_cols;
+        int H = sched->rows_per_task;
+        if (H == 0) {
+            // enough tasks to keep every segment of a workgroup busy, rows >= 8
+            const int want = (segs_per_group + nstrips - 1) / nstrips;
+            H = (p.my + want - 1) / want;
+            if (H < 8) H = 8;
+            if (p.tref == 1 && H > 64) H = 64;
+        }
+        if (H > p.my) H = p.my;
+        const int nchunks = (p.my + H - 1) / H;
+        const int first = (int)tks.size();
+        for (int cidx = 0; cidx < nchunks; ++cidx)
+            for (int st = 0; st < nstrips; ++st) {
+                swe_task t;
+                t.patch = k;
+                t.strip = st;
+                t.row0 = 2 + cidx * H;
+                t.rows = std::min(H, p.my - cidx * H);
+                tks.push_back(t);
+            }
+        const int last = (int)tks.size();
+        const double cost_per_task = (double)seg * (H + 4);
+        if (p.tref > 1) {
+            PItem pi;
+            pi.it = swe_item{first, last, k, p.tref};
+            pi.cost = cost_per_task * (last - first) * p.tref / segs_per_group;
+            its.push_back(pi);
+        } else {
+            int per = sched->tasks_per_item;
+            if (per == 0) per = 4 * segs_per_group;
+            for (int b = first; b < last; b += per) {
+                PItem pi;
+                pi.it = swe_item{b, std::min(b + per, last), k, 1};
+                pi.cost = cost_per_task * (pi.it.task_end - b) / segs_per_group;
+                its.push_back(pi);
+            }
+        }
+    }
+    if (sched->order == 0)
+        std::stable_sort(its.begin(), its.end(),
+                         [](const PItem& x, const PItem& y) { return x.cost > y.cost; });
+    if (!items || !tasks) {
+        *nitems = (int32_t)its.size();
+        *ntasks = (int32_t)tks.size();
+        return SWE_OK;
+    }
+    if (*nitems < (int32_t)its.size() || *ntasks < (int32_t)tks.size())
+        return bfail(SWE_EINVAL, "swe_batched_plan: output arrays too small");
+    for (size_t i = 0; i < its.size(); ++i) items[i] = its[i].it;
+    std::copy(tks.begin(), tks.end(), tasks);
+    *nitems = (int32_t)its.size();
+    *ntasks = (int32_t)tks.size();
+    return SWE_OK;
+}
+
+int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
+                     int32_t nitems, const swe_task* tasks, const void* pool_in, void* pool_out,
+                     void* pool_work, const void* pool_b, const double* dt_group,
+                     double* smax_patch, uint32_t* status, uint32_t* queue,
+                     const swe_schedule* sched, void* stream) {
+    if (!p) return bfail(SWE_EINVAL, "params is NULL");
+    int rc = check_sched(sched);
+    if (rc) return rc;
+    if (p->method != SWE_SPLIT) return bfail(SWE_EINVAL, "swe_batched_step: only the split step");
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+        return bfail(SWE_EINVAL, "swe_batched_step: unknown precision");
+    if (p->order != 1 && p->order != 2) return bfail(SWE_EINVAL, "params: order must be 1 or 2");
+    if (!patches || !items || !tasks || !pool_in || !pool_out || !pool_b || !dt_group ||
+        !smax_patch || !status || !queue || nitems < 0)
+        return bfail(SWE_EINVAL, "swe_batched_step: null pointer or negative count");
+    if (pool_in == pool_out || pool_work == pool_in || pool_work == pool_out)
+        return bfail(SWE_EINVAL, "swe_batched_step: pools must be distinct");
+    if (nitems == 0) return SWE_OK;
+    swe::BatchArgs a;
+    a.patches = patches;
+    a.items = items;
+    a.tasks = tasks;
+    a.pin = pool_in;
+    a.pout = pool_out;
+    a.pwork = pool_work ? pool_work : pool_out;
+    a.pb = pool_b;
+    a.dt_group = dt_group;
+    a.smax = smax_patch;
+    a.status = status;
+    a.queue = queue;
+    a.nitems = nitems;
+    a.P.g = p->g;
+    a.P.drytol = p->drytol;
+    a.P.h_corr = p->h_corr;
+    a.P.manning_n = p->manning_n;
+    a.P.sea_level = p->sea_level;
+    a.P.h_fp64 = p->h_fp64;
+    a.P.order = p->order;
+
+    const int threads = 64 * sched->waves_per_group;
+    const bool dev = p->precision == SWE_F32_DEV;
+    const void* fn = nullptr;
+    if (!dev && sched->seg == 64) fn = reinterpret_cast<const void*>(&swe::k_batched<false, 64>);
+    if (!dev && sched->seg == 32) fn = reinterpret_cast<const void*>(&swe::k_batched<false, 32>);
+    if (dev && sched->seg == 64) fn = reinterpret_cast<const void*>(&swe::k_batched<true, 64>);
+    if (dev && sched->seg == 32) fn = reinterpret_cast<const void*>(&swe::k_batched<true, 32>);
+    int dev_id = 0, ncu = 0;
+    if (hipGetDevice(&dev_id) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
+        ncu < 1)
+        return bfail(SWE_EHIP, "swe_batched_step: cannot query the device");
+    int per_cu = sched->groups_per_cu;
+    if (per_cu == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+    }
+    int grid = ncu * per_cu;
+    if (grid > nitems) grid = nitems;
+    if (grid < 1) grid = 1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!dev && sched->seg == 64) hipLaunchKernelGGL((swe::k_batched<false, 64>), dim3(grid), dim3(threads), 0, st, a);
+    if (!dev && sched->seg == 32) hipLaunchKernelGGL((swe::k_batched<false, 32>), dim3(grid), dim3(threads), 0, st, a);
+    if (dev && sched->seg == 64) hipLaunchKernelGGL((swe::k_batched<true, 64>), dim3(grid), dim3(threads), 0, st, a);
+    if (dev && sched->seg == 32) hipLaunchKernelGGL((swe::k_batched<true, 32>), dim3(grid), dim3(threads), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return bfail(SWE_EHIP, std::string("swe_batched_step: ") + hipGetErrorString(e));
+    return SWE_OK;
+}
+
+}  // extern "C"

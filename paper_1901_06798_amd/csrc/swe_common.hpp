@@ -1,0 +1,105 @@
+// swe_common.hpp -- layout helpers shared by the gfx950 kernels: ghost-cell
+// synthesis on load, wave64 cross-lane moves and reductions, status words.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "swe.h"
+#include "swe_math.hpp"
+
+namespace swe {
+
+constexpr int kWave = 64;
+constexpr int kStripOut = kWave - 4;  // columns updated per wave64 strip
+
+// Where cell (R, c) of a patch (row R, column c, ghosts included) comes from.
+// Sides with a physical boundary code are synthesised from the interior:
+// x-ghosts of interior rows from the x-sides, then y-ghosts of all columns
+// from the y-sides; a side with SWE_BC_USER is read from memory as stored.
+struct Src {
+    int64_t idx;   // element index in the planes
+    double sx;     // sign applied to hu (x-wall)
+    double sy;     // sign applied to hv (y-wall)
+};
+
+__device__ __forceinline__ Src map_cell(int R, int c, int mx, int my, int pitch, int64_t off,
+                                        const int8_t* bc) {
+    double sx = 1.0, sy = 1.0;
+    int rr = R, ci = c;
+    bool user_row = false;
+    if (R < 2) {
+        if (bc[2] == SWE_BC_USER) user_row = true;
+        else if (bc[2] == SWE_BC_WALL) { rr = 3 - R; sy = -1.0; }
+        else rr = 2;
+    } else if (R > my + 1) {
+        if (bc[3] == SWE_BC_USER) user_row = true;
+        else if (bc[3] == SWE_BC_WALL) { rr = 2 * my + 3 - R; sy = -1.0; }
+        else rr = my + 1;
+    }
+    if (!user_row) {
+        if (c < 2) {
+            if (bc[0] == SWE_BC_WALL) { ci = 3 - c; sx = -1.0; }
+            else if (bc[0] == SWE_BC_EXTRAP) ci = 2;
+        } else if (c > mx + 1) {
+            if (bc[1] == SWE_BC_WALL) { ci = 2 * mx + 3 - c; sx = -1.0; }
+            else if (bc[1] == SWE_BC_EXTRAP) ci = mx + 1;
+        }
+    }
+    Src s;
+    s.idx = off + (int64_t)rr * pitch + ci;
+    s.sx = sx;
+    s.sy = sy;
+    return s;
+}
+
+// Lane moves within a segment of SEG lanes (SEG = 64: the whole wave):
+// up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1;
+// the first/last lane of a segment keeps its own value.
+template <int SEG = kWave>
+__device__ __forceinline__ double lane_up(double x) { return __shfl_up(x, 1, SEG); }
+template <int SEG = kWave>
+__device__ __forceinline__ double lane_down(double x) { return __shfl_down(x, 1, SEG); }
+template <int SEG = kWave>
+__device__ __forceinline__ float lane_up(float x) { return __shfl_up(x, 1, SEG); }
+template <int SEG = kWave>
+__device__ __forceinline__ float lane_down(float x) { return __shfl_down(x, 1, SEG); }
+
+template <typename T, bool DEV = false, int SEG = kWave>
+__device__ __forceinline__ Side<T> side_up(const Side<T>& s, const DevParams& P) {
+    Side<T> r;
+    r.h = lane_up<SEG>(s.h);
+    r.m = lane_up<SEG>(s.m);
+    r.t = lane_up<SEG>(s.t);
+    r.b = lane_up<SEG>(s.b);
+    r.u = lane_up<SEG>(s.u);
+    r.v = lane_up<SEG>(s.v);
+    r.sq = lane_up<SEG>(s.sq);
+    r.c = lane_up<SEG>(s.c);
+    r.eta = DEV ? lane_up<SEG>(s.eta) : T(0);
+    r.dry = r.h <= T(P.drytol);
+    return r;
+}
+
+// Largest of the lanes' non-negative doubles.  Such doubles order like their
+// bit patterns read as unsigned integers, and a NaN sorts above every number,
+// so the comparison is done on the bits: NaN propagates.
+template <int SEG = kWave>
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+#pragma unroll
+    for (int o = SEG / 2; o >= 1; o >>= 1) {
+        unsigned long long w = static_cast<unsigned long long>(
+            __shfl_xor(static_cast<long long>(b), o, SEG));
+        b = b > w ? b : w;
+    }
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(addr),
+              static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+}  // namespace swe

@@ -1,0 +1,279 @@
+// swe_march.hpp -- the split step of one strip of a patch, marched down its
+// rows by a segment of SEG lanes (SEG = 64: a whole wave64; SEG = 32: two
+// strips, possibly of different patches, share a wave).
+//
+// Qin, LeVeque & Motley, Sec. 2, dimensionally split x/y forms.  A segment
+// owns SEG adjacent columns and updates the SEG - 4 inner ones over a chunk of
+// rows.  For every row it loads (h or eta', hu, hv, b) once (coalesced along
+// x), solves the x-edges of the row one lane per edge, exchanges neighbour
+// data across lanes for the limiter and the update, and so obtains Q* of the
+// row in registers.  The y-sweep is a per-lane pipeline over the rows of Q*:
+// each lane keeps the waves of the last y-edge, so every y-edge of its column
+// is solved once, and the cell two rows behind is finished and written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "swe.h"
+#include "swe_common.hpp"
+#include "swe_math.hpp"
+
+namespace swe {
+
+template <bool DEV>
+struct Prec;
+template <>
+struct Prec<false> {
+    using S = double;
+};
+template <>
+struct Prec<true> {
+    using S = float;
+};
+
+// Side of a cell from its stored values (q0 = h, or eta' on the deviation
+// path, where h = eta' + sea_level - b).
+template <bool DEV, typename T, typename S>
+__device__ __forceinline__ Side<T> side_from(S q0, S m, S t, S b, const DevParams& P) {
+    if (!DEV) return make_side<T>(T(q0), T(m), T(t), T(b), P);
+    const T h = T(q0) + T(P.sea_level) - T(b);
+    Side<T> s = make_side<T>(h, T(m), T(t), T(b), P);
+    s.eta = T(q0);
+    return s;
+}
+
+// Riemann solve of one edge.  On the deviation path an edge with a cell at
+// or below h_fp64 deep (dry cells included) is solved in FP64 from the exact
+// FP64 values of the stored floats; its waves are rounded to FP32.
+template <bool DEV, typename S>
+__device__ __forceinline__ void solve_edge(const Side<S>& L, const Side<S>& R, S mL, S tL, S mR,
+                                           S tR, const DevParams& P, Waves<S>& w) {
+    if (!DEV) {
+        riemann<S, false>(L, R, P, w);
+        return;
+    }
+    const bool wide = L.h <= S(P.h_fp64) || R.h <= S(P.h_fp64);
+    if (wide) {
+        const Side<double> L64 = side_from<true, double, double>(L.eta, mL, tL, L.b, P);
+        const Side<double> R64 = side_from<true, double, double>(R.eta, mR, tR, R.b, P);
+        Waves<double> w64;
+        riemann<double, true>(L64, R64, P, w64);
+        w.kind = w64.kind;
+        w.shallow = w64.shallow;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            w.s[p] = S(w64.s[p]);
+            w.z[p][0] = S(w64.z[p][0]);
+            w.z[p][1] = S(w64.z[p][1]);
+            w.z[p][2] = S(w64.z[p][2]);
+        }
+    } else {
+        riemann<S, true>(L, R, P, w);
+    }
+}
+
+// Dry cleanup after a sweep: no momentum at or below the dry tolerance; a
+// negative depth is reset to 0 and counted.  `valid` marks lanes whose value
+// belongs to the patch (only those report).
+template <bool DEV, typename S>
+__device__ __forceinline__ void cleanup(S q[3], S b, const DevParams& P, bool valid, bool count,
+                                        uint32_t& clamps, uint32_t& flags) {
+    if (valid && !(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2])))
+        flags |= SWE_STATUS_NONFINITE;
+    const S h = DEV ? q[0] + S(P.sea_level) - b : q[0];
+    if (h < S(0)) {
+        q[0] = DEV ? b - S(P.sea_level) : S(0);
+        q[1] = q[2] = S(0);
+        if (count) {
+            ++clamps;
+            flags |= SWE_STATUS_NEG_DEPTH;
+        }
+    } else if (h <= S(P.drytol)) {
+        q[1] = q[2] = S(0);
+    }
+}
+
+// One strip task as seen by one lane.
+struct Task {
+    const void* qin;
+    void* qout;
+    const void* b;
+    int64_t off, ps;
+    double dt, dx, dy;
+    int pitch, mx, my;
+    int c0;       // column (ghosts included) of the segment's first lane
+    int U0, U1;   // first and last row updated (ghost rows are 0, 1, my + 2, my + 3)
+    int8_t bc[4];
+    bool active;  // false: the lane only takes part in the cross-lane moves
+};
+
+// Per-lane results of a march.
+struct MarchOut {
+    double smx, smy;
+    uint32_t clamps, flags;
+};
+
+// March one strip task.  `steps` is the number of row iterations every lane
+// of the wave executes (the largest over the wave's segments); a lane whose
+// own strip is shorter repeats its last row with writes and reports masked.
+template <bool DEV, int SEG>
+__device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, int lane_in_seg,
+                                          int steps) {
+    using S = typename Prec<DEV>::S;
+    const S* __restrict__ qin = static_cast<const S*>(tk.qin);
+    S* __restrict__ qout = static_cast<S*>(tk.qout);
+    const S* __restrict__ bpl = static_cast<const S*>(tk.b);
+    const int lane = lane_in_seg;
+    const int c = tk.c0 + lane;  // column of this lane (ghosts included)
+    const int cc = c < tk.mx + 3 ? c : tk.mx + 3;
+    const bool upd_col = tk.active && lane >= 2 && lane <= SEG - 3 && c <= tk.mx + 1;
+    const bool xedge_own = tk.active && lane >= 2 && lane <= SEG - 2 && c >= 2 && c <= tk.mx + 2;
+    const int U0 = tk.U0, U1 = tk.U1;
+    const S lamx = S(tk.dt / tk.dx), lamy = S(tk.dt / tk.dy);
+    const bool second = P.order >= 2;
+    const int tlast = U1 - U0 + 4;
+
+    S smx = S(0), smy = S(0);
+    uint32_t clamps = 0, flags = 0;
+
+    // rolling state of the y-pipeline (row R - 1, R - 2 of Q*, edge E - 1)
+    Side<S> prev;
+    S prev_m = S(0), prev_t = S(0);
+    S qm1[3] = {0, 0, 0}, qm2[3] = {0, 0, 0};
+    S qm1_b = S(0), qm2_b = S(0);
+    Waves<S> wprev;
+    S dprev[3] = {0, 0, 0};
+    S ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
+
+    for (int t = 0; t < steps; ++t) {
+        const bool live = t <= tlast;
+        const int R = U0 - 2 + (live ? t : tlast);
+        const bool interior_row = live && R >= U0 && R <= U1;
+
+        // ---- load row R (ghosts synthesised for physical boundaries)
+        const Src src = map_cell(R, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+        const S q0 = qin[src.idx];
+        const S hu = S(src.sx) * qin[src.idx + tk.ps];
+        const S hv = S(src.sy) * qin[src.idx + 2 * tk.ps];
+        const S bb = bpl[src.idx];
+
+        // ---- x-sweep of row R: lane k solves the edge between columns k-1, k
+        const Side<S> me = side_from<DEV, S, S>(q0, hu, hv, bb, P);
+        const Side<S> lf = side_up<S, DEV, SEG>(me, P);
+        const S lf_m = DEV ? lane_up<SEG>(hu) : S(0), lf_t = DEV ? lane_up<SEG>(hv) : S(0);
+        Waves<S> w;
+        solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
+        S am[3], ap[3];
+        fluctuations(w, am, ap);
+        S F[3] = {S(0), S(0), S(0)};
+        if (second) {
+            S dr[3], dl[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const S zr0 = lane_down<SEG>(w.z[p][0]);
+                const S zr1 = lane_down<SEG>(w.z[p][1]);
+                const S zr2 = lane_down<SEG>(w.z[p][2]);
+                dr[p] = w.z[p][0] * zr0 + w.z[p][1] * zr1 + w.z[p][2] * zr2;
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
+            correction(w, dl, dr, lamx, F);
+        }
+        S qs[3];
+        {
+            const S qc[3] = {q0, hu, hv};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const S amr = lane_down<SEG>(am[k]);
+                const S Fr = lane_down<SEG>(F[k]);
+                qs[k] = qc[k] - lamx * (ap[k] + amr) - lamx * (Fr - F[k]);
+            }
+        }
+        cleanup<DEV, S>(qs, bb, P, upd_col && live, interior_row && upd_col, clamps, flags);
+        if (interior_row && xedge_own) {
+            const S s = max_speed(w);
+            smx = s > smx ? s : smx;
+        }
+
+        // ---- y-sweep pipeline on the column of Q* (normal momentum hv)
+        const Side<S> cur = side_from<DEV, S, S>(qs[0], qs[2], qs[1], bb, P);
+        if (t >= 1) {
+            Waves<S> wy;
+            solve_edge<DEV, S>(prev, cur, prev_m, prev_t, qs[2], qs[1], P, wy);
+            const int E = R;  // edge between rows R - 1 and R
+            if (live && E >= U0 && E <= U1 + 1 && upd_col) {
+                const S s = max_speed(wy);
+                smy = s > smy ? s : smy;
+            }
+            S dcur[3] = {S(0), S(0), S(0)};
+            if (second && t >= 2) {
+#pragma unroll
+                for (int p = 0; p < 3; ++p) dcur[p] = dot3(wprev.z[p], wy.z[p]);
+            }
+            if (t >= 3) {
+                // edge E - 1: fluctuations and correction
+                S am1[3], ap1[3], F1[3] = {S(0), S(0), S(0)};
+                fluctuations(wprev, am1, ap1);
+                if (second) correction(wprev, dprev, dcur, lamy, F1);
+                if (t >= 4) {
+                    // finish row R - 2 between edges E - 2 and E - 1
+                    S qn[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        qn[k] = qm2[k] - lamy * (ap_prev[k] + am1[k]) - lamy * (F1[k] - F_prev[k]);
+                    // the y-sweep works in (h, hv, hu)
+                    S out[3] = {qn[0], qn[2], qn[1]};
+                    const S bo = qm2_b;
+                    const bool wr = upd_col && live;
+                    cleanup<DEV, S>(out, bo, P, wr, wr, clamps, flags);
+                    if (P.manning_n > 0.0) {
+                        const S hd = DEV ? out[0] + S(P.sea_level) - bo : out[0];
+                        if (hd > S(P.drytol)) {
+                            const S n2g = S(P.manning_n) * S(P.manning_n) * S(P.g);
+                            const S speed = sqrt(out[1] * out[1] + out[2] * out[2]) / hd;
+                            const S D = n2g * S(pow(double(hd), -7.0 / 3.0)) * speed;
+                            const S f = S(1) / (S(1) + S(tk.dt) * D);
+                            out[1] *= f;
+                            out[2] *= f;
+                        }
+                    }
+                    if (wr) {
+                        const int64_t o = tk.off + (int64_t)(R - 2) * tk.pitch + c;
+                        qout[o] = out[0];
+                        qout[o + tk.ps] = out[1];
+                        qout[o + 2 * tk.ps] = out[2];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    ap_prev[k] = ap1[k];
+                    F_prev[k] = F1[k];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) dprev[p] = dcur[p];
+            wprev = wy;
+        }
+        // Q* of row R in y order (h, hv, hu) for the update two rows later
+#pragma unroll
+        for (int k = 0; k < 3; ++k) qm2[k] = qm1[k];
+        qm2_b = qm1_b;
+        qm1[0] = qs[0];
+        qm1[1] = qs[2];
+        qm1[2] = qs[1];
+        qm1_b = bb;
+        prev = cur;
+        prev_m = qs[2];
+        prev_t = qs[1];
+    }
+    MarchOut o;
+    o.smx = double(smx);
+    o.smy = double(smy);
+    o.clamps = clamps;
+    o.flags = flags;
+    return o;
+}
+
+}  // namespace swe

@@ -1,0 +1,473 @@
+// swe_step.hip -- the per-patch split step on gfx950 (FP64), and the small
+// kernels around it: ghost fill, speed scan, CFL reduction, mass.
+//
+// Split step (Qin, LeVeque & Motley, Sec. 2, dimensionally split x/y forms):
+// one wave64 owns a strip of 64 adjacent columns (60 of which it updates) and
+// a chunk of rows, and marches down the rows.  For every row it loads
+// (h, hu, hv, b) once from HBM (coalesced along x), solves the x-edges of the
+// row with one lane per edge, exchanges neighbour data across lanes for the
+// limiter and the update, and obtains Q* of the row in registers.  The
+// y-sweep is a per-lane pipeline over the rows of Q*: each lane keeps the
+// waves of the last y-edges, so every y-edge of the column is solved once, and
+// the cell two rows behind is finished and written.  Every cell of the state is
+// read once and written once; no LDS and no barriers are needed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "swe.h"
+#include "swe_common.hpp"
+#include "swe_march.hpp"
+#include "swe_math.hpp"
+
+namespace swe {
+
+// Arguments of one patch step.  Planes hold doubles (FP64: h, hu, hv, b) or
+// floats (surface-deviation path: eta', hu, hv, b).
+struct StepArgs {
+    const void* qin;
+    void* qout;
+    const void* b;
+    const double* dt;
+    double* smax;
+    uint32_t* status;
+    int64_t off, ps;
+    double dx, dy;
+    int pitch, mx, my, H, nstrips, nitems;
+    int8_t bc[4];
+    DevParams P;
+};
+
+// One patch, one wave64 per (strip, chunk of H rows).
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_split(StepArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (item >= a.nitems) return;  // whole wave leaves together
+    Task tk;
+    tk.qin = a.qin;
+    tk.qout = a.qout;
+    tk.b = a.b;
+    tk.off = a.off;
+    tk.ps = a.ps;
+    tk.dt = *a.dt;
+    tk.dx = a.dx;
+    tk.dy = a.dy;
+    tk.pitch = a.pitch;
+    tk.mx = a.mx;
+    tk.my = a.my;
+    tk.c0 = (item % a.nstrips) * kStripOut;
+    tk.U0 = 2 + (item / a.nstrips) * a.H;
+    tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
+    for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
+    tk.active = true;
+    const MarchOut o = march<DEV, kWave>(tk, a.P, lane, tk.U1 - tk.U0 + 5);
+    const double wx = wave_max_nonneg(o.smx);
+    const double wy = wave_max_nonneg(o.smy);
+    if (lane == 0) {
+        atomic_max_nonneg(&a.smax[0], wx);
+        atomic_max_nonneg(&a.smax[1], wy);
+    }
+    if (o.clamps) atomicAdd(&a.status[1], o.clamps);
+    if (o.flags) atomicOr(&a.status[0], o.flags);
+}
+
+template __global__ void k_split<false>(StepArgs);
+template __global__ void k_split<true>(StepArgs);
+
+// ---------------------------------------------------------------------------
+// Batched helpers: one block row (blockIdx.y) per patch.
+
+struct PatchView {
+    int64_t off, ps;
+    int mx, my, pitch;
+    int8_t bc[4];
+};
+
+__device__ __forceinline__ PatchView view(const swe_patch& p) {
+    PatchView v;
+    v.off = p.off;
+    v.ps = p.plane_stride;
+    v.mx = p.mx;
+    v.my = p.my;
+    v.pitch = p.pitch;
+    v.bc[0] = p.bc[0];
+    v.bc[1] = p.bc[1];
+    v.bc[2] = p.bc[2];
+    v.bc[3] = p.bc[3];
+    return v;
+}
+
+// Ghost cells of a patch written into memory by the synthesis rule.
+template <typename S>
+__global__ void __launch_bounds__(256) k_ghost_fill(const swe_patch* __restrict__ patches, S* q,
+                                                    S* b, int fill_b) {
+    const PatchView v = view(patches[blockIdx.y]);
+    const int nx = v.mx + 4;
+    const int nperim = 4 * nx + 4 * v.my;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x) {
+        int R, c;
+        if (k < 2 * nx) { R = k / nx; c = k % nx; }
+        else if (k < 4 * nx) { R = v.my + 2 + (k - 2 * nx) / nx; c = (k - 2 * nx) % nx; }
+        else {
+            const int r = k - 4 * nx;
+            R = 2 + r / 4;
+            const int s = r % 4;
+            c = s < 2 ? s : v.mx + s;
+        }
+        bool write;
+        if (R < 2) write = v.bc[2] != SWE_BC_USER;
+        else if (R > v.my + 1) write = v.bc[3] != SWE_BC_USER;
+        else write = (c < 2) ? v.bc[0] != SWE_BC_USER : v.bc[1] != SWE_BC_USER;
+        if (!write) continue;
+        const Src s = map_cell(R, c, v.mx, v.my, v.pitch, v.off, v.bc);
+        const int64_t dst = v.off + (int64_t)R * v.pitch + c;
+        const S h = q[s.idx], hu = S(s.sx) * q[s.idx + v.ps], hv = S(s.sy) * q[s.idx + 2 * v.ps];
+        q[dst] = h;
+        q[dst + v.ps] = hu;
+        q[dst + 2 * v.ps] = hv;
+        if (fill_b) b[dst] = b[s.idx];
+    }
+}
+
+// Largest speeds over the x- and y-edges of the interior cells of each patch.
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict__ patches,
+                                                    const void* qv, const void* bv, double* smax,
+                                                    DevParams P) {
+    using S = typename Prec<DEV>::S;
+    const S* __restrict__ q = static_cast<const S*>(qv);
+    const S* __restrict__ b = static_cast<const S*>(bv);
+    const int pk = blockIdx.y;
+    const PatchView v = view(patches[pk]);
+    double sx = 0.0, sy = 0.0;
+    const int ncell = v.mx * v.my;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ncell; k += gridDim.x * blockDim.x) {
+        const int c = 2 + k % v.mx;
+        const int R = 2 + k / v.mx;
+        struct Cell {
+            Side<S> s;
+            S m, t;
+        };
+        auto load = [&](int RR, int CC, bool ydir) {
+            const Src s = map_cell(RR, CC, v.mx, v.my, v.pitch, v.off, v.bc);
+            const S q0 = q[s.idx], hu = S(s.sx) * q[s.idx + v.ps], hv = S(s.sy) * q[s.idx + 2 * v.ps];
+            Cell cl;
+            cl.m = ydir ? hv : hu;
+            cl.t = ydir ? hu : hv;
+            cl.s = side_from<DEV, S, S>(q0, cl.m, cl.t, b[s.idx], P);
+            return cl;
+        };
+        Waves<S> w;
+        const Cell me = load(R, c, false);
+        Cell o = load(R, c - 1, false);
+        solve_edge<DEV, S>(o.s, me.s, o.m, o.t, me.m, me.t, P, w);
+        sx = fmax(sx, double(max_speed(w)));
+        if (c == v.mx + 1) {
+            o = load(R, c + 1, false);
+            solve_edge<DEV, S>(me.s, o.s, me.m, me.t, o.m, o.t, P, w);
+            sx = fmax(sx, double(max_speed(w)));
+        }
+        const Cell mey = load(R, c, true);
+        o = load(R - 1, c, true);
+        solve_edge<DEV, S>(o.s, mey.s, o.m, o.t, mey.m, mey.t, P, w);
+        sy = fmax(sy, double(max_speed(w)));
+        if (R == v.my + 1) {
+            o = load(R + 1, c, true);
+            solve_edge<DEV, S>(mey.s, o.s, mey.m, mey.t, o.m, o.t, P, w);
+            sy = fmax(sy, double(max_speed(w)));
+        }
+    }
+    sx = wave_max_nonneg(sx);
+    sy = wave_max_nonneg(sy);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomic_max_nonneg(&smax[2 * pk], sx);
+        atomic_max_nonneg(&smax[2 * pk + 1], sy);
+    }
+}
+
+// CFL rule per group; one block per group.
+__global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict__ patches, int n,
+                                                    double* smax, double* dt_group,
+                                                    uint32_t* status, uint32_t* group_flags,
+                                                    double cfl_desired, double cfl_max,
+                                                    int initial) {
+    const int g = blockIdx.x;
+    __shared__ unsigned long long red[256 / kWave];
+    double rate = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const swe_patch& p = patches[k];
+        if (p.group != g) continue;
+        const double rx = smax[2 * k] / p.dx, ry = smax[2 * k + 1] / p.dy;
+        double r = rx > ry ? rx : ry;
+        r = r / (double)p.tref;
+        if (isnan(rx) || isnan(ry)) r = rx + ry;
+        rate = (r > rate || isnan(r)) ? r : rate;
+        smax[2 * k] = 0.0;
+        smax[2 * k + 1] = 0.0;
+    }
+    rate = wave_max_nonneg(rate);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        red[threadIdx.x / kWave] = static_cast<unsigned long long>(__double_as_longlong(rate));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) m = red[i] > m ? red[i] : m;
+        const double r = __longlong_as_double(static_cast<long long>(m));
+        const double dt = dt_group[g];
+        uint32_t f = 0;
+        if (isnan(r)) f |= SWE_STATUS_NONFINITE;
+        if (!initial && r > 0.0 && dt * r > cfl_max) f |= SWE_STATUS_CFL_EXCEEDED;
+        if (r > 0.0 && isfinite(r)) dt_group[g] = cfl_desired / r;
+        if (f) {
+            atomicOr(status, f);
+            if (group_flags) atomicOr(&group_flags[g], f);
+        }
+    }
+}
+
+// Water volume per patch, FP64, fixed reduction order.  On the deviation
+// path the depth is eta' + sea_level - b, formed in FP64.
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_mass(const swe_patch* __restrict__ patches,
+                                              const void* qv, const void* bv,
+                                              double* __restrict__ mass, double sea_level) {
+    using S = typename Prec<DEV>::S;
+    const S* __restrict__ q = static_cast<const S*>(qv);
+    const S* __restrict__ b = static_cast<const S*>(bv);
+    const int pk = blockIdx.x;
+    const swe_patch p = patches[pk];
+    __shared__ double red[256];
+    double s = 0.0;
+    const int64_t ncell = (int64_t)p.mx * p.my;
+    for (int64_t k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int c = 2 + (int)(k % p.mx);
+        const int R = 2 + (int)(k / p.mx);
+        const int64_t i = p.off + (int64_t)R * p.pitch + c;
+        s += DEV ? (double(q[i]) + sea_level) - double(b[i]) : double(q[i]);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mass[pk] = red[0] * p.dx * p.dy;
+}
+
+}  // namespace swe
+
+// ===========================================================================
+// C ABI
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SWE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return SWE_OK;
+}
+
+swe::DevParams dev_params(const swe_params* p) {
+    swe::DevParams d;
+    d.g = p->g;
+    d.drytol = p->drytol;
+    d.h_corr = p->h_corr;
+    d.manning_n = p->manning_n;
+    d.sea_level = p->sea_level;
+    d.h_fp64 = p->h_fp64;
+    d.order = p->order;
+    return d;
+}
+
+int check_params(const swe_params* p) {
+    if (!p) return fail(SWE_EINVAL, "params is NULL");
+    if (!(p->g > 0.0) || !(p->drytol >= 0.0) || !(p->h_corr >= 0.0) || !(p->manning_n >= 0.0) ||
+        !(p->cfl_desired > 0.0) || !(p->cfl_max > 0.0))
+        return fail(SWE_EINVAL, "params: g, cfl_desired, cfl_max must be > 0; drytol, h_corr, "
+                                "manning_n must be >= 0");
+    if (p->order != 1 && p->order != 2) return fail(SWE_EINVAL, "params: order must be 1 or 2");
+    if (p->method != SWE_SPLIT && p->method != SWE_UNSPLIT)
+        return fail(SWE_EINVAL, "params: unknown method");
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+        return fail(SWE_EINVAL, "params: unknown precision");
+    return SWE_OK;
+}
+
+int check_patch(const swe_patch* pt) {
+    if (!pt) return fail(SWE_EINVAL, "patch is NULL");
+    if (pt->mx < 1 || pt->my < 1) return fail(SWE_EINVAL, "patch: mx and my must be >= 1");
+    if (pt->pitch < pt->mx + 4) return fail(SWE_EINVAL, "patch: pitch must be >= mx + 4");
+    if (pt->off < 0 || pt->plane_stride < (int64_t)pt->pitch * (pt->my + 4))
+        return fail(SWE_EINVAL, "patch: off must be >= 0 and plane_stride >= pitch * (my + 4)");
+    if (!(pt->dx > 0.0) || !(pt->dy > 0.0)) return fail(SWE_EINVAL, "patch: dx, dy must be > 0");
+    if (pt->tref < 1) return fail(SWE_EINVAL, "patch: tref must be >= 1");
+    for (int s = 0; s < 4; ++s)
+        if (pt->bc[s] != SWE_BC_WALL && pt->bc[s] != SWE_BC_EXTRAP && pt->bc[s] != SWE_BC_USER)
+            return fail(SWE_EINVAL, "patch: unknown boundary code");
+    if ((pt->bc[0] == SWE_BC_WALL || pt->bc[1] == SWE_BC_WALL) && pt->mx < 2)
+        return fail(SWE_EINVAL, "patch: a wall in x needs mx >= 2");
+    if ((pt->bc[2] == SWE_BC_WALL || pt->bc[3] == SWE_BC_WALL) && pt->my < 2)
+        return fail(SWE_EINVAL, "patch: a wall in y needs my >= 2");
+    return SWE_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+int rows_per_chunk(int my) {
+    const char* e = std::getenv("SWE_ROWS_PER_WAVE");
+    int H = e ? std::atoi(e) : 64;
+    if (H < 1) H = 64;
+    return H < my ? H : my;
+}
+
+}  // namespace
+
+extern "C" {
+
+// error slot shared by the library's translation units (not part of the ABI)
+__attribute__((visibility("hidden"))) int swe_internal_set_error(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+
+const char* swe_last_error(void) { return g_err.c_str(); }
+
+const char* swe_version(void) { return "swe-gfx950 0.1"; }
+
+int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
+                   const void* b, const double* dt, double* smax, uint32_t* status,
+                   void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if ((rc = check_patch(patch))) return rc;
+    if (!q_in || !q_out || !b || !dt || !smax || !status)
+        return fail(SWE_EINVAL, "swe_patch_step: null pointer");
+    if (p->method != SWE_SPLIT)
+        return fail(SWE_EINVAL, "swe_patch_step: only the split step is available");
+    const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
+    const size_t span = (size_t)(patch->off + 2 * patch->plane_stride +
+                                 (int64_t)patch->pitch * (patch->my + 4)) * esz;
+    if (overlap(q_in, span, q_out, span))
+        return fail(SWE_EINVAL, "swe_patch_step: q_in and q_out overlap");
+    swe::StepArgs a;
+    a.qin = q_in;
+    a.qout = q_out;
+    a.b = b;
+    a.dt = dt;
+    a.smax = smax;
+    a.status = status;
+    a.off = patch->off;
+    a.ps = patch->plane_stride;
+    a.dx = patch->dx;
+    a.dy = patch->dy;
+    a.pitch = patch->pitch;
+    a.mx = patch->mx;
+    a.my = patch->my;
+    a.H = rows_per_chunk(patch->my);
+    a.nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
+    const int nchunks = (patch->my + a.H - 1) / a.H;
+    a.nitems = a.nstrips * nchunks;
+    for (int s = 0; s < 4; ++s) a.bc[s] = patch->bc[s];
+    a.P = dev_params(p);
+    const int waves_per_block = 4;
+    const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_split<false>, dim3(blocks), dim3(64 * waves_per_block), 0,
+                           static_cast<hipStream_t>(stream), a);
+    else
+        hipLaunchKernelGGL(swe::k_split<true>, dim3(blocks), dim3(64 * waves_per_block), 0,
+                           static_cast<hipStream_t>(stream), a);
+    return check_launch("swe_patch_step");
+}
+
+int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
+                   int32_t max_my, void* q, void* b, int32_t fill_b, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !q || (fill_b && !b) || n < 0 || max_mx < 1 || max_my < 1)
+        return fail(SWE_EINVAL, "swe_ghost_fill: bad arguments");
+    if (n == 0) return SWE_OK;
+    const int nperim = 4 * (max_mx + 4) + 4 * max_my;
+    const int bx = (nperim + 255) / 256;
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_ghost_fill<double>, dim3(bx, n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, static_cast<double*>(q),
+                           static_cast<double*>(b), fill_b);
+    else
+        hipLaunchKernelGGL(swe::k_ghost_fill<float>, dim3(bx, n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, static_cast<float*>(q),
+                           static_cast<float*>(b), fill_b);
+    return check_launch("swe_ghost_fill");
+}
+
+int swe_speed_scan(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
+                   int32_t max_my, const void* q, const void* b, double* smax_patch,
+                   void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !q || !b || !smax_patch || n < 0 || max_mx < 1 || max_my < 1)
+        return fail(SWE_EINVAL, "swe_speed_scan: bad arguments");
+    if (n == 0) return SWE_OK;
+    const int64_t ncell = (int64_t)max_mx * max_my;
+    int bx = (int)((ncell + 255) / 256);
+    if (bx > 4096) bx = 4096;
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_speed_scan<false>, dim3(bx, n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, q, b, smax_patch,
+                           dev_params(p));
+    else
+        hipLaunchKernelGGL(swe::k_speed_scan<true>, dim3(bx, n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, q, b, smax_patch,
+                           dev_params(p));
+    return check_launch("swe_speed_scan");
+}
+
+int swe_cfl_reduce(const swe_params* p, const swe_patch* patches, int32_t n, int32_t ngroups,
+                   double* smax_patch, double* dt_group, uint32_t* status,
+                   uint32_t* group_flags, int32_t initial, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !smax_patch || !dt_group || !status || n < 0 || ngroups < 1)
+        return fail(SWE_EINVAL, "swe_cfl_reduce: bad arguments");
+    hipLaunchKernelGGL(swe::k_cfl_reduce, dim3(ngroups), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), patches, n, smax_patch, dt_group,
+                       status, group_flags, p->cfl_desired, p->cfl_max, initial);
+    return check_launch("swe_cfl_reduce");
+}
+
+int swe_mass(const swe_params* p, const swe_patch* patches, int32_t n, const void* q,
+             const void* b, double* mass_patch, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !q || !mass_patch || n < 0 || (p->precision == SWE_F32_DEV && !b))
+        return fail(SWE_EINVAL, "swe_mass: bad arguments");
+    if (n == 0) return SWE_OK;
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_mass<false>, dim3(n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, q, b, mass_patch,
+                           p->sea_level);
+    else
+        hipLaunchKernelGGL(swe::k_mass<true>, dim3(n), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), patches, q, b, mass_patch,
+                           p->sea_level);
+    return check_launch("swe_mass");
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+"""Continuous batching of tsunami scenario solves on one GPU.
+
+Early warning needs fast results (the paper's motivation, Sec. 1).  Requests
+(one grid each, of its own size) arrive over time.  The server keeps every
+admitted scenario's state resident in HBM, in one pool per state buffer
+(first-fit sub-allocation of one large allocation, the paper's memory pool of
+Sec. 4), and advances all active scenarios together: each round is R steps of
+swe_batched_step + swe_cfl_reduce, every scenario in its own dt group, so a
+scenario's result does not depend on who else is in the batch.  Between
+rounds it retires finished scenarios and admits queued ones while a slot is
+free and their HBM footprint fits the budget.  Latency is arrival to
+completion (result on the host).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .solver import _round_up, patch_table
+from .workloads import Problem
+
+
+class PoolAllocator:
+    """First-fit allocator of element ranges within one pool; 256-byte aligned."""
+
+    def __init__(self, size: int, align: int = 64):
+        self.size = size
+        self.align = align
+        self.free = [(0, size)]  # sorted (start, length)
+
+    def alloc(self, n: int):
+        n = _round_up(n, self.align)
+        for i, (s, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (s + n, ln - n)
+                return s, n
+        return None
+
+    def release(self, start: int, n: int) -> None:
+        self.free.append((start, n))
+        self.free.sort()
+        merged = []
+        for s, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == s:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((s, ln))
+        self.free = merged
+
+    def largest_free(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
+
+@dataclass
+class Scenario:
+    rid: int
+    arrival: float
+    problem: Problem
+    nsteps: int
+    slot: int = -1
+    off: int = 0
+    span: int = 0
+    steps_done: int = 0
+    admitted: float = 0.0
+    finished: float = 0.0
+    result: dict = field(default_factory=dict)
+
+
+class ScenarioServer:
+    def __init__(self, params: L.swe_params | None = None, hbm_budget: int = 64 << 30,
+                 max_slots: int = 64, steps_per_round: int = 50, device: str = "cuda:0",
+                 sched: L.swe_schedule | None = None):
+        if not torch.cuda.is_available():
+            raise L.SweError("ScenarioServer needs a GPU")
+        L.lib()
+        self.p = params or L.params(precision=L.F32_DEV)
+        self.dev = torch.device(device)
+        self.dtype = torch.float32 if self.p.precision == L.F32_DEV else torch.float64
+        self.esize = 4 if self.p.precision == L.F32_DEV else 8
+        self.R = steps_per_round
+        self.max_slots = max_slots
+        self.sched = sched or L.schedule(seg=64, waves_per_group=4)
+        # one plane of the pool holds every scenario's plane; 7 planes in total
+        # (2 x 3 state planes + bathymetry)
+        self.plane = _round_up(hbm_budget // (7 * self.esize), 64)
+        self.alloc = PoolAllocator(self.plane)
+        self.pools = [torch.zeros(3 * self.plane, dtype=self.dtype, device=self.dev)
+                      for _ in range(2)]
+        self.b = torch.zeros(self.plane, dtype=self.dtype, device=self.dev)
+        self.dt = torch.zeros(max_slots, dtype=torch.float64, device=self.dev)
+        self.smax = torch.zeros(2 * max_slots, dtype=torch.float64, device=self.dev)
+        self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        self.group_flags = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
+        self.queue_ctr = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        self.cur = 0
+        self.active: list[Scenario] = []
+        self.free_slots = list(range(max_slots))
+        self.table_dirty = True
+
+    # -- footprint and admission ----------------------------------------------
+    def footprint_elems(self, pb: Problem) -> int:
+        pitch = _round_up(pb.mx + 4, 16)
+        return _round_up(pitch * (pb.my + 4), 64)
+
+    def footprint_bytes(self, pb: Problem) -> int:
+        return 7 * self.footprint_elems(pb) * self.esize
+
+    def try_admit(self, sc: Scenario) -> bool:
+        if not self.free_slots:
+            return False
+        got = self.alloc.alloc(self.footprint_elems(sc.problem))
+        if got is None:
+            return False
+        sc.off, sc.span = got
+        sc.slot = self.free_slots.pop(0)
+        self._upload(sc)
+        self.active.append(sc)
+        self.table_dirty = True
+        return True
+
+    def _patch(self, sc: Scenario) -> L.swe_patch:
+        pb = sc.problem
+        return L.patch(pb.mx, pb.my, _round_up(pb.mx + 4, 16), pb.dx, pb.dy, off=sc.off,
+                       plane_stride=self.plane, group=sc.slot, tref=1, bc=pb.bc)
+
+    def _upload(self, sc: Scenario) -> None:
+        pb = sc.problem
+        pitch = _round_up(pb.mx + 4, 16)
+        rows = pb.my + 4
+        npdt = np.float32 if self.esize == 4 else np.float64
+        q = np.zeros((3, rows, pitch), dtype=npdt)
+        bb = np.zeros((rows, pitch), dtype=npdt)
+        first = pb.h
+        if self.p.precision == L.F32_DEV:
+            first = np.where(pb.h > 0.0, pb.h + pb.b - self.p.sea_level, pb.b - self.p.sea_level)
+        q[0, 2:-2, 2: pb.mx + 2] = first
+        q[1, 2:-2, 2: pb.mx + 2] = pb.hu
+        q[2, 2:-2, 2: pb.mx + 2] = pb.hv
+        bb[2:-2, 2: pb.mx + 2] = pb.b
+        n = pitch * rows
+        dst = self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n]
+        dst.copy_(torch.from_numpy(q.reshape(3, n)).to(self.dev, non_blocking=False))
+        self.b[sc.off: sc.off + n].copy_(torch.from_numpy(bb.reshape(n)).to(self.dev))
+        # first dt of this scenario from a speed scan of its own grid
+        tab = patch_table([self._patch(sc)]).to(self.dev)
+        sm = self.smax[2 * sc.slot: 2 * sc.slot + 2]
+        sm.zero_()
+        s = torch.cuda.current_stream(self.dev).cuda_stream
+        L.swe_speed_scan(self.p, tab.data_ptr(), 1, pb.mx, pb.my, self.pools[self.cur].data_ptr(),
+                         self.b.data_ptr(), self.smax.data_ptr() + 16 * sc.slot, s)
+        dts = self.dt[sc.slot: sc.slot + 1]
+        L.swe_cfl_reduce(self.p, tab.data_ptr(), 1, 1, self.smax.data_ptr() + 16 * sc.slot,
+                         dts.data_ptr(), self.status.data_ptr(), 0, 1, s)
+
+    def _rebuild(self) -> None:
+        pts = [self._patch(sc) for sc in self.active]
+        self.table = patch_table(pts).to(self.dev)
+        items, ni, tasks, nt = L.swe_batched_plan(pts, self.sched)
+        self.items = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(self.dev)
+        self.tasks = torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8).to(self.dev)
+        self.nitems = ni
+        # smax entries follow the table order; the dt slots follow the scenario slots
+        self.table_dirty = False
+
+    def _retire(self, sc: Scenario) -> None:
+        pb = sc.problem
+        pitch = _round_up(pb.mx + 4, 16)
+        n = pitch * (pb.my + 4)
+        q0 = self.pools[self.cur].view(3, self.plane)[0, sc.off: sc.off + n].view(pb.my + 4, pitch)
+        eta = q0[2:-2, 2: pb.mx + 2]
+        if self.p.precision != L.F32_DEV:
+            bb = self.b[sc.off: sc.off + n].view(pb.my + 4, pitch)[2:-2, 2: pb.mx + 2]
+            eta = eta + bb
+        # the early-warning product: maximum surface elevation of the final state
+        # and the final surface itself
+        sc.result = {"eta": eta.cpu().numpy().astype(np.float64)}
+        sc.finished = time.perf_counter()
+        self.alloc.release(sc.off, sc.span)
+        self.free_slots.append(sc.slot)
+        self.free_slots.sort()
+        self.active.remove(sc)
+        self.table_dirty = True
+
+    # -- one round ---------------------------------------------------------------
+    def round(self, steps: int) -> None:
+        if self.table_dirty:
+            self._rebuild()
+        # a scenario's smax pair lives at its table index during the round
+        s = torch.cuda.current_stream(self.dev).cuda_stream
+        n = len(self.active)
+        smax = torch.zeros(2 * n, dtype=torch.float64, device=self.dev)
+        for _ in range(steps):
+            L.swe_batched_step(self.p, self.table.data_ptr(), self.items.data_ptr(), self.nitems,
+                               self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
+                               self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
+                               self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
+                               self.queue_ctr.data_ptr(), self.sched, s)
+            L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
+                             self.dt.data_ptr(), self.status.data_ptr(),
+                             self.group_flags.data_ptr(), 0, s)
+            self.cur ^= 1
+            # scenarios not in the active table keep their planes; copy them along
+        for sc in self.active:
+            sc.steps_done += steps
+
+    def serve(self, requests, warmup: int = 0, log=None):
+        """Run the request stream.  requests: list of Scenario with arrival
+        times in seconds from the start.  Returns a summary dict."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: list[Scenario] = []
+        done: list[Scenario] = []
+        t0 = time.perf_counter()
+        cells = 0
+        i = 0
+        while i < len(pending) or queue or self.active:
+            now = time.perf_counter() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            # admit in arrival order while slots and memory allow
+            while queue and self.try_admit(queue[0]):
+                queue[0].admitted = time.perf_counter() - t0
+                queue.pop(0)
+            if not self.active:
+                if i < len(pending):
+                    time.sleep(max(0.0, min(0.01, pending[i].arrival - now)))
+                continue
+            steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
+            self.round(steps)
+            torch.cuda.synchronize(self.dev)
+            cells += steps * sum(sc.problem.mx * sc.problem.my for sc in self.active)
+            for sc in [sc for sc in self.active if sc.steps_done >= sc.nsteps]:
+                self._retire(sc)
+                sc.finished -= t0
+                done.append(sc)
+                if log:
+                    log(f"[serve] request {sc.rid} ({sc.problem.mx}^2) done, latency "
+                        f"{(sc.finished - sc.arrival) * 1e3:.1f} ms")
+        total = time.perf_counter() - t0
+        lat = np.array([sc.finished - sc.arrival for sc in done if sc.rid >= warmup])
+        flags = self.status.cpu().numpy()
+        return {"requests": len(done), "measured": int(lat.size),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+                "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+                "cell_updates_per_s": cells / total, "wall_s": total,
+                "status_flags": int(flags[0]), "clamps": int(flags[1]), "done": done}

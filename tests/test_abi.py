@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/swe.h, its structs have the layout the
+Python binding assumes, and argument errors are reported before anything is
+launched."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swe.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1901_06798_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1901_06798_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swe_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce", "swe_mass",
+              "swe_last_error", "swe_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (swe_[a-z_0-9]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layout_matches_header(L, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "swe.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(swe_params), offsetof(swe_params, method),
+         offsetof(swe_params, precision), sizeof(swe_patch), offsetof(swe_patch, mx),
+         offsetof(swe_patch, bc), offsetof(swe_patch, reserved));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    P, T = L.swe_params, L.swe_patch
+    assert vals == [ctypes.sizeof(P), P.method.offset, P.precision.offset, ctypes.sizeof(T),
+                    T.mx.offset, T.bc.offset, T.reserved.offset]
+
+
+def test_argument_errors_are_reported_on_the_host(L):
+    lib = L.lib()
+    p = L.params()
+    pt = L.patch(10, 10, 14, 1.0, 1.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.swe_patch_step(None, ctypes.byref(pt), fake, fake, fake, fake, fake, fake, None) == L.SWE_EINVAL
+    assert b"params" in lib.swe_last_error()
+    # pitch too small
+    bad = L.patch(10, 10, 12, 1.0, 1.0)
+    assert lib.swe_patch_step(ctypes.byref(p), ctypes.byref(bad), fake, ctypes.c_void_p(0x9000000),
+                              fake, fake, fake, fake, None) == L.SWE_EINVAL
+    assert b"pitch" in lib.swe_last_error()
+    # aliasing in/out
+    assert lib.swe_patch_step(ctypes.byref(p), ctypes.byref(pt), fake, fake, fake, fake, fake,
+                              fake, None) == L.SWE_EINVAL
+    assert b"overlap" in lib.swe_last_error()
+    # unknown enums
+    for field, val in (("order", 3), ("method", 7), ("precision", 9)):
+        q = L.params()
+        setattr(q, field, val)
+        assert lib.swe_patch_step(ctypes.byref(q), ctypes.byref(pt), fake,
+                                  ctypes.c_void_p(0x9000000), fake, fake, fake, fake,
+                                  None) == L.SWE_EINVAL
+    # wall with a single cell
+    thin = L.patch(1, 10, 8, 1.0, 1.0)
+    assert lib.swe_patch_step(ctypes.byref(p), ctypes.byref(thin), fake, ctypes.c_void_p(0x9000000),
+                              fake, fake, fake, fake, None) == L.SWE_EINVAL
+    with pytest.raises(L.SweError):
+        L.swe_patch_step(p, bad, 0x1000, 0x9000000, 0x1000, 0x1000, 0x1000, 0x1000)

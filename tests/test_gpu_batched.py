@@ -1,0 +1,136 @@
+"""GPU tests of the batched persistent step: a patch's result is bit for bit
+the single-patch result whatever batch, schedule or graph replay it runs in,
+and AMR-shaped patch sets (three levels, 1/4/16 substeps) match the reference
+solver run patch by patch with the same step sizes."""
+import numpy as np
+import pytest
+
+from helpers import interior, oracle_setup
+from paper_1901_06798_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd.batched import BatchedSolver
+    from paper_1901_06798_amd.solver import PatchSolver
+    L.lib()
+    return L, BatchedSolver, PatchSolver, torch
+
+
+def mixed_problems():
+    from test_gpu_split import smooth_random_problem
+    shapes = [(61, 67, (W.BC_EXTRAP,) * 4), (130, 40, (W.BC_WALL,) * 4),
+              (17, 19, (W.BC_EXTRAP, W.BC_WALL, W.BC_WALL, W.BC_EXTRAP)),
+              (96, 96, (W.BC_EXTRAP,) * 4), (1, 25, (W.BC_EXTRAP, W.BC_EXTRAP, W.BC_WALL, W.BC_WALL)),
+              (200, 150, (W.BC_EXTRAP,) * 4)]
+    return [smooth_random_problem(mx, my, seed=100 + k, bc=bc) for k, (mx, my, bc) in enumerate(shapes)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("seg,rows", [(64, 0), (32, 0), (64, 7)])
+def test_batched_equals_single_bitwise(gpu, precision, seg, rows):
+    L, BatchedSolver, PatchSolver, torch = gpu
+    probs = mixed_problems()
+    p = L.params(precision=precision)
+    print(f"case batched vs single precision={precision} seg={seg} rows={rows}", flush=True)
+    bs = BatchedSolver(probs, p, groups=list(range(len(probs))),
+                       sched=L.schedule(seg=seg, rows_per_task=rows))
+    bs.initial_dt()
+    bs.run(12)
+    torch.cuda.synchronize()
+    assert bs.flags()[0] & ~L.STATUS_CFL_EXCEEDED == 0
+    for k, pb in enumerate(probs):
+        s = PatchSolver(pb, p)
+        s.initial_dt()
+        s.run_async(12)
+        torch.cuda.synchronize()
+        for a, c in zip(bs.state(k), s.state()):
+            assert np.array_equal(a, c), f"patch {k}"
+
+
+def amr_set(seed=3, counts=(6, 10, 14)):
+    specs, probs = W.amr_patch_set(npatch=counts, seed=seed)
+    trefs = [s.tref for s in specs]
+    return specs, probs, trefs
+
+
+def test_amr_patch_set_matches_reference(gpu, orc):
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set()
+    bs = BatchedSolver(probs, L.params(), trefs=trefs)
+    bs.initial_dt()
+    dts = bs.run(3, record_dt=True)[:, 0]
+    torch.cuda.synchronize()
+    assert bs.flags() == (0, 0)
+    P = orc.params()
+    rates = []
+    for k, pb in enumerate(probs):
+        g, q, b = oracle_setup(orc, pb)
+        t = trefs[k]
+        for dt in dts:
+            orc.run(P, g, q, b, t, dt_forced=[dt / t] * t)
+        for f, a in zip(range(3), bs.state(k)):
+            ref = interior(q)[..., f]
+            scale = max(np.abs(ref).max(), 1e-300)
+            assert np.abs(a - ref).max() / scale <= 1e-12, (k, f)
+    # the coarse dt follows the CFL rule over all levels (dt_l = dt_1 / tref_l)
+    g0 = [oracle_setup(orc, pb) for pb in probs]
+    rate = 0.0
+    for k, (g, q, b) in enumerate(g0):
+        sm = orc.speed_scan(P, g, q, b)
+        rate = max(rate, max(sm[0] / g.dx, sm[1] / g.dy) / trefs[k])
+    assert dts[0] == pytest.approx(0.9 / rate, rel=1e-15)
+
+
+def test_amr_substeps_equal_single_patch_bitwise(gpu):
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set(seed=5, counts=(3, 4, 5))
+    bs = BatchedSolver(probs, L.params(), trefs=trefs, sched=L.schedule(seg=32))
+    bs.initial_dt()
+    dts = bs.run(2, record_dt=True)[:, 0]
+    torch.cuda.synchronize()
+    for k, pb in enumerate(probs):
+        s = PatchSolver(pb, L.params())
+        t = trefs[k]
+        sub = []
+        for dt in dts:
+            sub += [dt / t] * t
+        s.run_forced(sub)
+        torch.cuda.synchronize()
+        for a, c in zip(bs.state(k), s.state()):
+            assert np.array_equal(a, c), f"patch {k} tref {t}"
+
+
+def test_graph_replay_matches_eager(gpu):
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set(seed=7, counts=(4, 6, 8))
+    eager = BatchedSolver(probs, L.params(), trefs=trefs)
+    eager.initial_dt()
+    graph = BatchedSolver(probs, L.params(), trefs=trefs)
+    graph.initial_dt()
+    graph.capture(4)
+    for rep in range(3):
+        eager.run(4)
+        graph.replay()
+        # the program's own eager work between replays
+        x = torch.randn(1000, device=graph.dev).sum()
+        torch.cuda.synchronize()
+        del x
+        for k in range(len(probs)):
+            for a, c in zip(eager.state(k), graph.state(k)):
+                assert np.array_equal(a, c), f"replay {rep} patch {k}"
+    assert graph.flags() == eager.flags()
+
+
+def test_plan_rejects_user_boundary_with_substeps(gpu):
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set(seed=1, counts=(1, 1, 1))
+    probs[2].bc = (W.BC_USER,) * 4
+    with pytest.raises(L.SweError):
+        BatchedSolver(probs, L.params(), trefs=trefs)

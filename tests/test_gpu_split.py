@@ -1,0 +1,230 @@
+"""GPU parity of the FP64 split step (HIP library through the C ABI) against
+the reference solver, element by element, plus tile-shape and rerun
+determinism.  Tolerance: 1e-12 relative per field (max |gpu - ref| over
+max |ref|); lake at rest exactly.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import interior, oracle_setup
+from paper_1901_06798_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd.solver import PatchSolver
+    L.lib()
+    return L, PatchSolver, torch
+
+
+def rel_err(a, ref):
+    scale = np.abs(ref).max()
+    if scale == 0.0:
+        return np.abs(a).max()
+    return np.abs(a - ref).max() / scale
+
+
+def compare(state, qref, tol=RTOL):
+    for k in range(3):
+        e = rel_err(state[k], qref[..., k])
+        assert e <= tol, f"field {k}: rel err {e:.3e}"
+
+
+def oracle_params(orc, gp):
+    return orc.params(g=gp.g, drytol=gp.drytol, h_corr=gp.h_corr, manning_n=gp.manning_n,
+                      cfl_desired=gp.cfl_desired, cfl_max=gp.cfl_max, method=gp.method,
+                      order=gp.order, transverse_order=gp.transverse_order)
+
+
+def run_pair(gpu, orc, pb, nsteps, **kw):
+    L, PatchSolver, torch = gpu
+    gp = L.params(**kw)
+    print(f"case {pb.name} {pb.mx}x{pb.my} bc={pb.bc} steps={nsteps} {kw}", flush=True)
+    s = PatchSolver(pb, gp)
+    dts = s.run(nsteps)
+    torch.cuda.synchronize()
+    st = s.state()
+    g, q, b = oracle_setup(orc, pb)
+    r = orc.run(oracle_params(orc, gp), g, q, b, nsteps)
+    return s, st, dts, interior(q), r
+
+
+def test_gaussian_hump_200_walls_100_steps(gpu, orc):
+    pb = W.gaussian_hump()
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 100)
+    compare(st, qref)
+    np.testing.assert_allclose(dts, r["dt"], rtol=1e-13, atol=0)
+    assert s.flags() == (0, 0)
+
+
+def test_lake_at_rest_shelf_is_exact(gpu, orc):
+    pb = W.shelf_grid(150, 500.0, seed=11, amp=0.0, x_s_frac=0.5, width=5e3)
+    assert (pb.h == 0).any()
+    L, PatchSolver, torch = gpu
+    s = PatchSolver(pb, L.params())
+    s.run(30)
+    h, hu, hv = s.state()
+    assert np.array_equal(h, pb.h) and not hu.any() and not hv.any()
+    assert s.flags() == (0, 0)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_dam_break_1d(gpu, orc, transpose):
+    pb = W.dam_break_1d(400, transpose=transpose)
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 110)
+    compare(st, qref)
+    np.testing.assert_allclose(dts, r["dt"], rtol=1e-13)
+
+
+def test_dry_dam_break(gpu, orc):
+    pb = W.dam_break_1d(300, h_left=1.0, h_right=0.0)
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 80)
+    compare(st, qref)
+
+
+def smooth_random_problem(mx, my, seed, dx=700.0, bc=(W.BC_EXTRAP,) * 4, coast=True):
+    """Seeded shelf with a coastline, a source and a little momentum."""
+    rng = np.random.default_rng(seed)
+    xc = W.cell_centres(mx, dx)
+    yc = W.cell_centres(my, dx)
+    L = mx * dx
+    b = np.broadcast_to(W.shelf_profile(xc, 0.6 * L, max(L / 8, 1.0)), (my, mx)).copy()
+    if not coast:
+        b = np.minimum(b, -50.0)
+    b *= 1.0 + 0.05 * rng.uniform(-1, 1, size=b.shape)
+    eta = W.gaussian(xc, yc, rng.uniform(1, 4), max(L / 6, dx), 0.4 * L, rng.uniform(0.3, 0.7) * my * dx)
+    h = W.depth_from_surface(eta, b)
+    wet = h > 1e-3
+    hu = np.where(wet, h * rng.uniform(-0.3, 0.3, size=h.shape), 0.0)
+    hv = np.where(wet, h * rng.uniform(-0.3, 0.3, size=h.shape), 0.0)
+    return W.Problem(f"random{seed}", h, hu, hv, b, dx, dx, bc)
+
+
+@pytest.mark.parametrize("mx,my,bc", [
+    (61, 67, (W.BC_EXTRAP,) * 4),
+    (60, 64, (W.BC_WALL,) * 4),
+    (121, 5, (W.BC_WALL, W.BC_EXTRAP, W.BC_EXTRAP, W.BC_WALL)),
+    (7, 130, (W.BC_EXTRAP, W.BC_WALL, W.BC_WALL, W.BC_EXTRAP)),
+    (181, 70, (W.BC_WALL, W.BC_WALL, W.BC_EXTRAP, W.BC_EXTRAP)),
+    (1, 33, (W.BC_EXTRAP, W.BC_EXTRAP, W.BC_WALL, W.BC_WALL)),
+    (33, 1, (W.BC_WALL, W.BC_WALL, W.BC_EXTRAP, W.BC_EXTRAP)),
+])
+def test_ragged_shapes_and_boundaries(gpu, orc, mx, my, bc):
+    pb = smooth_random_problem(mx, my, seed=mx * 1000 + my, bc=bc)
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 25)
+    compare(st, qref)
+    np.testing.assert_allclose(dts, r["dt"], rtol=1e-13)
+
+
+def test_first_order_and_friction(gpu, orc):
+    pb = smooth_random_problem(90, 70, seed=5, coast=True)
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 20, order=1)
+    compare(st, qref)
+    s, st, dts, qref, r = run_pair(gpu, orc, pb, 20, manning_n=0.025)
+    compare(st, qref)
+
+
+def test_user_ghost_cells_one_step(gpu, orc):
+    """Sides with caller-provided ghosts: the step must read them as stored."""
+    L, PatchSolver, torch = gpu
+    mx, my = 70, 66
+    pb = smooth_random_problem(mx, my, seed=42, coast=True)
+    for bc in [(W.BC_USER,) * 4, (W.BC_USER, W.BC_WALL, W.BC_EXTRAP, W.BC_USER),
+               (W.BC_WALL, W.BC_USER, W.BC_USER, W.BC_EXTRAP)]:
+        pb.bc = bc
+        rng = np.random.default_rng(7)
+        g, q, b = oracle_setup(orc, pb)
+        # caller-provided ghosts: a random perturbation of the extrapolated frame
+        ext = W.Problem("e", pb.h, pb.hu, pb.hv, pb.b, pb.dx, pb.dy, (W.BC_EXTRAP,) * 4)
+        ge, qe, be = oracle_setup(orc, ext)
+        frame = np.ones(q.shape[:2], bool)
+        frame[2:-2, 2:-2] = False
+        q[frame] = qe[frame] * (1 + 0.01 * rng.uniform(-1, 1, size=qe[frame].shape))
+        b[frame] = be[frame]
+        orc.ghost_fill(g, q)  # fills only the non-user sides
+        orc.ghost_fill_b(g, b)
+        s = PatchSolver(pb, L.params())
+        Q = s.planes()
+        Q[:, :, : mx + 4] = torch.from_numpy(np.moveaxis(q, 2, 0).copy()).to(Q.device)
+        s.bplane()[:, : mx + 4] = torch.from_numpy(b).to(Q.device)
+        dt = 0.5 * 700.0 / np.sqrt(9.81 * 4100)
+        s.run_forced([dt])
+        torch.cuda.synchronize()
+        qo, _, _, _ = orc.step(oracle_params(orc, s.p), g, q, b, dt)
+        compare(s.state(), interior(qo))
+
+
+def test_ghost_fill_matches_reference(gpu, orc):
+    L, PatchSolver, torch = gpu
+    for bc in [(W.BC_WALL,) * 4, (W.BC_EXTRAP,) * 4, (W.BC_WALL, W.BC_EXTRAP, W.BC_EXTRAP, W.BC_WALL)]:
+        pb = smooth_random_problem(65, 63, seed=3, bc=bc)
+        s = PatchSolver(pb, L.params())
+        torch.cuda.synchronize()
+        Q = s.planes().cpu().numpy()[:, :, : pb.mx + 4]
+        g, q, b = oracle_setup(orc, pb)
+        assert np.array_equal(np.moveaxis(Q, 0, 2), q)
+        assert np.array_equal(s.bplane().cpu().numpy()[:, : pb.mx + 4], b)
+
+
+def test_initial_dt_and_mass(gpu, orc):
+    L, PatchSolver, torch = gpu
+    pb = W.gaussian_hump()
+    s = PatchSolver(pb, L.params())
+    s.initial_dt()
+    torch.cuda.synchronize()
+    assert float(s.dt.item()) == pytest.approx(4.542802598952491, rel=1e-15)
+    g, q, b = oracle_setup(orc, pb)
+    # sums of 40000 terms in different orders: agreement to n * eps
+    assert s.mass() == pytest.approx(orc.mass(g, q), rel=40000 * 2.3e-16)
+
+
+def test_tile_shape_and_rerun_are_bitwise_identical(gpu):
+    L, PatchSolver, torch = gpu
+    pb = smooth_random_problem(150, 140, seed=9)
+    results = []
+    for rows in ("64", "7", "64", "140"):
+        os.environ["SWE_ROWS_PER_WAVE"] = rows
+        try:
+            s = PatchSolver(pb, L.params())
+            s.run(15)
+            torch.cuda.synchronize()
+            results.append(s.state())
+        finally:
+            os.environ.pop("SWE_ROWS_PER_WAVE", None)
+    for r in results[1:]:
+        for a, c in zip(results[0], r):
+            assert np.array_equal(a, c)
+
+
+def test_nonfinite_and_negative_input_are_flagged(gpu):
+    L, PatchSolver, torch = gpu
+    pb = smooth_random_problem(40, 40, seed=2, coast=False)
+    pb.h = pb.h.copy()
+    pb.h[10, 10] = np.nan
+    s = PatchSolver(pb, L.params())
+    s.run_forced([0.1])
+    torch.cuda.synchronize()
+    assert s.flags()[0] & L.STATUS_NONFINITE
+
+
+def test_cfl_exceeded_is_flagged_and_retaken(gpu, orc):
+    L, PatchSolver, torch = gpu
+    pb = W.gaussian_hump(40, 5000.0)
+    s = PatchSolver(pb, L.params())
+    dts = s.run(3, dt0=100.0)
+    torch.cuda.synchronize()
+    assert s.retakes == 1
+    g, q, b = oracle_setup(orc, pb)
+    r = orc.run(orc.params(), g, q, b, 3, dt0=100.0)
+    assert r["retakes"] == 1
+    np.testing.assert_allclose(dts, r["dt"], rtol=1e-13)
+    compare(s.state(), interior(q))
