@@ -1,9 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of the shallow water patch step on one MI355X.
 
-Workload (default): 4096 x 4096 cells, dx = 250 m, tanh continental shelf with
+Headline workload: 4096 x 4096 cells, dx = 250 m, tanh continental shelf with
 5% seeded roughness and a dry coast, 2 m Gaussian uplift of sigma 30 km,
-extrapolation boundaries; FP64 dimensionally split step with the MC-limited
+extrapolation boundaries; FP64 dimensionally split step with MC-limited
 corrections and the CFL rule on the device.  One step = one patch_step launch
 (the whole split update) plus the CFL reduction that sets the next dt.
 
@@ -12,7 +12,11 @@ steps (state resident in HBM).  `roofline` reports the step kernel's
 algorithmic HBM bytes per launch over its average launch time measured with
 HIP events on the launch stream.  `cpu_baseline` times the reference solver
 (test infrastructure, FP64, OpenMP over rows) on a bounded sample of the same
-grid on the host cores.
+grid on the host cores.  `variants` adds the FP32 surface-deviation path on
+the same grid (and, with --batched, the AMR-shaped patch set).
+
+--calib-copy MB runs only a plain device copy of MB megabytes (for scaling
+the FETCH_SIZE / WRITE_SIZE counters of a profiler run).
 """
 from __future__ import annotations
 
@@ -28,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL_F64 = 56  # read h, hu, hv, b (4 x 8 B), write h, hu, hv (3 x 8 B)
+BYTES_PER_CELL = {0: 56, 1: 28}  # FP64: 4 x 8 B read + 3 x 8 B written; FP32-dev: half
 
 
 def parse():
@@ -38,10 +42,30 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="also time the AMR patch set")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM KiB per launch (fetch, write)")
+                    help="JSON file with the measured HBM bytes per launch of the step kernel")
+    ap.add_argument("--calib-copy", type=float, default=0.0,
+                    help="only run a plain device copy of this many MB, 10 times")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def calib_copy(mb: float) -> None:
+    import torch
+    n = int(mb * 1e6 / 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": 8 * n, "calib_copy_bytes_written": 8 * n,
+                      "launches": 10}), flush=True)
 
 
 def cpu_baseline(pb, seconds: float):
@@ -70,40 +94,28 @@ def cpu_baseline(pb, seconds: float):
                       f"({el:.1f} s, {threads} OpenMP threads)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
-              f"single-GPU in this build", file=sys.stderr)
-        sys.exit(2)
+def time_patch(pb, params, steps: int, warmup: int):
+    """Time `steps` steps of one patch; kernel time from HIP events around each
+    step launch on the launch stream."""
     import torch
 
     from paper_1901_06798_amd import _lib as L
-    from paper_1901_06798_amd import workloads as W
     from paper_1901_06798_amd.solver import PatchSolver
 
-    if not torch.cuda.is_available():
-        print("no GPU available", file=sys.stderr)
-        sys.exit(1)
-    n = args.n
-    print(f"[bench] building {n}x{n} shelf workload", file=sys.stderr, flush=True)
-    pb = W.shelf_4096(n=n, dx=250.0 * 4096 / n)
-    s = PatchSolver(pb, L.params(), "cuda:0")
+    s = PatchSolver(pb, params, "cuda:0")
     s.initial_dt()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         s.enqueue_step()
     torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-
     stream = torch.cuda.current_stream()
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    for k in range(args.steps):
+    for k in range(steps):
         ev0[k].record(stream)
         L.swe_patch_step(s.p, s.pt, s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(),
                          s.b.data_ptr(), s.dt.data_ptr(), s.smax.data_ptr(),
@@ -118,27 +130,82 @@ def main():
     total_ms = start.elapsed_time(end)
     kern_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
     flags, clamps = s.flags()
-    print(f"[bench] timed {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
-          f"flags={flags} clamps={clamps}", file=sys.stderr, flush=True)
-
     cells = pb.mx * pb.my
-    ms_per_step = total_ms / args.steps
-    cups = cells * args.steps / (total_ms * 1e-3)
-    alg_bytes = BYTES_PER_CELL_F64 * cells
+    nbytes = BYTES_PER_CELL[int(params.precision)] * cells
     kavg = float(kern_ms.mean())
-    achieved = alg_bytes / (kavg * 1e-3) / 1e9
+    return {"solver": s, "total_ms": total_ms, "wall_s": wall, "ms_per_step": total_ms / steps,
+            "cups": cells * steps / (total_ms * 1e-3), "kernel_ms_avg": kavg,
+            "kernel_ms_p50": float(np.percentile(kern_ms, 50)),
+            "kernel_ms_p99": float(np.percentile(kern_ms, 99)), "alg_bytes": nbytes,
+            "achieved_gbs": nbytes / (kavg * 1e-3) / 1e9, "flags": flags, "clamps": clamps}
+
+
+def time_batched(precision: int, steps: int = 10):
+    import torch
+
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.batched import BatchedSolver
+
+    specs, probs = W.amr_patch_set()
+    trefs = [s.tref for s in specs]
+    bs = BatchedSolver(probs, L.params(precision=precision), trefs=trefs,
+                       sched=L.schedule(seg=64, waves_per_group=4))
+    bs.initial_dt()
+    bs.run(2)
+    bs.capture(2)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps // 2):
+        bs.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / (2 * (steps // 2))
+    upd = bs.cells()
+    nbytes = BYTES_PER_CELL[precision] * upd
+    return {"patches": len(probs), "cell_updates_per_coarse_step": upd,
+            "ms_per_coarse_step": ms, "cups": upd / (ms * 1e-3),
+            "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
+              f"single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    if args.calib_copy > 0:
+        calib_copy(args.calib_copy)
+        return
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+
+    n = args.n
+    log(f"[bench] building {n}x{n} shelf workload")
+    pb = W.shelf_4096(n=n, dx=250.0 * 4096 / n)
+    log("[bench] FP64 split step")
+    r64 = time_patch(pb, L.params(), args.steps, args.warmup)
+    log(f"[bench] FP64: {r64['ms_per_step']:.3f} ms/step, kernel {r64['kernel_ms_avg']:.3f} ms, "
+        f"{r64['cups']:.3e} CUPS, flags={r64['flags']}")
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
             traffic = json.load(f).get("bytes_per_launch")
     out = {
         "metric": "cell-updates/s (FP64 split step, 4096^2 shelf)",
-        "value": cups,
+        "value": r64["cups"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -146,18 +213,37 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"shelf_{n}x{n}_dx{pb.dx:g}_fp64_split", "grid": [n, n],
                    "boundary": "extrapolation", "cfl": 0.9, "limiter": "MC"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_split_f64", "kernel_ms_avg": kavg,
-                     "kernel_ms_p50": float(np.percentile(kern_ms, 50)),
-                     "kernel_ms_p99": float(np.percentile(kern_ms, 99)),
-                     "alg_bytes_per_launch": alg_bytes},
-        "hbm_gbs_alg_step": cells * BYTES_PER_CELL_F64 / (ms_per_step * 1e-3) / 1e9,
-        "status_flags": flags,
-        "clamps": clamps,
+        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "swe::k_split<false>",
+                     "kernel_ms_avg": r64["kernel_ms_avg"],
+                     "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
+                     "alg_bytes_per_launch": r64["alg_bytes"]},
+        "hbm_gbs_alg_step": r64["alg_bytes"] / (r64["ms_per_step"] * 1e-3) / 1e9,
+        "status_flags": r64["flags"],
+        "clamps": r64["clamps"],
     }
+    if not args.no_variants:
+        log("[bench] FP32 surface-deviation split step")
+        h64 = r64["solver"].surface()
+        del r64["solver"]
+        torch.cuda.empty_cache()
+        r32 = time_patch(pb, L.params(precision=L.F32_DEV), args.steps, args.warmup)
+        h32 = r32.pop("solver").surface()
+        wet = (h64 > -1e30)
+        out["variants"] = {"fp32_dev": {
+            "cups": r32["cups"], "ms_per_step": r32["ms_per_step"],
+            "kernel_ms_avg": r32["kernel_ms_avg"], "achieved_gbs": r32["achieved_gbs"],
+            "frac": r32["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r32["alg_bytes"],
+            "speedup_vs_fp64": r32["cups"] / r64["cups"], "flags": r32["flags"],
+            "free_running_max_surface_diff_m": float(np.abs(h32 - h64)[wet].max())}}
+        if args.batched:
+            for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
+                log(f"[bench] {name}")
+                out["variants"][name] = time_batched(prec)
+    r64.pop("solver", None)
     if not args.no_cpu_baseline:
-        print("[bench] timing the reference solver on the host", file=sys.stderr, flush=True)
+        log("[bench] timing the reference solver on the host")
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

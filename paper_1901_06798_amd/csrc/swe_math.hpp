@@ -10,9 +10,9 @@
 // All functions are templated on the real type so the FP64 path and the
 // FP32 surface-deviation path share one instruction sequence per type; the
 // library is built with -ffp-contract=off, so a cell's result does not depend
-// on which lane, tile or launch computed it.  Every quotient and root is a
-// correctly rounded IEEE division or square root, and products and sums are
-// grouped as the method's formulas are written: in deep water the momentum is
+// on which lane, tile or launch computed it.  In FP64 every quotient and root
+// is a correctly rounded IEEE division or square root, and products and sums
+// are grouped as the method's formulas are written: in deep water the momentum is
 // a small signal over a large depth, and two groupings of the same formula
 // already differ there by about 1e-11 of the momentum after 100 steps, so
 // the FP64 path keeps one fixed, plain grouping.
@@ -30,6 +30,15 @@ struct DevParams {
     double g, drytol, h_corr, manning_n, sea_level, h_fp64;
     int order;
 };
+
+// Quotients and roots.  In FP64 they are the correctly rounded IEEE
+// operations (the FP64 path reproduces the reference arithmetic).  In FP32
+// (the surface-deviation path, whose bar is an error in metres against FP64)
+// they are the hardware reciprocal and square root (about 1 ulp).
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // One side of an edge, seen along the edge normal: depth, normal and
 // transverse momentum, bed, and the derived velocities and celerity.
@@ -59,10 +68,10 @@ __device__ __forceinline__ Side<T> make_side(T h, T m, T t, T b, const DevParams
     } else {
         s.m = m;
         s.t = t;
-        s.u = m / h;
-        s.v = t / h;
-        s.sq = sqrt(h);
-        s.c = sqrt(T(P.g) * h);
+        s.u = qdiv(m, h);
+        s.v = qdiv(t, h);
+        s.sq = qsqrt(h);
+        s.c = qsqrt(T(P.g) * h);
     }
     return s;
 }
@@ -103,7 +112,7 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
     if (dryR) {
         T a = cL + T(0.5) * uL;
         a = a < T(0) ? T(0) : a;
-        T hstar = a * a / g;
+        T hstar = qdiv(a * a, g);
         hstar = hstar < hL ? hL : hstar;
         if (hstar + bL < bR) {
             w.kind = kEdgeWallR;
@@ -114,7 +123,7 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
     } else if (dryL) {
         T a = cR - T(0.5) * uR;
         a = a < T(0) ? T(0) : a;
-        T hstar = a * a / g;
+        T hstar = qdiv(a * a, g);
         hstar = hstar < hR ? hR : hstar;
         if (hstar + bR < bL) {
             w.kind = kEdgeWallL;
@@ -133,8 +142,8 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
         s1 = uR - T(2) * cR;
         s3 = uR + cR;
     } else {
-        T uhat = (sqL * uL + sqR * uR) / (sqL + sqR);
-        T chat = sqrt(g * (T(0.5) * (hL + hR)));
+        T uhat = qdiv(sqL * uL + sqR * uR, sqL + sqR);
+        T chat = qsqrt(g * (T(0.5) * (hL + hR)));
         T a = uL - cL, c = uhat - chat;
         s1 = a < c ? a : c;
         a = uR + cR;
@@ -155,17 +164,17 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
     bool clamped = false;
     T delta = -db;
     if (s1 < T(0) && s3 > T(0)) {
-        beta1 = (s3 * deta - dm) / (s3 - s1);
-        beta3 = (dm - s1 * deta) / (s3 - s1);
+        beta1 = qdiv(s3 * deta - dm, s3 - s1);
+        beta3 = qdiv(dm - s1 * deta, s3 - s1);
         if (hL + beta1 < T(0)) {
-            T hm = (s3 * hR - s1 * hL - dm) / (s3 - s1);
+            T hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
             hm = hm < T(0) ? T(0) : hm;
-            delta = hm * (s3 - s1) / s3;
+            delta = qdiv(hm * (s3 - s1), s3);
             clamped = true;
         } else if (hR - beta3 < T(0)) {
-            T hm = (s3 * hR - s1 * hL - dm) / (s3 - s1);
+            T hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
             hm = hm < T(0) ? T(0) : hm;
-            delta = hm * (s3 - s1) / s1;
+            delta = qdiv(hm * (s3 - s1), s1);
             clamped = true;
         }
     } else {
@@ -175,14 +184,14 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
             if (delta > hR) { delta = hR; clamped = true; }
         }
         if (!clamped) {
-            beta1 = (s3 * deta - dm) / (s3 - s1);
-            beta3 = (dm - s1 * deta) / (s3 - s1);
+            beta1 = qdiv(s3 * deta - dm, s3 - s1);
+            beta3 = qdiv(dm - s1 * deta, s3 - s1);
         }
     }
     if (clamped) {
         const T dh = (hR - hL) - delta;
-        beta1 = (s3 * dh - dm) / (s3 - s1);
-        beta3 = (dm - s1 * dh) / (s3 - s1);
+        beta1 = qdiv(s3 * dh - dm, s3 - s1);
+        beta3 = qdiv(dm - s1 * dh, s3 - s1);
     }
 
     const T hbar = T(0.5) * (hL + hR);
@@ -277,13 +286,69 @@ __device__ __forceinline__ void correction(const Waves<T>& w, const T dl[3], con
         if (s == T(0)) continue;
         const T zz = dot3(w.z[p], w.z[p]);
         if (zz == T(0)) continue;
-        const T theta = (s > T(0) ? dl[p] : dr[p]) / zz;
+        const T theta = qdiv(s > T(0) ? dl[p] : dr[p], zz);
         const T phi = mc_limiter(theta);
         const T sg = s > T(0) ? T(1) : T(-1);
         const T as = s > T(0) ? s : -s;
         const T coef = T(0.5) * sg * (T(1) - lam * as) * phi;
 #pragma unroll
         for (int k = 0; k < 3; ++k) F[k] += coef * w.z[p][k];
+    }
+}
+
+// A cell as seen by the transverse solver: depth, bed, velocities along the
+// edge normal (un) and along the split direction (ut; 0 when dry), sqrt(h).
+template <typename T>
+struct TCell {
+    T h, b, un, ut, sq;
+};
+
+// Roe averages of a pair of cells along the split direction.
+template <typename T>
+struct TPair {
+    T un, ut, c;
+    bool all_dry;
+};
+
+template <typename T>
+__device__ __forceinline__ TPair<T> tpair(const TCell<T>& l, const TCell<T>& r,
+                                          const DevParams& P) {
+    TPair<T> q;
+    const bool dl = l.h <= T(P.drytol), dr = r.h <= T(P.drytol);
+    q.all_dry = dl && dr;
+    q.un = qdiv(l.sq * l.un + r.sq * r.un, l.sq + r.sq);
+    q.ut = qdiv(l.sq * l.ut + r.sq * r.ut, l.sq + r.sq);
+    q.c = qsqrt(T(P.g) * (T(0.5) * (l.h + r.h)));
+    return q;
+}
+
+// Transverse split of the amount a = (mass, normal, transverse) entering cell
+// C, with the Roe eigenstructure along the split direction of the pair (l, r):
+// eigenvalues ut - c, ut, ut + c; eigenvectors (1, un, ut - c), (0, 1, 0),
+// (1, un, ut + c).  sgn > 0 keeps the positive-speed part (moving toward r),
+// sgn < 0 the negative-speed part.  c_is_left tells which of the pair is C.
+// The part is 0 if the pair is dry, or if the neighbour is dry with its bed at
+// or above C's surface.
+template <typename T>
+__device__ __forceinline__ void transverse(const TCell<T>& l, const TCell<T>& r,
+                                           const TPair<T>& q, bool c_is_left, const T a[3],
+                                           int sgn, const DevParams& P, T out[3]) {
+    out[0] = out[1] = out[2] = T(0);
+    const TCell<T>& C = c_is_left ? l : r;
+    const TCell<T>& N = c_is_left ? r : l;
+    if (q.all_dry) return;
+    if (N.h <= T(P.drytol) && N.b >= C.h + C.b) return;
+    const T lam[3] = {q.ut - q.c, q.ut, q.ut + q.c};
+    T gam[3];
+    gam[0] = qdiv((q.ut + q.c) * a[0] - a[2], T(2) * q.c);
+    gam[1] = a[1] - q.un * a[0];
+    gam[2] = qdiv(a[2] - (q.ut - q.c) * a[0], T(2) * q.c);
+    const T rv[3][3] = {{T(1), q.un, q.ut - q.c}, {T(0), T(1), T(0)}, {T(1), q.un, q.ut + q.c}};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const T l2 = sgn > 0 ? (lam[p] > T(0) ? lam[p] : T(0)) : (lam[p] < T(0) ? lam[p] : T(0));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[k] += l2 * gam[p] * rv[p][k];
     }
 }
 

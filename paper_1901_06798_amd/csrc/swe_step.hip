@@ -23,6 +23,7 @@
 #include "swe.h"
 #include "swe_common.hpp"
 #include "swe_march.hpp"
+#include "swe_unsplit.hpp"
 #include "swe_math.hpp"
 
 namespace swe {
@@ -79,6 +80,39 @@ __global__ void __launch_bounds__(256) k_split(StepArgs a) {
 
 template __global__ void k_split<false>(StepArgs);
 template __global__ void k_split<true>(StepArgs);
+
+// One patch, unsplit with transverse waves (FP64).
+__global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_order) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (item >= a.nitems) return;
+    Task tk;
+    tk.qin = a.qin;
+    tk.qout = a.qout;
+    tk.b = a.b;
+    tk.off = a.off;
+    tk.ps = a.ps;
+    tk.dt = *a.dt;
+    tk.dx = a.dx;
+    tk.dy = a.dy;
+    tk.pitch = a.pitch;
+    tk.mx = a.mx;
+    tk.my = a.my;
+    tk.c0 = (item % a.nstrips) * kStripOut;
+    tk.U0 = 2 + (item / a.nstrips) * a.H;
+    tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
+    for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
+    tk.active = true;
+    const MarchOut o = march_unsplit<kWave>(tk, a.P, lane, tk.U1 - tk.U0 + 5, transverse_order);
+    const double wx = wave_max_nonneg(o.smx);
+    const double wy = wave_max_nonneg(o.smy);
+    if (lane == 0) {
+        atomic_max_nonneg(&a.smax[0], wx);
+        atomic_max_nonneg(&a.smax[1], wy);
+    }
+    if (o.clamps) atomicAdd(&a.status[1], o.clamps);
+    if (o.flags) atomicOr(&a.status[0], o.flags);
+}
 
 // ---------------------------------------------------------------------------
 // Batched helpers: one block row (blockIdx.y) per patch.
@@ -359,8 +393,10 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     if ((rc = check_patch(patch))) return rc;
     if (!q_in || !q_out || !b || !dt || !smax || !status)
         return fail(SWE_EINVAL, "swe_patch_step: null pointer");
-    if (p->method != SWE_SPLIT)
-        return fail(SWE_EINVAL, "swe_patch_step: only the split step is available");
+    if (p->method == SWE_UNSPLIT && p->precision != SWE_F64)
+        return fail(SWE_EINVAL, "swe_patch_step: the unsplit step is available in FP64 only");
+    if (p->method == SWE_UNSPLIT && p->transverse_order != 1 && p->transverse_order != 2)
+        return fail(SWE_EINVAL, "params: transverse_order must be 1 or 2");
     const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
     const size_t span = (size_t)(patch->off + 2 * patch->plane_stride +
                                  (int64_t)patch->pitch * (patch->my + 4)) * esz;
@@ -388,7 +424,10 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     a.P = dev_params(p);
     const int waves_per_block = 4;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
-    if (p->precision == SWE_F64)
+    if (p->method == SWE_UNSPLIT)
+        hipLaunchKernelGGL(swe::k_unsplit, dim3(blocks), dim3(64 * waves_per_block), 0,
+                           static_cast<hipStream_t>(stream), a, (int)p->transverse_order);
+    else if (p->precision == SWE_F64)
         hipLaunchKernelGGL(swe::k_split<false>, dim3(blocks), dim3(64 * waves_per_block), 0,
                            static_cast<hipStream_t>(stream), a);
     else

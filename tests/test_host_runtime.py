@@ -1,0 +1,91 @@
+"""Host-side pieces of the runtime that need no GPU: the pool allocator of
+the scenario server and the batched planner of the C library."""
+import os
+
+import pytest
+
+from paper_1901_06798_amd import workloads as W
+
+
+def test_pool_allocator_first_fit_and_merge():
+    from paper_1901_06798_amd.serve import PoolAllocator
+    a = PoolAllocator(1000, align=10)
+    x = a.alloc(95)
+    y = a.alloc(300)
+    z = a.alloc(500)
+    assert x == (0, 100) and y == (100, 300) and z == (400, 500)
+    assert a.alloc(200) is None
+    a.release(*y)
+    assert a.alloc(250) == (100, 250)
+    a.release(100, 250)
+    a.release(*x)
+    a.release(*z)
+    assert a.free == [(0, 1000)]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1901_06798_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1901_06798_amd import build
+        build.build()
+    return _lib
+
+
+def amr_patches(L, counts=(5, 7, 9)):
+    specs, probs = W.amr_patch_set(npatch=counts, seed=3)
+    pts, off = [], 0
+    for s, pb in zip(specs, probs):
+        pitch = pb.mx + 4
+        size = pitch * (pb.my + 4)
+        pts.append(L.patch(pb.mx, pb.my, pitch, pb.dx, pb.dy, off=off, plane_stride=10 ** 8,
+                           tref=s.tref, level=s.level, bc=pb.bc))
+        off += size
+    return specs, pts
+
+
+@pytest.mark.parametrize("seg", [64, 32])
+def test_plan_covers_every_cell_once(L, seg):
+    specs, pts = amr_patches(L)
+    items, ni, tasks, nt = L.swe_batched_plan(pts, L.schedule(seg=seg))
+    cover = {}
+    for k in range(nt):
+        t = tasks[k]
+        p = pts[t.patch]
+        c0 = t.strip * (seg - 4) + 2
+        for r in range(t.row0, t.row0 + t.rows):
+            for c in range(c0, min(c0 + seg - 4, p.mx + 2)):
+                cover[(t.patch, r, c)] = cover.get((t.patch, r, c), 0) + 1
+    expect = sum(p.mx * p.my for p in pts)
+    assert len(cover) == expect and set(cover.values()) == {1}
+    # every task belongs to exactly one item of its own patch
+    seen = []
+    for i in range(ni):
+        it = items[i]
+        assert all(tasks[k].patch == it.patch for k in range(it.task_begin, it.task_end))
+        seen += list(range(it.task_begin, it.task_end))
+        # patches with substeps are whole in one item
+        if pts[it.patch].tref > 1:
+            assert it.substeps == pts[it.patch].tref
+    assert sorted(seen) == list(range(nt))
+
+
+def test_plan_orders_longest_first(L):
+    specs, pts = amr_patches(L)
+    items, ni, tasks, nt = L.swe_batched_plan(pts, L.schedule(order=0))
+
+    def cost(it):
+        p = pts[it.patch]
+        return sum((tasks[k].rows + 4) for k in range(it.task_begin, it.task_end)) * it.substeps
+    costs = [cost(items[i]) for i in range(ni)]
+    assert costs == sorted(costs, reverse=True)
+
+
+def test_plan_rejects_bad_input(L):
+    specs, pts = amr_patches(L, (1, 1, 1))
+    bad = L.schedule(seg=48)
+    with pytest.raises(L.SweError):
+        L.swe_batched_plan(pts, bad)
+    pts[2].bc[0] = L.BC_USER
+    with pytest.raises(L.SweError, match="tref"):
+        L.swe_batched_plan(pts, L.schedule())
