@@ -49,6 +49,10 @@ def parse():
                     help="JSON file with the measured HBM bytes per launch of the step kernel")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
+    ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="only run the serving stream with this many requests")
+    ap.add_argument("--serve-steps", type=int, default=1000)
     return ap.parse_args()
 
 
@@ -170,6 +174,89 @@ def time_batched(precision: int, steps: int = 10):
             "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0]}
 
 
+def precision_study(n: int = 2048, steps: int = 2000):
+    """FP32 surface deviation vs FP64 on the walled shelf: surface error on
+    cells wet in both runs (FP32 driven by the FP64 step sizes, and free
+    running), mass drift, and the lake-at-rest residual of both paths."""
+    import torch
+
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.solver import PatchSolver
+
+    pb = W.shelf_walls(n=n, dx=1024e3 / n, seed=4, nsteps=steps)
+    res = {"grid": [n, n], "steps": steps, "dx": pb.dx}
+    s64 = PatchSolver(pb, L.params())
+    m64 = s64.mass()
+    s64.initial_dt()
+    dt_log = torch.zeros(steps, dtype=torch.float64, device=s64.dev)
+    for k in range(steps):
+        dt_log[k].copy_(s64.dt[0])
+        s64.enqueue_step()
+    torch.cuda.synchronize()
+    h64, _, _ = s64.state()
+    eta64 = s64.surface()
+    res["mass_drift_fp64"] = (s64.mass() - m64) / m64
+    res["flags_fp64"] = s64.flags()
+    del s64
+    for mode in ("same_dt", "free_running"):
+        s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+        m32 = s32.mass()
+        if mode == "same_dt":
+            for k in range(steps):
+                s32.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
+                s32.smax.zero_()
+        else:
+            s32.initial_dt()
+            s32.run_async(steps)
+        torch.cuda.synchronize()
+        h32, _, _ = s32.state()
+        eta32 = s32.surface()
+        both = (h32 > 1e-2) & (h64 > 1e-2)
+        err = np.abs(eta32 - eta64)
+        deep = both & (h64 > 10.0)
+        shore = both & (h64 <= 10.0)
+        res[mode] = {"max_surface_err_m": float(err[both].max()),
+                     "max_err_deep_m": float(err[deep].max()) if deep.any() else None,
+                     "max_err_nearshore_m": float(err[shore].max()) if shore.any() else None,
+                     "wetdry_mismatch_cells": int(((h32 > 1e-3) != (h64 > 1e-3)).sum()),
+                     "mass_drift_fp32": (s32.mass() - m32) / m32, "flags": s32.flags()}
+        del s32
+    rest = W.shelf_walls(n=n, dx=1024e3 / n, seed=4, amp=0.0)
+    for prec, name in ((L.F64, "lake_at_rest_fp64"), (L.F32_DEV, "lake_at_rest_fp32_dev")):
+        s = PatchSolver(rest, L.params(precision=prec))
+        s.run_async(200)
+        torch.cuda.synchronize()
+        h, hu, hv = s.state()
+        wet = rest.h > 0
+        res[name] = {"steps": 200, "max_abs_surface_m": float(np.abs(s.surface()[wet]).max()),
+                     "max_abs_momentum": float(max(np.abs(hu).max(), np.abs(hv).max()))}
+        del s
+    return res
+
+
+def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0):
+    """Poisson stream of scenario requests served with continuous batching."""
+    import torch
+
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.serve import Scenario, ScenarioServer
+
+    stream = W.request_stream(count=nreq, rate=rate, nsteps=steps)
+    log(f"[bench] generating {nreq} scenarios")
+    reqs = [Scenario(k, t, W.scenario(k, n=n, nsteps=steps), steps) for k, t, n in stream]
+    srv = ScenarioServer(L.params(precision=L.F32_DEV), hbm_budget=200 << 30, max_slots=64,
+                         steps_per_round=50)
+    # warm the kernels outside the measured stream
+    srv.serve([Scenario(-1, 0.0, W.scenario(0, n=256, nsteps=50), 50)])
+    out = srv.serve(reqs, warmup=warmup)
+    out.pop("done")
+    out.update({"rate_per_s": rate, "steps_per_request": steps, "warmup_requests": warmup,
+                "sizes": "n ~ U{256..2048}, dx 500 m", "precision": "fp32_dev"})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -183,6 +270,11 @@ def main():
         sys.exit(1)
     if args.calib_copy > 0:
         calib_copy(args.calib_copy)
+        return
+    if args.serve > 0:
+        out = serving(args.serve, max(1, args.serve // 6), args.serve_steps)
+        out["metric"] = "scenario latency p50/p99 (ms) and cell-updates/s"
+        print(json.dumps(out), flush=True)
         return
     from paper_1901_06798_amd import _lib as L
     from paper_1901_06798_amd import workloads as W
@@ -241,6 +333,10 @@ def main():
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")
                 out["variants"][name] = time_batched(prec)
+        if not args.no_precision_study:
+            log("[bench] precision study (2048^2 walled shelf, 2000 steps)")
+            torch.cuda.empty_cache()
+            out["precision_study"] = precision_study()
     r64.pop("solver", None)
     if not args.no_cpu_baseline:
         log("[bench] timing the reference solver on the host")

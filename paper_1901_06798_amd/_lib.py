@@ -12,7 +12,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libswe.so")
+LIB_PATH = os.environ.get("SWE_LIB_PATH", os.path.join(_HERE, "libswe.so"))
 
 SWE_OK, SWE_EINVAL, SWE_EHIP = 0, -1, -2
 STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED = 1, 2, 4

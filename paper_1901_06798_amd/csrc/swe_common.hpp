@@ -57,6 +57,35 @@ __device__ __forceinline__ Src map_cell(int R, int c, int mx, int my, int pitch,
 // Lane moves within a segment of SEG lanes (SEG = 64: the whole wave):
 // up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1;
 // the first/last lane of a segment keeps its own value.
+#if SWE_LANE_DPP
+// Whole-wave DPP shifts (wave_shr:1 / wave_shl:1): one VALU move per dword.
+// They cross segment boundaries, which only feeds the halo lanes of a
+// segment, whose results are never used.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+__device__ __forceinline__ int dpp_up(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, kDppWaveShr1, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_down(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, kDppWaveShl1, 0xf, 0xf, false);
+}
+template <int SEG = kWave>
+__device__ __forceinline__ double lane_up(double x) {
+    return __hiloint2double(dpp_up(__double2hiint(x)), dpp_up(__double2loint(x)));
+}
+template <int SEG = kWave>
+__device__ __forceinline__ double lane_down(double x) {
+    return __hiloint2double(dpp_down(__double2hiint(x)), dpp_down(__double2loint(x)));
+}
+template <int SEG = kWave>
+__device__ __forceinline__ float lane_up(float x) {
+    return __int_as_float(dpp_up(__float_as_int(x)));
+}
+template <int SEG = kWave>
+__device__ __forceinline__ float lane_down(float x) {
+    return __int_as_float(dpp_down(__float_as_int(x)));
+}
+#else
 template <int SEG = kWave>
 __device__ __forceinline__ double lane_up(double x) { return __shfl_up(x, 1, SEG); }
 template <int SEG = kWave>
@@ -65,6 +94,7 @@ template <int SEG = kWave>
 __device__ __forceinline__ float lane_up(float x) { return __shfl_up(x, 1, SEG); }
 template <int SEG = kWave>
 __device__ __forceinline__ float lane_down(float x) { return __shfl_down(x, 1, SEG); }
+#endif
 
 template <typename T, bool DEV = false, int SEG = kWave>
 __device__ __forceinline__ Side<T> side_up(const Side<T>& s, const DevParams& P) {

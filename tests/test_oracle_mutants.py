@@ -1,0 +1,197 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies the reference solver's C source to a temporary directory,
+plants one mistake (a dropped term, a wrong sign, a wrong index, a swapped
+operand), compiles it, and checks that at least one of the fast pins below
+fails on the mutant while all of them pass on the unmodified source.  The
+oracle's own source is never modified.
+
+Not listed: how a wave of exactly zero speed is shared between A-dQ and A+dQ.
+An f-wave is its speed times its jump, so a stationary wave carries a zero
+f-wave (Rankine-Hugoniot); the sharing rule cannot be observed beyond
+roundoff, and no pin can tell the two apart.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import analytic
+from helpers import interior, oracle_setup
+from paper_1901_06798_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "swe_oracle.c")
+HDR = os.path.join(ROOT, "oracle", "swe_oracle.h")
+
+MUTANTS = {
+    "drop_bed_source": ("double dphi = (mR * uR - mL * uL) + g * hbar * deta;",
+                        "double dphi = (mR * uR - mL * uL);"),
+    "bed_jump_sign": ("double db = bR - bL;", "double db = bL - bR;"),
+    "beta1_operand": ("double beta1 = (s3 * dh - dm) / (s3 - s1);",
+                      "double beta1 = (s1 * dh - dm) / (s3 - s1);"),
+    "s1_min_max": ("s1 = a < c ? a : c;", "s1 = a > c ? a : c;"),
+    "update_index": ("W->amdq[c + 1][k])", "W->amdq[c][k])"),
+    "upwind_edge": ("const orc_waves *up = s > 0.0 ? wl : wr;",
+                    "const orc_waves *up = s > 0.0 ? wr : wl;"),
+    "mc_limiter_sign": ("double a = 0.5 * (1.0 + theta);", "double a = 0.5 * (1.0 - theta);"),
+    "correction_sign": ("(1.0 - lam * fabs(s))", "(1.0 + lam * fabs(s))"),
+    "y_sweep_momentum": ("line[c][1] = qc[2]; /* normal momentum of the y-sweep is hv */",
+                         "line[c][1] = qc[1]; /* normal momentum of the y-sweep is hv */"),
+    "wall_ghost_sign": ("if (is_state && G->bc[0] == ORC_BC_WALL) a[IDX(G, gi, j) * ncomp + 1] = -a[IDX(G, gi, j) * ncomp + 1];",
+                        "if (is_state && G->bc[0] == ORC_BC_WALL) a[IDX(G, gi, j) * ncomp + 1] = a[IDX(G, gi, j) * ncomp + 1];"),
+    "wall_drop_side": ("int drop = (w->kind == ORC_EDGE_WALL_R && w->s[p] > 0.0) ||",
+                       "int drop = (w->kind == ORC_EDGE_WALL_R && w->s[p] < 0.0) ||"),
+    "transverse_sign": ("for (int m = 0; m < 3; ++m) Gt[ky][m] -= 0.5 * lamx * up[m];",
+                        "for (int m = 0; m < 3; ++m) Gt[ky][m] += 0.5 * lamx * up[m];"),
+    "transverse_eigen": ("gam[2] = (a[2] - (ut - c) * a[0]) / (2.0 * c);",
+                         "gam[2] = (a[2] - (ut + c) * a[0]) / (2.0 * c);"),
+    "cfl_rule": ("dt = r > 0.0 ? P->cfl_desired / r : 1.0;", "dt = r > 0.0 ? P->cfl_max / r : 1.0;"),
+    "clamp_bound": ("if (hL + b1 < 0.0) {", "if (hL - b1 < 0.0) {"),
+}
+
+
+def build_variant(tmp_path, name, old=None, new=None):
+    d = tmp_path / name
+    d.mkdir()
+    src = open(SRC).read()
+    if old is not None:
+        assert src.count(old) == 1, f"mutation anchor not unique for {name}"
+        src = src.replace(old, new)
+    (d / "swe_oracle.c").write_text(src)
+    shutil.copy(HDR, d / "swe_oracle.h")
+    so = d / "lib.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    str(d / "swe_oracle.c"), "-o", str(so), "-lm"], check=True)
+    return str(so)
+
+
+def pins(O):
+    """Fast pins; returns the names of those that fail."""
+    failed = []
+    P = O.params()
+    rng = np.random.default_rng(1)
+    # f-waves sum to the flux jump plus the bed source
+    for _ in range(40):
+        hL, hR = rng.uniform(0.5, 100, 2)
+        uL, vL, uR, vR = rng.uniform(-2, 2, 4)
+        bL, bR = rng.uniform(-100, 0, 2)
+        Z, s, kind, _ = O.riemann((hL, hL * uL, hL * vL, bL), (hR, hR * uR, hR * vR, bR))
+        g = 9.81
+        f = lambda h, u, v: np.array([h * u, h * u * u + 0.5 * g * h * h, h * u * v])
+        expect = f(hR, uR, vR) - f(hL, uL, vL)
+        expect[1] += g * 0.5 * (hL + hR) * (bR - bL)
+        if not np.allclose(Z.sum(axis=0), expect, rtol=1e-9, atol=1e-9):
+            failed.append("flux_identity")
+            break
+        if not (s[0] <= s[1] <= s[2]):
+            failed.append("speed_order")
+            break
+    # mirror symmetry
+    for _ in range(40):
+        hL, hR = rng.uniform(0.5, 100, 2)
+        mL, tL, mR, tR = rng.uniform(-20, 20, 4)
+        bL, bR = rng.uniform(-100, 0, 2)
+        Z, s, _, _ = O.riemann((hL, mL, tL, bL), (hR, mR, tR, bR))
+        Zm, sm, _, _ = O.riemann((hR, -mR, tR, bR), (hL, -mL, tL, bL))
+        if not (np.allclose(sm, -s[::-1], atol=1e-12) and
+                np.allclose(Zm, Z[::-1] * np.array([1.0, -1.0, 1.0]), atol=1e-9)):
+            failed.append("mirror")
+            break
+    # wall edge against a high dry bank = mirror state, and nothing into the bank
+    am, ap = O.fluctuations((2.0, 3.0, 1.0, -2.0), (0.0, 0.0, 0.0, 100.0))
+    Zm, sm, _, _ = O.riemann((2.0, 3.0, 1.0, -2.0), (2.0, -3.0, 1.0, -2.0))
+    left = Zm[sm < 0].sum(axis=0) + 0.5 * Zm[sm == 0].sum(axis=0)
+    if not (np.allclose(am, left, atol=1e-9) and np.all(ap == 0)):
+        failed.append("wall_edge")
+    # the fluctuations split the flux jump (plus bed source) between the two
+    # cells, also when a wave has exactly zero speed (symmetric shear problem)
+    for left, right in (((3.0, 1.5, 2.0, -1.0), (3.0, -1.5, -1.0, -1.0)),
+                        ((2.0, 0.5, 0.3, -4.0), (1.0, 0.2, -0.4, -3.5))):
+        am, ap = O.fluctuations(left, right)
+        fl = lambda h, m, t: np.array([m, m * m / h + 0.5 * 9.81 * h * h, m * t / h])
+        expect = fl(*right[:3]) - fl(*left[:3])
+        expect[1] += 9.81 * 0.5 * (left[0] + right[0]) * (right[3] - left[3])
+        if not np.allclose(am + ap, expect, rtol=1e-12, atol=1e-12):
+            failed.append("fluctuation_split")
+            break
+    if abs(O.mc_limiter(0.5) - 0.75) > 1e-15 or abs(O.mc_limiter(2.0) - 1.5) > 1e-15:
+        failed.append("mc_table")
+    # lake at rest with a coast stays exactly at rest
+    for bc in (W.BC_EXTRAP, W.BC_WALL):
+        pb = W.shelf_grid(40, 500.0, seed=11, amp=0.0, bc=(bc,) * 4, x_s_frac=0.5, width=3e3)
+        g, q, b = oracle_setup(O, pb)
+        q0 = q.copy()
+        O.run(P, g, q, b, 10)
+        if not np.array_equal(interior(q), interior(q0)):
+            failed.append("lake_at_rest")
+            break
+    # hump with walls: mass, symmetry, linear closed form, dt closed form
+    n, dx = 50, 4000.0
+    pb = W.gaussian_hump(n, dx, sigma=20e3)
+    g, q, b = oracle_setup(O, pb)
+    m0 = O.mass(g, q)
+    r = O.run(P, g, q, b, 30)
+    H = interior(q)[..., 0]
+    if abs(O.mass(g, q) - m0) / m0 > 1e-13:
+        failed.append("mass")
+    if np.abs(H - H[:, ::-1]).max() > 1e-10 or np.abs(H - H[::-1, :]).max() > 1e-10:
+        failed.append("symmetry")
+    hc = pb.h.max()
+    if abs(r["dt"][0] - 0.9 * dx / math.sqrt(9.81 * hc)) > 1e-12 * r["dt"][0]:
+        failed.append("dt0")
+    T = float(np.sum(r["dt"]))
+    xc = W.cell_centres(n, dx)
+    ex = analytic.radial_hump_walls(xc, xc, T, 1.0, 20e3, 4000.0, n * dx, n * dx / 2, n * dx / 2)
+    if np.sqrt(np.mean((H - 4000.0 - ex) ** 2)) > 2e-3:
+        failed.append("linear_closed_form")
+    # Stoker plateau
+    pb = W.dam_break_1d(200)
+    g, q, b = oracle_setup(O, pb)
+    r = O.run(P, g, q, b, 50)
+    t = float(np.sum(r["dt"]))
+    st = analytic.stoker_state(2.0, 1.0)
+    x = W.cell_centres(200, 2.0, -200.0)
+    plateau = (x > st["tail"] * t + 8) & (x < st["shock"] * t - 8)
+    if not plateau.any() or np.abs(q[2, 2:-2, 0][plateau] - st["h_m"]).max() > 3e-3:
+        failed.append("stoker")
+    # unsplit: mass, x <-> y symmetry
+    Pu = O.params(method=1)
+    pb = W.gaussian_hump(30, 6000.0, sigma=20e3)
+    pb.h = pb.h + 0.0
+    g, q, b = oracle_setup(O, pb)
+    m0 = O.mass(g, q)
+    O.run(Pu, g, q, b, 15)
+    Q = interior(q)
+    if abs(O.mass(g, q) - m0) / m0 > 1e-13 or np.abs(Q[..., 0] - Q[..., 0].T).max() > 1e-9:
+        failed.append("unsplit")
+    return failed
+
+
+@pytest.fixture
+def swap_lib():
+    import oracle as O
+    saved = (O._lib, O._LIB_PATH)
+
+    def use(path):
+        O._lib = None
+        O._LIB_PATH = path
+        return O
+    yield use
+    O._lib, O._LIB_PATH = saved
+
+
+def test_unmodified_source_passes_every_pin(tmp_path, swap_lib):
+    O = swap_lib(build_variant(tmp_path, "original"))
+    assert pins(O) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, swap_lib, name):
+    old, new = MUTANTS[name]
+    O = swap_lib(build_variant(tmp_path, name, old, new))
+    failed = pins(O)
+    assert failed, f"no pin caught mutant {name}"

@@ -59,6 +59,20 @@ def test_fwaves_sum_to_flux_jump_plus_source(orc, hL, uL, vL, bL, hR, uR, vR, bR
 
 
 @settings(max_examples=300, deadline=None)
+@given(wet_h, mom, mom, mom, mom, bed)
+def test_fluctuations_split_the_flux_jump(orc, h, u, vL, vR, shift, b):
+    # symmetric normal velocities give a shear wave of exactly zero speed; the
+    # two fluctuations together must still carry the whole flux jump
+    for left, right in (((h, h * u, h * vL, b), (h, -h * u, h * vR, b)),
+                        ((h, h * u, h * vL, b), (h + abs(shift), h * vR, h * u, b - 1.0))):
+        am, ap = orc.fluctuations(left, right)
+        expect = _flux(right[0], right[1], right[2]) - _flux(left[0], left[1], left[2])
+        expect[1] += G * 0.5 * (left[0] + right[0]) * (right[3] - left[3])
+        scale = np.abs(_flux(*left[:3])) + np.abs(_flux(*right[:3])) + G * (left[0] + right[0]) * abs(b) + 1.0
+        assert np.all(np.abs(am + ap - expect) <= 1e-12 * scale)
+
+
+@settings(max_examples=300, deadline=None)
 @given(st.floats(min_value=-4000.0, max_value=-0.01), st.floats(min_value=-4000.0, max_value=-0.01),
        st.floats(min_value=-2.0, max_value=2.0))
 def test_lake_at_rest_wet_wet_is_exactly_zero(orc, bL, bR, eta):
