@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--batched", action="store_true", help="also time the AMR patch set")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with the measured HBM bytes per launch of the step kernel")
+                    help="counter record (key = value) with the step kernel's HBM bytes per launch")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
     ap.add_argument("--no-precision-study", action="store_true")
@@ -58,6 +58,41 @@ def parse():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; measured traffic is used only for this hash."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1901_06798_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_split_f64_shelf4096_traffic.txt")
+
+
+def measured_traffic(path: str | None):
+    """HBM bytes per launch of the FP64 step kernel from the counter record
+    (key = value lines), if it was measured on the current kernel sources."""
+    path = path or TRAFFIC_RECORD
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def calib_copy(mb: float) -> None:
@@ -174,10 +209,12 @@ def time_batched(precision: int, steps: int = 10):
             "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0]}
 
 
-def precision_study(n: int = 2048, steps: int = 2000):
-    """FP32 surface deviation vs FP64 on the walled shelf: surface error on
-    cells wet in both runs (FP32 driven by the FP64 step sizes, and free
-    running), mass drift, and the lake-at-rest residual of both paths."""
+def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
+    """FP32 surface deviation vs FP64 on the walled shelf.  Both runs advance
+    in lockstep (FP32 driven by the FP64 step sizes); at every checkpoint the
+    surface error on cells wet (h > 1e-2 m) in both runs is reported, split into
+    deep water (h > 10 m) and near shore.  Then a free-running FP32 run, the
+    mass drift of both, and the lake-at-rest residual of both paths."""
     import torch
 
     from paper_1901_06798_amd import _lib as L
@@ -187,41 +224,50 @@ def precision_study(n: int = 2048, steps: int = 2000):
     pb = W.shelf_walls(n=n, dx=1024e3 / n, seed=4, nsteps=steps)
     res = {"grid": [n, n], "steps": steps, "dx": pb.dx}
     s64 = PatchSolver(pb, L.params())
-    m64 = s64.mass()
+    s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    m64, m32 = s64.mass(), s32.mass()
     s64.initial_dt()
     dt_log = torch.zeros(steps, dtype=torch.float64, device=s64.dev)
-    for k in range(steps):
-        dt_log[k].copy_(s64.dt[0])
-        s64.enqueue_step()
-    torch.cuda.synchronize()
-    h64, _, _ = s64.state()
-    eta64 = s64.surface()
-    res["mass_drift_fp64"] = (s64.mass() - m64) / m64
-    res["flags_fp64"] = s64.flags()
-    del s64
-    for mode in ("same_dt", "free_running"):
-        s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
-        m32 = s32.mass()
-        if mode == "same_dt":
-            for k in range(steps):
-                s32.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
-                s32.smax.zero_()
-        else:
-            s32.initial_dt()
-            s32.run_async(steps)
-        torch.cuda.synchronize()
-        h32, _, _ = s32.state()
-        eta32 = s32.surface()
+    hist = []
+
+    def errors(a64, a32):
+        h64, _, _ = a64.state()
+        h32, _, _ = a32.state()
+        e64, e32 = a64.surface(), a32.surface()
         both = (h32 > 1e-2) & (h64 > 1e-2)
-        err = np.abs(eta32 - eta64)
+        err = np.abs(e32 - e64)
         deep = both & (h64 > 10.0)
         shore = both & (h64 <= 10.0)
-        res[mode] = {"max_surface_err_m": float(err[both].max()),
-                     "max_err_deep_m": float(err[deep].max()) if deep.any() else None,
-                     "max_err_nearshore_m": float(err[shore].max()) if shore.any() else None,
-                     "wetdry_mismatch_cells": int(((h32 > 1e-3) != (h64 > 1e-3)).sum()),
-                     "mass_drift_fp32": (s32.mass() - m32) / m32, "flags": s32.flags()}
-        del s32
+        return {"max_surface_err_m": float(err[both].max()),
+                "max_err_deep_m": float(err[deep].max()) if deep.any() else None,
+                "max_err_nearshore_m": float(err[shore].max()) if shore.any() else None,
+                "wetdry_mismatch_cells": int(((h32 > 1e-3) != (h64 > 1e-3)).sum()),
+                "max_abs_surface_m": float(np.abs(e64[h64 > 1e-2]).max())}
+
+    for k0 in range(0, steps, every):
+        for k in range(k0, min(k0 + every, steps)):
+            dt_log[k].copy_(s64.dt[0])
+            s64.enqueue_step()
+            s32.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
+            s32.smax.zero_()
+        torch.cuda.synchronize()
+        e = errors(s64, s32)
+        e["step"] = min(k0 + every, steps)
+        hist.append(e)
+    res["same_dt"] = dict(hist[-1])
+    res["same_dt"]["history"] = hist
+    res["mass_drift_fp64"] = (s64.mass() - m64) / m64
+    res["same_dt"]["mass_drift_fp32"] = (s32.mass() - m32) / m32
+    res["flags_fp64"] = s64.flags()
+    res["same_dt"]["flags"] = s32.flags()
+    del s32
+    f32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    f32.initial_dt()
+    f32.run_async(steps)
+    torch.cuda.synchronize()
+    res["free_running"] = errors(s64, f32)
+    res["free_running"]["flags"] = f32.flags()
+    del s64, f32
     rest = W.shelf_walls(n=n, dx=1024e3 / n, seed=4, amp=0.0)
     for prec, name in ((L.F64, "lake_at_rest_fp64"), (L.F32_DEV, "lake_at_rest_fp32_dev")):
         s = PatchSolver(rest, L.params(precision=prec))
@@ -286,10 +332,7 @@ def main():
     r64 = time_patch(pb, L.params(), args.steps, args.warmup)
     log(f"[bench] FP64: {r64['ms_per_step']:.3f} ms/step, kernel {r64['kernel_ms_avg']:.3f} ms, "
         f"{r64['cups']:.3e} CUPS, flags={r64['flags']}")
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = measured_traffic(args.traffic)
     out = {
         "metric": "cell-updates/s (FP64 split step, 4096^2 shelf)",
         "value": r64["cups"],

@@ -57,6 +57,9 @@ __device__ __forceinline__ Src map_cell(int R, int c, int mx, int my, int pitch,
 // Lane moves within a segment of SEG lanes (SEG = 64: the whole wave):
 // up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1;
 // the first/last lane of a segment keeps its own value.
+#ifndef SWE_LANE_DPP
+#define SWE_LANE_DPP 1
+#endif
 #if SWE_LANE_DPP
 // Whole-wave DPP shifts (wave_shr:1 / wave_shl:1): one VALU move per dword.
 // They cross segment boundaries, which only feeds the halo lanes of a

@@ -148,8 +148,11 @@ class ScenarioServer:
         dst = self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n]
         dst.copy_(torch.from_numpy(q.reshape(3, n)).to(self.dev, non_blocking=False))
         self.b[sc.off: sc.off + n].copy_(torch.from_numpy(bb.reshape(n)).to(self.dev))
-        # first dt of this scenario from a speed scan of its own grid
-        tab = patch_table([self._patch(sc)]).to(self.dev)
+        # first dt of this scenario from a speed scan of its own grid: a one-patch
+        # table whose patch is group 0 of a one-group reduction into dt[slot]
+        one = self._patch(sc)
+        one.group = 0
+        tab = patch_table([one]).to(self.dev)
         sm = self.smax[2 * sc.slot: 2 * sc.slot + 2]
         sm.zero_()
         s = torch.cuda.current_stream(self.dev).cuda_stream
