@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
     ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--make-traffic-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
+                    help="write the traffic record from rocprofv3 --pmc runs and exit")
     ap.add_argument("--serve", type=int, default=0,
                     help="only run the serving stream with this many requests")
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -93,6 +95,56 @@ def measured_traffic(path: str | None):
         return float(rec["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _pmc_mean(run_dir: str, counter: str, kernel_sub: str):
+    import csv
+    import glob
+    vals = []
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and kernel_sub in r["Kernel_Name"]:
+                    vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} samples for {kernel_sub} under {run_dir}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def make_traffic_record(root: str, out: str) -> None:
+    """Traffic record of the FP64 step kernel from four rocprofv3 --pmc runs
+    under `root`: pmc_fetch/, pmc_write/ (bench.py) and calib_fetch/,
+    calib_write/ (bench.py --calib-copy 1024).  Each counter is scaled by the
+    ratio of the copy kernel's known bytes to what the counter read for it."""
+    kern = "k_split<false>"
+    fetch, nf = _pmc_mean(os.path.join(root, "pmc_fetch"), "FETCH_SIZE", kern)
+    write, nw = _pmc_mean(os.path.join(root, "pmc_write"), "WRITE_SIZE", kern)
+    cf, _ = _pmc_mean(os.path.join(root, "calib_fetch"), "FETCH_SIZE", "copyBuffer")
+    cw, _ = _pmc_mean(os.path.join(root, "calib_write"), "WRITE_SIZE", "copyBuffer")
+    copy_kib = CALIB_BYTES / 1024.0
+    sf, sw = copy_kib / cf, copy_kib / cw
+    total = (fetch * sf + write * sw) * 1024.0
+    lines = [
+        "# FP64 split step k_split<false>, 4096^2 shelf: HBM traffic per launch",
+        "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the copy calibration",
+        f"kernel_source_hash = {kernel_source_hash()}",
+        f"fetch_kib_per_launch = {fetch:.1f}",
+        f"write_kib_per_launch = {write:.1f}",
+        f"dispatches_fetch = {nf}",
+        f"dispatches_write = {nw}",
+        f"calibration_copy_bytes = {CALIB_BYTES}",
+        f"calib_fetch_kib = {cf:.1f}",
+        f"calib_write_kib = {cw:.1f}",
+        f"fetch_scale = {sf:.4f}",
+        f"write_scale = {sw:.4f}",
+        f"hbm_bytes_per_launch = {total:.0f}",
+    ]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+CALIB_BYTES = 1024000000
 
 
 def calib_copy(mb: float) -> None:
@@ -305,6 +357,9 @@ def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0):
 
 def main():
     args = parse()
+    if args.make_traffic_record:
+        make_traffic_record(*args.make_traffic_record)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
               f"single-GPU in this build", file=sys.stderr)
