@@ -21,6 +21,7 @@ the FETCH_SIZE / WRITE_SIZE counters of a profiler run).
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -50,6 +51,8 @@ def parse():
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
     ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--make-valu-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
+                    help="write the VALU counter record from a rocprofv3 --pmc run and exit")
     ap.add_argument("--make-traffic-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
                     help="write the traffic record from rocprofv3 --pmc runs and exit")
     ap.add_argument("--serve", type=int, default=0,
@@ -145,6 +148,69 @@ def make_traffic_record(root: str, out: str) -> None:
 
 
 CALIB_BYTES = 1024000000
+
+VALU_RECORD = os.path.join(ROOT, "profiles", "k_split_f64_shelf4096_valu.txt")
+# one VALU lane-operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VALU",
+               "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
+
+
+def make_valu_record(root: str, out: str) -> None:
+    """Instruction counters of the FP64 step kernel from one rocprofv3 --pmc
+    run under root/sq1 (counters SQ_COUNTERS, bench.py)."""
+    kern = "k_split<false>"
+    lines = ["# FP64 split step k_split<false>, 4096^2 shelf: SQ counters per dispatch",
+             f"kernel_source_hash = {kernel_source_hash()}"]
+    for c in SQ_COUNTERS:
+        v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern)
+        lines.append(f"{c} = {v:.0f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_valu(kernel_ms: float):
+    """VALU figures of the FP64 step kernel from the counter record, if it was
+    taken on the current kernel sources."""
+    if not os.path.exists(VALU_RECORD):
+        return None
+    rec = {}
+    with open(VALU_RECORD) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    insts = float(rec["SQ_INSTS_VALU"])
+    lane_ops = 64.0 * insts / (kernel_ms * 1e-3)
+    return {"valu_insts_per_launch": insts, "salu_insts_per_launch": float(rec["SQ_INSTS_SALU"]),
+            "waves_per_launch": float(rec["SQ_WAVES"]),
+            "lane_ops_per_s": lane_ops, "peak_lane_ops_per_s": VALU_PEAK_LANE_OPS,
+            "frac": lane_ops / VALU_PEAK_LANE_OPS,
+            "lane_ops_per_cell_update": 64.0 * insts / (4096.0 * 4096.0)}
+
+
+def edge_stats(h, hu, hv, b, drytol: float = 1e-3, h_fp64: float = 1.0, lanes: int = 64,
+               out_cols: int = 60):
+    """Share of x-edges between interior cells that are quiet (both cells wet,
+    at rest, surface jump (h_R - h_L) + (b_R - b_L) exactly 0), share of
+    (row, 64-lane strip) groups whose edges are all quiet (those skip the
+    Riemann solve), and share of edges with a cell at or below h_fp64."""
+    hL, hR = h[:, :-1], h[:, 1:]
+    wet = (hL > drytol) & (hR > drytol)
+    rest = (hu[:, :-1] == 0) & (hu[:, 1:] == 0) & (hv[:, :-1] == 0) & (hv[:, 1:] == 0)
+    quiet = wet & rest & (((hR - hL) + (b[:, 1:] - b[:, :-1])) == 0.0)
+    ny, ne = quiet.shape
+    groups = []
+    for c0 in range(0, ne, out_cols):
+        groups.append(quiet[:, c0: c0 + lanes].all(axis=1))
+    strip_rows = np.concatenate(groups)
+    shallow = (hL <= h_fp64) | (hR <= h_fp64)
+    return {"quiet_edge_frac": float(quiet.mean()),
+            "quiet_strip_row_frac": float(strip_rows.mean()),
+            "fp64_island_edge_frac": float(shallow.mean())}
 
 
 def calib_copy(mb: float) -> None:
@@ -243,6 +309,12 @@ def time_batched(precision: int, steps: int = 10):
     bs = BatchedSolver(probs, L.params(precision=precision), trefs=trefs,
                        sched=L.schedule(seg=64, waves_per_group=4))
     bs.initial_dt()
+    # schedule from the autotuner (timed on this patch set; no cache, so the
+    # choice is made on the machine that runs the bench)
+    from paper_1901_06798_amd.autotune import _sched_dict, tune
+    best = tune(bs, use_cache=False)
+    tuned = {"schedule": _sched_dict(best), "candidates": len(bs.tune_results),
+             "best_ms": bs.tune_results[0][0], "worst_ms": bs.tune_results[-1][0]}
     bs.run(2)
     bs.capture(2)
     torch.cuda.synchronize()
@@ -258,7 +330,7 @@ def time_batched(precision: int, steps: int = 10):
     nbytes = BYTES_PER_CELL[precision] * upd
     return {"patches": len(probs), "cell_updates_per_coarse_step": upd,
             "ms_per_coarse_step": ms, "cups": upd / (ms * 1e-3),
-            "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0]}
+            "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0], "autotune": tuned}
 
 
 def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
@@ -277,10 +349,20 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     res = {"grid": [n, n], "steps": steps, "dx": pb.dx}
     s64 = PatchSolver(pb, L.params())
     s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    # conditioning check: FP64 started from the values the FP32 run starts
+    # from (bed and surface deviation rounded to FP32), so only the initial
+    # rounding differs from the FP64 run
+    sea = L.params().sea_level
+    b32 = pb.b.astype(np.float32).astype(np.float64)
+    eta32 = np.where(pb.h > 0.0, pb.h + pb.b - sea, pb.b - sea).astype(np.float32).astype(np.float64)
+    pbc = copy.copy(pb)
+    pbc.b = b32
+    pbc.h = np.where(pb.h > 0.0, np.maximum(eta32 + sea - b32, 0.0), 0.0)
+    s64c = PatchSolver(pbc, L.params())
     m64, m32 = s64.mass(), s32.mass()
     s64.initial_dt()
     dt_log = torch.zeros(steps, dtype=torch.float64, device=s64.dev)
-    hist = []
+    hist, hist_c = [], []
 
     def errors(a64, a32):
         h64, _, _ = a64.state()
@@ -302,12 +384,20 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
             s64.enqueue_step()
             s32.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
             s32.smax.zero_()
+            s64c.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
+            s64c.smax.zero_()
         torch.cuda.synchronize()
         e = errors(s64, s32)
         e["step"] = min(k0 + every, steps)
         hist.append(e)
+        c = errors(s64, s64c)
+        c["step"] = e["step"]
+        hist_c.append(c)
     res["same_dt"] = dict(hist[-1])
     res["same_dt"]["history"] = hist
+    res["fp64_from_fp32_rounded_start"] = dict(hist_c[-1])
+    res["fp64_from_fp32_rounded_start"]["history"] = hist_c
+    del s64c
     res["mass_drift_fp64"] = (s64.mass() - m64) / m64
     res["same_dt"]["mass_drift_fp32"] = (s32.mass() - m32) / m32
     res["flags_fp64"] = s64.flags()
@@ -359,6 +449,9 @@ def main():
     args = parse()
     if args.make_traffic_record:
         make_traffic_record(*args.make_traffic_record)
+        return
+    if args.make_valu_record:
+        make_valu_record(*args.make_valu_record)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -413,20 +506,37 @@ def main():
         "status_flags": r64["flags"],
         "clamps": r64["clamps"],
     }
+    valu = measured_valu(r64["kernel_ms_avg"])
+    if valu:
+        out["valu"] = valu
+    st64 = r64["solver"].state()
+    out["edges_at_end"] = edge_stats(*st64, pb.b)
     if not args.no_variants:
         log("[bench] FP32 surface-deviation split step")
         h64 = r64["solver"].surface()
         del r64["solver"]
         torch.cuda.empty_cache()
         r32 = time_patch(pb, L.params(precision=L.F32_DEV), args.steps, args.warmup)
-        h32 = r32.pop("solver").surface()
-        wet = (h64 > -1e30)
+        s32 = r32.pop("solver")
+        h32 = s32.surface()
+        d32 = s32.state()[0]
+        wet = (st64[0] > 1e-2) & (d32 > 1e-2)
+        del s32
         out["variants"] = {"fp32_dev": {
             "cups": r32["cups"], "ms_per_step": r32["ms_per_step"],
             "kernel_ms_avg": r32["kernel_ms_avg"], "achieved_gbs": r32["achieved_gbs"],
             "frac": r32["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r32["alg_bytes"],
             "speedup_vs_fp64": r32["cups"] / r64["cups"], "flags": r32["flags"],
-            "free_running_max_surface_diff_m": float(np.abs(h32 - h64)[wet].max())}}
+            "free_running_max_surface_diff_m": float(np.abs(h32 - h64)[wet].max()),
+            "fp64_island_edge_frac": edge_stats(d32, *st64[1:], pb.b)["fp64_island_edge_frac"]}}
+        log("[bench] FP64 unsplit step (transverse waves)")
+        torch.cuda.empty_cache()
+        ru = time_patch(pb, L.params(method=L.UNSPLIT), args.steps, args.warmup)
+        ru.pop("solver")
+        out["variants"]["unsplit_fp64"] = {
+            "cups": ru["cups"], "ms_per_step": ru["ms_per_step"],
+            "kernel_ms_avg": ru["kernel_ms_avg"], "achieved_gbs": ru["achieved_gbs"],
+            "frac": ru["achieved_gbs"] / HBM_PEAK_GBS, "flags": ru["flags"]}
         if args.batched:
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")

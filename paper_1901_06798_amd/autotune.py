@@ -17,8 +17,9 @@ import torch
 
 from . import _lib as L
 
-CACHE = os.environ.get("SWE_TUNE_CACHE",
-                       os.path.join(os.path.expanduser("~"), ".cache", "swe_gfx950_tune.json"))
+def default_cache() -> str:
+    return os.environ.get("SWE_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "swe_gfx950_tune.json"))
 
 BUCKETS = (32, 64, 96, 128, 256, 1024, 1 << 30)
 
@@ -54,6 +55,8 @@ def time_schedule(solver, sched: L.swe_schedule, steps: int = 5) -> float:
     # restore the same state for every candidate so timings compare
     saved = [t.clone() for t in solver.pools]
     dt = solver.dt.clone()
+    status = solver.status.clone()
+    cur = solver.cur
     solver.enqueue_step(cfl=False)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     st = torch.cuda.current_stream(solver.dev)
@@ -66,16 +69,25 @@ def time_schedule(solver, sched: L.swe_schedule, steps: int = 5) -> float:
     for t, s in zip(solver.pools, saved):
         t.copy_(s)
     solver.dt.copy_(dt)
+    solver.status.copy_(status)
+    solver.cur = cur
     solver.smax.zero_()
     return float(np.median(ms))
 
 
-def tune(solver, cands=None, use_cache: bool = True, log=None) -> L.swe_schedule:
+def tune(solver, cands=None, use_cache: bool = True, log=None,
+         cache_path: str | None = None) -> L.swe_schedule:
+    """Time every candidate on the solver's patch set (its state is restored
+    after each) and leave the solver planned with the fastest.  With the cache
+    on, a patch set of the same signature reuses the stored choice without
+    timing anything."""
+    path = cache_path or default_cache()
     sig = signature(solver)
     cache = {}
-    if use_cache and os.path.exists(CACHE):
+    solver.tune_results = []
+    if use_cache and os.path.exists(path):
         try:
-            with open(CACHE) as f:
+            with open(path) as f:
                 cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
@@ -95,9 +107,9 @@ def tune(solver, cands=None, use_cache: bool = True, log=None) -> L.swe_schedule
     solver.replan(best)
     if use_cache:
         cache[sig] = {"schedule": _sched_dict(best), "ms": best_ms}
-        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
-        with open(CACHE + ".tmp", "w") as f:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path + ".tmp", "w") as f:
             json.dump(cache, f, indent=1)
-        os.replace(CACHE + ".tmp", CACHE)
+        os.replace(path + ".tmp", path)
     solver.tune_results = sorted(results, key=lambda r: r[0])
     return best

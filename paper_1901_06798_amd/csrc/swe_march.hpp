@@ -99,25 +99,32 @@ __device__ __forceinline__ void cleanup(S q[3], S b, const DevParams& P, bool va
 #define SWE_QUIET 1
 #endif
 
-// An edge whose two cells are wet, carry no momentum and have bitwise equal
-// surfaces gives exactly zero waves (the decomposition of a zero jump), and
-// its largest speed is max(c_L, c_R): with u = 0 the speed bounds are
-// -max(c_L, c_hat) and max(c_R, c_hat), and c_hat = sqrt(g (h_L + h_R) / 2)
-// never exceeds max(c_L, c_R), also after rounding.  When every lane of the
-// wave has such an edge the solve is skipped; the results are the ones the
-// solve would give.
+// Edges whose waves are known without a solve:
+// - both cells dry: no waves, all speeds 0 (the solver's first exit);
+// - both cells wet, no momentum, bitwise equal surfaces: the decomposition of
+//   a zero jump, so all f-waves are exactly 0, and the largest speed is
+//   max(c_L, c_R): with u = 0 the speed bounds are -max(c_L, c_hat) and
+//   max(c_R, c_hat), and c_hat = sqrt(g (h_L + h_R) / 2) never exceeds
+//   max(c_L, c_R), also after rounding.
+// When every lane of the wave has such an edge the solve is skipped.  With
+// zero f-waves the fluctuations and corrections are 0 whatever the speeds, so
+// the step's results, including the speed maximum, are the solver's.
 template <bool DEV, typename S>
 __device__ __forceinline__ bool quiet_edge(const Side<S>& L, const Side<S>& R) {
     const S deta = DEV ? (R.eta - L.eta) : (R.h - L.h) + (R.b - L.b);
-    return !L.dry && !R.dry && L.m == S(0) && L.t == S(0) && R.m == S(0) && R.t == S(0) &&
-           deta == S(0);
+    const bool rest = !L.dry && !R.dry && L.m == S(0) && L.t == S(0) && R.m == S(0) &&
+                      R.t == S(0) && deta == S(0);
+    return rest || (L.dry && R.dry);
 }
 
 template <typename S>
-__device__ __forceinline__ void quiet_waves(const Side<S>& L, const Side<S>& R, Waves<S>& w) {
-    const S m = L.c > R.c ? L.c : R.c;
-    w.kind = kEdgeWet;
-    w.shallow = false;
+__device__ __forceinline__ void quiet_waves(const Side<S>& L, const Side<S>& R,
+                                            const DevParams& P, Waves<S>& w) {
+    const bool dry = L.dry && R.dry;
+    const S c = L.c > R.c ? L.c : R.c;
+    const S m = dry ? S(0) : c;
+    w.kind = dry ? kEdgeDry : kEdgeWet;
+    w.shallow = L.h <= S(P.h_corr) || R.h <= S(P.h_corr);
 #pragma unroll
     for (int p = 0; p < 3; ++p) w.z[p][0] = w.z[p][1] = w.z[p][2] = S(0);
     w.s[0] = -m;
@@ -170,24 +177,54 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 
     // rolling state of the y-pipeline (row R - 1, R - 2 of Q*, edge E - 1)
     Side<S> prev;
+    prev.h = prev.m = prev.t = prev.b = prev.u = prev.v = prev.sq = prev.c = prev.eta = S(0);
+    prev.dry = true;
     S prev_m = S(0), prev_t = S(0);
-    S qm1[3] = {0, 0, 0}, qm2[3] = {0, 0, 0};
-    S qm1_b = S(0), qm2_b = S(0);
+    S qm2[3] = {0, 0, 0};
+    S qm2_b = S(0);
     Waves<S> wprev;
     S dprev[3] = {0, 0, 0};
     S ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
+
+    // Row t of the march is patch row U0 - 2 + min(t, tlast): every row index
+    // stays within 0 .. my + 3, also one past the last iteration, so the
+    // next row's loads are issued unconditionally one iteration ahead and
+    // their latency hides behind the current row's arithmetic.  Signs of
+    // mirrored ghost momenta are applied at use, so no arithmetic waits on
+    // the loads before then.
+    S nq0, nhu, nhv, nbb;
+    bool nfx, nfy;
+    {
+        const Src s0 = map_cell(U0 - 2, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+        nq0 = qin[s0.idx];
+        nhu = qin[s0.idx + tk.ps];
+        nhv = qin[s0.idx + 2 * tk.ps];
+        nbb = bpl[s0.idx];
+        nfx = s0.sx < 0.0;
+        nfy = s0.sy < 0.0;
+    }
 
     for (int t = 0; t < steps; ++t) {
         const bool live = t <= tlast;
         const int R = U0 - 2 + (live ? t : tlast);
         const bool interior_row = live && R >= U0 && R <= U1;
 
-        // ---- load row R (ghosts synthesised for physical boundaries)
-        const Src src = map_cell(R, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
-        const S q0 = qin[src.idx];
-        const S hu = S(src.sx) * qin[src.idx + tk.ps];
-        const S hv = S(src.sy) * qin[src.idx + 2 * tk.ps];
-        const S bb = bpl[src.idx];
+        // ---- row R (ghosts synthesised for physical boundaries), loaded one
+        // iteration ago; then issue the loads of the next row
+        const S q0 = nq0;
+        const S hu = nfx ? -nhu : nhu;
+        const S hv = nfy ? -nhv : nhv;
+        const S bb = nbb;
+        {
+            const int Rn = U0 - 2 + (t + 1 <= tlast ? t + 1 : tlast);
+            const Src sn = map_cell(Rn, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+            nq0 = qin[sn.idx];
+            nhu = qin[sn.idx + tk.ps];
+            nhv = qin[sn.idx + 2 * tk.ps];
+            nbb = bpl[sn.idx];
+            nfx = sn.sx < 0.0;
+            nfy = sn.sy < 0.0;
+        }
 
         // ---- x-sweep of row R: lane k solves the edge between columns k-1, k
         const Side<S> me = side_from<DEV, S, S>(q0, hu, hv, bb, P);
@@ -195,7 +232,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         const S lf_m = DEV ? lane_up<SEG>(hu) : S(0), lf_t = DEV ? lane_up<SEG>(hv) : S(0);
         Waves<S> w;
         if (SWE_QUIET && __all(quiet_edge<DEV, S>(lf, me)))
-            quiet_waves(lf, me, w);
+            quiet_waves(lf, me, P, w);
         else
             solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
         S am[3], ap[3];
@@ -235,7 +272,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         if (t >= 1) {
             Waves<S> wy;
             if (SWE_QUIET && __all(quiet_edge<DEV, S>(prev, cur)))
-                quiet_waves(prev, cur, wy);
+                quiet_waves(prev, cur, P, wy);
             else
                 solve_edge<DEV, S>(prev, cur, prev_m, prev_t, qs[2], qs[1], P, wy);
             const int E = R;  // edge between rows R - 1 and R
@@ -292,14 +329,13 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             for (int p = 0; p < 3; ++p) dprev[p] = dcur[p];
             wprev = wy;
         }
-        // Q* of row R in y order (h, hv, hu) for the update two rows later
-#pragma unroll
-        for (int k = 0; k < 3; ++k) qm2[k] = qm1[k];
-        qm2_b = qm1_b;
-        qm1[0] = qs[0];
-        qm1[1] = qs[2];
-        qm1[2] = qs[1];
-        qm1_b = bb;
+        // Q* of row R - 1 in y order (h or eta', hv, hu) is what `prev` was
+        // made from: after the cleanup a dry cell carries no momentum, so
+        // prev.m and prev.t are the stored hv and hu also there
+        qm2[0] = DEV ? prev.eta : prev.h;
+        qm2[1] = prev.m;
+        qm2[2] = prev.t;
+        qm2_b = prev.b;
         prev = cur;
         prev_m = qs[2];
         prev_t = qs[1];

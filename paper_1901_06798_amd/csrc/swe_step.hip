@@ -18,7 +18,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 
 #include "swe.h"
 #include "swe_common.hpp"
@@ -45,8 +48,10 @@ struct StepArgs {
 };
 
 // One patch, one wave64 per (strip, chunk of H rows).
+// Waves per SIMD the register budget is fitted to: the FP32 march fits three
+// (at most 168 VGPRs) without spilling; the FP64 one needs more registers.
 template <bool DEV>
-__global__ void __launch_bounds__(256) k_split(StepArgs a) {
+__global__ void __launch_bounds__(256, DEV ? 3 : 2) k_split(StepArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int item = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (item >= a.nitems) return;  // whole wave leaves together
@@ -364,10 +369,40 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-int rows_per_chunk(int my) {
+// Waves of a kernel that the device holds at once (occupancy x compute units),
+// cached per device and kernel.
+int resident_waves(const void* kernel, int kidx, int block) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, kidx});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = cus = 0;
+    }
+    const int w = per_cu * cus * (block / swe::kWave);
+    cache[{dev, kidx}] = w;
+    return w;
+}
+
+// Rows per strip task.  A wave marches H rows plus 4 rows of pipeline fill,
+// so longer chunks waste less; the chunk count per strip is the largest that
+// keeps every task of the launch resident at once (one round of waves, no
+// tail), and H is at least 16.  SWE_ROWS_PER_WAVE overrides.
+int rows_per_chunk(int mx, int my, int resident) {
     const char* e = std::getenv("SWE_ROWS_PER_WAVE");
-    int H = e ? std::atoi(e) : 64;
-    if (H < 1) H = 64;
+    int H = e ? std::atoi(e) : 0;
+    if (H < 1) {
+        const int nstrips = (mx + swe::kStripOut - 1) / swe::kStripOut;
+        const int chunks = resident > nstrips ? resident / nstrips : 1;
+        H = (my + chunks - 1) / chunks;
+        if (H < 16) H = 16;
+    }
     return H < my ? H : my;
 }
 
@@ -416,13 +451,23 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     a.pitch = patch->pitch;
     a.mx = patch->mx;
     a.my = patch->my;
-    a.H = rows_per_chunk(patch->my);
+    const char* wpb = std::getenv("SWE_WAVES_PER_BLOCK");
+    int waves_per_block = wpb ? std::atoi(wpb) : 4;
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        waves_per_block = 4;
+    const void* kern = p->method == SWE_UNSPLIT ? reinterpret_cast<const void*>(&swe::k_unsplit)
+                       : p->precision == SWE_F64
+                           ? reinterpret_cast<const void*>(&swe::k_split<false>)
+                           : reinterpret_cast<const void*>(&swe::k_split<true>);
+    const int kidx = p->method == SWE_UNSPLIT ? 2 : p->precision == SWE_F64 ? 0 : 1;
+    a.H = rows_per_chunk(patch->mx, patch->my,
+                         resident_waves(kern, 8 * kidx + waves_per_block,
+                                        swe::kWave * waves_per_block));
     a.nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
     const int nchunks = (patch->my + a.H - 1) / a.H;
     a.nitems = a.nstrips * nchunks;
     for (int s = 0; s < 4; ++s) a.bc[s] = patch->bc[s];
     a.P = dev_params(p);
-    const int waves_per_block = 4;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     if (p->method == SWE_UNSPLIT)
         hipLaunchKernelGGL(swe::k_unsplit, dim3(blocks), dim3(64 * waves_per_block), 0,
