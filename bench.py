@@ -51,13 +51,16 @@ def parse():
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
     ap.add_argument("--no-precision-study", action="store_true")
-    ap.add_argument("--make-valu-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
-                    help="write the VALU counter record from a rocprofv3 --pmc run and exit")
+    ap.add_argument("--make-valu-record", nargs=2, metavar=("PMC_ROOT", "OUTDIR"), default=None,
+                    help="write the VALU counter records from a rocprofv3 --pmc run and exit")
     ap.add_argument("--make-traffic-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
                     help="write the traffic record from rocprofv3 --pmc runs and exit")
     ap.add_argument("--serve", type=int, default=0,
                     help="only run the serving stream with this many requests")
     ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=36,
+                    help="requests in the serving run of the default bench")
+    ap.add_argument("--no-serving", action="store_true")
     return ap.parse_args()
 
 
@@ -156,18 +159,30 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VAL
                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
 
 
-def make_valu_record(root: str, out: str) -> None:
-    """Instruction counters of the FP64 step kernel from one rocprofv3 --pmc
-    run under root/sq1 (counters SQ_COUNTERS, bench.py)."""
-    kern = "k_split<false>"
-    lines = ["# FP64 split step k_split<false>, 4096^2 shelf: SQ counters per dispatch",
-             f"kernel_source_hash = {kernel_source_hash()}"]
-    for c in SQ_COUNTERS:
-        v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern)
-        lines.append(f"{c} = {v:.0f}")
-    with open(out, "w") as f:
-        f.write("\n".join(lines) + "\n")
-    print("\n".join(lines))
+VALU_KERNELS = (("k_split<false>", "k_split_f64_shelf4096_valu.txt", "FP64 split step"),
+                ("k_split<true>", "k_split_f32dev_shelf4096_valu.txt",
+                 "FP32 surface-deviation split step"),
+                ("k_unsplit", "k_unsplit_f64_shelf4096_valu.txt", "FP64 unsplit step"))
+
+
+def make_valu_record(root: str, outdir: str) -> None:
+    """Instruction counters per dispatch of the step kernels from one
+    rocprofv3 --pmc run under root/sq1 (counters SQ_COUNTERS, bench.py with
+    its variants), one record per kernel in outdir."""
+    for kern, fname, what in VALU_KERNELS:
+        lines = [f"# {what} {kern}, 4096^2 shelf: SQ counters per dispatch",
+                 f"kernel_source_hash = {kernel_source_hash()}"]
+        try:
+            for c in SQ_COUNTERS:
+                v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern)
+                lines.append(f"{c} = {v:.0f}")
+        except SystemExit as e:
+            print(f"skipping {kern}: {e}")
+            continue
+        lines.append(f"dispatches = {n}")
+        with open(os.path.join(outdir, fname), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
 
 
 def measured_valu(kernel_ms: float):
@@ -423,25 +438,41 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     return res
 
 
-def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0):
+def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0, budget_gb: float = 200.0,
+            max_slots: int = 64, steps_per_round: int = 50):
     """Poisson stream of scenario requests served with continuous batching."""
-    import torch
-
     from paper_1901_06798_amd import _lib as L
     from paper_1901_06798_amd import workloads as W
     from paper_1901_06798_amd.serve import Scenario, ScenarioServer
 
     stream = W.request_stream(count=nreq, rate=rate, nsteps=steps)
-    log(f"[bench] generating {nreq} scenarios")
+    log(f"[bench] serving: generating {nreq} scenarios")
     reqs = [Scenario(k, t, W.scenario(k, n=n, nsteps=steps), steps) for k, t, n in stream]
-    srv = ScenarioServer(L.params(precision=L.F32_DEV), hbm_budget=200 << 30, max_slots=64,
-                         steps_per_round=50)
+    srv = ScenarioServer(L.params(precision=L.F32_DEV), hbm_budget=int(budget_gb * (1 << 30)),
+                         max_slots=max_slots, steps_per_round=steps_per_round)
     # warm the kernels outside the measured stream
     srv.serve([Scenario(-1, 0.0, W.scenario(0, n=256, nsteps=50), 50)])
+    log(f"[bench] serving: {nreq} requests at {rate}/s, budget {budget_gb} GB")
     out = srv.serve(reqs, warmup=warmup)
-    out.pop("done")
+    done = out.pop("done")
+    waits = [sc.admitted - sc.arrival for sc in done if sc.rid >= warmup]
     out.update({"rate_per_s": rate, "steps_per_request": steps, "warmup_requests": warmup,
-                "sizes": "n ~ U{256..2048}, dx 500 m", "precision": "fp32_dev"})
+                "hbm_budget_gb": budget_gb, "max_slots": max_slots,
+                "steps_per_round": steps_per_round,
+                "max_queue_wait_ms": float(max(waits) * 1e3) if waits else None,
+                "sizes": "n ~ U{256..2048}, dx 500 m", "precision": "fp32_dev",
+                "sample": f"first {nreq} requests of the Poisson stream (seed 5)"})
+    return out
+
+
+def serving_pair(nreq: int, steps: int) -> dict:
+    """The stream with a large HBM budget, then the first part of it with a
+    budget of about four of the largest grids, which makes requests queue."""
+    import torch
+    out = {"budget_200gb": serving(nreq, max(1, nreq // 6), steps)}
+    torch.cuda.empty_cache()
+    small = max(6, nreq // 3)
+    out["budget_0.5gb"] = serving(small, max(1, small // 6), steps, budget_gb=0.5)
     return out
 
 
@@ -466,7 +497,7 @@ def main():
         calib_copy(args.calib_copy)
         return
     if args.serve > 0:
-        out = serving(args.serve, max(1, args.serve // 6), args.serve_steps)
+        out = serving_pair(args.serve, args.serve_steps)
         out["metric"] = "scenario latency p50/p99 (ms) and cell-updates/s"
         print(json.dumps(out), flush=True)
         return
@@ -541,6 +572,9 @@ def main():
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")
                 out["variants"][name] = time_batched(prec)
+        if not args.no_serving:
+            torch.cuda.empty_cache()
+            out["serving"] = serving_pair(args.serve_requests, args.serve_steps)
         if not args.no_precision_study:
             log("[bench] precision study (2048^2 walled shelf, 2000 steps)")
             torch.cuda.empty_cache()

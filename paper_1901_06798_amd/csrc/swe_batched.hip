@@ -42,7 +42,7 @@ struct BatchArgs {
     DevParams P;
 };
 
-template <bool DEV, int SEG>
+template <bool DEV, int SEG, bool FRIC>
 __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
     constexpr int kSegPerWave = kWave / SEG;
     __shared__ int s_item;
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.queue[0], 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= a.nitems) break;
         const swe_item it = a.items[item];
@@ -70,7 +70,9 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
             // no substep reads the buffer it writes
             void* dst = ((it.substeps - 1 - s) % 2 == 0) ? a.pout : a.pwork;
             for (int base = it.task_begin; base < it.task_end; base += nseg) {
-                const int tid = base + seg_id;
+                // with one segment per wave the task is the wave's: scalar
+                const int tid = SEG == kWave ? __builtin_amdgcn_readfirstlane(base + seg_id)
+                                             : base + seg_id;
                 const bool active = tid < it.task_end;
                 const swe_task tsk = a.tasks[active ? tid : it.task_begin];
                 Task tk;
@@ -100,7 +102,9 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
                     const int other = __shfl_xor(steps, o, kWave);
                     steps = other > steps ? other : steps;
                 }
-                const MarchOut r = march<DEV, SEG>(tk, a.P, lane_in_seg, steps);
+                // the same for every lane after the reduction: a scalar trip count
+                steps = __builtin_amdgcn_readfirstlane(steps);
+                const MarchOut r = march<DEV, SEG, FRIC>(tk, a.P, lane_in_seg, steps);
                 smx = r.smx > smx ? r.smx : smx;
                 smy = r.smy > smy ? r.smy : smy;
                 clamps += r.clamps;
@@ -134,10 +138,14 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
     }
 }
 
-template __global__ void k_batched<false, 64>(BatchArgs);
-template __global__ void k_batched<false, 32>(BatchArgs);
-template __global__ void k_batched<true, 64>(BatchArgs);
-template __global__ void k_batched<true, 32>(BatchArgs);
+template __global__ void k_batched<false, 64, false>(BatchArgs);
+template __global__ void k_batched<false, 32, false>(BatchArgs);
+template __global__ void k_batched<true, 64, false>(BatchArgs);
+template __global__ void k_batched<true, 32, false>(BatchArgs);
+template __global__ void k_batched<false, 64, true>(BatchArgs);
+template __global__ void k_batched<false, 32, true>(BatchArgs);
+template __global__ void k_batched<true, 64, true>(BatchArgs);
+template __global__ void k_batched<true, 32, true>(BatchArgs);
 
 }  // namespace swe
 
@@ -299,11 +307,16 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
 
     const int threads = 64 * sched->waves_per_group;
     const bool dev = p->precision == SWE_F32_DEV;
-    const void* fn = nullptr;
-    if (!dev && sched->seg == 64) fn = reinterpret_cast<const void*>(&swe::k_batched<false, 64>);
-    if (!dev && sched->seg == 32) fn = reinterpret_cast<const void*>(&swe::k_batched<false, 32>);
-    if (dev && sched->seg == 64) fn = reinterpret_cast<const void*>(&swe::k_batched<true, 64>);
-    if (dev && sched->seg == 32) fn = reinterpret_cast<const void*>(&swe::k_batched<true, 32>);
+    const bool fric = p->manning_n > 0.0;
+    using Kern = void (*)(swe::BatchArgs);
+    // [precision][segment 64 / 32][friction]
+    const Kern table[2][2][2] = {
+        {{swe::k_batched<false, 64, false>, swe::k_batched<false, 64, true>},
+         {swe::k_batched<false, 32, false>, swe::k_batched<false, 32, true>}},
+        {{swe::k_batched<true, 64, false>, swe::k_batched<true, 64, true>},
+         {swe::k_batched<true, 32, false>, swe::k_batched<true, 32, true>}}};
+    const Kern kern = table[dev ? 1 : 0][sched->seg == 64 ? 0 : 1][fric ? 1 : 0];
+    const void* fn = reinterpret_cast<const void*>(kern);
     int dev_id = 0, ncu = 0;
     if (hipGetDevice(&dev_id) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
@@ -319,10 +332,7 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
     if (grid > nitems) grid = nitems;
     if (grid < 1) grid = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (!dev && sched->seg == 64) hipLaunchKernelGGL((swe::k_batched<false, 64>), dim3(grid), dim3(threads), 0, st, a);
-    if (!dev && sched->seg == 32) hipLaunchKernelGGL((swe::k_batched<false, 32>), dim3(grid), dim3(threads), 0, st, a);
-    if (dev && sched->seg == 64) hipLaunchKernelGGL((swe::k_batched<true, 64>), dim3(grid), dim3(threads), 0, st, a);
-    if (dev && sched->seg == 32) hipLaunchKernelGGL((swe::k_batched<true, 32>), dim3(grid), dim3(threads), 0, st, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return bfail(SWE_EHIP, std::string("swe_batched_step: ") + hipGetErrorString(e));

@@ -155,7 +155,10 @@ struct MarchOut {
 // March one strip task.  `steps` is the number of row iterations every lane
 // of the wave executes (the largest over the wave's segments); a lane whose
 // own strip is shorter repeats its last row with writes and reports masked.
-template <bool DEV, int SEG>
+// FRIC: the Manning friction step is compiled in (the caller picks it when
+// the friction coefficient is positive), so the step without friction
+// carries none of its registers.
+template <bool DEV, int SEG, bool FRIC>
 __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, int lane_in_seg,
                                           int steps) {
     using S = typename Prec<DEV>::S;
@@ -179,12 +182,16 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     Side<S> prev;
     prev.h = prev.m = prev.t = prev.b = prev.u = prev.v = prev.sq = prev.c = prev.eta = S(0);
     prev.dry = true;
-    S prev_m = S(0), prev_t = S(0);
     S qm2[3] = {0, 0, 0};
     S qm2_b = S(0);
     Waves<S> wprev;
     S dprev[3] = {0, 0, 0};
     S ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
+    // finished row held for one iteration: its stores are issued before the
+    // next row's loads, so waiting for those loads never waits for stores
+    S po[3] = {0, 0, 0};
+    int po_row = 0;
+    bool po_wr = false;
 
     // Row t of the march is patch row U0 - 2 + min(t, tlast): every row index
     // stays within 0 .. my + 3, also one past the last iteration, so the
@@ -215,6 +222,13 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         const S hu = nfx ? -nhu : nhu;
         const S hv = nfy ? -nhv : nhv;
         const S bb = nbb;
+        if (po_wr) {
+            const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;
+            qout[o] = po[0];
+            qout[o + tk.ps] = po[1];
+            qout[o + 2 * tk.ps] = po[2];
+        }
+        po_wr = false;
         {
             const int Rn = U0 - 2 + (t + 1 <= tlast ? t + 1 : tlast);
             const Src sn = map_cell(Rn, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
@@ -274,7 +288,9 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             if (SWE_QUIET && __all(quiet_edge<DEV, S>(prev, cur)))
                 quiet_waves(prev, cur, P, wy);
             else
-                solve_edge<DEV, S>(prev, cur, prev_m, prev_t, qs[2], qs[1], P, wy);
+                // Q* is cleaned up, so a dry side's stored momenta are 0 and
+                // the Sides carry the stored values for the FP64 islands too
+                solve_edge<DEV, S>(prev, cur, prev.m, prev.t, cur.m, cur.t, P, wy);
             const int E = R;  // edge between rows R - 1 and R
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
                 const S s = max_speed(wy);
@@ -301,7 +317,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                     const S bo = qm2_b;
                     const bool wr = upd_col && live;
                     cleanup<DEV, S>(out, bo, P, wr, wr, clamps, flags);
-                    if (P.manning_n > 0.0) {
+                    if (FRIC) {
                         const S hd = DEV ? out[0] + S(P.sea_level) - bo : out[0];
                         if (hd > S(P.drytol)) {
                             const S n2g = S(P.manning_n) * S(P.manning_n) * S(P.g);
@@ -312,12 +328,10 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                             out[2] *= f;
                         }
                     }
-                    if (wr) {
-                        const int64_t o = tk.off + (int64_t)(R - 2) * tk.pitch + c;
-                        qout[o] = out[0];
-                        qout[o + tk.ps] = out[1];
-                        qout[o + 2 * tk.ps] = out[2];
-                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) po[k] = out[k];
+                    po_row = R - 2;
+                    po_wr = wr;
                 }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -337,8 +351,12 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         qm2[2] = prev.t;
         qm2_b = prev.b;
         prev = cur;
-        prev_m = qs[2];
-        prev_t = qs[1];
+    }
+    if (po_wr) {
+        const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;
+        qout[o] = po[0];
+        qout[o + tk.ps] = po[1];
+        qout[o + 2 * tk.ps] = po[2];
     }
     MarchOut o;
     o.smx = double(smx);

@@ -235,19 +235,19 @@ __device__ __forceinline__ void fluctuations(const Waves<T>& w, T am[3], T ap[3]
         am[k] = T(0);
         ap[k] = T(0);
     }
+    // Branch-free: each sum takes the wave, half of it, or +0.  A sum that
+    // starts at +0 never becomes -0 by adding, so adding +0 leaves it as it
+    // is, and the sums equal those of adding each wave to its side only.
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const T s = w.s[p];
+        const bool neg = s < T(0), pos = s > T(0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            if (s < T(0)) {
-                am[k] += w.z[p][k];
-            } else if (s > T(0)) {
-                ap[k] += w.z[p][k];
-            } else {
-                am[k] += T(0.5) * w.z[p][k];
-                ap[k] += T(0.5) * w.z[p][k];
-            }
+            const T z = w.z[p][k];
+            const T half = T(0.5) * z;
+            am[k] += neg ? z : (pos ? T(0) : half);
+            ap[k] += pos ? z : (neg ? T(0) : half);
         }
     }
     // written as value selects so the arrays stay in registers
@@ -280,19 +280,21 @@ __device__ __forceinline__ void correction(const Waves<T>& w, const T dl[3], con
                                            T F[3]) {
     F[0] = F[1] = F[2] = T(0);
     if (w.shallow) return;
+    // Branch-free over the waves: a wave of zero speed or zero size adds +0
+    // (its quotient is computed and discarded), which leaves the sums as they
+    // are (they start at +0 and never become -0 by adding).
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const T s = w.s[p];
-        if (s == T(0)) continue;
         const T zz = dot3(w.z[p], w.z[p]);
-        if (zz == T(0)) continue;
+        const bool use = s != T(0) && zz != T(0);
         const T theta = qdiv(s > T(0) ? dl[p] : dr[p], zz);
         const T phi = mc_limiter(theta);
         const T sg = s > T(0) ? T(1) : T(-1);
         const T as = s > T(0) ? s : -s;
         const T coef = T(0.5) * sg * (T(1) - lam * as) * phi;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) F[k] += coef * w.z[p][k];
+        for (int k = 0; k < 3; ++k) F[k] += use ? coef * w.z[p][k] : T(0);
     }
 }
 

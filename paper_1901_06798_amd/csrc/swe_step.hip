@@ -48,12 +48,16 @@ struct StepArgs {
 };
 
 // One patch, one wave64 per (strip, chunk of H rows).
-// Waves per SIMD the register budget is fitted to: the FP32 march fits three
-// (at most 168 VGPRs) without spilling; the FP64 one needs more registers.
-template <bool DEV>
-__global__ void __launch_bounds__(256, DEV ? 3 : 2) k_split(StepArgs a) {
+// Waves per SIMD the register budget is fitted to, without spilling: the
+// FP32 march takes four (at most 128 VGPRs), the FP64 one three (168); with
+// the friction step compiled in, one fewer.
+template <bool DEV, bool FRIC>
+__global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(StepArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int item = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    // the task, and with it the row loop's trip count, is the same for the
+    // whole wave: keep it in scalar registers
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
+                                                    (threadIdx.x / kWave));
     if (item >= a.nitems) return;  // whole wave leaves together
     Task tk;
     tk.qin = a.qin;
@@ -72,7 +76,7 @@ __global__ void __launch_bounds__(256, DEV ? 3 : 2) k_split(StepArgs a) {
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
     tk.active = true;
-    const MarchOut o = march<DEV, kWave>(tk, a.P, lane, tk.U1 - tk.U0 + 5);
+    const MarchOut o = march<DEV, kWave, FRIC>(tk, a.P, lane, tk.U1 - tk.U0 + 5);
     const double wx = wave_max_nonneg(o.smx);
     const double wy = wave_max_nonneg(o.smy);
     if (lane == 0) {
@@ -83,13 +87,17 @@ __global__ void __launch_bounds__(256, DEV ? 3 : 2) k_split(StepArgs a) {
     if (o.flags) atomicOr(&a.status[0], o.flags);
 }
 
-template __global__ void k_split<false>(StepArgs);
-template __global__ void k_split<true>(StepArgs);
+template __global__ void k_split<false, false>(StepArgs);
+template __global__ void k_split<true, false>(StepArgs);
+template __global__ void k_split<false, true>(StepArgs);
+template __global__ void k_split<true, true>(StepArgs);
 
 // One patch, unsplit with transverse waves (FP64).
+template <bool FRIC>
 __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_order) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int item = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
+                                                    (threadIdx.x / kWave));
     if (item >= a.nitems) return;
     Task tk;
     tk.qin = a.qin;
@@ -108,7 +116,8 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
     tk.active = true;
-    const MarchOut o = march_unsplit<kWave>(tk, a.P, lane, tk.U1 - tk.U0 + 5, transverse_order);
+    const MarchOut o =
+        march_unsplit<kWave, FRIC>(tk, a.P, lane, tk.U1 - tk.U0 + 5, transverse_order);
     const double wx = wave_max_nonneg(o.smx);
     const double wy = wave_max_nonneg(o.smy);
     if (lane == 0) {
@@ -118,6 +127,9 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     if (o.clamps) atomicAdd(&a.status[1], o.clamps);
     if (o.flags) atomicOr(&a.status[0], o.flags);
 }
+
+template __global__ void k_unsplit<false>(StepArgs, int);
+template __global__ void k_unsplit<true>(StepArgs, int);
 
 // ---------------------------------------------------------------------------
 // Batched helpers: one block row (blockIdx.y) per patch.
@@ -455,11 +467,19 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     int waves_per_block = wpb ? std::atoi(wpb) : 4;
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
         waves_per_block = 4;
-    const void* kern = p->method == SWE_UNSPLIT ? reinterpret_cast<const void*>(&swe::k_unsplit)
-                       : p->precision == SWE_F64
-                           ? reinterpret_cast<const void*>(&swe::k_split<false>)
-                           : reinterpret_cast<const void*>(&swe::k_split<true>);
-    const int kidx = p->method == SWE_UNSPLIT ? 2 : p->precision == SWE_F64 ? 0 : 1;
+    const bool fric = p->manning_n > 0.0;
+    const bool f64 = p->precision == SWE_F64;
+    const void* kern;
+    if (p->method == SWE_UNSPLIT)
+        kern = fric ? reinterpret_cast<const void*>(&swe::k_unsplit<true>)
+                    : reinterpret_cast<const void*>(&swe::k_unsplit<false>);
+    else if (f64)
+        kern = fric ? reinterpret_cast<const void*>(&swe::k_split<false, true>)
+                    : reinterpret_cast<const void*>(&swe::k_split<false, false>);
+    else
+        kern = fric ? reinterpret_cast<const void*>(&swe::k_split<true, true>)
+                    : reinterpret_cast<const void*>(&swe::k_split<true, false>);
+    const int kidx = (p->method == SWE_UNSPLIT ? 2 : f64 ? 0 : 1) + (fric ? 3 : 0);
     a.H = rows_per_chunk(patch->mx, patch->my,
                          resident_waves(kern, 8 * kidx + waves_per_block,
                                         swe::kWave * waves_per_block));
@@ -469,15 +489,19 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     for (int s = 0; s < 4; ++s) a.bc[s] = patch->bc[s];
     a.P = dev_params(p);
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
-    if (p->method == SWE_UNSPLIT)
-        hipLaunchKernelGGL(swe::k_unsplit, dim3(blocks), dim3(64 * waves_per_block), 0,
-                           static_cast<hipStream_t>(stream), a, (int)p->transverse_order);
-    else if (p->precision == SWE_F64)
-        hipLaunchKernelGGL(swe::k_split<false>, dim3(blocks), dim3(64 * waves_per_block), 0,
-                           static_cast<hipStream_t>(stream), a);
-    else
-        hipLaunchKernelGGL(swe::k_split<true>, dim3(blocks), dim3(64 * waves_per_block), 0,
-                           static_cast<hipStream_t>(stream), a);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid(blocks), block(64 * waves_per_block);
+    const int tord = (int)p->transverse_order;
+    if (p->method == SWE_UNSPLIT) {
+        if (fric) hipLaunchKernelGGL(swe::k_unsplit<true>, grid, block, 0, st, a, tord);
+        else hipLaunchKernelGGL(swe::k_unsplit<false>, grid, block, 0, st, a, tord);
+    } else if (f64) {
+        if (fric) hipLaunchKernelGGL((swe::k_split<false, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((swe::k_split<false, false>), grid, block, 0, st, a);
+    } else {
+        if (fric) hipLaunchKernelGGL((swe::k_split<true, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((swe::k_split<true, false>), grid, block, 0, st, a);
+    }
     return check_launch("swe_patch_step");
 }
 

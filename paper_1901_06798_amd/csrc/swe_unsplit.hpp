@@ -58,7 +58,7 @@ __device__ __forceinline__ TCell<double> tcell(double h, double hu, double hv, d
     return t;
 }
 
-template <int SEG>
+template <int SEG, bool FRIC>
 __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParams& P,
                                                   int lane_in_seg, int steps,
                                                   int transverse_order) {
@@ -241,7 +241,7 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
                     }
                     const bool wr = upd_col && live;
                     cleanup<false, S>(out, bb, P, wr, wr, clamps, flags);
-                    if (P.manning_n > 0.0 && out[0] > P.drytol) {
+                    if (FRIC && out[0] > P.drytol) {
                         const S n2g = P.manning_n * P.manning_n * P.g;
                         const S speed = sqrt(out[1] * out[1] + out[2] * out[2]) / out[0];
                         const S D = n2g * pow(out[0], -7.0 / 3.0) * speed;

@@ -10,10 +10,18 @@ scenario's result does not depend on who else is in the batch.  Between
 rounds it retires finished scenarios and admits queued ones while a slot is
 free and their HBM footprint fits the budget.  Latency is arrival to
 completion (result on the host).
+
+The host stays one round ahead of the device: all device work (uploads,
+rounds, result copies) is ordered on one stream, uploads and result copies go
+through pinned staging buffers without blocking, and the host waits only for
+the round before the one it just queued.  A retired scenario's pool range and
+slot can be handed to a new scenario at once, because the new scenario's
+upload is queued after the old scenario's last copy.
 """
 from __future__ import annotations
 
 import time
+from collections import deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -73,6 +81,27 @@ class Scenario:
     result: dict = field(default_factory=dict)
 
 
+class PinnedPool:
+    """Pinned host buffers, reused once the copies that use them are done."""
+
+    def __init__(self, dtype: torch.dtype):
+        self.dtype = dtype
+        self.free: list[torch.Tensor] = []
+
+    def get(self, n: int) -> torch.Tensor:
+        best = None
+        for k, t in enumerate(self.free):
+            if t.numel() >= n and (best is None or t.numel() < self.free[best].numel()):
+                best = k
+        if best is not None:
+            return self.free.pop(best)[:n]
+        return torch.empty(max(n, 1 << 16), dtype=self.dtype, pin_memory=True)[:n]
+
+    def put(self, t: torch.Tensor) -> None:
+        base = t._base if t._base is not None else t
+        self.free.append(base)
+
+
 class ScenarioServer:
     def __init__(self, params: L.swe_params | None = None, hbm_budget: int = 64 << 30,
                  max_slots: int = 64, steps_per_round: int = 50, device: str = "cuda:0",
@@ -103,6 +132,20 @@ class ScenarioServer:
         self.active: list[Scenario] = []
         self.free_slots = list(range(max_slots))
         self.table_dirty = True
+        self.host_state = PinnedPool(self.dtype)
+        self.host_bytes = PinnedPool(torch.uint8)
+        self.hold: list = []  # pinned buffers read by copies not yet known to be done
+
+    @property
+    def stream(self) -> int:
+        return torch.cuda.current_stream(self.dev).cuda_stream
+
+    def _to_device(self, host: torch.Tensor) -> torch.Tensor:
+        """Asynchronous copy of a small CPU tensor through pinned memory."""
+        st = self.host_bytes.get(host.numel())
+        st.copy_(host)
+        self.hold.append((self.host_bytes, st))
+        return st.to(self.dev, non_blocking=True)
 
     # -- footprint and admission ----------------------------------------------
     def footprint_elems(self, pb: Problem) -> int:
@@ -134,45 +177,46 @@ class ScenarioServer:
         pb = sc.problem
         pitch = _round_up(pb.mx + 4, 16)
         rows = pb.my + 4
-        npdt = np.float32 if self.esize == 4 else np.float64
-        q = np.zeros((3, rows, pitch), dtype=npdt)
-        bb = np.zeros((rows, pitch), dtype=npdt)
+        n = pitch * rows
+        stage = self.host_state.get(4 * n)
+        stage.zero_()
+        planes = stage.view(4, rows, pitch).numpy()
         first = pb.h
         if self.p.precision == L.F32_DEV:
             first = np.where(pb.h > 0.0, pb.h + pb.b - self.p.sea_level, pb.b - self.p.sea_level)
-        q[0, 2:-2, 2: pb.mx + 2] = first
-        q[1, 2:-2, 2: pb.mx + 2] = pb.hu
-        q[2, 2:-2, 2: pb.mx + 2] = pb.hv
-        bb[2:-2, 2: pb.mx + 2] = pb.b
-        n = pitch * rows
+        inner = (slice(2, pb.my + 2), slice(2, pb.mx + 2))
+        planes[0][inner] = first
+        planes[1][inner] = pb.hu
+        planes[2][inner] = pb.hv
+        planes[3][inner] = pb.b
+        self.hold.append((self.host_state, stage))
         dst = self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n]
-        dst.copy_(torch.from_numpy(q.reshape(3, n)).to(self.dev, non_blocking=False))
-        self.b[sc.off: sc.off + n].copy_(torch.from_numpy(bb.reshape(n)).to(self.dev))
+        dst.copy_(stage[: 3 * n].view(3, n), non_blocking=True)
+        self.b[sc.off: sc.off + n].copy_(stage[3 * n: 4 * n], non_blocking=True)
         # first dt of this scenario from a speed scan of its own grid: a one-patch
         # table whose patch is group 0 of a one-group reduction into dt[slot]
         one = self._patch(sc)
         one.group = 0
-        tab = patch_table([one]).to(self.dev)
-        sm = self.smax[2 * sc.slot: 2 * sc.slot + 2]
-        sm.zero_()
-        s = torch.cuda.current_stream(self.dev).cuda_stream
+        tab = self._to_device(patch_table([one]))
+        self.smax[2 * sc.slot: 2 * sc.slot + 2].zero_()
         L.swe_speed_scan(self.p, tab.data_ptr(), 1, pb.mx, pb.my, self.pools[self.cur].data_ptr(),
-                         self.b.data_ptr(), self.smax.data_ptr() + 16 * sc.slot, s)
+                         self.b.data_ptr(), self.smax.data_ptr() + 16 * sc.slot, self.stream)
         dts = self.dt[sc.slot: sc.slot + 1]
         L.swe_cfl_reduce(self.p, tab.data_ptr(), 1, 1, self.smax.data_ptr() + 16 * sc.slot,
-                         dts.data_ptr(), self.status.data_ptr(), 0, 1, s)
+                         dts.data_ptr(), self.status.data_ptr(), 0, 1, self.stream)
 
     def _rebuild(self) -> None:
         pts = [self._patch(sc) for sc in self.active]
-        self.table = patch_table(pts).to(self.dev)
+        self.table = self._to_device(patch_table(pts))
         items, ni, tasks, nt = L.swe_batched_plan(pts, self.sched)
-        self.items = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(self.dev)
-        self.tasks = torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8).to(self.dev)
+        self.items = self._to_device(torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8))
+        self.tasks = self._to_device(torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8))
         self.nitems = ni
-        # smax entries follow the table order; the dt slots follow the scenario slots
         self.table_dirty = False
 
-    def _retire(self, sc: Scenario) -> None:
+    def _retire(self, sc: Scenario):
+        """Queue the copy of a finished scenario's surface and free its pool
+        range and slot; returns the pinned buffer the surface lands in."""
         pb = sc.problem
         pitch = _round_up(pb.mx + 4, 16)
         n = pitch * (pb.my + 4)
@@ -181,22 +225,34 @@ class ScenarioServer:
         if self.p.precision != L.F32_DEV:
             bb = self.b[sc.off: sc.off + n].view(pb.my + 4, pitch)[2:-2, 2: pb.mx + 2]
             eta = eta + bb
-        # the early-warning product: maximum surface elevation of the final state
-        # and the final surface itself
-        sc.result = {"eta": eta.cpu().numpy().astype(np.float64)}
-        sc.finished = time.perf_counter()
+        out = self.host_state.get(pb.mx * pb.my)
+        out.view(pb.my, pb.mx).copy_(eta, non_blocking=True)
         self.alloc.release(sc.off, sc.span)
         self.free_slots.append(sc.slot)
         self.free_slots.sort()
         self.active.remove(sc)
         self.table_dirty = True
+        return sc, out
+
+    def _finish(self, results, t0: float) -> list:
+        done = []
+        for sc, out in results:
+            pb = sc.problem
+            eta = out.view(pb.my, pb.mx).numpy().astype(np.float64)
+            if self.p.precision == L.F32_DEV:
+                eta = eta + self.p.sea_level
+            # the early-warning product: the final surface
+            sc.result = {"eta": eta}
+            sc.finished = time.perf_counter() - t0
+            self.host_state.put(out)
+            done.append(sc)
+        return done
 
     # -- one round ---------------------------------------------------------------
     def round(self, steps: int) -> None:
         if self.table_dirty:
             self._rebuild()
         # a scenario's smax pair lives at its table index during the round
-        s = torch.cuda.current_stream(self.dev).cuda_stream
         n = len(self.active)
         smax = torch.zeros(2 * n, dtype=torch.float64, device=self.dev)
         for _ in range(steps):
@@ -204,12 +260,11 @@ class ScenarioServer:
                                self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
                                self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
                                self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
-                               self.queue_ctr.data_ptr(), self.sched, s)
+                               self.queue_ctr.data_ptr(), self.sched, self.stream)
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
                              self.dt.data_ptr(), self.status.data_ptr(),
-                             self.group_flags.data_ptr(), 0, s)
+                             self.group_flags.data_ptr(), 0, self.stream)
             self.cur ^= 1
-            # scenarios not in the active table keep their planes; copy them along
         for sc in self.active:
             sc.steps_done += steps
 
@@ -219,10 +274,27 @@ class ScenarioServer:
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: list[Scenario] = []
         done: list[Scenario] = []
+        inflight: deque = deque()  # (event, results, pinned buffers held)
         t0 = time.perf_counter()
         cells = 0
         i = 0
-        while i < len(pending) or queue or self.active:
+
+        def settle(block: bool) -> None:
+            ev, results, held = inflight[0]
+            if block:
+                ev.synchronize()
+            elif not ev.query():
+                return
+            inflight.popleft()
+            for pool, buf in held:
+                pool.put(buf)
+            for sc in self._finish(results, t0):
+                done.append(sc)
+                if log:
+                    log(f"[serve] request {sc.rid} ({sc.problem.mx}^2) done, latency "
+                        f"{(sc.finished - sc.arrival) * 1e3:.1f} ms")
+
+        while i < len(pending) or queue or self.active or inflight:
             now = time.perf_counter() - t0
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
@@ -231,21 +303,32 @@ class ScenarioServer:
             while queue and self.try_admit(queue[0]):
                 queue[0].admitted = time.perf_counter() - t0
                 queue.pop(0)
-            if not self.active:
-                if i < len(pending):
-                    time.sleep(max(0.0, min(0.01, pending[i].arrival - now)))
-                continue
-            steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
-            self.round(steps)
-            torch.cuda.synchronize(self.dev)
-            cells += steps * sum(sc.problem.mx * sc.problem.my for sc in self.active)
-            for sc in [sc for sc in self.active if sc.steps_done >= sc.nsteps]:
-                self._retire(sc)
-                sc.finished -= t0
-                done.append(sc)
-                if log:
-                    log(f"[serve] request {sc.rid} ({sc.problem.mx}^2) done, latency "
-                        f"{(sc.finished - sc.arrival) * 1e3:.1f} ms")
+            if queue and not self.active and not inflight:
+                raise L.SweError(f"request {queue[0].rid} needs "
+                                 f"{self.footprint_bytes(queue[0].problem)} bytes of HBM, more "
+                                 f"than the server's budget of {7 * self.plane * self.esize}")
+            if self.active:
+                steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
+                self.round(steps)
+                cells += steps * sum(sc.problem.mx * sc.problem.my for sc in self.active)
+                results = [self._retire(sc) for sc in
+                           [sc for sc in self.active if sc.steps_done >= sc.nsteps]]
+                ev = torch.cuda.Event()
+                ev.record(torch.cuda.current_stream(self.dev))
+                inflight.append((ev, results, self.hold))
+                self.hold = []
+            # stay one round ahead: wait for the older of two queued rounds, or
+            # for the last one when nothing else can be queued
+            if inflight and (len(inflight) > 1 or not self.active):
+                settle(block=True)
+            while inflight:
+                before = len(inflight)
+                settle(block=False)
+                if len(inflight) == before:
+                    break
+            if not self.active and not inflight and not queue and i < len(pending):
+                time.sleep(max(0.0, min(0.01, pending[i].arrival - (time.perf_counter() - t0))))
+        torch.cuda.synchronize(self.dev)
         total = time.perf_counter() - t0
         lat = np.array([sc.finished - sc.arrival for sc in done if sc.rid >= warmup])
         flags = self.status.cpu().numpy()
