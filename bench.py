@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="only run a plain device copy of this many MB, 10 times")
     ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--valu", type=str, default=None,
+                    help="counter record (key = value) with the step kernel's SQ counters")
     ap.add_argument("--make-valu-record", nargs=2, metavar=("PMC_ROOT", "OUTDIR"), default=None,
                     help="write the VALU counter records from a rocprofv3 --pmc run and exit")
     ap.add_argument("--make-traffic-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
@@ -122,7 +124,7 @@ def make_traffic_record(root: str, out: str) -> None:
     under `root`: pmc_fetch/, pmc_write/ (bench.py) and calib_fetch/,
     calib_write/ (bench.py --calib-copy 1024).  Each counter is scaled by the
     ratio of the copy kernel's known bytes to what the counter read for it."""
-    kern = "k_split<false>"
+    kern = "k_split<false, false>"
     fetch, nf = _pmc_mean(os.path.join(root, "pmc_fetch"), "FETCH_SIZE", kern)
     write, nw = _pmc_mean(os.path.join(root, "pmc_write"), "WRITE_SIZE", kern)
     cf, _ = _pmc_mean(os.path.join(root, "calib_fetch"), "FETCH_SIZE", "copyBuffer")
@@ -131,7 +133,7 @@ def make_traffic_record(root: str, out: str) -> None:
     sf, sw = copy_kib / cf, copy_kib / cw
     total = (fetch * sf + write * sw) * 1024.0
     lines = [
-        "# FP64 split step k_split<false>, 4096^2 shelf: HBM traffic per launch",
+        "# FP64 split step k_split<false, false>, 4096^2 shelf: HBM traffic per launch",
         "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the copy calibration",
         f"kernel_source_hash = {kernel_source_hash()}",
         f"fetch_kib_per_launch = {fetch:.1f}",
@@ -159,10 +161,10 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VAL
                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
 
 
-VALU_KERNELS = (("k_split<false>", "k_split_f64_shelf4096_valu.txt", "FP64 split step"),
-                ("k_split<true>", "k_split_f32dev_shelf4096_valu.txt",
+VALU_KERNELS = (("k_split<false, false>", "k_split_f64_shelf4096_valu.txt", "FP64 split step"),
+                ("k_split<true, false>", "k_split_f32dev_shelf4096_valu.txt",
                  "FP32 surface-deviation split step"),
-                ("k_unsplit", "k_unsplit_f64_shelf4096_valu.txt", "FP64 unsplit step"))
+                ("k_unsplit<false>", "k_unsplit_f64_shelf4096_valu.txt", "FP64 unsplit step"))
 
 
 def make_valu_record(root: str, outdir: str) -> None:
@@ -185,13 +187,14 @@ def make_valu_record(root: str, outdir: str) -> None:
         print("\n".join(lines))
 
 
-def measured_valu(kernel_ms: float):
+def measured_valu(kernel_ms: float, path: str | None = None):
     """VALU figures of the FP64 step kernel from the counter record, if it was
     taken on the current kernel sources."""
-    if not os.path.exists(VALU_RECORD):
+    path = path or VALU_RECORD
+    if not os.path.exists(path):
         return None
     rec = {}
-    with open(VALU_RECORD) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
@@ -293,6 +296,14 @@ def time_patch(pb, params, steps: int, warmup: int):
                          s.b.data_ptr(), s.dt.data_ptr(), s.smax.data_ptr(),
                          s.status.data_ptr(), stream.cuda_stream)
         ev1[k].record(stream)
+        # CFL rule with the retake on the device (a gated launch that does
+        # nothing unless the step went above cfl_max)
+        L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
+                         s.status.data_ptr(), 0, 0, stream.cuda_stream,
+                         retake=s.retake.data_ptr())
+        L.swe_patch_retake(s.p, s.pt, s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(),
+                           s.b.data_ptr(), s.dt.data_ptr(), s.smax.data_ptr(),
+                           s.status.data_ptr(), s.retake.data_ptr(), stream.cuda_stream)
         L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
                          s.status.data_ptr(), 0, 0, stream.cuda_stream)
         s.cur ^= 1
@@ -364,6 +375,8 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     res = {"grid": [n, n], "steps": steps, "dx": pb.dx}
     s64 = PatchSolver(pb, L.params())
     s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    # the same with every edge shallower than 50 m solved in FP64
+    s32w = PatchSolver(pb, L.params(precision=L.F32_DEV, h_fp64=50.0))
     # conditioning check: FP64 started from the values the FP32 run starts
     # from (bed and surface deviation rounded to FP32), so only the initial
     # rounding differs from the FP64 run
@@ -377,7 +390,7 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     m64, m32 = s64.mass(), s32.mass()
     s64.initial_dt()
     dt_log = torch.zeros(steps, dtype=torch.float64, device=s64.dev)
-    hist, hist_c = [], []
+    hist, hist_c, hist_w = [], [], []
 
     def errors(a64, a32):
         h64, _, _ = a64.state()
@@ -396,11 +409,13 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     for k0 in range(0, steps, every):
         for k in range(k0, min(k0 + every, steps)):
             dt_log[k].copy_(s64.dt[0])
-            s64.enqueue_step()
+            s64.enqueue_step(retake=False)
             s32.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
             s32.smax.zero_()
             s64c.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
             s64c.smax.zero_()
+            s32w.enqueue_step(dt_log.data_ptr() + 8 * k, cfl=False)
+            s32w.smax.zero_()
         torch.cuda.synchronize()
         e = errors(s64, s32)
         e["step"] = min(k0 + every, steps)
@@ -408,11 +423,16 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
         c = errors(s64, s64c)
         c["step"] = e["step"]
         hist_c.append(c)
+        w = errors(s64, s32w)
+        w["step"] = e["step"]
+        hist_w.append(w)
     res["same_dt"] = dict(hist[-1])
     res["same_dt"]["history"] = hist
     res["fp64_from_fp32_rounded_start"] = dict(hist_c[-1])
     res["fp64_from_fp32_rounded_start"]["history"] = hist_c
-    del s64c
+    res["same_dt_h_fp64_50m"] = dict(hist_w[-1])
+    res["same_dt_h_fp64_50m"]["history"] = hist_w
+    del s64c, s32w
     res["mass_drift_fp64"] = (s64.mass() - m64) / m64
     res["same_dt"]["mass_drift_fp32"] = (s32.mass() - m32) / m32
     res["flags_fp64"] = s64.flags()
@@ -529,7 +549,7 @@ def main():
                    "boundary": "extrapolation", "cfl": 0.9, "limiter": "MC"},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "swe::k_split<false>",
+                     "traffic": traffic, "kernel": "swe::k_split<false, false>",
                      "kernel_ms_avg": r64["kernel_ms_avg"],
                      "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
                      "alg_bytes_per_launch": r64["alg_bytes"]},
@@ -537,7 +557,7 @@ def main():
         "status_flags": r64["flags"],
         "clamps": r64["clamps"],
     }
-    valu = measured_valu(r64["kernel_ms_avg"])
+    valu = measured_valu(r64["kernel_ms_avg"], args.valu)
     if valu:
         out["valu"] = valu
     st64 = r64["solver"].state()

@@ -46,9 +46,12 @@
  *  - Conditions found on the device are OR-ed into status[0] (a device
  *    uint32_t pair; status[1] counts depth clamps): SWE_STATUS_NEG_DEPTH (a
  *    negative depth was reset to 0), SWE_STATUS_NONFINITE (an updated value
- *    is NaN/Inf), SWE_STATUS_CFL_EXCEEDED (the Courant number of the step
- *    exceeded cfl_max; the caller retakes it with the reduced dt that
- *    swe_cfl_reduce wrote).  The caller reads status after synchronising.
+ *    is NaN/Inf), SWE_STATUS_CFL_EXCEEDED (the Courant number of a step
+ *    exceeded cfl_max and the step stands: the caller retakes it with the
+ *    reduced dt that swe_cfl_reduce wrote, or accepts it),
+ *    SWE_STATUS_RETAKEN (a step exceeded cfl_max and was marked for a retake
+ *    on the device, see swe_cfl_reduce).  The caller reads status after
+ *    synchronising.
  */
 #ifndef SWE_H
 #define SWE_H
@@ -67,6 +70,7 @@ extern "C" {
 #define SWE_STATUS_NEG_DEPTH 1u
 #define SWE_STATUS_NONFINITE 2u
 #define SWE_STATUS_CFL_EXCEEDED 4u
+#define SWE_STATUS_RETAKEN 8u
 
 enum swe_method { SWE_SPLIT = 0, SWE_UNSPLIT = 1 };
 enum swe_precision { SWE_F64 = 0, SWE_F32_DEV = 1 };
@@ -131,17 +135,37 @@ int swe_speed_scan(const swe_params *p, const swe_patch *patches, int32_t n, int
                    int32_t max_my, const void *q, const void *b, double *smax_patch,
                    void *stream);
 
-/* CFL rule (Sec. 2).  For each group g, with rate_k = max(smax_x / dx,
+/* CFL rule (Sec. 2: the step size follows the largest wave speed so that
+ * the Courant number stays at or below 1; a step above the limit is redone
+ * with a smaller step).  For each group g, with rate_k = max(smax_x / dx,
  * smax_y / dy) / tref over the patches k of g (patches: device array):
- *   nu = dt_group[g] * max_k rate_k; nu > cfl_max sets SWE_STATUS_CFL_EXCEEDED
- *   in status[0] and group_flags[g] (if not NULL);
- *   dt_group[g] = cfl_desired / max_k rate_k (unchanged if that rate is 0).
+ *   nu = dt_group[g] * max_k rate_k;
+ *   nu > cfl_max sets SWE_STATUS_CFL_EXCEEDED in status[0] and
+ *   group_flags[g] (if not NULL), or, when retake is not NULL,
+ *   SWE_STATUS_RETAKEN instead;
+ *   retake[g] (device uint32_t per group, may be NULL) = 1 if nu > cfl_max,
+ *   else 0: the flags swe_patch_retake and swe_batched_retake act on;
+ *   dt_group[g] = cfl_desired / max_k rate_k (unchanged if that rate is 0),
+ *   which is the next step size, or the retake's if nu > cfl_max.
  * smax_patch entries are reset to 0 for the next step.  If
  * initial != 0 the CFL test is skipped (first dt from swe_speed_scan).
  * p: host.  Groups are 0 .. ngroups - 1. */
 int swe_cfl_reduce(const swe_params *p, const swe_patch *patches, int32_t n, int32_t ngroups,
                    double *smax_patch, double *dt_group, uint32_t *status,
-                   uint32_t *group_flags, int32_t initial, void *stream);
+                   uint32_t *group_flags, uint32_t *retake, int32_t initial, void *stream);
+
+/* Retake on the device (Sec. 2, a step above the Courant limit is redone):
+ * the same step as swe_patch_step, enqueued unconditionally but carried out
+ * only if retake[patch->group] != 0 as written by the swe_cfl_reduce that
+ * followed the step; pass the q_in and q_out of the step being redone (q_in
+ * is unchanged by a step) and dt_group, which holds the reduced step size.
+ * A swe_cfl_reduce after it yields the next dt (with retake NULL it flags
+ * SWE_STATUS_CFL_EXCEEDED if the retaken step is still above cfl_max).
+ * Lets a device-resident loop or a captured graph follow the rule without
+ * a host round trip.  retake: device array, NULL is an error. */
+int swe_patch_retake(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
+                     const void *b, const double *dt, double *smax, uint32_t *status,
+                     const uint32_t *retake, void *stream);
 
 /* Water volume sum(h) dx dy over the interior of each patch, in FP64,
  * written to mass_patch[k] (deterministic order).  In SWE_F32_DEV, h is
@@ -206,6 +230,18 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
                      void *pool_work, const void *pool_b, const double *dt_group,
                      double *smax_patch, uint32_t *status, uint32_t *queue,
                      const swe_schedule *sched, void *stream);
+
+/* Retake on the device for the batched step: redoes, from pool_in to
+ * pool_out, the items of the patches whose group g has retake[g] != 0 (as
+ * written by swe_cfl_reduce after swe_batched_step); the items of every
+ * other patch are skipped, so their results stand.  Arguments as for
+ * swe_batched_step, with the same pools as the step being redone. */
+int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_item *items,
+                       int32_t nitems, const swe_task *tasks, const void *pool_in,
+                       void *pool_out, void *pool_work, const void *pool_b,
+                       const double *dt_group, double *smax_patch, uint32_t *status,
+                       uint32_t *queue, const swe_schedule *sched, const uint32_t *retake,
+                       void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);

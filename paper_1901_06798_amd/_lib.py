@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SWE_LIB_PATH", os.path.join(_HERE, "libswe.so"))
 
 SWE_OK, SWE_EINVAL, SWE_EHIP = 0, -1, -2
-STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED = 1, 2, 4
+STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED, STATUS_RETAKEN = 1, 2, 4, 8
 SPLIT, UNSPLIT = 0, 1
 F64, F32_DEV = 0, 1
 BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
@@ -96,17 +96,22 @@ def lib():
         L.swe_patch_step.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P, _P]
         L.swe_ghost_fill.argtypes = [pp, _P, i32, i32, i32, _P, _P, i32, _P]
         L.swe_speed_scan.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P]
-        L.swe_cfl_reduce.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, i32, _P]
+        L.swe_cfl_reduce.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, _P, i32, _P]
+        L.swe_patch_retake.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
+                                       _P, _P]
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32]
         L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ps,
                                        _P]
+        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                         ps, _P, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
-                     "swe_mass", "swe_batched_plan", "swe_batched_step"):
+                     "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
+                     "swe_batched_retake"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -142,9 +147,15 @@ def swe_speed_scan(p: swe_params, patches: int, n: int, max_mx: int, max_my: int
 
 def swe_cfl_reduce(p: swe_params, patches: int, n: int, ngroups: int, smax_patch: int,
                    dt_group: int, status: int, group_flags: int, initial: int,
-                   stream: int = 0) -> None:
+                   stream: int = 0, retake: int = 0) -> None:
     _check(lib().swe_cfl_reduce(ctypes.byref(p), patches, n, ngroups, smax_patch, dt_group,
-                                status, group_flags, initial, stream), "swe_cfl_reduce")
+                                status, group_flags, retake, initial, stream), "swe_cfl_reduce")
+
+
+def swe_patch_retake(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                     smax: int, status: int, retake: int, stream: int = 0) -> None:
+    _check(lib().swe_patch_retake(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
+                                  status, retake, stream), "swe_patch_retake")
 
 
 def swe_mass(p: swe_params, patches: int, n: int, q: int, b: int, mass_patch: int,
@@ -175,3 +186,13 @@ def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks
     _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
                                   pool_out, pool_work, pool_b, dt_group, smax_patch, status,
                                   queue, ctypes.byref(sched), stream), "swe_batched_step")
+
+
+def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
+                       pool_in: int, pool_out: int, pool_work: int, pool_b: int, dt_group: int,
+                       smax_patch: int, status: int, queue: int, sched: swe_schedule,
+                       retake: int, stream: int = 0) -> None:
+    _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
+                                    pool_out, pool_work, pool_b, dt_group, smax_patch, status,
+                                    queue, ctypes.byref(sched), retake, stream),
+           "swe_batched_retake")

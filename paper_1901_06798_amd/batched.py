@@ -68,6 +68,7 @@ class BatchedSolver:
         self.smax = torch.zeros(2 * max(n, 1), dtype=torch.float64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.group_flags = torch.zeros(self.ngroups, dtype=torch.int32, device=self.dev)
+        self.retake = torch.zeros(self.ngroups, dtype=torch.int32, device=self.dev)
         self.queue = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.max_mx = max(pb.mx for pb in self.problems)
         self.max_my = max(pb.my for pb in self.problems)
@@ -123,19 +124,32 @@ class BatchedSolver:
                          self.dt.data_ptr(), self.status.data_ptr(), self.group_flags.data_ptr(), 1,
                          self.stream)
 
-    def enqueue_step(self, cfl: bool = True, dt_ptr: int | None = None) -> None:
-        """One coarse step of every patch: pools[cur] -> pools[1 - cur]."""
-        L.swe_batched_step(self.p, self.table.data_ptr(), self.items.data_ptr(), self.nitems,
-                           self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
-                           self.pools[1 - self.cur].data_ptr(),
-                           self.work.data_ptr() if self.work is not None else 0,
-                           self.b.data_ptr(), dt_ptr if dt_ptr is not None else self.dt.data_ptr(),
+    def enqueue_step(self, cfl: bool = True, dt_ptr: int | None = None,
+                     retake: bool = True) -> None:
+        """One coarse step of every patch: pools[cur] -> pools[1 - cur].  With
+        cfl the CFL reduction writes each group's next dt; with retake as
+        well, the groups whose step went above cfl_max are redone once on the
+        device with their reduced dt."""
+        args = (self.table.data_ptr(), self.items.data_ptr(), self.nitems,
+                self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
+                self.pools[1 - self.cur].data_ptr(),
+                self.work.data_ptr() if self.work is not None else 0, self.b.data_ptr())
+        L.swe_batched_step(self.p, *args, dt_ptr if dt_ptr is not None else self.dt.data_ptr(),
                            self.smax.data_ptr(), self.status.data_ptr(), self.queue.data_ptr(),
                            self.sched, self.stream)
         if cfl:
+            rt = self.retake.data_ptr() if retake else 0
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), self.n, self.ngroups,
                              self.smax.data_ptr(), self.dt.data_ptr(), self.status.data_ptr(),
-                             self.group_flags.data_ptr(), 0, self.stream)
+                             self.group_flags.data_ptr(), 0, self.stream, retake=rt)
+            if retake:
+                L.swe_batched_retake(self.p, *args, self.dt.data_ptr(), self.smax.data_ptr(),
+                                     self.status.data_ptr(), self.queue.data_ptr(), self.sched,
+                                     rt, self.stream)
+                L.swe_cfl_reduce(self.p, self.table.data_ptr(), self.n, self.ngroups,
+                                 self.smax.data_ptr(), self.dt.data_ptr(),
+                                 self.status.data_ptr(), self.group_flags.data_ptr(), 0,
+                                 self.stream)
         self.cur ^= 1
 
     def run(self, nsteps: int, record_dt: bool = False):

@@ -40,6 +40,7 @@ struct BatchArgs {
     uint32_t* queue;  // [0] next item, [1] finished workgroups
     int nitems;
     DevParams P;
+    const uint32_t* retake;  // retake launch: only groups with retake[g] != 0; NULL: all
 };
 
 template <bool DEV, int SEG, bool FRIC>
@@ -61,6 +62,7 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
         if (item >= a.nitems) break;
         const swe_item it = a.items[item];
         const swe_patch pt = a.patches[it.patch];
+        if (a.retake && a.retake[pt.group] == 0) continue;  // the group's step stands
         const double dt_sub = a.dt_group[pt.group] / (double)pt.tref;
         double smx = 0.0, smy = 0.0;
         uint32_t clamps = 0, flags = 0;
@@ -266,11 +268,12 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
     return SWE_OK;
 }
 
-int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
-                     int32_t nitems, const swe_task* tasks, const void* pool_in, void* pool_out,
-                     void* pool_work, const void* pool_b, const double* dt_group,
-                     double* smax_patch, uint32_t* status, uint32_t* queue,
-                     const swe_schedule* sched, void* stream) {
+static int batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
+                        int32_t nitems, const swe_task* tasks, const void* pool_in,
+                        void* pool_out, void* pool_work, const void* pool_b,
+                        const double* dt_group, double* smax_patch, uint32_t* status,
+                        uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
+                        void* stream) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -304,6 +307,7 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
     a.P.sea_level = p->sea_level;
     a.P.h_fp64 = p->h_fp64;
     a.P.order = p->order;
+    a.retake = retake;
 
     const int threads = 64 * sched->waves_per_group;
     const bool dev = p->precision == SWE_F32_DEV;
@@ -337,6 +341,26 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
     if (e != hipSuccess)
         return bfail(SWE_EHIP, std::string("swe_batched_step: ") + hipGetErrorString(e));
     return SWE_OK;
+}
+
+int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
+                     int32_t nitems, const swe_task* tasks, const void* pool_in, void* pool_out,
+                     void* pool_work, const void* pool_b, const double* dt_group,
+                     double* smax_patch, uint32_t* status, uint32_t* queue,
+                     const swe_schedule* sched, void* stream) {
+    return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
+                        dt_group, smax_patch, status, queue, sched, nullptr, stream);
+}
+
+int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
+                       int32_t nitems, const swe_task* tasks, const void* pool_in,
+                       void* pool_out, void* pool_work, const void* pool_b,
+                       const double* dt_group, double* smax_patch, uint32_t* status,
+                       uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
+                       void* stream) {
+    if (!retake) return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags");
+    return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
+                        dt_group, smax_patch, status, queue, sched, retake, stream);
 }
 
 }  // extern "C"

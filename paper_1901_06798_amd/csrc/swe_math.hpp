@@ -228,34 +228,33 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
 
 // A-dQ (left-going) and A+dQ (right-going); a zero-speed wave is shared half
 // and half; at a wall the side facing the dry bank receives nothing.
+//
+// Branch-free: each wave enters each sum with a weight 1, 1/2 or 0 chosen
+// from its speed (and the wall kind).  For finite waves this is exactly the
+// sum of the waves on their sides: 1 * z and 0.5 * z are the values added
+// there, and 0 * z is a zero, which leaves a sum as it is (the sums start at
+// +0 and never become -0 by adding).
 template <typename T>
 __device__ __forceinline__ void fluctuations(const Waves<T>& w, T am[3], T ap[3]) {
+    const bool zap = w.kind == kEdgeWallR, zam = w.kind == kEdgeWallL;
+    T wm[3], wp[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const T s = w.s[p];
+        const T m = s < T(0) ? T(1) : (s > T(0) ? T(0) : T(0.5));
+        const T q = s > T(0) ? T(1) : (s < T(0) ? T(0) : T(0.5));
+        wm[p] = zam ? T(0) : m;
+        wp[p] = zap ? T(0) : q;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         am[k] = T(0);
         ap[k] = T(0);
-    }
-    // Branch-free: each sum takes the wave, half of it, or +0.  A sum that
-    // starts at +0 never becomes -0 by adding, so adding +0 leaves it as it
-    // is, and the sums equal those of adding each wave to its side only.
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const T s = w.s[p];
-        const bool neg = s < T(0), pos = s > T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T z = w.z[p][k];
-            const T half = T(0.5) * z;
-            am[k] += neg ? z : (pos ? T(0) : half);
-            ap[k] += pos ? z : (neg ? T(0) : half);
+        for (int p = 0; p < 3; ++p) {
+            am[k] += wm[p] * w.z[p][k];
+            ap[k] += wp[p] * w.z[p][k];
         }
-    }
-    // written as value selects so the arrays stay in registers
-    const bool zap = w.kind == kEdgeWallR, zam = w.kind == kEdgeWallL;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        ap[k] = zap ? T(0) : ap[k];
-        am[k] = zam ? T(0) : am[k];
     }
 }
 
@@ -280,9 +279,10 @@ __device__ __forceinline__ void correction(const Waves<T>& w, const T dl[3], con
                                            T F[3]) {
     F[0] = F[1] = F[2] = T(0);
     if (w.shallow) return;
-    // Branch-free over the waves: a wave of zero speed or zero size adds +0
-    // (its quotient is computed and discarded), which leaves the sums as they
-    // are (they start at +0 and never become -0 by adding).
+    // Branch-free over the waves: a wave of zero speed or zero size enters
+    // with coefficient 0 (its quotient is computed and discarded), so for
+    // finite waves it adds a zero, which leaves the sums as they are (they
+    // start at +0 and never become -0 by adding).
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const T s = w.s[p];
@@ -293,8 +293,9 @@ __device__ __forceinline__ void correction(const Waves<T>& w, const T dl[3], con
         const T sg = s > T(0) ? T(1) : T(-1);
         const T as = s > T(0) ? s : -s;
         const T coef = T(0.5) * sg * (T(1) - lam * as) * phi;
+        const T cu = use ? coef : T(0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) F[k] += use ? coef * w.z[p][k] : T(0);
+        for (int k = 0; k < 3; ++k) F[k] += cu * w.z[p][k];
     }
 }
 

@@ -18,10 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <string>
-#include <utility>
 
 #include "swe.h"
 #include "swe_common.hpp"
@@ -45,6 +42,7 @@ struct StepArgs {
     int pitch, mx, my, H, nstrips, nitems;
     int8_t bc[4];
     DevParams P;
+    const uint32_t* gate;  // retake launch: run only if *gate != 0; NULL: always
 };
 
 // One patch, one wave64 per (strip, chunk of H rows).
@@ -59,6 +57,7 @@ __global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(S
     const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
                                                     (threadIdx.x / kWave));
     if (item >= a.nitems) return;  // whole wave leaves together
+    if (a.gate && *a.gate == 0) return;  // no step to retake
     Task tk;
     tk.qin = a.qin;
     tk.qout = a.qout;
@@ -99,6 +98,7 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
                                                     (threadIdx.x / kWave));
     if (item >= a.nitems) return;
+    if (a.gate && *a.gate == 0) return;  // no step to retake
     Task tk;
     tk.qin = a.qin;
     tk.qout = a.qout;
@@ -246,8 +246,8 @@ __global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict_
 __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict__ patches, int n,
                                                     double* smax, double* dt_group,
                                                     uint32_t* status, uint32_t* group_flags,
-                                                    double cfl_desired, double cfl_max,
-                                                    int initial) {
+                                                    uint32_t* retake, double cfl_desired,
+                                                    double cfl_max, int initial) {
     const int g = blockIdx.x;
     __shared__ unsigned long long red[256 / kWave];
     double rate = 0.0;
@@ -273,7 +273,9 @@ __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict_
         const double dt = dt_group[g];
         uint32_t f = 0;
         if (isnan(r)) f |= SWE_STATUS_NONFINITE;
-        if (!initial && r > 0.0 && dt * r > cfl_max) f |= SWE_STATUS_CFL_EXCEEDED;
+        const bool over = !initial && r > 0.0 && dt * r > cfl_max;
+        if (over) f |= retake ? SWE_STATUS_RETAKEN : SWE_STATUS_CFL_EXCEEDED;
+        if (retake) retake[g] = over ? 1u : 0u;
         if (r > 0.0 && isfinite(r)) dt_group[g] = cfl_desired / r;
         if (f) {
             atomicOr(status, f);
@@ -381,40 +383,15 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-// Waves of a kernel that the device holds at once (occupancy x compute units),
-// cached per device and kernel.
-int resident_waves(const void* kernel, int kidx, int block) {
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find({dev, kidx});
-    if (it != cache.end()) return it->second;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        per_cu = cus = 0;
-    }
-    const int w = per_cu * cus * (block / swe::kWave);
-    cache[{dev, kidx}] = w;
-    return w;
-}
-
-// Rows per strip task.  A wave marches H rows plus 4 rows of pipeline fill,
-// so longer chunks waste less; the chunk count per strip is the largest that
-// keeps every task of the launch resident at once (one round of waves, no
-// tail), and H is at least 16.  SWE_ROWS_PER_WAVE overrides.
-int rows_per_chunk(int mx, int my, int resident) {
+// Rows per strip task.  A wave marches H rows plus 4 rows of pipeline fill.
+// Waves over water at rest skip their Riemann solves and finish early, so
+// short tasks (many more than the device holds at once) let the hardware
+// dispatcher balance the launch; 32 rows keeps the fill overhead at 1/8.
+// SWE_ROWS_PER_WAVE overrides.
+int rows_per_chunk(int my) {
     const char* e = std::getenv("SWE_ROWS_PER_WAVE");
-    int H = e ? std::atoi(e) : 0;
-    if (H < 1) {
-        const int nstrips = (mx + swe::kStripOut - 1) / swe::kStripOut;
-        const int chunks = resident > nstrips ? resident / nstrips : 1;
-        H = (my + chunks - 1) / chunks;
-        if (H < 16) H = 16;
-    }
+    int H = e ? std::atoi(e) : 32;
+    if (H < 1) H = 32;
     return H < my ? H : my;
 }
 
@@ -432,9 +409,9 @@ const char* swe_last_error(void) { return g_err.c_str(); }
 
 const char* swe_version(void) { return "swe-gfx950 0.1"; }
 
-int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
-                   const void* b, const double* dt, double* smax, uint32_t* status,
-                   void* stream) {
+static int patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
+                      const void* b, const double* dt, double* smax, uint32_t* status,
+                      const uint32_t* gate, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_patch(patch))) return rc;
@@ -463,31 +440,20 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
     a.pitch = patch->pitch;
     a.mx = patch->mx;
     a.my = patch->my;
+    // one wave per workgroup: the finest unit the dispatcher can balance
     const char* wpb = std::getenv("SWE_WAVES_PER_BLOCK");
-    int waves_per_block = wpb ? std::atoi(wpb) : 4;
+    int waves_per_block = wpb ? std::atoi(wpb) : 1;
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-        waves_per_block = 4;
+        waves_per_block = 1;
     const bool fric = p->manning_n > 0.0;
     const bool f64 = p->precision == SWE_F64;
-    const void* kern;
-    if (p->method == SWE_UNSPLIT)
-        kern = fric ? reinterpret_cast<const void*>(&swe::k_unsplit<true>)
-                    : reinterpret_cast<const void*>(&swe::k_unsplit<false>);
-    else if (f64)
-        kern = fric ? reinterpret_cast<const void*>(&swe::k_split<false, true>)
-                    : reinterpret_cast<const void*>(&swe::k_split<false, false>);
-    else
-        kern = fric ? reinterpret_cast<const void*>(&swe::k_split<true, true>)
-                    : reinterpret_cast<const void*>(&swe::k_split<true, false>);
-    const int kidx = (p->method == SWE_UNSPLIT ? 2 : f64 ? 0 : 1) + (fric ? 3 : 0);
-    a.H = rows_per_chunk(patch->mx, patch->my,
-                         resident_waves(kern, 8 * kidx + waves_per_block,
-                                        swe::kWave * waves_per_block));
+    a.H = rows_per_chunk(patch->my);
     a.nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
     const int nchunks = (patch->my + a.H - 1) / a.H;
     a.nitems = a.nstrips * nchunks;
     for (int s = 0; s < 4; ++s) a.bc[s] = patch->bc[s];
     a.P = dev_params(p);
+    a.gate = gate;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid(blocks), block(64 * waves_per_block);
@@ -503,6 +469,21 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
         else hipLaunchKernelGGL((swe::k_split<true, false>), grid, block, 0, st, a);
     }
     return check_launch("swe_patch_step");
+}
+
+int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
+                   const void* b, const double* dt, double* smax, uint32_t* status,
+                   void* stream) {
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, stream);
+}
+
+int swe_patch_retake(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
+                     const void* b, const double* dt, double* smax, uint32_t* status,
+                     const uint32_t* retake, void* stream) {
+    if (!retake) return fail(SWE_EINVAL, "swe_patch_retake: null retake flags");
+    if (patch && patch->group < 0) return fail(SWE_EINVAL, "swe_patch_retake: negative group");
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
+                      patch ? retake + patch->group : retake, stream);
 }
 
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
@@ -549,14 +530,14 @@ int swe_speed_scan(const swe_params* p, const swe_patch* patches, int32_t n, int
 
 int swe_cfl_reduce(const swe_params* p, const swe_patch* patches, int32_t n, int32_t ngroups,
                    double* smax_patch, double* dt_group, uint32_t* status,
-                   uint32_t* group_flags, int32_t initial, void* stream) {
+                   uint32_t* group_flags, uint32_t* retake, int32_t initial, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if (!patches || !smax_patch || !dt_group || !status || n < 0 || ngroups < 1)
         return fail(SWE_EINVAL, "swe_cfl_reduce: bad arguments");
     hipLaunchKernelGGL(swe::k_cfl_reduce, dim3(ngroups), dim3(256), 0,
                        static_cast<hipStream_t>(stream), patches, n, smax_patch, dt_group,
-                       status, group_flags, p->cfl_desired, p->cfl_max, initial);
+                       status, group_flags, retake, p->cfl_desired, p->cfl_max, initial);
     return check_launch("swe_cfl_reduce");
 }
 

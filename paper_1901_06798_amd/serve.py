@@ -127,6 +127,7 @@ class ScenarioServer:
         self.smax = torch.zeros(2 * max_slots, dtype=torch.float64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.group_flags = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
+        self.retake = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
         self.queue_ctr = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.cur = 0
         self.active: list[Scenario] = []
@@ -256,11 +257,18 @@ class ScenarioServer:
         n = len(self.active)
         smax = torch.zeros(2 * n, dtype=torch.float64, device=self.dev)
         for _ in range(steps):
-            L.swe_batched_step(self.p, self.table.data_ptr(), self.items.data_ptr(), self.nitems,
-                               self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
-                               self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
-                               self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
-                               self.queue_ctr.data_ptr(), self.sched, self.stream)
+            args = (self.table.data_ptr(), self.items.data_ptr(), self.nitems,
+                    self.tasks.data_ptr(), self.pools[self.cur].data_ptr(),
+                    self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
+                    self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
+                    self.queue_ctr.data_ptr(), self.sched)
+            L.swe_batched_step(self.p, *args, self.stream)
+            # CFL rule per scenario; a step above cfl_max is redone once on the device
+            L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
+                             self.dt.data_ptr(), self.status.data_ptr(),
+                             self.group_flags.data_ptr(), 0, self.stream,
+                             retake=self.retake.data_ptr())
+            L.swe_batched_retake(self.p, *args, self.retake.data_ptr(), self.stream)
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
                              self.dt.data_ptr(), self.status.data_ptr(),
                              self.group_flags.data_ptr(), 0, self.stream)

@@ -55,6 +55,7 @@ class PatchSolver:
         self.dt = torch.zeros(1, dtype=f64, device=self.dev)
         self.smax = torch.zeros(2, dtype=f64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        self.retake = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.upload(pb)
 
     # -- layout helpers ------------------------------------------------------
@@ -98,15 +99,27 @@ class PatchSolver:
         L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
                          self.dt.data_ptr(), self.status.data_ptr(), 0, 1, self.stream)
 
-    def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True) -> None:
-        """One step q[cur] -> q[1 - cur]; dt from dt_ptr (device) or self.dt."""
-        L.swe_patch_step(self.p, self.pt, self.q[self.cur].data_ptr(),
-                         self.q[1 - self.cur].data_ptr(), self.b.data_ptr(),
-                         dt_ptr if dt_ptr is not None else self.dt.data_ptr(),
-                         self.smax.data_ptr(), self.status.data_ptr(), self.stream)
+    def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True,
+                     retake: bool = True) -> None:
+        """One step q[cur] -> q[1 - cur]; dt from dt_ptr (device) or self.dt.
+        With cfl, the CFL reduction writes the next dt; with retake as well, a
+        step above cfl_max is redone once on the device with the reduced dt
+        (a retaken step still above the limit is flagged CFL_EXCEEDED)."""
+        qi, qo = self.q[self.cur].data_ptr(), self.q[1 - self.cur].data_ptr()
+        dt = dt_ptr if dt_ptr is not None else self.dt.data_ptr()
+        L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt, self.smax.data_ptr(),
+                         self.status.data_ptr(), self.stream)
         if cfl:
+            rt = self.retake.data_ptr() if retake else 0
             L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
-                             self.dt.data_ptr(), self.status.data_ptr(), 0, 0, self.stream)
+                             self.dt.data_ptr(), self.status.data_ptr(), 0, 0, self.stream,
+                             retake=rt)
+            if retake:
+                L.swe_patch_retake(self.p, self.pt, qi, qo, self.b.data_ptr(),
+                                   self.dt.data_ptr(), self.smax.data_ptr(),
+                                   self.status.data_ptr(), rt, self.stream)
+                L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
+                                 self.dt.data_ptr(), self.status.data_ptr(), 0, 0, self.stream)
         self.cur ^= 1
 
     def run(self, nsteps: int, dt0: float | None = None, record_dt: bool = True):
@@ -122,7 +135,7 @@ class PatchSolver:
         s = 0
         while s < nsteps:
             dt_now = self.dt.clone() if record_dt else None
-            self.enqueue_step()
+            self.enqueue_step(retake=False)
             st = self.status.cpu()
             if int(st[0]) & L.STATUS_CFL_EXCEEDED:
                 # discard: the output buffer is dropped and the step retaken with

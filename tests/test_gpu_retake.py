@@ -1,0 +1,99 @@
+"""GPU tests of the CFL rule's retake on the device: a step whose Courant
+number exceeds cfl_max is redone, with the reduced step size, by a gated
+launch that follows the CFL reduction (no host round trip).  The result is
+the reference solver's, which redoes the step on the host, and the host
+retake loop's, bit for bit; in a batch only the offending group is redone."""
+import numpy as np
+import pytest
+
+from helpers import interior, oracle_setup
+from paper_1901_06798_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd.batched import BatchedSolver
+    from paper_1901_06798_amd.solver import PatchSolver
+    L.lib()
+    return L, PatchSolver, BatchedSolver, torch
+
+
+def too_large_dt(PatchSolver, pb, p, factor):
+    s = PatchSolver(pb, p)
+    s.initial_dt()
+    return float(s.dt.item()) * factor
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_device_retake_equals_host_retake(gpu, orc, precision):
+    L, PatchSolver, _, torch = gpu
+    pb = W.gaussian_hump(96, 1000.0, sigma=8e3)
+    p = L.params(precision=precision)
+    big = too_large_dt(PatchSolver, pb, p, 2.2)
+    print(f"case retake hump 96x96 precision={precision} dt0={big}", flush=True)
+    host = PatchSolver(pb, p)
+    host.run(12, dt0=big)
+    dev = PatchSolver(pb, p)
+    dev.dt.fill_(big)
+    dev.run_async(12)
+    torch.cuda.synchronize()
+    assert host.retakes >= 1
+    st = int(dev.status[0].item())
+    assert st & L.STATUS_RETAKEN
+    assert not st & L.STATUS_CFL_EXCEEDED
+    for a, c in zip(host.state(), dev.state()):
+        assert np.array_equal(a, c)
+    assert float(host.dt.item()) == float(dev.dt.item())
+    if precision == 0:
+        # and the reference solver, which retakes on the host, agrees exactly
+        g, q, b = oracle_setup(orc, pb)
+        r = orc.run(orc.params(), g, q, b, 12, dt0=big)
+        assert r["retakes"] >= 1
+        ref = interior(q)
+        for k, a in enumerate(dev.state()):
+            assert np.array_equal(a, ref[..., k])
+
+
+def test_batched_retake_redoes_only_the_offending_group(gpu):
+    L, PatchSolver, BatchedSolver, torch = gpu
+    probs = [W.gaussian_hump(64 + 16 * k, 1000.0, sigma=6e3) for k in range(4)]
+    p = L.params()
+    factors = [1.0, 2.2, 1.0, 1.6]
+    print("case batched retake, 4 patches, groups 1 and 3 start above the limit", flush=True)
+    bs = BatchedSolver(probs, p, groups=list(range(len(probs))))
+    bs.initial_dt()
+    bs.dt.mul_(torch.tensor(factors, dtype=torch.float64, device=bs.dev))
+    bs.run(10)
+    torch.cuda.synchronize()
+    st = int(bs.status[0].item())
+    assert st & L.STATUS_RETAKEN
+    assert not st & L.STATUS_CFL_EXCEEDED
+    for k, pb in enumerate(probs):
+        s = PatchSolver(pb, p)
+        s.initial_dt()
+        d0 = float(s.dt.item()) * factors[k]
+        s.run(10, dt0=d0)
+        torch.cuda.synchronize()
+        assert (s.retakes >= 1) == (factors[k] > 1.5), f"patch {k}"
+        for a, c in zip(bs.state(k), s.state()):
+            assert np.array_equal(a, c), f"patch {k}"
+
+
+def test_retake_flags_are_cleared_each_step(gpu):
+    L, PatchSolver, _, torch = gpu
+    pb = W.gaussian_hump(64, 1000.0, sigma=6e3)
+    p = L.params()
+    s = PatchSolver(pb, p)
+    s.dt.fill_(too_large_dt(PatchSolver, pb, p, 2.2))
+    s.run_async(1)
+    torch.cuda.synchronize()
+    assert int(s.retake.item()) == 1  # the first step was redone
+    s.run_async(1)
+    torch.cuda.synchronize()
+    assert int(s.retake.item()) == 0  # the next one stood
