@@ -234,14 +234,15 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
 /* Retake on the device for the batched step: redoes, from pool_in to
  * pool_out, the items of the patches whose group g has retake[g] != 0 (as
  * written by swe_cfl_reduce after swe_batched_step); the items of every
- * other patch are skipped, so their results stand.  Arguments as for
- * swe_batched_step, with the same pools as the step being redone. */
+ * other patch are skipped, so their results stand, and with no flagged group
+ * the launch ends at once.  Arguments as for swe_batched_step, with the same
+ * pools as the step being redone; retake: device uint32_t[ngroups]. */
 int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_item *items,
                        int32_t nitems, const swe_task *tasks, const void *pool_in,
                        void *pool_out, void *pool_work, const void *pool_b,
                        const double *dt_group, double *smax_patch, uint32_t *status,
                        uint32_t *queue, const swe_schedule *sched, const uint32_t *retake,
-                       void *stream);
+                       int32_t ngroups, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);

@@ -106,7 +106,7 @@ def lib():
         L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ps,
                                        _P]
         L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                                         ps, _P, _P]
+                                         ps, _P, i32, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
@@ -191,8 +191,8 @@ def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
                        pool_in: int, pool_out: int, pool_work: int, pool_b: int, dt_group: int,
                        smax_patch: int, status: int, queue: int, sched: swe_schedule,
-                       retake: int, stream: int = 0) -> None:
+                       retake: int, ngroups: int, stream: int = 0) -> None:
     _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
                                     pool_out, pool_work, pool_b, dt_group, smax_patch, status,
-                                    queue, ctypes.byref(sched), retake, stream),
+                                    queue, ctypes.byref(sched), retake, ngroups, stream),
            "swe_batched_retake")

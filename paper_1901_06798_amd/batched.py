@@ -145,7 +145,7 @@ class BatchedSolver:
             if retake:
                 L.swe_batched_retake(self.p, *args, self.dt.data_ptr(), self.smax.data_ptr(),
                                      self.status.data_ptr(), self.queue.data_ptr(), self.sched,
-                                     rt, self.stream)
+                                     rt, self.ngroups, self.stream)
                 L.swe_cfl_reduce(self.p, self.table.data_ptr(), self.n, self.ngroups,
                                  self.smax.data_ptr(), self.dt.data_ptr(),
                                  self.status.data_ptr(), self.group_flags.data_ptr(), 0,

@@ -41,10 +41,14 @@ struct BatchArgs {
     int nitems;
     DevParams P;
     const uint32_t* retake;  // retake launch: only groups with retake[g] != 0; NULL: all
+    int ngroups;             // entries of retake
 };
 
+// The FP32 march fits three waves per SIMD (at most 168 VGPRs) without
+// spilling, which 256-thread workgroups can use; the FP64 one, and the
+// variants with friction, two.
 template <bool DEV, int SEG, bool FRIC>
-__global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
+__global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchArgs a) {
     constexpr int kSegPerWave = kWave / SEG;
     __shared__ int s_item;
     const int wave = threadIdx.x / kWave;
@@ -53,6 +57,13 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a) {
     const int lane_in_seg = lane % SEG;
     const int nseg = (blockDim.x / kWave) * kSegPerWave;
     const int seg_id = wave * kSegPerWave + seg_in_wave;
+    if (a.retake) {
+        // a retake launch with no flagged group ends at once; every workgroup
+        // reads the same flags, so all of them leave and the queue stays at 0
+        uint32_t any = 0;
+        for (int g = 0; g < a.ngroups; ++g) any |= a.retake[g];
+        if (!any) return;
+    }
 
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.queue[0], 1u);
@@ -273,7 +284,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
                         void* pool_out, void* pool_work, const void* pool_b,
                         const double* dt_group, double* smax_patch, uint32_t* status,
                         uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
-                        void* stream) {
+                        int32_t ngroups, void* stream) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -308,6 +319,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.P.h_fp64 = p->h_fp64;
     a.P.order = p->order;
     a.retake = retake;
+    a.ngroups = ngroups;
 
     const int threads = 64 * sched->waves_per_group;
     const bool dev = p->precision == SWE_F32_DEV;
@@ -349,7 +361,7 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
                      double* smax_patch, uint32_t* status, uint32_t* queue,
                      const swe_schedule* sched, void* stream) {
     return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
-                        dt_group, smax_patch, status, queue, sched, nullptr, stream);
+                        dt_group, smax_patch, status, queue, sched, nullptr, 0, stream);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
@@ -357,10 +369,11 @@ int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_
                        void* pool_out, void* pool_work, const void* pool_b,
                        const double* dt_group, double* smax_patch, uint32_t* status,
                        uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
-                       void* stream) {
-    if (!retake) return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags");
+                       int32_t ngroups, void* stream) {
+    if (!retake || ngroups < 1)
+        return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags or ngroups < 1");
     return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
-                        dt_group, smax_patch, status, queue, sched, retake, stream);
+                        dt_group, smax_patch, status, queue, sched, retake, ngroups, stream);
 }
 
 }  // extern "C"

@@ -55,22 +55,26 @@ __device__ __forceinline__ Src map_cell(int R, int c, int mx, int my, int pitch,
 }
 
 // Lane moves within a segment of SEG lanes (SEG = 64: the whole wave):
-// up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1;
-// the first/last lane of a segment keeps its own value.
+// up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1.
+// What the first lane of a segment receives from up(), and the last from
+// down(), is unspecified: those are halo lanes, whose edges and cells feed
+// no result (callers also leave them out of wave-wide votes).
 #ifndef SWE_LANE_DPP
 #define SWE_LANE_DPP 1
 #endif
 #if SWE_LANE_DPP
-// Whole-wave DPP shifts (wave_shr:1 / wave_shl:1): one VALU move per dword.
-// They cross segment boundaries, which only feeds the halo lanes of a
-// segment, whose results are never used.
-constexpr int kDppWaveShr1 = 0x138;
-constexpr int kDppWaveShl1 = 0x130;
+// Whole-wave DPP rotations (wave_ror:1 / wave_rol:1), one VALU move per
+// dword.  Lane 0 receives lane 63's value and lane 63 lane 0's: real cells of
+// the strip, so a halo lane's edge takes the same code path as its
+// neighbours' (no divergence at the strip ends).  The rotations cross segment
+// boundaries, which only feeds the halo lanes of a segment.
+constexpr int kDppWaveRor1 = 0x13C;
+constexpr int kDppWaveRol1 = 0x134;
 __device__ __forceinline__ int dpp_up(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, kDppWaveShr1, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, kDppWaveRor1, 0xf, 0xf, false);
 }
 __device__ __forceinline__ int dpp_down(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, kDppWaveShl1, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, kDppWaveRol1, 0xf, 0xf, false);
 }
 template <int SEG = kWave>
 __device__ __forceinline__ double lane_up(double x) {

@@ -106,7 +106,9 @@ __device__ __forceinline__ void cleanup(S q[3], S b, const DevParams& P, bool va
 //   max(c_L, c_R): with u = 0 the speed bounds are -max(c_L, c_hat) and
 //   max(c_R, c_hat), and c_hat = sqrt(g (h_L + h_R) / 2) never exceeds
 //   max(c_L, c_R), also after rounding.
-// When every lane of the wave has such an edge the solve is skipped.  With
+// When every lane of the wave whose edge feeds a result has such an edge the
+// solve is skipped (the halo lanes then carry waves that are not their
+// solver's, which reach no result).  With
 // zero f-waves the fluctuations and corrections are 0 whatever the speeds, so
 // the step's results, including the speed maximum, are the solver's.
 template <bool DEV, typename S>
@@ -245,7 +247,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         const Side<S> lf = side_up<S, DEV, SEG>(me, P);
         const S lf_m = DEV ? lane_up<SEG>(hu) : S(0), lf_t = DEV ? lane_up<SEG>(hv) : S(0);
         Waves<S> w;
-        if (SWE_QUIET && __all(quiet_edge<DEV, S>(lf, me)))
+        // lane 0's edge (its left cell lies outside the segment) feeds nothing
+        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, S>(lf, me)))
             quiet_waves(lf, me, P, w);
         else
             solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
@@ -285,7 +288,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         const Side<S> cur = side_from<DEV, S, S>(qs[0], qs[2], qs[1], bb, P);
         if (t >= 1) {
             Waves<S> wy;
-            if (SWE_QUIET && __all(quiet_edge<DEV, S>(prev, cur)))
+            // the y-sweep of a lane feeds only its own column's update
+            if (SWE_QUIET && __all(!upd_col || quiet_edge<DEV, S>(prev, cur)))
                 quiet_waves(prev, cur, P, wy);
             else
                 // Q* is cleaned up, so a dry side's stored momenta are 0 and

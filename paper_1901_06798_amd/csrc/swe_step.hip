@@ -440,9 +440,11 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.pitch = patch->pitch;
     a.mx = patch->mx;
     a.my = patch->my;
-    // one wave per workgroup: the finest unit the dispatcher can balance
+    // one wave per workgroup: the finest unit the dispatcher can balance; a
+    // gated retake launch, which mostly ends at once, takes four (fewer
+    // workgroups to dispatch; results do not depend on the tiling)
     const char* wpb = std::getenv("SWE_WAVES_PER_BLOCK");
-    int waves_per_block = wpb ? std::atoi(wpb) : 1;
+    int waves_per_block = gate ? 4 : wpb ? std::atoi(wpb) : 1;
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
         waves_per_block = 1;
     const bool fric = p->manning_n > 0.0;

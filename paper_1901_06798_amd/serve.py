@@ -268,7 +268,8 @@ class ScenarioServer:
                              self.dt.data_ptr(), self.status.data_ptr(),
                              self.group_flags.data_ptr(), 0, self.stream,
                              retake=self.retake.data_ptr())
-            L.swe_batched_retake(self.p, *args, self.retake.data_ptr(), self.stream)
+            L.swe_batched_retake(self.p, *args, self.retake.data_ptr(), self.max_slots,
+                                 self.stream)
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
                              self.dt.data_ptr(), self.status.data_ptr(),
                              self.group_flags.data_ptr(), 0, self.stream)
