@@ -105,14 +105,19 @@ def measured_traffic(path: str | None):
         return None
 
 
-def _pmc_mean(run_dir: str, counter: str, kernel_sub: str):
+def _pmc_mean(run_dir: str, counter: str, kernel_sub: str, workgroup: int | None = None):
+    """Mean of a counter over the dispatches of a kernel; `workgroup` keeps
+    only dispatches of that workgroup size (the step kernels' retake launches,
+    which end at once unless a step is redone, use 256-thread workgroups, the
+    steps themselves 64)."""
     import csv
     import glob
     vals = []
     for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] == counter and kernel_sub in r["Kernel_Name"]:
+                if r["Counter_Name"] == counter and kernel_sub in r["Kernel_Name"] and (
+                        workgroup is None or int(r["Workgroup_Size"]) == workgroup):
                     vals.append(float(r["Counter_Value"]))
     if not vals:
         raise SystemExit(f"no {counter} samples for {kernel_sub} under {run_dir}")
@@ -125,8 +130,8 @@ def make_traffic_record(root: str, out: str) -> None:
     calib_write/ (bench.py --calib-copy 1024).  Each counter is scaled by the
     ratio of the copy kernel's known bytes to what the counter read for it."""
     kern = "k_split<false, false>"
-    fetch, nf = _pmc_mean(os.path.join(root, "pmc_fetch"), "FETCH_SIZE", kern)
-    write, nw = _pmc_mean(os.path.join(root, "pmc_write"), "WRITE_SIZE", kern)
+    fetch, nf = _pmc_mean(os.path.join(root, "pmc_fetch"), "FETCH_SIZE", kern, STEP_WG)
+    write, nw = _pmc_mean(os.path.join(root, "pmc_write"), "WRITE_SIZE", kern, STEP_WG)
     cf, _ = _pmc_mean(os.path.join(root, "calib_fetch"), "FETCH_SIZE", "copyBuffer")
     cw, _ = _pmc_mean(os.path.join(root, "calib_write"), "WRITE_SIZE", "copyBuffer")
     copy_kib = CALIB_BYTES / 1024.0
@@ -153,6 +158,7 @@ def make_traffic_record(root: str, out: str) -> None:
 
 
 CALIB_BYTES = 1024000000
+STEP_WG = 64  # threads per workgroup of a step launch (its retake launch uses 256)
 
 VALU_RECORD = os.path.join(ROOT, "profiles", "k_split_f64_shelf4096_valu.txt")
 # one VALU lane-operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -176,7 +182,7 @@ def make_valu_record(root: str, outdir: str) -> None:
                  f"kernel_source_hash = {kernel_source_hash()}"]
         try:
             for c in SQ_COUNTERS:
-                v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern)
+                v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern, STEP_WG)
                 lines.append(f"{c} = {v:.0f}")
         except SystemExit as e:
             print(f"skipping {kern}: {e}")
