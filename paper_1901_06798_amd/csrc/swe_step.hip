@@ -197,10 +197,11 @@ __global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict_
     const int pk = blockIdx.y;
     const PatchView v = view(patches[pk]);
     double sx = 0.0, sy = 0.0;
-    const int ncell = v.mx * v.my;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ncell; k += gridDim.x * blockDim.x) {
-        const int c = 2 + k % v.mx;
-        const int R = 2 + k / v.mx;
+    const int64_t ncell = (int64_t)v.mx * v.my;
+    for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int c = 2 + (int)(k % v.mx);
+        const int R = 2 + (int)(k / v.mx);
         struct Cell {
             Side<S> s;
             S m, t;
