@@ -175,22 +175,25 @@ int swe_mass(const swe_params *p, const swe_patch *patches, int32_t n, const voi
 
 /* ------------------------------------------------------------------------
  * Batched step: many patches (e.g. the patches of an AMR hierarchy, or the
- * grids of several scenarios) in one persistent launch (Sec. 3: patches of
- * several levels, each level refining dx and dt by an integer ratio; Sec. 4:
- * memory pool and many small patches, whose launch overhead the paper could
- * not hide).
+ * grids of several scenarios) in one call of at most two launches (Sec. 3:
+ * patches of several levels, each level refining dx and dt by an integer
+ * ratio; Sec. 4: memory pool and many small patches, whose launch overhead
+ * the paper could not hide).
  *
  * A plan splits every patch into strip tasks (a strip of seg - 4 columns and
- * a run of rows, marched by a segment of seg lanes) and groups the tasks into
- * items; one workgroup takes one item at a time from a queue ordered longest
- * first.  A patch with tref > 1 forms a single item, whose workgroup runs its
- * tref substeps back to back with a barrier in between.
+ * a run of rows, marched by a segment of seg lanes).  A patch with tref > 1
+ * forms an item: persistent workgroups take items from a queue ordered
+ * longest first, and an item's workgroup runs its tref substeps back to back
+ * with a barrier in between.  The tasks of patches with tref == 1 ("plain"
+ * tasks, the last nplain of the plan's tasks) run one wave each in a second
+ * launch.
  */
 typedef struct swe_schedule {
     int32_t seg;             /* lanes per strip: 64 or 32 */
-    int32_t rows_per_task;   /* rows per task; 0 = choose from the patch size */
+    int32_t rows_per_task;   /* rows per task; 0 = 32 for tref == 1, else enough
+                                tasks for the workgroup (at least 8 rows) */
     int32_t waves_per_group; /* waves per workgroup: 1, 2, 4 or 8 */
-    int32_t tasks_per_item;  /* tref == 1 patches: tasks per item; 0 = auto */
+    int32_t tasks_per_item;  /* reserved (ignored): plain tasks run one wave each */
     int32_t order;           /* 0 = longest item first, 1 = patch order */
     int32_t groups_per_cu;   /* persistent workgroups per compute unit; 0 = occupancy */
 } swe_schedule;
@@ -209,27 +212,31 @@ typedef struct swe_item {
 } swe_item;
 
 /* Build a plan on the host.  patches: host array of n patches.  With items
- * and tasks NULL only the counts are returned in *nitems, *ntasks; otherwise
- * the arrays (host, sized from a previous query) are filled.  Fails with
- * SWE_EINVAL if a patch that needs several items has tref > 1, or a
- * SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
+ * and tasks NULL only the counts are returned in *nitems, *ntasks (all
+ * tasks) and *nplain (the plain ones among them); otherwise the arrays
+ * (host, sized from a previous query) are filled: the items' tasks first,
+ * then the nplain plain tasks.  Fails with SWE_EINVAL for a bad patch or if
+ * a SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
  * substeps). */
 int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sched,
-                     swe_item *items, int32_t *nitems, swe_task *tasks, int32_t *ntasks);
+                     swe_item *items, int32_t *nitems, swe_task *tasks, int32_t *ntasks,
+                     int32_t *nplain);
 
 /* Advance every patch of the plan: patch k takes tref_k substeps of
  * dt_group[group_k] / tref_k from pool_in to pool_out (pool_in is not
  * modified; pool_work, same size as the pools, holds intermediate substeps of
  * patches with tref > 1; NULL is allowed when every tref is 1).  The largest
  * speeds of all substeps are max-combined into smax_patch[2 k], [2 k + 1].
- * patches, items, tasks: device copies of the table and of the plan.
+ * patches, items, tasks: device copies of the table and of the plan; plain:
+ * device pointer to the plan's nplain plain tasks (tasks + ntasks - nplain).
  * queue: device uint32_t[2], zero before the first call; the launch leaves it
  * zero again.  sched: host, the schedule the plan was built with. */
 int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_item *items,
-                     int32_t nitems, const swe_task *tasks, const void *pool_in, void *pool_out,
-                     void *pool_work, const void *pool_b, const double *dt_group,
-                     double *smax_patch, uint32_t *status, uint32_t *queue,
-                     const swe_schedule *sched, void *stream);
+                     int32_t nitems, const swe_task *tasks, const swe_task *plain,
+                     int32_t nplain, const void *pool_in, void *pool_out, void *pool_work,
+                     const void *pool_b, const double *dt_group, double *smax_patch,
+                     uint32_t *status, uint32_t *queue, const swe_schedule *sched,
+                     void *stream);
 
 /* Retake on the device for the batched step: redoes, from pool_in to
  * pool_out, the items of the patches whose group g has retake[g] != 0 (as
@@ -238,11 +245,11 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
  * the launch ends at once.  Arguments as for swe_batched_step, with the same
  * pools as the step being redone; retake: device uint32_t[ngroups]. */
 int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_item *items,
-                       int32_t nitems, const swe_task *tasks, const void *pool_in,
-                       void *pool_out, void *pool_work, const void *pool_b,
-                       const double *dt_group, double *smax_patch, uint32_t *status,
-                       uint32_t *queue, const swe_schedule *sched, const uint32_t *retake,
-                       int32_t ngroups, void *stream);
+                       int32_t nitems, const swe_task *tasks, const swe_task *plain,
+                       int32_t nplain, const void *pool_in, void *pool_out, void *pool_work,
+                       const void *pool_b, const double *dt_group, double *smax_patch,
+                       uint32_t *status, uint32_t *queue, const swe_schedule *sched,
+                       const uint32_t *retake, int32_t ngroups, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);

@@ -102,11 +102,11 @@ def lib():
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
-        L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32]
-        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ps,
-                                       _P]
-        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                                         ps, _P, i32, _P]
+        L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32]
+        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P,
+                                       _P, ps, _P]
+        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P,
+                                         _P, _P, ps, _P, i32, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
@@ -164,35 +164,43 @@ def swe_mass(p: swe_params, patches: int, n: int, q: int, b: int, mass_patch: in
 
 
 def swe_batched_plan(patches, sched: swe_schedule):
-    """Plan for a host list of swe_patch; returns (items, tasks) ctypes arrays."""
+    """Plan for a host list of swe_patch; returns (items, nitems, tasks, ntasks,
+    nplain): ctypes arrays and counts; the last nplain tasks are the plain
+    (single-substep) ones."""
     n = len(patches)
     arr = (swe_patch * n)(*patches)
     ni = ctypes.c_int32(0)
     nt = ctypes.c_int32(0)
+    npl = ctypes.c_int32(0)
     _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched), None,
-                                  ctypes.byref(ni), None, ctypes.byref(nt)), "swe_batched_plan")
+                                  ctypes.byref(ni), None, ctypes.byref(nt), ctypes.byref(npl)),
+           "swe_batched_plan")
     items = (swe_item * max(ni.value, 1))()
     tasks = (swe_task * max(nt.value, 1))()
     _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched),
                                   ctypes.addressof(items), ctypes.byref(ni),
-                                  ctypes.addressof(tasks), ctypes.byref(nt)), "swe_batched_plan")
-    return items, ni.value, tasks, nt.value
+                                  ctypes.addressof(tasks), ctypes.byref(nt), ctypes.byref(npl)),
+           "swe_batched_plan")
+    return items, ni.value, tasks, nt.value, npl.value
+
+
+SWE_TASK_BYTES = ctypes.sizeof(swe_task)
 
 
 def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
-                     pool_in: int, pool_out: int, pool_work: int, pool_b: int, dt_group: int,
-                     smax_patch: int, status: int, queue: int, sched: swe_schedule,
-                     stream: int = 0) -> None:
-    _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
-                                  pool_out, pool_work, pool_b, dt_group, smax_patch, status,
-                                  queue, ctypes.byref(sched), stream), "swe_batched_step")
+                     plain: int, nplain: int, pool_in: int, pool_out: int, pool_work: int,
+                     pool_b: int, dt_group: int, smax_patch: int, status: int, queue: int,
+                     sched: swe_schedule, stream: int = 0) -> None:
+    _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, plain, nplain,
+                                  pool_in, pool_out, pool_work, pool_b, dt_group, smax_patch,
+                                  status, queue, ctypes.byref(sched), stream), "swe_batched_step")
 
 
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
-                       pool_in: int, pool_out: int, pool_work: int, pool_b: int, dt_group: int,
-                       smax_patch: int, status: int, queue: int, sched: swe_schedule,
-                       retake: int, ngroups: int, stream: int = 0) -> None:
-    _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, pool_in,
-                                    pool_out, pool_work, pool_b, dt_group, smax_patch, status,
-                                    queue, ctypes.byref(sched), retake, ngroups, stream),
-           "swe_batched_retake")
+                       plain: int, nplain: int, pool_in: int, pool_out: int, pool_work: int,
+                       pool_b: int, dt_group: int, smax_patch: int, status: int, queue: int,
+                       sched: swe_schedule, retake: int, ngroups: int, stream: int = 0) -> None:
+    _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, plain,
+                                    nplain, pool_in, pool_out, pool_work, pool_b, dt_group,
+                                    smax_patch, status, queue, ctypes.byref(sched), retake,
+                                    ngroups, stream), "swe_batched_retake")

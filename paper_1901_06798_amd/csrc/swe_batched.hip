@@ -2,12 +2,14 @@
 //
 // Patches of an AMR hierarchy (Qin, LeVeque & Motley, Sec. 3: levels refined
 // in space and time by integer ratios) or the grids of several scenarios are
-// advanced together.  A host-side plan cuts every patch into strip tasks and
-// groups them into items; a fixed grid of workgroups pulls items from a
-// device queue ordered longest first.  A patch with tref substeps forms one
-// item: its workgroup runs the substeps back to back, with a workgroup
-// barrier between them (the patch's writes of one substep are the next
-// substep's reads, and all of them stay on one compute unit).  Ghost cells of
+// advanced together.  A host-side plan cuts every patch into strip tasks.
+// A patch with tref > 1 substeps forms one item: a fixed grid of workgroups
+// pulls items from a device queue ordered longest first, and an item's
+// workgroup runs the substeps back to back, with a workgroup barrier between
+// them (the patch's writes of one substep are the next substep's reads, and
+// all of them stay on one compute unit).  The tasks of single-substep
+// patches run one wave each in a second launch, which the hardware
+// dispatcher balances as it does the single-patch step.  Ghost cells of
 // physical boundaries are synthesised on load, so each substep refreshes
 // them without a separate pass.  The arithmetic per cell is the same device
 // code as the single-patch step, so a patch's result does not depend on the
@@ -151,6 +153,61 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
     }
 }
 
+// Single-substep tasks (`tasks` is the plan's plain part, `nitems` its
+// length): one wave per workgroup, SEG = 64 one task per wave, SEG = 32 two.
+template <bool DEV, int SEG, bool FRIC>
+__global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_plain(BatchArgs a) {
+    constexpr int kSegPerWave = kWave / SEG;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int seg_in_wave = lane / SEG;
+    const int lane_in_seg = lane % SEG;
+    const int t0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kSegPerWave);
+    const int tid = SEG == kWave ? t0 : t0 + seg_in_wave;
+    const bool exists = tid < a.nitems;
+    const swe_task tsk = a.tasks[exists ? tid : t0];
+    const swe_patch pt = a.patches[tsk.patch];
+    // on a retake launch only the tasks of flagged groups run
+    const bool run = exists && (!a.retake || a.retake[pt.group] != 0);
+    if (!__any(run)) return;
+    Task tk;
+    tk.qin = a.pin;
+    tk.qout = a.pout;
+    tk.b = a.pb;
+    tk.off = pt.off;
+    tk.ps = pt.plane_stride;
+    tk.dt = a.dt_group[pt.group];
+    tk.dx = pt.dx;
+    tk.dy = pt.dy;
+    tk.pitch = pt.pitch;
+    tk.mx = pt.mx;
+    tk.my = pt.my;
+    tk.c0 = tsk.strip * (SEG - 4);
+    tk.U0 = tsk.row0;
+    tk.U1 = tsk.row0 + tsk.rows - 1;
+    tk.bc[0] = pt.bc[0];
+    tk.bc[1] = pt.bc[1];
+    tk.bc[2] = pt.bc[2];
+    tk.bc[3] = pt.bc[3];
+    tk.active = run;
+    int steps = tsk.rows + 4;
+    if (SEG != kWave) {
+        const int other = __shfl_xor(steps, SEG, kWave);
+        steps = other > steps ? other : steps;
+    }
+    steps = __builtin_amdgcn_readfirstlane(steps);
+    const MarchOut r = march<DEV, SEG, FRIC>(tk, a.P, lane_in_seg, steps);
+    // each segment reports to its own patch (NaN propagates through the
+    // bit-pattern maximum)
+    const double wx = wave_max_nonneg<SEG>(r.smx);
+    const double wy = wave_max_nonneg<SEG>(r.smy);
+    if (lane_in_seg == 0 && run) {
+        atomic_max_nonneg(&a.smax[2 * tsk.patch], wx);
+        atomic_max_nonneg(&a.smax[2 * tsk.patch + 1], wy);
+    }
+    if (r.clamps) atomicAdd(&a.status[1], r.clamps);
+    if (r.flags) atomicOr(&a.status[0], r.flags);
+}
+
 template __global__ void k_batched<false, 64, false>(BatchArgs);
 template __global__ void k_batched<false, 32, false>(BatchArgs);
 template __global__ void k_batched<true, 64, false>(BatchArgs);
@@ -159,6 +216,14 @@ template __global__ void k_batched<false, 64, true>(BatchArgs);
 template __global__ void k_batched<false, 32, true>(BatchArgs);
 template __global__ void k_batched<true, 64, true>(BatchArgs);
 template __global__ void k_batched<true, 32, true>(BatchArgs);
+template __global__ void k_plain<false, 64, false>(BatchArgs);
+template __global__ void k_plain<false, 32, false>(BatchArgs);
+template __global__ void k_plain<true, 64, false>(BatchArgs);
+template __global__ void k_plain<true, 32, false>(BatchArgs);
+template __global__ void k_plain<false, 64, true>(BatchArgs);
+template __global__ void k_plain<false, 32, true>(BatchArgs);
+template __global__ void k_plain<true, 64, true>(BatchArgs);
+template __global__ void k_plain<true, 32, true>(BatchArgs);
 
 }  // namespace swe
 
@@ -194,10 +259,11 @@ int bfail(int code, const std::string& msg) { return swe_internal_set_error(code
 extern "C" {
 
 int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sched,
-                     swe_item* items, int32_t* nitems, swe_task* tasks, int32_t* ntasks) {
+                     swe_item* items, int32_t* nitems, swe_task* tasks, int32_t* ntasks,
+                     int32_t* nplain) {
     int rc = check_sched(sched);
     if (rc) return rc;
-    if (!patches || n < 0 || !nitems || !ntasks)
+    if (!patches || n < 0 || !nitems || !ntasks || !nplain)
         return bfail(SWE_EINVAL, "swe_batched_plan: bad arguments");
     const int seg = sched->seg;
     const int out_cols = seg - 4;
@@ -207,7 +273,8 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
         double cost;
     };
     std::vector<PItem> its;
-    std::vector<swe_task> tks;
+    std::vector<swe_task> tks;    // tasks of the substep items
+    std::vector<swe_task> plain;  // tasks of single-substep patches
     for (int k = 0; k < n; ++k) {
         const swe_patch& p = patches[k];
         if (p.mx < 1 || p.my < 1 || p.pitch < p.mx + 4 || p.tref < 1 || !(p.dx > 0) ||
@@ -226,15 +293,20 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
         const int nstrips = (p.mx + out_cols - 1) / out_cols;
         int H = sched->rows_per_task;
         if (H == 0) {
-            // enough tasks to keep every segment of a workgroup busy, rows >= 8
-            const int want = (segs_per_group + nstrips - 1) / nstrips;
-            H = (p.my + want - 1) / want;
-            if (H < 8) H = 8;
-            if (p.tref == 1 && H > 64) H = 64;
+            if (p.tref == 1) {
+                // short tasks balance best (waves over water at rest finish early)
+                H = 32;
+            } else {
+                // enough tasks to keep every segment of the workgroup busy, rows >= 8
+                const int want = (segs_per_group + nstrips - 1) / nstrips;
+                H = (p.my + want - 1) / want;
+                if (H < 8) H = 8;
+            }
         }
         if (H > p.my) H = p.my;
         const int nchunks = (p.my + H - 1) / H;
-        const int first = (int)tks.size();
+        std::vector<swe_task>& dst = p.tref > 1 ? tks : plain;
+        const int first = (int)dst.size();
         for (int cidx = 0; cidx < nchunks; ++cidx)
             for (int st = 0; st < nstrips; ++st) {
                 swe_task t;
@@ -242,49 +314,43 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
                 t.strip = st;
                 t.row0 = 2 + cidx * H;
                 t.rows = std::min(H, p.my - cidx * H);
-                tks.push_back(t);
+                dst.push_back(t);
             }
-        const int last = (int)tks.size();
-        const double cost_per_task = (double)seg * (H + 4);
         if (p.tref > 1) {
+            const int last = (int)tks.size();
             PItem pi;
             pi.it = swe_item{first, last, k, p.tref};
-            pi.cost = cost_per_task * (last - first) * p.tref / segs_per_group;
+            pi.cost = (double)seg * (H + 4) * (last - first) * p.tref / segs_per_group;
             its.push_back(pi);
-        } else {
-            int per = sched->tasks_per_item;
-            if (per == 0) per = 4 * segs_per_group;
-            for (int b = first; b < last; b += per) {
-                PItem pi;
-                pi.it = swe_item{b, std::min(b + per, last), k, 1};
-                pi.cost = cost_per_task * (pi.it.task_end - b) / segs_per_group;
-                its.push_back(pi);
-            }
         }
     }
     if (sched->order == 0)
         std::stable_sort(its.begin(), its.end(),
                          [](const PItem& x, const PItem& y) { return x.cost > y.cost; });
+    const int32_t nt = (int32_t)(tks.size() + plain.size());
     if (!items || !tasks) {
         *nitems = (int32_t)its.size();
-        *ntasks = (int32_t)tks.size();
+        *ntasks = nt;
+        *nplain = (int32_t)plain.size();
         return SWE_OK;
     }
-    if (*nitems < (int32_t)its.size() || *ntasks < (int32_t)tks.size())
+    if (*nitems < (int32_t)its.size() || *ntasks < nt)
         return bfail(SWE_EINVAL, "swe_batched_plan: output arrays too small");
     for (size_t i = 0; i < its.size(); ++i) items[i] = its[i].it;
     std::copy(tks.begin(), tks.end(), tasks);
+    std::copy(plain.begin(), plain.end(), tasks + tks.size());
     *nitems = (int32_t)its.size();
-    *ntasks = (int32_t)tks.size();
+    *ntasks = nt;
+    *nplain = (int32_t)plain.size();
     return SWE_OK;
 }
 
 static int batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
-                        int32_t nitems, const swe_task* tasks, const void* pool_in,
-                        void* pool_out, void* pool_work, const void* pool_b,
-                        const double* dt_group, double* smax_patch, uint32_t* status,
-                        uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
-                        int32_t ngroups, void* stream) {
+                        int32_t nitems, const swe_task* tasks, const swe_task* plain,
+                        int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
+                        const void* pool_b, const double* dt_group, double* smax_patch,
+                        uint32_t* status, uint32_t* queue, const swe_schedule* sched,
+                        const uint32_t* retake, int32_t ngroups, void* stream) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -292,12 +358,14 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
         return bfail(SWE_EINVAL, "swe_batched_step: unknown precision");
     if (p->order != 1 && p->order != 2) return bfail(SWE_EINVAL, "params: order must be 1 or 2");
-    if (!patches || !items || !tasks || !pool_in || !pool_out || !pool_b || !dt_group ||
-        !smax_patch || !status || !queue || nitems < 0)
-        return bfail(SWE_EINVAL, "swe_batched_step: null pointer or negative count");
+    if (nitems < 0 || nplain < 0)
+        return bfail(SWE_EINVAL, "swe_batched_step: negative count");
+    if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch || !status ||
+        (nitems > 0 && (!items || !tasks || !queue)) || (nplain > 0 && !plain))
+        return bfail(SWE_EINVAL, "swe_batched_step: null pointer");
     if (pool_in == pool_out || pool_work == pool_in || pool_work == pool_out)
         return bfail(SWE_EINVAL, "swe_batched_step: pools must be distinct");
-    if (nitems == 0) return SWE_OK;
+    if (nitems == 0 && nplain == 0) return SWE_OK;
     swe::BatchArgs a;
     a.patches = patches;
     a.items = items;
@@ -321,34 +389,53 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.retake = retake;
     a.ngroups = ngroups;
 
-    const int threads = 64 * sched->waves_per_group;
     const bool dev = p->precision == SWE_F32_DEV;
     const bool fric = p->manning_n > 0.0;
-    using Kern = void (*)(swe::BatchArgs);
-    // [precision][segment 64 / 32][friction]
-    const Kern table[2][2][2] = {
-        {{swe::k_batched<false, 64, false>, swe::k_batched<false, 64, true>},
-         {swe::k_batched<false, 32, false>, swe::k_batched<false, 32, true>}},
-        {{swe::k_batched<true, 64, false>, swe::k_batched<true, 64, true>},
-         {swe::k_batched<true, 32, false>, swe::k_batched<true, 32, true>}}};
-    const Kern kern = table[dev ? 1 : 0][sched->seg == 64 ? 0 : 1][fric ? 1 : 0];
-    const void* fn = reinterpret_cast<const void*>(kern);
-    int dev_id = 0, ncu = 0;
-    if (hipGetDevice(&dev_id) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
-        ncu < 1)
-        return bfail(SWE_EHIP, "swe_batched_step: cannot query the device");
-    int per_cu = sched->groups_per_cu;
-    if (per_cu == 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-    }
-    int grid = ncu * per_cu;
-    if (grid > nitems) grid = nitems;
-    if (grid < 1) grid = 1;
+    const int si = sched->seg == 64 ? 0 : 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, a);
+    using Kern = void (*)(swe::BatchArgs);
+    if (nitems > 0) {
+        // substep items: persistent workgroups on the item queue
+        // [precision][segment 64 / 32][friction]
+        const Kern table[2][2][2] = {
+            {{swe::k_batched<false, 64, false>, swe::k_batched<false, 64, true>},
+             {swe::k_batched<false, 32, false>, swe::k_batched<false, 32, true>}},
+            {{swe::k_batched<true, 64, false>, swe::k_batched<true, 64, true>},
+             {swe::k_batched<true, 32, false>, swe::k_batched<true, 32, true>}}};
+        const Kern kern = table[dev ? 1 : 0][si][fric ? 1 : 0];
+        const int threads = 64 * sched->waves_per_group;
+        int dev_id = 0, ncu = 0;
+        if (hipGetDevice(&dev_id) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) !=
+                hipSuccess ||
+            ncu < 1)
+            return bfail(SWE_EHIP, "swe_batched_step: cannot query the device");
+        int per_cu = sched->groups_per_cu;
+        if (per_cu == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void*>(kern), threads, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+        }
+        int grid = ncu * per_cu;
+        if (grid > nitems) grid = nitems;
+        if (grid < 1) grid = 1;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, a);
+    }
+    if (nplain > 0) {
+        // single-substep tasks: one wave each, balanced by the dispatcher
+        const Kern table[2][2][2] = {
+            {{swe::k_plain<false, 64, false>, swe::k_plain<false, 64, true>},
+             {swe::k_plain<false, 32, false>, swe::k_plain<false, 32, true>}},
+            {{swe::k_plain<true, 64, false>, swe::k_plain<true, 64, true>},
+             {swe::k_plain<true, 32, false>, swe::k_plain<true, 32, true>}}};
+        swe::BatchArgs b = a;
+        b.tasks = plain;
+        b.nitems = nplain;
+        const int per_wave = sched->seg == 64 ? 1 : 2;
+        const int grid = (nplain + per_wave - 1) / per_wave;
+        hipLaunchKernelGGL(table[dev ? 1 : 0][si][fric ? 1 : 0], dim3(grid), dim3(64), 0, st, b);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return bfail(SWE_EHIP, std::string("swe_batched_step: ") + hipGetErrorString(e));
@@ -356,24 +443,27 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
 }
 
 int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
-                     int32_t nitems, const swe_task* tasks, const void* pool_in, void* pool_out,
-                     void* pool_work, const void* pool_b, const double* dt_group,
-                     double* smax_patch, uint32_t* status, uint32_t* queue,
-                     const swe_schedule* sched, void* stream) {
-    return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
-                        dt_group, smax_patch, status, queue, sched, nullptr, 0, stream);
+                     int32_t nitems, const swe_task* tasks, const swe_task* plain,
+                     int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
+                     const void* pool_b, const double* dt_group, double* smax_patch,
+                     uint32_t* status, uint32_t* queue, const swe_schedule* sched,
+                     void* stream) {
+    return batched_step(p, patches, items, nitems, tasks, plain, nplain, pool_in, pool_out,
+                        pool_work, pool_b, dt_group, smax_patch, status, queue, sched, nullptr,
+                        0, stream);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
-                       int32_t nitems, const swe_task* tasks, const void* pool_in,
-                       void* pool_out, void* pool_work, const void* pool_b,
-                       const double* dt_group, double* smax_patch, uint32_t* status,
-                       uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
-                       int32_t ngroups, void* stream) {
+                       int32_t nitems, const swe_task* tasks, const swe_task* plain,
+                       int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
+                       const void* pool_b, const double* dt_group, double* smax_patch,
+                       uint32_t* status, uint32_t* queue, const swe_schedule* sched,
+                       const uint32_t* retake, int32_t ngroups, void* stream) {
     if (!retake || ngroups < 1)
         return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags or ngroups < 1");
-    return batched_step(p, patches, items, nitems, tasks, pool_in, pool_out, pool_work, pool_b,
-                        dt_group, smax_patch, status, queue, sched, retake, ngroups, stream);
+    return batched_step(p, patches, items, nitems, tasks, plain, nplain, pool_in, pool_out,
+                        pool_work, pool_b, dt_group, smax_patch, status, queue, sched, retake,
+                        ngroups, stream);
 }
 
 }  // extern "C"

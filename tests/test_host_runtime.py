@@ -47,7 +47,7 @@ def amr_patches(L, counts=(5, 7, 9)):
 @pytest.mark.parametrize("seg", [64, 32])
 def test_plan_covers_every_cell_once(L, seg):
     specs, pts = amr_patches(L)
-    items, ni, tasks, nt = L.swe_batched_plan(pts, L.schedule(seg=seg))
+    items, ni, tasks, nt, npl = L.swe_batched_plan(pts, L.schedule(seg=seg))
     cover = {}
     for k in range(nt):
         t = tasks[k]
@@ -58,21 +58,25 @@ def test_plan_covers_every_cell_once(L, seg):
                 cover[(t.patch, r, c)] = cover.get((t.patch, r, c), 0) + 1
     expect = sum(p.mx * p.my for p in pts)
     assert len(cover) == expect and set(cover.values()) == {1}
-    # every task belongs to exactly one item of its own patch
+    # a patch with substeps is one item holding all its tasks; the tasks of
+    # single-substep patches are the last npl tasks, in no item
     seen = []
     for i in range(ni):
         it = items[i]
+        assert pts[it.patch].tref > 1 and it.substeps == pts[it.patch].tref
         assert all(tasks[k].patch == it.patch for k in range(it.task_begin, it.task_end))
         seen += list(range(it.task_begin, it.task_end))
-        # patches with substeps are whole in one item
-        if pts[it.patch].tref > 1:
-            assert it.substeps == pts[it.patch].tref
-    assert sorted(seen) == list(range(nt))
+    assert sorted(seen) == list(range(nt - npl))
+    assert all(pts[tasks[k].patch].tref == 1 for k in range(nt - npl, nt))
+    assert {tasks[k].patch for k in range(nt - npl, nt)} == {
+        k for k, p in enumerate(pts) if p.tref == 1}
+    # plain tasks are at most 32 rows by default
+    assert all(tasks[k].rows <= 32 for k in range(nt - npl, nt))
 
 
 def test_plan_orders_longest_first(L):
     specs, pts = amr_patches(L)
-    items, ni, tasks, nt = L.swe_batched_plan(pts, L.schedule(order=0))
+    items, ni, tasks, nt, npl = L.swe_batched_plan(pts, L.schedule(order=0))
 
     def cost(it):
         p = pts[it.patch]
