@@ -186,14 +186,20 @@ int swe_mass(const swe_params *p, const swe_patch *patches, int32_t n, const voi
  * longest first, and an item's workgroup runs its tref substeps back to back
  * with a barrier in between.  The tasks of patches with tref == 1 ("plain"
  * tasks, the last nplain of the plan's tasks) run one wave each in a second
- * launch.
+ * launch.  With per_substep = 1 every task is plain and a call makes one
+ * launch per substep (patches are independent, so substep s of every patch
+ * with tref > s can run together; the launch boundary orders a patch's
+ * substeps).
  */
 typedef struct swe_schedule {
     int32_t seg;             /* lanes per strip: 64 or 32 */
     int32_t rows_per_task;   /* rows per task; 0 = 32 for tref == 1, else enough
                                 tasks for the workgroup (at least 8 rows) */
     int32_t waves_per_group; /* waves per workgroup: 1, 2, 4 or 8 */
-    int32_t tasks_per_item;  /* reserved (ignored): plain tasks run one wave each */
+    int32_t per_substep;     /* 0: patches with substeps run as items of one
+                                persistent launch; 1: every patch's tasks are
+                                plain and substep s of all patches with tref > s
+                                is one launch (max tref launches per call) */
     int32_t order;           /* 0 = longest item first, 1 = patch order */
     int32_t groups_per_cu;   /* persistent workgroups per compute unit; 0 = occupancy */
 } swe_schedule;
@@ -213,14 +219,16 @@ typedef struct swe_item {
 
 /* Build a plan on the host.  patches: host array of n patches.  With items
  * and tasks NULL only the counts are returned in *nitems, *ntasks (all
- * tasks) and *nplain (the plain ones among them); otherwise the arrays
- * (host, sized from a previous query) are filled: the items' tasks first,
- * then the nplain plain tasks.  Fails with SWE_EINVAL for a bad patch or if
- * a SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
+ * tasks), *nplain (the plain ones among them) and *nsub (the launches the
+ * plain tasks take: 1, or the largest tref with per_substep = 1; 0 without
+ * plain tasks); otherwise the arrays (host, sized from a previous query) are
+ * filled: the items' tasks first, then the nplain plain tasks (ordered by
+ * tref, largest first).  Fails with SWE_EINVAL for a bad patch or if a
+ * SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
  * substeps). */
 int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sched,
                      swe_item *items, int32_t *nitems, swe_task *tasks, int32_t *ntasks,
-                     int32_t *nplain);
+                     int32_t *nplain, int32_t *nsub);
 
 /* Advance every patch of the plan: patch k takes tref_k substeps of
  * dt_group[group_k] / tref_k from pool_in to pool_out (pool_in is not
@@ -228,12 +236,14 @@ int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sc
  * patches with tref > 1; NULL is allowed when every tref is 1).  The largest
  * speeds of all substeps are max-combined into smax_patch[2 k], [2 k + 1].
  * patches, items, tasks: device copies of the table and of the plan; plain:
- * device pointer to the plan's nplain plain tasks (tasks + ntasks - nplain).
+ * device pointer to the plan's nplain plain tasks (tasks + ntasks - nplain),
+ * nsub: the plan's launch count for them.
  * queue: device uint32_t[2], zero before the first call; the launch leaves it
  * zero again.  sched: host, the schedule the plan was built with. */
 int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_item *items,
                      int32_t nitems, const swe_task *tasks, const swe_task *plain,
-                     int32_t nplain, const void *pool_in, void *pool_out, void *pool_work,
+                     int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
+                     void *pool_work,
                      const void *pool_b, const double *dt_group, double *smax_patch,
                      uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                      void *stream);
@@ -246,7 +256,8 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
  * pools as the step being redone; retake: device uint32_t[ngroups]. */
 int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_item *items,
                        int32_t nitems, const swe_task *tasks, const swe_task *plain,
-                       int32_t nplain, const void *pool_in, void *pool_out, void *pool_work,
+                       int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
+                       void *pool_work,
                        const void *pool_b, const double *dt_group, double *smax_patch,
                        uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                        const uint32_t *retake, int32_t ngroups, void *stream);

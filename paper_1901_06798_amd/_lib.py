@@ -47,7 +47,7 @@ assert ctypes.sizeof(swe_patch) == 64
 
 class swe_schedule(ctypes.Structure):
     _fields_ = [("seg", ctypes.c_int32), ("rows_per_task", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32), ("tasks_per_item", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("per_substep", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
 
 
@@ -61,9 +61,9 @@ class swe_item(ctypes.Structure):
                 ("patch", ctypes.c_int32), ("substeps", ctypes.c_int32)]
 
 
-def schedule(seg=64, rows_per_task=0, waves_per_group=4, tasks_per_item=0, order=0,
+def schedule(seg=64, rows_per_task=0, waves_per_group=4, per_substep=0, order=0,
              groups_per_cu=0) -> swe_schedule:
-    return swe_schedule(seg, rows_per_task, waves_per_group, tasks_per_item, order, groups_per_cu)
+    return swe_schedule(seg, rows_per_task, waves_per_group, per_substep, order, groups_per_cu)
 
 
 def params(g=9.81, drytol=1e-3, h_corr=0.1, manning_n=0.0, cfl_desired=0.9, cfl_max=1.0,
@@ -102,11 +102,11 @@ def lib():
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
-        L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32]
-        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P, _P,
-                                       _P, ps, _P]
-        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, _P, _P, _P, _P, _P, _P,
-                                         _P, _P, ps, _P, i32, _P]
+        L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
+        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P, _P, _P,
+                                       _P, _P, ps, _P]
+        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P, _P,
+                                         _P, _P, _P, ps, _P, i32, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
@@ -164,43 +164,58 @@ def swe_mass(p: swe_params, patches: int, n: int, q: int, b: int, mass_patch: in
 
 
 def swe_batched_plan(patches, sched: swe_schedule):
-    """Plan for a host list of swe_patch; returns (items, nitems, tasks, ntasks,
-    nplain): ctypes arrays and counts; the last nplain tasks are the plain
-    (single-substep) ones."""
+    """Plan for a host list of swe_patch; returns a Plan: ctypes arrays items and
+    tasks with the counts nitems, ntasks, nplain (the last nplain tasks are
+    the plain ones) and nsub (launches of the plain tasks)."""
     n = len(patches)
     arr = (swe_patch * n)(*patches)
     ni = ctypes.c_int32(0)
     nt = ctypes.c_int32(0)
     npl = ctypes.c_int32(0)
+    nsb = ctypes.c_int32(0)
     _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched), None,
-                                  ctypes.byref(ni), None, ctypes.byref(nt), ctypes.byref(npl)),
-           "swe_batched_plan")
+                                  ctypes.byref(ni), None, ctypes.byref(nt), ctypes.byref(npl),
+                                  ctypes.byref(nsb)), "swe_batched_plan")
     items = (swe_item * max(ni.value, 1))()
     tasks = (swe_task * max(nt.value, 1))()
     _check(lib().swe_batched_plan(ctypes.addressof(arr), n, ctypes.byref(sched),
                                   ctypes.addressof(items), ctypes.byref(ni),
-                                  ctypes.addressof(tasks), ctypes.byref(nt), ctypes.byref(npl)),
-           "swe_batched_plan")
-    return items, ni.value, tasks, nt.value, npl.value
+                                  ctypes.addressof(tasks), ctypes.byref(nt), ctypes.byref(npl),
+                                  ctypes.byref(nsb)), "swe_batched_plan")
+    return Plan(items, ni.value, tasks, nt.value, npl.value, nsb.value)
+
+
+class Plan:
+    def __init__(self, items, nitems, tasks, ntasks, nplain, nsub):
+        self.items, self.nitems, self.tasks, self.ntasks = items, nitems, tasks, ntasks
+        self.nplain, self.nsub = nplain, nsub
+
+    def device(self, dev):
+        """(items, tasks) as uint8 device tensors."""
+        import torch
+        to = lambda a: torch.frombuffer(bytearray(bytes(a)), dtype=torch.uint8).to(dev)
+        return to(self.items), to(self.tasks)
 
 
 SWE_TASK_BYTES = ctypes.sizeof(swe_task)
 
 
 def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
-                     plain: int, nplain: int, pool_in: int, pool_out: int, pool_work: int,
-                     pool_b: int, dt_group: int, smax_patch: int, status: int, queue: int,
-                     sched: swe_schedule, stream: int = 0) -> None:
+                     plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
+                     pool_work: int, pool_b: int, dt_group: int, smax_patch: int, status: int,
+                     queue: int, sched: swe_schedule, stream: int = 0) -> None:
     _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, plain, nplain,
-                                  pool_in, pool_out, pool_work, pool_b, dt_group, smax_patch,
-                                  status, queue, ctypes.byref(sched), stream), "swe_batched_step")
+                                  nsub, pool_in, pool_out, pool_work, pool_b, dt_group,
+                                  smax_patch, status, queue, ctypes.byref(sched), stream),
+           "swe_batched_step")
 
 
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
-                       plain: int, nplain: int, pool_in: int, pool_out: int, pool_work: int,
-                       pool_b: int, dt_group: int, smax_patch: int, status: int, queue: int,
-                       sched: swe_schedule, retake: int, ngroups: int, stream: int = 0) -> None:
+                       plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
+                       pool_work: int, pool_b: int, dt_group: int, smax_patch: int,
+                       status: int, queue: int, sched: swe_schedule, retake: int, ngroups: int,
+                       stream: int = 0) -> None:
     _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, plain,
-                                    nplain, pool_in, pool_out, pool_work, pool_b, dt_group,
-                                    smax_patch, status, queue, ctypes.byref(sched), retake,
-                                    ngroups, stream), "swe_batched_retake")
+                                    nplain, nsub, pool_in, pool_out, pool_work, pool_b,
+                                    dt_group, smax_patch, status, queue, ctypes.byref(sched),
+                                    retake, ngroups, stream), "swe_batched_retake")

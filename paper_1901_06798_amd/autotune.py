@@ -1,7 +1,8 @@
 """Schedule autotuner for the batched persistent step.
 
 Candidates are (segment width, rows per task, waves per workgroup, workgroups
-per compute unit).  Each is timed on the actual patch set with HIP events
+per compute unit) for the persistent item launch, and (segment width, rows
+per task) for one launch per substep.  Each is timed on the actual patch set with HIP events
 (warm-up, then the median of several steps); the fastest is kept.  Results
 are cached in a JSON file keyed by the precision and a histogram of patch
 sizes and substep counts, so a patch set of the same shape reuses them.
@@ -39,10 +40,13 @@ def candidates():
     out = []
     for seg in (64, 32):
         for rows in (0, 8, 16, 32):
+            # patches with substeps as items of one persistent launch
             for waves in (2, 4, 8):
                 for per_cu in (0, 1, 2):
                     out.append(L.schedule(seg=seg, rows_per_task=rows, waves_per_group=waves,
                                           groups_per_cu=per_cu))
+            # one launch per substep, every task one wave
+            out.append(L.schedule(seg=seg, rows_per_task=rows, per_substep=1))
     return out
 
 

@@ -77,10 +77,10 @@ class BatchedSolver:
 
     def replan(self, sched: L.swe_schedule) -> None:
         self.sched = sched
-        items, ni, tasks, nt, npl = L.swe_batched_plan(self.patches, sched)
-        self.nitems, self.ntasks, self.nplain = ni, nt, npl
-        self.items = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(self.dev)
-        self.tasks = torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8).to(self.dev)
+        plan = L.swe_batched_plan(self.patches, sched)
+        self.nitems, self.ntasks, self.nplain, self.nsub = (plan.nitems, plan.ntasks,
+                                                            plan.nplain, plan.nsub)
+        self.items, self.tasks = plan.device(self.dev)
         self.graph = None
 
     @property
@@ -133,7 +133,7 @@ class BatchedSolver:
         args = (self.table.data_ptr(), self.items.data_ptr(), self.nitems,
                 self.tasks.data_ptr(),
                 self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
-                self.nplain, self.pools[self.cur].data_ptr(),
+                self.nplain, self.nsub, self.pools[self.cur].data_ptr(),
                 self.pools[1 - self.cur].data_ptr(),
                 self.work.data_ptr() if self.work is not None else 0, self.b.data_ptr())
         L.swe_batched_step(self.p, *args, dt_ptr if dt_ptr is not None else self.dt.data_ptr(),

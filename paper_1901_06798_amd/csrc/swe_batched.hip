@@ -44,6 +44,7 @@ struct BatchArgs {
     DevParams P;
     const uint32_t* retake;  // retake launch: only groups with retake[g] != 0; NULL: all
     int ngroups;             // entries of retake
+    int sub;                 // plain launches: the substep this launch runs
 };
 
 // The FP32 march fits three waves per SIMD (at most 168 VGPRs) without
@@ -153,8 +154,11 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
     }
 }
 
-// Single-substep tasks (`tasks` is the plan's plain part, `nitems` its
-// length): one wave per workgroup, SEG = 64 one task per wave, SEG = 32 two.
+// Plain tasks (`tasks` is the plan's plain part, `nitems` its length): one
+// wave per workgroup, SEG = 64 one task per wave, SEG = 32 two.  The launch
+// runs substep `sub` of each task's patch (a patch with tref <= sub has no
+// such substep); substeps alternate between pool_out and pool_work so that
+// the last one lands in pool_out, as in the item kernel.
 template <bool DEV, int SEG, bool FRIC>
 __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_plain(BatchArgs a) {
     constexpr int kSegPerWave = kWave / SEG;
@@ -167,15 +171,17 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_plain(Ba
     const swe_task tsk = a.tasks[exists ? tid : t0];
     const swe_patch pt = a.patches[tsk.patch];
     // on a retake launch only the tasks of flagged groups run
-    const bool run = exists && (!a.retake || a.retake[pt.group] != 0);
+    const bool run =
+        exists && a.sub < pt.tref && (!a.retake || a.retake[pt.group] != 0);
     if (!__any(run)) return;
+    const int last = pt.tref - 1;
     Task tk;
-    tk.qin = a.pin;
-    tk.qout = a.pout;
+    tk.qin = a.sub == 0 ? a.pin : ((last - (a.sub - 1)) % 2 == 0 ? a.pout : a.pwork);
+    tk.qout = (last - a.sub) % 2 == 0 ? a.pout : a.pwork;
     tk.b = a.pb;
     tk.off = pt.off;
     tk.ps = pt.plane_stride;
-    tk.dt = a.dt_group[pt.group];
+    tk.dt = a.dt_group[pt.group] / (double)pt.tref;
     tk.dx = pt.dx;
     tk.dy = pt.dy;
     tk.pitch = pt.pitch;
@@ -240,9 +246,10 @@ int check_sched(const swe_schedule* s) {
     if (s->waves_per_group != 1 && s->waves_per_group != 2 && s->waves_per_group != 4 &&
         s->waves_per_group != 8)
         return bfail(SWE_EINVAL, "schedule: waves_per_group must be 1, 2, 4 or 8");
-    if (s->rows_per_task < 0 || s->tasks_per_item < 0 || s->groups_per_cu < 0 ||
+    if (s->rows_per_task < 0 || s->per_substep < 0 || s->per_substep > 1 ||
+        s->groups_per_cu < 0 ||
         (s->order != 0 && s->order != 1))
-        return bfail(SWE_EINVAL, "schedule: bad rows_per_task, tasks_per_item, groups_per_cu or order");
+        return bfail(SWE_EINVAL, "schedule: bad rows_per_task, per_substep, groups_per_cu or order");
     return SWE_OK;
 }
 
@@ -260,11 +267,13 @@ extern "C" {
 
 int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sched,
                      swe_item* items, int32_t* nitems, swe_task* tasks, int32_t* ntasks,
-                     int32_t* nplain) {
+                     int32_t* nplain, int32_t* nsub) {
     int rc = check_sched(sched);
     if (rc) return rc;
-    if (!patches || n < 0 || !nitems || !ntasks || !nplain)
+    if (!patches || n < 0 || !nitems || !ntasks || !nplain || !nsub)
         return bfail(SWE_EINVAL, "swe_batched_plan: bad arguments");
+    const bool per_sub = sched->per_substep != 0;
+    int max_tref = 0;
     const int seg = sched->seg;
     const int out_cols = seg - 4;
     const int segs_per_group = sched->waves_per_group * (64 / seg);
@@ -291,9 +300,10 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
         if ((p.bc[2] == SWE_BC_WALL || p.bc[3] == SWE_BC_WALL) && p.my < 2)
             return bfail(SWE_EINVAL, "swe_batched_plan: a wall in y needs my >= 2");
         const int nstrips = (p.mx + out_cols - 1) / out_cols;
+        const bool item = p.tref > 1 && !per_sub;
         int H = sched->rows_per_task;
         if (H == 0) {
-            if (p.tref == 1) {
+            if (!item) {
                 // short tasks balance best (waves over water at rest finish early)
                 H = 32;
             } else {
@@ -305,8 +315,9 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
         }
         if (H > p.my) H = p.my;
         const int nchunks = (p.my + H - 1) / H;
-        std::vector<swe_task>& dst = p.tref > 1 ? tks : plain;
+        std::vector<swe_task>& dst = item ? tks : plain;
         const int first = (int)dst.size();
+        if (!item && p.tref > max_tref) max_tref = p.tref;
         for (int cidx = 0; cidx < nchunks; ++cidx)
             for (int st = 0; st < nstrips; ++st) {
                 swe_task t;
@@ -316,7 +327,7 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
                 t.rows = std::min(H, p.my - cidx * H);
                 dst.push_back(t);
             }
-        if (p.tref > 1) {
+        if (item) {
             const int last = (int)tks.size();
             PItem pi;
             pi.it = swe_item{first, last, k, p.tref};
@@ -327,7 +338,12 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
     if (sched->order == 0)
         std::stable_sort(its.begin(), its.end(),
                          [](const PItem& x, const PItem& y) { return x.cost > y.cost; });
+    // plain tasks by tref, largest first (a patch's tasks stay together)
+    std::stable_sort(plain.begin(), plain.end(), [&](const swe_task& x, const swe_task& y) {
+        return patches[x.patch].tref > patches[y.patch].tref;
+    });
     const int32_t nt = (int32_t)(tks.size() + plain.size());
+    *nsub = plain.empty() ? 0 : max_tref;
     if (!items || !tasks) {
         *nitems = (int32_t)its.size();
         *ntasks = nt;
@@ -347,7 +363,8 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
 
 static int batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
                         int32_t nitems, const swe_task* tasks, const swe_task* plain,
-                        int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
+                        int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
+                        void* pool_work,
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
                         const uint32_t* retake, int32_t ngroups, void* stream) {
@@ -358,8 +375,10 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
         return bfail(SWE_EINVAL, "swe_batched_step: unknown precision");
     if (p->order != 1 && p->order != 2) return bfail(SWE_EINVAL, "params: order must be 1 or 2");
-    if (nitems < 0 || nplain < 0)
-        return bfail(SWE_EINVAL, "swe_batched_step: negative count");
+    if (nitems < 0 || nplain < 0 || nsub < 0 || (nplain > 0 && nsub < 1))
+        return bfail(SWE_EINVAL, "swe_batched_step: bad counts");
+    if (nsub > 1 && !pool_work)
+        return bfail(SWE_EINVAL, "swe_batched_step: substeps need pool_work");
     if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch || !status ||
         (nitems > 0 && (!items || !tasks || !queue)) || (nplain > 0 && !plain))
         return bfail(SWE_EINVAL, "swe_batched_step: null pointer");
@@ -388,6 +407,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.P.order = p->order;
     a.retake = retake;
     a.ngroups = ngroups;
+    a.sub = 0;
 
     const bool dev = p->precision == SWE_F32_DEV;
     const bool fric = p->manning_n > 0.0;
@@ -434,7 +454,11 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
         b.nitems = nplain;
         const int per_wave = sched->seg == 64 ? 1 : 2;
         const int grid = (nplain + per_wave - 1) / per_wave;
-        hipLaunchKernelGGL(table[dev ? 1 : 0][si][fric ? 1 : 0], dim3(grid), dim3(64), 0, st, b);
+        for (int sub = 0; sub < nsub; ++sub) {
+            b.sub = sub;
+            hipLaunchKernelGGL(table[dev ? 1 : 0][si][fric ? 1 : 0], dim3(grid), dim3(64), 0,
+                               st, b);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -444,26 +468,27 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
 
 int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
                      int32_t nitems, const swe_task* tasks, const swe_task* plain,
-                     int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
-                     const void* pool_b, const double* dt_group, double* smax_patch,
-                     uint32_t* status, uint32_t* queue, const swe_schedule* sched,
-                     void* stream) {
-    return batched_step(p, patches, items, nitems, tasks, plain, nplain, pool_in, pool_out,
-                        pool_work, pool_b, dt_group, smax_patch, status, queue, sched, nullptr,
-                        0, stream);
+                     int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
+                     void* pool_work, const void* pool_b, const double* dt_group,
+                     double* smax_patch, uint32_t* status, uint32_t* queue,
+                     const swe_schedule* sched, void* stream) {
+    return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
+                        pool_out, pool_work, pool_b, dt_group, smax_patch, status, queue, sched,
+                        nullptr, 0, stream);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
                        int32_t nitems, const swe_task* tasks, const swe_task* plain,
-                       int32_t nplain, const void* pool_in, void* pool_out, void* pool_work,
-                       const void* pool_b, const double* dt_group, double* smax_patch,
-                       uint32_t* status, uint32_t* queue, const swe_schedule* sched,
-                       const uint32_t* retake, int32_t ngroups, void* stream) {
+                       int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
+                       void* pool_work, const void* pool_b, const double* dt_group,
+                       double* smax_patch, uint32_t* status, uint32_t* queue,
+                       const swe_schedule* sched, const uint32_t* retake, int32_t ngroups,
+                       void* stream) {
     if (!retake || ngroups < 1)
         return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags or ngroups < 1");
-    return batched_step(p, patches, items, nitems, tasks, plain, nplain, pool_in, pool_out,
-                        pool_work, pool_b, dt_group, smax_patch, status, queue, sched, retake,
-                        ngroups, stream);
+    return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
+                        pool_out, pool_work, pool_b, dt_group, smax_patch, status, queue, sched,
+                        retake, ngroups, stream);
 }
 
 }  // extern "C"

@@ -209,11 +209,13 @@ class ScenarioServer:
     def _rebuild(self) -> None:
         pts = [self._patch(sc) for sc in self.active]
         self.table = self._to_device(patch_table(pts))
-        items, ni, tasks, nt, npl = L.swe_batched_plan(pts, self.sched)
-        self.items = self._to_device(torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8))
-        self.tasks = self._to_device(torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8))
-        self.nitems = ni
-        self.ntasks, self.nplain = nt, npl
+        plan = L.swe_batched_plan(pts, self.sched)
+        self.items = self._to_device(torch.frombuffer(bytearray(bytes(plan.items)),
+                                                      dtype=torch.uint8))
+        self.tasks = self._to_device(torch.frombuffer(bytearray(bytes(plan.tasks)),
+                                                      dtype=torch.uint8))
+        self.nitems = plan.nitems
+        self.ntasks, self.nplain, self.nsub = plan.ntasks, plan.nplain, plan.nsub
         self.table_dirty = False
 
     def _retire(self, sc: Scenario):
@@ -261,7 +263,7 @@ class ScenarioServer:
             args = (self.table.data_ptr(), self.items.data_ptr(), self.nitems,
                     self.tasks.data_ptr(),
                     self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
-                    self.nplain, self.pools[self.cur].data_ptr(),
+                    self.nplain, self.nsub, self.pools[self.cur].data_ptr(),
                     self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
                     self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
                     self.queue_ctr.data_ptr(), self.sched)

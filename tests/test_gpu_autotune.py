@@ -28,16 +28,17 @@ def small_set():
     return probs, [s.tref for s in specs]
 
 
-CANDS = [(64, 0, 4, 0), (32, 0, 4, 0), (64, 8, 2, 1), (32, 16, 8, 0)]
+CANDS = [(64, 0, 4, 0, 0), (32, 0, 4, 0, 0), (64, 8, 2, 1, 0), (32, 16, 8, 0, 0),
+         (64, 0, 4, 0, 1)]
 
 
 def test_tune_picks_fastest_keeps_state_and_caches(gpu, tmp_path):
     L, A, BatchedSolver, torch = gpu
     probs, trefs = small_set()
     p = L.params()
-    cands = [L.schedule(seg=s, rows_per_task=r, waves_per_group=w, groups_per_cu=g)
-             for s, r, w, g in CANDS]
-    print("case autotune small AMR set, 4 candidates", flush=True)
+    cands = [L.schedule(seg=s, rows_per_task=r, waves_per_group=w, groups_per_cu=g,
+                        per_substep=u) for s, r, w, g, u in CANDS]
+    print("case autotune small AMR set, 5 candidates", flush=True)
     bs = BatchedSolver(probs, p, trefs=trefs)
     bs.initial_dt()
     bs.run(2)

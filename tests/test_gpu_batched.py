@@ -88,15 +88,21 @@ def test_amr_patch_set_matches_reference(gpu, orc):
     assert dts[0] == pytest.approx(0.9 / rate, rel=1e-15)
 
 
-def test_amr_substeps_equal_single_patch_bitwise(gpu):
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("seg,per_substep", [(32, 0), (64, 1), (32, 1)])
+def test_amr_substeps_equal_single_patch_bitwise(gpu, precision, seg, per_substep):
     L, BatchedSolver, PatchSolver, torch = gpu
     specs, probs, trefs = amr_set(seed=5, counts=(3, 4, 5))
-    bs = BatchedSolver(probs, L.params(), trefs=trefs, sched=L.schedule(seg=32))
+    print(f"case AMR substeps precision={precision} seg={seg} per_substep={per_substep}",
+          flush=True)
+    p = L.params(precision=precision)
+    bs = BatchedSolver(probs, p, trefs=trefs,
+                       sched=L.schedule(seg=seg, per_substep=per_substep))
     bs.initial_dt()
     dts = bs.run(2, record_dt=True)[:, 0]
     torch.cuda.synchronize()
     for k, pb in enumerate(probs):
-        s = PatchSolver(pb, L.params())
+        s = PatchSolver(pb, p)
         t = trefs[k]
         sub = []
         for dt in dts:
@@ -107,12 +113,14 @@ def test_amr_substeps_equal_single_patch_bitwise(gpu):
             assert np.array_equal(a, c), f"patch {k} tref {t}"
 
 
-def test_graph_replay_matches_eager(gpu):
+@pytest.mark.parametrize("per_substep", [0, 1])
+def test_graph_replay_matches_eager(gpu, per_substep):
     L, BatchedSolver, PatchSolver, torch = gpu
     specs, probs, trefs = amr_set(seed=7, counts=(4, 6, 8))
-    eager = BatchedSolver(probs, L.params(), trefs=trefs)
+    sched = L.schedule(per_substep=per_substep)
+    eager = BatchedSolver(probs, L.params(), trefs=trefs, sched=sched)
     eager.initial_dt()
-    graph = BatchedSolver(probs, L.params(), trefs=trefs)
+    graph = BatchedSolver(probs, L.params(), trefs=trefs, sched=sched)
     graph.initial_dt()
     graph.capture(4)
     for rep in range(3):

@@ -56,12 +56,12 @@ def advance(L, torch, p, pt, table, qin, qout, b, steps, batched=False, plan=Non
     for k in range(steps):
         a, c = bufs[k % 2], bufs[(k + 1) % 2]
         if batched:
-            items, ni, tasks, nt, npl, sched = plan
-            plain = tasks.data_ptr() + L.SWE_TASK_BYTES * (nt - npl)
-            L.swe_batched_step(p, table.data_ptr(), items.data_ptr(), ni, tasks.data_ptr(),
-                               plain, npl, a.data_ptr(), c.data_ptr(), 0, b.data_ptr(),
-                               dt.data_ptr(), smax.data_ptr(), status.data_ptr(),
-                               queue.data_ptr(), sched, s)
+            pl, items, tasks, sched = plan
+            plain = tasks.data_ptr() + L.SWE_TASK_BYTES * (pl.ntasks - pl.nplain)
+            L.swe_batched_step(p, table.data_ptr(), items.data_ptr(), pl.nitems,
+                               tasks.data_ptr(), plain, pl.nplain, pl.nsub, a.data_ptr(),
+                               c.data_ptr(), 0, b.data_ptr(), dt.data_ptr(), smax.data_ptr(),
+                               status.data_ptr(), queue.data_ptr(), sched, s)
         else:
             L.swe_patch_step(p, pt, a.data_ptr(), c.data_ptr(), b.data_ptr(), dt.data_ptr(),
                              smax.data_ptr(), status.data_ptr(), s)
@@ -98,10 +98,8 @@ def test_offsets_beyond_2_31_elements(gpu, batched):
         plan = None
         if batched:
             sched = L.schedule(seg=64, waves_per_group=4)
-            items, ni, tasks, nt, npl = L.swe_batched_plan([pt], sched)
-            plan = (torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(dev), ni,
-                    torch.frombuffer(bytearray(bytes(tasks)), dtype=torch.uint8).to(dev), nt,
-                    npl, sched)
+            pl = L.swe_batched_plan([pt], sched)
+            plan = (pl, *pl.device(dev), sched)
         res, st = advance(L, torch, p, pt, table, qin, qout, b, steps, batched, plan)
         assert st & (L.STATUS_NONFINITE | L.STATUS_NEG_DEPTH) == 0
         results.append(torch.stack([res[o + k * stride: o + k * stride + n] for k in range(3)])
@@ -126,7 +124,7 @@ def test_empty_batches(gpu):
     L.swe_speed_scan(p, z.data_ptr(), 0, 1, 1, z.data_ptr(), z.data_ptr(), z.data_ptr(), s)
     L.swe_mass(p, z.data_ptr(), 0, z.data_ptr(), z.data_ptr(), z.data_ptr(), s)
     sched = L.schedule()
-    L.swe_batched_step(p, z.data_ptr(), z.data_ptr(), 0, z.data_ptr(), z.data_ptr(), 0,
+    L.swe_batched_step(p, z.data_ptr(), z.data_ptr(), 0, z.data_ptr(), z.data_ptr(), 0, 0,
                        z.data_ptr(), z[32:].data_ptr(), 0, z.data_ptr(), z.data_ptr(),
                        z.data_ptr(), st.data_ptr(), q.data_ptr(), sched, s)
     torch.cuda.synchronize()

@@ -45,9 +45,11 @@ def amr_patches(L, counts=(5, 7, 9)):
 
 
 @pytest.mark.parametrize("seg", [64, 32])
-def test_plan_covers_every_cell_once(L, seg):
+@pytest.mark.parametrize("per_substep", [0, 1])
+def test_plan_covers_every_cell_once(L, seg, per_substep):
     specs, pts = amr_patches(L)
-    items, ni, tasks, nt, npl = L.swe_batched_plan(pts, L.schedule(seg=seg))
+    plan = L.swe_batched_plan(pts, L.schedule(seg=seg, per_substep=per_substep))
+    items, ni, tasks, nt, npl = plan.items, plan.nitems, plan.tasks, plan.ntasks, plan.nplain
     cover = {}
     for k in range(nt):
         t = tasks[k]
@@ -58,8 +60,9 @@ def test_plan_covers_every_cell_once(L, seg):
                 cover[(t.patch, r, c)] = cover.get((t.patch, r, c), 0) + 1
     expect = sum(p.mx * p.my for p in pts)
     assert len(cover) == expect and set(cover.values()) == {1}
-    # a patch with substeps is one item holding all its tasks; the tasks of
-    # single-substep patches are the last npl tasks, in no item
+    # a patch with substeps is one item holding all its tasks (or, launched
+    # per substep, plain like the rest); the plain tasks are the last npl
+    # tasks, in no item, ordered by tref, largest first
     seen = []
     for i in range(ni):
         it = items[i]
@@ -67,16 +70,23 @@ def test_plan_covers_every_cell_once(L, seg):
         assert all(tasks[k].patch == it.patch for k in range(it.task_begin, it.task_end))
         seen += list(range(it.task_begin, it.task_end))
     assert sorted(seen) == list(range(nt - npl))
-    assert all(pts[tasks[k].patch].tref == 1 for k in range(nt - npl, nt))
-    assert {tasks[k].patch for k in range(nt - npl, nt)} == {
-        k for k, p in enumerate(pts) if p.tref == 1}
+    plain_patches = {tasks[k].patch for k in range(nt - npl, nt)}
+    if per_substep:
+        assert ni == 0 and npl == nt and plain_patches == set(range(len(pts)))
+        assert plan.nsub == max(p.tref for p in pts)
+    else:
+        assert plain_patches == {k for k, p in enumerate(pts) if p.tref == 1}
+        assert plan.nsub == 1
+    trefs = [pts[tasks[k].patch].tref for k in range(nt - npl, nt)]
+    assert trefs == sorted(trefs, reverse=True)
     # plain tasks are at most 32 rows by default
     assert all(tasks[k].rows <= 32 for k in range(nt - npl, nt))
 
 
 def test_plan_orders_longest_first(L):
     specs, pts = amr_patches(L)
-    items, ni, tasks, nt, npl = L.swe_batched_plan(pts, L.schedule(order=0))
+    plan = L.swe_batched_plan(pts, L.schedule(order=0))
+    items, ni, tasks = plan.items, plan.nitems, plan.tasks
 
     def cost(it):
         p = pts[it.patch]
