@@ -58,6 +58,14 @@ __device__ __forceinline__ TCell<double> tcell(double h, double hu, double hv, d
     return t;
 }
 
+__device__ __forceinline__ bool zero3(const double a[3]) {
+    return a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0;
+}
+
+// A zero amount splits into zero transverse parts (its coefficients are 0, or
+// the pair is dry and the part is 0 by rule), so when nothing enters the
+// cells of a wave the Roe averages and the splits are skipped; the parts are
+// then +0 where the split could give -0, which changes no value.
 template <int SEG, bool FRIC>
 __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParams& P,
                                                   int lane_in_seg, int steps,
@@ -95,17 +103,52 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
     S bP2[3] = {0, 0, 0};            // amount entering (c, R-2) through y-edge R-2
     S Gt2[3] = {0, 0, 0};            // G~ total of y-edge R-2
 
+    // finished row held for one iteration (its stores go out before the next
+    // row's loads) and the next row's values, loaded one iteration ahead
+    S po[3] = {0, 0, 0};
+    int po_row = 0;
+    bool po_wr = false;
+    S nh, nhu, nhv, nbb;
+    bool nfx, nfy;
+    {
+        const Src s0 = map_cell(U0 - 2, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+        nh = qin[s0.idx];
+        nhu = qin[s0.idx + tk.ps];
+        nhv = qin[s0.idx + 2 * tk.ps];
+        nbb = bpl[s0.idx];
+        nfx = s0.sx < 0.0;
+        nfy = s0.sy < 0.0;
+    }
+
     for (int t = 0; t < steps; ++t) {
         const bool live = t <= tlast;
         const int R = U0 - 2 + (live ? t : tlast);
         const bool interior_row = live && R >= U0 && R <= U1;
 
-        // ---- load row R of Q^n
-        const Src src = map_cell(R, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
-        const S h = qin[src.idx];
-        const S hu = S(src.sx) * qin[src.idx + tk.ps];
-        const S hv = S(src.sy) * qin[src.idx + 2 * tk.ps];
-        const S bb = bpl[src.idx];
+        // ---- row R of Q^n (loaded one iteration ago); flush the finished
+        // row, then issue the loads of the next one (every row index of the
+        // march stays inside the patch, one past the last iteration too)
+        const S h = nh;
+        const S hu = nfx ? -nhu : nhu;
+        const S hv = nfy ? -nhv : nhv;
+        const S bb = nbb;
+        if (po_wr) {
+            const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;
+            qout[o] = po[0];
+            qout[o + tk.ps] = po[1];
+            qout[o + 2 * tk.ps] = po[2];
+        }
+        po_wr = false;
+        {
+            const int Rn = U0 - 2 + (t + 1 <= tlast ? t + 1 : tlast);
+            const Src sn = map_cell(Rn, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+            nh = qin[sn.idx];
+            nhu = qin[sn.idx + tk.ps];
+            nhv = qin[sn.idx + 2 * tk.ps];
+            nbb = bpl[sn.idx];
+            nfx = sn.sx < 0.0;
+            nfy = sn.sy < 0.0;
+        }
         const TCell<S> tv0 = tcell(h, hu, hv, bb, false, P);
         const TCell<S> th0 = tcell(h, hu, hv, bb, true, P);
 
@@ -113,7 +156,11 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
         const Side<S> me = make_side<S>(h, hu, hv, bb, P);
         const Side<S> lf = side_up<S, false, SEG>(me, P);
         Waves<S> w;
-        riemann<S, false>(lf, me, P, w);
+        // lane 0's edge feeds no result; see quiet_edge
+        if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(lf, me)))
+            quiet_waves(lf, me, P, w);
+        else
+            riemann<S, false>(lf, me, P, w);
         S xam0[3], xap0[3];
         fluctuations(w, xam0, xap0);
         S xF0[3] = {0.0, 0.0, 0.0};
@@ -149,7 +196,11 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
         const Side<S> sy0 = make_side<S>(h, hv, hu, bb, P);
         if (t >= 1) {
             Waves<S> wy;
-            riemann<S, false>(sy1, sy0, P, wy);
+            // lane 0's y-edge feeds only lane 1, whose cell is not updated
+            if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(sy1, sy0)))
+                quiet_waves(sy1, sy0, P, wy);
+            else
+                riemann<S, false>(sy1, sy0, P, wy);
             const int E = R;
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
                 const S s = max_speed(wy);
@@ -158,7 +209,11 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
             // transverse parts of the x-edge amounts of rows R - 1 (up) and R
             // (down), all through the pair (R - 1, R) of this column
             S T0[4][3];
-            {
+            if (__all(lane == 0 || (zero3(aP1) && zero3(aM1) && zero3(aP0) && zero3(aM0)))) {
+                // nothing enters: every transverse part is a zero
+#pragma unroll
+                for (int i = 0; i < 4; ++i) T0[i][0] = T0[i][1] = T0[i][2] = S(0);
+            } else {
                 const TPair<S> pv = tpair(tv1, tv0, P);
                 transverse(tv1, tv0, pv, true, aP1, +1, P, T0[0]);
                 transverse(tv1, tv0, pv, true, aM1, +1, P, T0[1]);
@@ -201,7 +256,6 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
                 if (t >= 4) {
                     // F~ of the x-edge between columns c - 1 and c on row R - 2
                     const TCell<S> thl = tcell_up<SEG>(th2);
-                    const TPair<S> ph = tpair(thl, th2, P);
                     S bPl[3], bMl[3];
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
@@ -214,10 +268,17 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
                     const S a3[3] = {bP2[0], bP2[2], bP2[1]};
                     const S a4[3] = {bM1[0], bM1[2], bM1[1]};
                     S r1[3], r2[3], l1[3], l2[3];
-                    transverse(thl, th2, ph, true, a1, +1, P, r1);
-                    transverse(thl, th2, ph, true, a2, +1, P, r2);
-                    transverse(thl, th2, ph, false, a3, -1, P, l1);
-                    transverse(thl, th2, ph, false, a4, -1, P, l2);
+                    if (__all(lane == 0 ||
+                              (zero3(a1) && zero3(a2) && zero3(a3) && zero3(a4)))) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) r1[k] = r2[k] = l1[k] = l2[k] = S(0);
+                    } else {
+                        const TPair<S> ph = tpair(thl, th2, P);
+                        transverse(thl, th2, ph, true, a1, +1, P, r1);
+                        transverse(thl, th2, ph, true, a2, +1, P, r2);
+                        transverse(thl, th2, ph, false, a3, -1, P, l1);
+                        transverse(thl, th2, ph, false, a4, -1, P, l2);
+                    }
                     const S sy = 0.5 * lamy;
                     // back to (h, hu, hv): local (h, hv, hu)
                     const int perm[3] = {0, 2, 1};
@@ -249,12 +310,10 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
                         out[1] *= f;
                         out[2] *= f;
                     }
-                    if (wr) {
-                        const int64_t o = tk.off + (int64_t)(R - 2) * tk.pitch + c;
-                        qout[o] = out[0];
-                        qout[o + tk.ps] = out[1];
-                        qout[o + 2 * tk.ps] = out[2];
-                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) po[k] = out[k];
+                    po_row = R - 2;
+                    po_wr = wr;
                 }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -291,6 +350,12 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
         q1[0] = h;
         q1[1] = hu;
         q1[2] = hv;
+    }
+    if (po_wr) {
+        const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;
+        qout[o] = po[0];
+        qout[o + tk.ps] = po[1];
+        qout[o + 2 * tk.ps] = po[2];
     }
     MarchOut o;
     o.smx = smx;
