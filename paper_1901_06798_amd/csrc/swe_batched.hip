@@ -159,8 +159,12 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
 // runs substep `sub` of each task's patch (a patch with tref <= sub has no
 // such substep); substeps alternate between pool_out and pool_work so that
 // the last one lands in pool_out, as in the item kernel.
+// Register budget as for the single-patch step (FP32 four waves per SIMD,
+// FP64 three), one wave fewer with friction or with two segments per wave
+// (whose tasks are per lane rather than scalar).
 template <bool DEV, int SEG, bool FRIC>
-__global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_plain(BatchArgs a) {
+__global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == kWave ? 0 : 1))
+    k_plain(BatchArgs a) {
     constexpr int kSegPerWave = kWave / SEG;
     const int lane = threadIdx.x & (kWave - 1);
     const int seg_in_wave = lane / SEG;

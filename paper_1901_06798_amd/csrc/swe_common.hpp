@@ -103,6 +103,8 @@ template <int SEG = kWave>
 __device__ __forceinline__ float lane_down(float x) { return __shfl_down(x, 1, SEG); }
 #endif
 
+// The left neighbour's side: the fields side_base makes (velocities and
+// sqrt(h) are moved separately, once the neighbour has computed them).
 template <typename T, bool DEV = false, int SEG = kWave>
 __device__ __forceinline__ Side<T> side_up(const Side<T>& s, const DevParams& P) {
     Side<T> r;
@@ -110,9 +112,9 @@ __device__ __forceinline__ Side<T> side_up(const Side<T>& s, const DevParams& P)
     r.m = lane_up<SEG>(s.m);
     r.t = lane_up<SEG>(s.t);
     r.b = lane_up<SEG>(s.b);
-    r.u = lane_up<SEG>(s.u);
-    r.v = lane_up<SEG>(s.v);
-    r.sq = lane_up<SEG>(s.sq);
+    r.u = T(0);
+    r.v = T(0);
+    r.sq = T(0);
     r.c = lane_up<SEG>(s.c);
     r.eta = DEV ? lane_up<SEG>(s.eta) : T(0);
     r.dry = r.h <= T(P.drytol);

@@ -36,11 +36,18 @@ struct Prec<true> {
 // Side of a cell from its stored values (q0 = h, or eta' on the deviation
 // path, where h = eta' + sea_level - b).
 template <bool DEV, typename T, typename S>
-__device__ __forceinline__ Side<T> side_from(S q0, S m, S t, S b, const DevParams& P) {
-    if (!DEV) return make_side<T>(T(q0), T(m), T(t), T(b), P);
+__device__ __forceinline__ Side<T> side_base_from(S q0, S m, S t, S b, const DevParams& P) {
+    if (!DEV) return side_base<T>(T(q0), T(m), T(t), T(b), P);
     const T h = T(q0) + T(P.sea_level) - T(b);
-    Side<T> s = make_side<T>(h, T(m), T(t), T(b), P);
+    Side<T> s = side_base<T>(h, T(m), T(t), T(b), P);
     s.eta = T(q0);
+    return s;
+}
+
+template <bool DEV, typename T, typename S>
+__device__ __forceinline__ Side<T> side_from(S q0, S m, S t, S b, const DevParams& P) {
+    Side<T> s = side_base_from<DEV, T, S>(q0, m, t, b, P);
+    side_finish(s);
     return s;
 }
 
@@ -187,6 +194,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     S qm2[3] = {0, 0, 0};
     S qm2_b = S(0);
     Waves<S> wprev;
+    bool wprev_quiet = false;  // wprev came from the quiet-edge path (zero f-waves)
+    bool prev_full = false;    // prev carries its velocities and sqrt(h)
     S dprev[3] = {0, 0, 0};
     S ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
     // finished row held for one iteration: its stores are issued before the
@@ -243,33 +252,42 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         }
 
         // ---- x-sweep of row R: lane k solves the edge between columns k-1, k
-        const Side<S> me = side_from<DEV, S, S>(q0, hu, hv, bb, P);
-        const Side<S> lf = side_up<S, DEV, SEG>(me, P);
-        const S lf_m = DEV ? lane_up<SEG>(hu) : S(0), lf_t = DEV ? lane_up<SEG>(hv) : S(0);
+        Side<S> me = side_base_from<DEV, S, S>(q0, hu, hv, bb, P);
+        Side<S> lf = side_up<S, DEV, SEG>(me, P);
         Waves<S> w;
-        // lane 0's edge (its left cell lies outside the segment) feeds nothing
-        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, S>(lf, me)))
-            quiet_waves(lf, me, P, w);
-        else
-            solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
-        S am[3], ap[3];
-        fluctuations(w, am, ap);
-        S F[3] = {S(0), S(0), S(0)};
-        if (second) {
-            S dr[3], dl[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const S zr0 = lane_down<SEG>(w.z[p][0]);
-                const S zr1 = lane_down<SEG>(w.z[p][1]);
-                const S zr2 = lane_down<SEG>(w.z[p][2]);
-                dr[p] = w.z[p][0] * zr0 + w.z[p][1] * zr1 + w.z[p][2] * zr2;
-            }
-#pragma unroll
-            for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
-            correction(w, dl, dr, lamx, F);
-        }
         S qs[3];
-        {
+        // lane 0's edge (its left cell lies outside the segment) feeds nothing
+        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, S>(lf, me))) {
+            // zero f-waves: the fluctuations and corrections are +0 and the
+            // update returns Q itself, as the arithmetic below would
+            quiet_waves(lf, me, P, w);
+            qs[0] = q0;
+            qs[1] = hu;
+            qs[2] = hv;
+        } else {
+            side_finish(me);
+            lf.u = lane_up<SEG>(me.u);
+            lf.v = lane_up<SEG>(me.v);
+            lf.sq = lane_up<SEG>(me.sq);
+            const S lf_m = DEV ? lane_up<SEG>(hu) : S(0);
+            const S lf_t = DEV ? lane_up<SEG>(hv) : S(0);
+            solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
+            S am[3], ap[3];
+            fluctuations(w, am, ap);
+            S F[3] = {S(0), S(0), S(0)};
+            if (second) {
+                S dr[3], dl[3];
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    const S zr0 = lane_down<SEG>(w.z[p][0]);
+                    const S zr1 = lane_down<SEG>(w.z[p][1]);
+                    const S zr2 = lane_down<SEG>(w.z[p][2]);
+                    dr[p] = w.z[p][0] * zr0 + w.z[p][1] * zr1 + w.z[p][2] * zr2;
+                }
+#pragma unroll
+                for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
+                correction(w, dl, dr, lamx, F);
+            }
             const S qc[3] = {q0, hu, hv};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -285,31 +303,44 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         }
 
         // ---- y-sweep pipeline on the column of Q* (normal momentum hv)
-        const Side<S> cur = side_from<DEV, S, S>(qs[0], qs[2], qs[1], bb, P);
+        Side<S> cur = side_base_from<DEV, S, S>(qs[0], qs[2], qs[1], bb, P);
+        bool cur_full = false;
         if (t >= 1) {
             Waves<S> wy;
             // the y-sweep of a lane feeds only its own column's update
-            if (SWE_QUIET && __all(!upd_col || quiet_edge<DEV, S>(prev, cur)))
+            const bool yq = SWE_QUIET && __all(!upd_col || quiet_edge<DEV, S>(prev, cur));
+            if (yq) {
                 quiet_waves(prev, cur, P, wy);
-            else
+            } else {
+                // velocities and sqrt(h) only for a solve (same values whenever
+                // they are computed)
+                if (!prev_full) side_finish(prev);
+                side_finish(cur);
+                cur_full = true;
                 // Q* is cleaned up, so a dry side's stored momenta are 0 and
                 // the Sides carry the stored values for the FP64 islands too
                 solve_edge<DEV, S>(prev, cur, prev.m, prev.t, cur.m, cur.t, P, wy);
+            }
             const int E = R;  // edge between rows R - 1 and R
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
                 const S s = max_speed(wy);
                 smy = s > smy ? s : smy;
             }
+            // with either edge quiet the dot product is a zero, and a zero
+            // numerator gives theta = +-0, whose limiter value is +0 either way
             S dcur[3] = {S(0), S(0), S(0)};
-            if (second && t >= 2) {
+            if (second && t >= 2 && !yq && !wprev_quiet) {
 #pragma unroll
                 for (int p = 0; p < 3; ++p) dcur[p] = dot3(wprev.z[p], wy.z[p]);
             }
             if (t >= 3) {
-                // edge E - 1: fluctuations and correction
-                S am1[3], ap1[3], F1[3] = {S(0), S(0), S(0)};
-                fluctuations(wprev, am1, ap1);
-                if (second) correction(wprev, dprev, dcur, lamy, F1);
+                // edge E - 1: fluctuations and correction (+0 for a quiet edge)
+                S am1[3] = {S(0), S(0), S(0)}, ap1[3] = {S(0), S(0), S(0)};
+                S F1[3] = {S(0), S(0), S(0)};
+                if (!wprev_quiet) {
+                    fluctuations(wprev, am1, ap1);
+                    if (second) correction(wprev, dprev, dcur, lamy, F1);
+                }
                 if (t >= 4) {
                     // finish row R - 2 between edges E - 2 and E - 1
                     S qn[3];
@@ -346,6 +377,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 #pragma unroll
             for (int p = 0; p < 3; ++p) dprev[p] = dcur[p];
             wprev = wy;
+            wprev_quiet = yq;
         }
         // Q* of row R - 1 in y order (h or eta', hv, hu) is what `prev` was
         // made from: after the cleanup a dry cell carries no momentum, so
@@ -355,6 +387,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         qm2[2] = prev.t;
         qm2_b = prev.b;
         prev = cur;
+        prev_full = cur_full;
     }
     if (po_wr) {
         const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;

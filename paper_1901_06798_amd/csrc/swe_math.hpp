@@ -51,28 +51,38 @@ struct Side {
     bool dry;
 };
 
+// The fields a quiet-edge test and the wave speeds need: depth, momenta, bed,
+// dry flag and celerity.  side_finish adds the velocities and sqrt(h) that
+// the Riemann solve needs; make_side is both.
 template <typename T>
-__device__ __forceinline__ Side<T> make_side(T h, T m, T t, T b, const DevParams& P) {
+__device__ __forceinline__ Side<T> side_base(T h, T m, T t, T b, const DevParams& P) {
     Side<T> s;
     s.h = h;
     s.b = b;
     s.eta = T(0);
+    s.u = T(0);
+    s.v = T(0);
+    s.sq = T(0);
     s.dry = h <= T(P.drytol);
-    if (s.dry) {
-        s.m = T(0);
-        s.t = T(0);
-        s.u = T(0);
-        s.v = T(0);
-        s.sq = T(0);
-        s.c = T(0);
-    } else {
-        s.m = m;
-        s.t = t;
-        s.u = qdiv(m, h);
-        s.v = qdiv(t, h);
-        s.sq = qsqrt(h);
-        s.c = qsqrt(T(P.g) * h);
+    s.m = s.dry ? T(0) : m;
+    s.t = s.dry ? T(0) : t;
+    s.c = s.dry ? T(0) : qsqrt(T(P.g) * h);
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void side_finish(Side<T>& s) {
+    if (!s.dry) {
+        s.u = qdiv(s.m, s.h);
+        s.v = qdiv(s.t, s.h);
+        s.sq = qsqrt(s.h);
     }
+}
+
+template <typename T>
+__device__ __forceinline__ Side<T> make_side(T h, T m, T t, T b, const DevParams& P) {
+    Side<T> s = side_base(h, m, t, b, P);
+    side_finish(s);
     return s;
 }
 

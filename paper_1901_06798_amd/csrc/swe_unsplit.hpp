@@ -154,13 +154,17 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
 
         // ---- x-edges of row R
         const Side<S> me = make_side<S>(h, hu, hv, bb, P);
-        const Side<S> lf = side_up<S, false, SEG>(me, P);
+        Side<S> lf = side_up<S, false, SEG>(me, P);
         Waves<S> w;
         // lane 0's edge feeds no result; see quiet_edge
-        if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(lf, me)))
+        if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(lf, me))) {
             quiet_waves(lf, me, P, w);
-        else
+        } else {
+            lf.u = lane_up<SEG>(me.u);
+            lf.v = lane_up<SEG>(me.v);
+            lf.sq = lane_up<SEG>(me.sq);
             riemann<S, false>(lf, me, P, w);
+        }
         S xam0[3], xap0[3];
         fluctuations(w, xam0, xap0);
         S xF0[3] = {0.0, 0.0, 0.0};
