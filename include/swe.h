@@ -167,6 +167,34 @@ int swe_patch_retake(const swe_params *p, const swe_patch *patch, const void *q_
                      const void *b, const double *dt, double *smax, uint32_t *status,
                      const uint32_t *retake, void *stream);
 
+/* Number of strip tasks (waves) of one step of `patch` (host), or SWE_EINVAL
+ * for a bad patch.  Sizes the schedule buffer of swe_patch_step_sched. */
+int32_t swe_patch_tasks(const swe_patch *patch);
+
+/* swe_patch_step with its tasks launched in a given order (scheduling only:
+ * q_out, smax and status are bitwise those of swe_patch_step), meant for
+ * heaviest first.  Tasks over water at rest or dry land skip their Riemann
+ * solves (Sec. 2: such edges carry no waves) and end several times sooner
+ * than tasks under a moving wave; launched in index order, a few long tasks
+ * start late and the launch ends on them.
+ * sched: device uint32_t[2 n], n = swe_patch_tasks(patch), that the caller
+ * allocates once per patch, fills with zeros and passes to every step of that
+ * patch; between calls the library owns its contents.  sched[0, n) is the
+ * launch order: position k runs task sched[k] - 1 (task k where sched[k] is
+ * 0, as after the zero fill, or out of range).  Each task writes its work
+ * (row sweeps that needed solves) into sched[n + task].  NULL sched is an
+ * error. */
+int swe_patch_step_sched(const swe_params *p, const swe_patch *patch, const void *q_in,
+                         void *q_out, const void *b, const double *dt, double *smax,
+                         uint32_t *status, uint32_t *sched, void *stream);
+
+/* Launch order for the next swe_patch_step_sched of `patch` (host) from the
+ * work its last one recorded: sched[0, n) = the tasks by work, largest
+ * first, ties by task index (one small launch; work above 127 sorts as 127).
+ * Enqueue it after the step on the same stream, every step or every few
+ * steps.  NULL sched is an error. */
+int swe_patch_order(const swe_patch *patch, uint32_t *sched, void *stream);
+
 /* Water volume sum(h) dx dy over the interior of each patch, in FP64,
  * written to mass_patch[k] (deterministic order).  In SWE_F32_DEV, h is
  * eta' + sea_level - b accumulated in FP64. */

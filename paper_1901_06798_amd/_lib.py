@@ -100,6 +100,11 @@ def lib():
         L.swe_patch_retake.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                        _P, _P]
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
+        L.swe_patch_tasks.argtypes = [ctypes.POINTER(swe_patch)]
+        L.swe_patch_tasks.restype = i32
+        L.swe_patch_step_sched.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
+                                           _P, _P]
+        L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
@@ -111,7 +116,7 @@ def lib():
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
                      "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
-                     "swe_batched_retake"):
+                     "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -131,6 +136,23 @@ def swe_patch_step(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, 
                    smax: int, status: int, stream: int = 0) -> None:
     _check(lib().swe_patch_step(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
                                 status, stream), "swe_patch_step")
+
+
+def swe_patch_tasks(pt: swe_patch) -> int:
+    n = lib().swe_patch_tasks(ctypes.byref(pt))
+    if n < 0:
+        _check(n, "swe_patch_tasks")
+    return n
+
+
+def swe_patch_step_sched(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                         smax: int, status: int, sched: int, stream: int = 0) -> None:
+    _check(lib().swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
+                                      smax, status, sched, stream), "swe_patch_step_sched")
+
+
+def swe_patch_order(pt: swe_patch, sched: int, stream: int = 0) -> None:
+    _check(lib().swe_patch_order(ctypes.byref(pt), sched, stream), "swe_patch_order")
 
 
 def swe_ghost_fill(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,

@@ -159,6 +159,7 @@ struct Task {
 struct MarchOut {
     double smx, smy;
     uint32_t clamps, flags;
+    uint32_t work;  // row sweeps (x or y) that needed Riemann solves
 };
 
 // March one strip task.  `steps` is the number of row iterations every lane
@@ -186,6 +187,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 
     S smx = S(0), smy = S(0);
     uint32_t clamps = 0, flags = 0;
+    uint32_t work = 0;
 
     // rolling state of the y-pipeline (row R - 1, R - 2 of Q*, edge E - 1)
     Side<S> prev;
@@ -265,6 +267,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             qs[1] = hu;
             qs[2] = hv;
         } else {
+            ++work;
             side_finish(me);
             lf.u = lane_up<SEG>(me.u);
             lf.v = lane_up<SEG>(me.v);
@@ -312,6 +315,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             if (yq) {
                 quiet_waves(prev, cur, P, wy);
             } else {
+                ++work;
                 // velocities and sqrt(h) only for a solve (same values whenever
                 // they are computed)
                 if (!prev_full) side_finish(prev);
@@ -400,6 +404,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     o.smy = double(smy);
     o.clamps = clamps;
     o.flags = flags;
+    o.work = work;
     return o;
 }
 

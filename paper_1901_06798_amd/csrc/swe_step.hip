@@ -43,7 +43,18 @@ struct StepArgs {
     int8_t bc[4];
     DevParams P;
     const uint32_t* gate;  // retake launch: run only if *gate != 0; NULL: always
+    // launch order (NULL: task k at position k): position k runs task
+    // order[k] - 1, or task k where order[k] is 0 or out of range
+    const uint32_t* order;
+    uint32_t* cost;  // per task, the march's solved row sweeps (NULL: not kept)
 };
+
+// Task at launch position `pos` (wave-uniform).
+__device__ __forceinline__ int task_at(const StepArgs& a, int pos) {
+    if (!a.order) return pos;
+    const uint32_t v = a.order[pos];
+    return (v != 0 && v <= (uint32_t)a.nitems) ? (int)v - 1 : pos;
+}
 
 // One patch, one wave64 per (strip, chunk of H rows).
 // Waves per SIMD the register budget is fitted to, without spilling: the
@@ -54,10 +65,11 @@ __global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(S
     const int lane = threadIdx.x & (kWave - 1);
     // the task, and with it the row loop's trip count, is the same for the
     // whole wave: keep it in scalar registers
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
-                                                    (threadIdx.x / kWave));
-    if (item >= a.nitems) return;  // whole wave leaves together
+    const int pos = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
+                                                   (threadIdx.x / kWave));
+    if (pos >= a.nitems) return;  // whole wave leaves together
     if (a.gate && *a.gate == 0) return;  // no step to retake
+    const int item = __builtin_amdgcn_readfirstlane(task_at(a, pos));
     Task tk;
     tk.qin = a.qin;
     tk.qout = a.qout;
@@ -81,6 +93,7 @@ __global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(S
     if (lane == 0) {
         atomic_max_nonneg(&a.smax[0], wx);
         atomic_max_nonneg(&a.smax[1], wy);
+        if (a.cost) a.cost[item] = o.work;
     }
     if (o.clamps) atomicAdd(&a.status[1], o.clamps);
     if (o.flags) atomicOr(&a.status[0], o.flags);
@@ -95,10 +108,11 @@ template __global__ void k_split<true, true>(StepArgs);
 template <bool FRIC>
 __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_order) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
-                                                    (threadIdx.x / kWave));
-    if (item >= a.nitems) return;
+    const int pos = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) +
+                                                   (threadIdx.x / kWave));
+    if (pos >= a.nitems) return;
     if (a.gate && *a.gate == 0) return;  // no step to retake
+    const int item = __builtin_amdgcn_readfirstlane(task_at(a, pos));
     Task tk;
     tk.qin = a.qin;
     tk.qout = a.qout;
@@ -123,6 +137,7 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     if (lane == 0) {
         atomic_max_nonneg(&a.smax[0], wx);
         atomic_max_nonneg(&a.smax[1], wy);
+        if (a.cost) a.cost[item] = o.work;
     }
     if (o.clamps) atomicAdd(&a.status[1], o.clamps);
     if (o.flags) atomicOr(&a.status[0], o.flags);
@@ -130,6 +145,124 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
 
 template __global__ void k_unsplit<false>(StepArgs, int);
 template __global__ void k_unsplit<true>(StepArgs, int);
+
+// Launch order of the next step of a patch: its tasks by the work their
+// marches recorded, largest first, ties by task index (the order is a
+// function of the work alone).  Tasks over water at rest or dry land skip
+// their solves and finish several times faster than tasks under a moving
+// wave; launched in index order, some long tasks start late and the launch
+// ends on them.  Heaviest first, it ends on short tasks.
+//
+// A counting sort over kOrderBins bins of `width` work units, in one
+// workgroup.  A round covers up to kOrderRound tasks, kOrderPer consecutive
+// ones per thread.  C[b][t] counts the tasks of bin b held by thread t; an
+// exclusive scan of C read bins descending, then threads ascending, gives
+// every (bin, thread) pair the number of tasks placed before its first one
+// within the round.  Patches with more than one round first count every bin
+// over all tasks (start[]) and carry a per-bin cursor across rounds.
+constexpr int kOrderBins = 16;
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderPer = 16;
+constexpr int kOrderRound = kOrderThreads * kOrderPer;
+constexpr int kOrderWaves = kOrderThreads / kWave;
+constexpr int kOrderRowThreads = kOrderThreads / kOrderPer;  // threads per bin row
+static_assert(kOrderWaves == kOrderBins, "one wave per bin in the count pass");
+
+__device__ __forceinline__ int order_bin(uint32_t c, uint32_t width) {
+    const uint32_t q = c / width;
+    return q < (uint32_t)kOrderBins ? (int)q : kOrderBins - 1;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_order(uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ cost,
+                                                         int n, uint32_t width) {
+    __shared__ uint16_t C[kOrderBins][kOrderThreads];
+    __shared__ uint32_t wsum[kOrderWaves];
+    __shared__ uint32_t start[kOrderBins], cursor[kOrderBins], rowbase[kOrderBins];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    const bool multi = n > kOrderRound;
+    if (multi) {
+        for (int bn = 0; bn < kOrderBins; ++bn) C[bn][t] = 0;
+        for (int i = t; i < n; i += kOrderThreads) {
+            const int bn = order_bin(cost[i], width);
+            C[bn][t] = (uint16_t)(C[bn][t] + 1);
+        }
+        __syncthreads();
+        uint32_t sum = 0;  // wave wv totals bin wv
+        for (int k = lane; k < kOrderThreads; k += kWave) sum += C[wv][k];
+        sum = wave_inclusive_sum(sum);
+        if (lane == kWave - 1) wsum[wv] = sum;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t run = 0;
+            for (int bn = kOrderBins - 1; bn >= 0; --bn) {
+                start[bn] = run;
+                run += wsum[bn];
+            }
+        }
+    }
+    if (t < kOrderBins) cursor[t] = 0;
+    for (int r0 = 0; r0 < n; r0 += kOrderRound) {
+        const int R = min(n - r0, kOrderRound);
+        const int K = (R + kOrderThreads - 1) / kOrderThreads;
+        int bins[kOrderPer];
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) {
+            const int i = t * K + j;
+            bins[j] = (j < K && i < R) ? order_bin(cost[r0 + i], width) : -1;
+        }
+        __syncthreads();  // the last pass over C has ended
+#pragma unroll
+        for (int bn = 0; bn < kOrderBins; ++bn) C[bn][t] = 0;
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j)
+            if (bins[j] >= 0) C[bins[j]][t] = (uint16_t)(C[bins[j]][t] + 1);
+        __syncthreads();
+        // thread t scans kOrderPer consecutive entries of bin row fb
+        const int fb = kOrderBins - 1 - t / kOrderRowThreads;
+        const int c0 = (t % kOrderRowThreads) * kOrderPer;
+        uint32_t v[kOrderPer], own = 0;
+#pragma unroll
+        for (int e = 0; e < kOrderPer; ++e) {
+            v[e] = C[fb][c0 + e];
+            own += v[e];
+        }
+        const uint32_t incl = wave_inclusive_sum(own);
+        if (lane == kWave - 1) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - own;
+        for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+        for (int e = 0; e < kOrderPer; ++e) {
+            C[fb][c0 + e] = (uint16_t)run;
+            run += v[e];
+        }
+        __syncthreads();
+        if (t < kOrderBins) rowbase[t] = C[t][0];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) {
+            const int bn = bins[j];
+            if (bn < 0) continue;
+            const uint32_t within = (uint32_t)C[bn][t] - (multi ? rowbase[bn] : 0u);
+            const uint32_t pos = (multi ? start[bn] + cursor[bn] : 0u) + within;
+            C[bn][t] = (uint16_t)(C[bn][t] + 1);
+            order[pos] = (uint32_t)(r0 + t * K + j) + 1u;
+        }
+        __syncthreads();
+        if (t < kOrderBins) cursor[t] += (uint32_t)C[t][kOrderThreads - 1] - rowbase[t];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Batched helpers: one block row (blockIdx.y) per patch.
@@ -410,9 +543,16 @@ const char* swe_last_error(void) { return g_err.c_str(); }
 
 const char* swe_version(void) { return "swe-gfx950 0.1"; }
 
+// Strip tasks of one patch step (the launch's waves).
+static int patch_tasks(const swe_patch* patch) {
+    const int H = rows_per_chunk(patch->my);
+    const int nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
+    return nstrips * ((patch->my + H - 1) / H);
+}
+
 static int patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                       const void* b, const double* dt, double* smax, uint32_t* status,
-                      const uint32_t* gate, void* stream) {
+                      const uint32_t* gate, uint32_t* sched, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_patch(patch))) return rc;
@@ -457,6 +597,8 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     for (int s = 0; s < 4; ++s) a.bc[s] = patch->bc[s];
     a.P = dev_params(p);
     a.gate = gate;
+    a.order = sched;
+    a.cost = sched ? sched + a.nitems : nullptr;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid(blocks), block(64 * waves_per_block);
@@ -477,7 +619,32 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
 int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                    const void* b, const double* dt, double* smax, uint32_t* status,
                    void* stream) {
-    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, stream);
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, nullptr, stream);
+}
+
+int32_t swe_patch_tasks(const swe_patch* patch) {
+    const int rc = check_patch(patch);
+    return rc ? rc : patch_tasks(patch);
+}
+
+int swe_patch_step_sched(const swe_params* p, const swe_patch* patch, const void* q_in,
+                         void* q_out, const void* b, const double* dt, double* smax,
+                         uint32_t* status, uint32_t* sched, void* stream) {
+    if (!sched) return fail(SWE_EINVAL, "swe_patch_step_sched: null schedule buffer");
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched, stream);
+}
+
+int swe_patch_order(const swe_patch* patch, uint32_t* sched, void* stream) {
+    int rc = check_patch(patch);
+    if (rc) return rc;
+    if (!sched) return fail(SWE_EINVAL, "swe_patch_order: null schedule buffer");
+    const int n = patch_tasks(patch);
+    // a task marches H + 5 rows, each with an x- and a y-sweep
+    const int most = 2 * (rows_per_chunk(patch->my) + 5);
+    const uint32_t width = (uint32_t)((most + swe::kOrderBins) / swe::kOrderBins);
+    hipLaunchKernelGGL(swe::k_order, dim3(1), dim3(swe::kOrderThreads), 0,
+                       static_cast<hipStream_t>(stream), sched, sched + n, n, width);
+    return check_launch("swe_patch_order");
 }
 
 int swe_patch_retake(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
@@ -486,7 +653,7 @@ int swe_patch_retake(const swe_params* p, const swe_patch* patch, const void* q_
     if (!retake) return fail(SWE_EINVAL, "swe_patch_retake: null retake flags");
     if (patch && patch->group < 0) return fail(SWE_EINVAL, "swe_patch_retake: negative group");
     return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
-                      patch ? retake + patch->group : retake, stream);
+                      patch ? retake + patch->group : retake, nullptr, stream);
 }
 
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,

@@ -87,6 +87,7 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
 
     S smx = 0.0, smy = 0.0;
     uint32_t clamps = 0, flags = 0;
+    uint32_t work = 0;
 
     // state carried between rows (suffix 1: row R - 1, suffix 2: row R - 2)
     TCell<S> tv1{}, th1{}, th2{};    // vertical-split view of row R-1; horizontal view of R-1, R-2
@@ -160,6 +161,7 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
         if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(lf, me))) {
             quiet_waves(lf, me, P, w);
         } else {
+            ++work;
             lf.u = lane_up<SEG>(me.u);
             lf.v = lane_up<SEG>(me.v);
             lf.sq = lane_up<SEG>(me.sq);
@@ -203,8 +205,10 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
             // lane 0's y-edge feeds only lane 1, whose cell is not updated
             if (SWE_QUIET && __all(lane == 0 || quiet_edge<false, S>(sy1, sy0)))
                 quiet_waves(sy1, sy0, P, wy);
-            else
+            else {
+                ++work;
                 riemann<S, false>(sy1, sy0, P, wy);
+            }
             const int E = R;
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
                 const S s = max_speed(wy);
@@ -366,6 +370,7 @@ __device__ __forceinline__ MarchOut march_unsplit(const Task& tk, const DevParam
     o.smy = smy;
     o.clamps = clamps;
     o.flags = flags;
+    o.work = work;
     return o;
 }
 

@@ -32,7 +32,8 @@ class PatchSolver:
     """One patch on one GPU with the CFL rule of Sec. 2 (dt from the previous
     step's speeds, a step above cfl_max is retaken with the reduced dt)."""
 
-    def __init__(self, pb: Problem, params: L.swe_params | None = None, device: str = "cuda:0"):
+    def __init__(self, pb: Problem, params: L.swe_params | None = None, device: str = "cuda:0",
+                 ordered: bool = True, order_every: int = 4):
         if not torch.cuda.is_available():
             raise L.SweError("PatchSolver needs a GPU (torch.cuda is not available)")
         L.lib()
@@ -56,6 +57,13 @@ class PatchSolver:
         self.smax = torch.zeros(2, dtype=f64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.retake = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        # launch order of the step's tasks, heaviest first from the last step
+        # (re-sorted after the first step, then every order_every steps: the
+        # work of a task changes slowly as the waves travel)
+        self.sched = (torch.zeros(2 * L.swe_patch_tasks(self.pt), dtype=torch.int32,
+                                  device=self.dev) if ordered else None)
+        self.order_every = max(1, int(order_every))
+        self.steps_launched = 0
         self.upload(pb)
 
     # -- layout helpers ------------------------------------------------------
@@ -99,6 +107,29 @@ class PatchSolver:
         L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
                          self.dt.data_ptr(), self.status.data_ptr(), 0, 1, self.stream)
 
+    def launch_step(self, qi: int, qo: int, dt: int, stream: int | None = None) -> None:
+        """The step launch alone: q_out = step(q_in, *dt)."""
+        st = self.stream if stream is None else stream
+        if self.sched is not None:
+            L.swe_patch_step_sched(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
+                                   self.smax.data_ptr(), self.status.data_ptr(),
+                                   self.sched.data_ptr(), st)
+        else:
+            L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
+                             self.smax.data_ptr(), self.status.data_ptr(), st)
+
+    def launch_order(self, stream: int | None = None) -> None:
+        """Next step's launch order from this step's work (ordered solvers)."""
+        if self.sched is not None:
+            L.swe_patch_order(self.pt, self.sched.data_ptr(),
+                              self.stream if stream is None else stream)
+
+    def after_step(self, stream: int | None = None) -> None:
+        """Count a step launch and re-sort the launch order when it is due."""
+        self.steps_launched += 1
+        if self.steps_launched % self.order_every == 1 or self.order_every == 1:
+            self.launch_order(stream)
+
     def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True,
                      retake: bool = True) -> None:
         """One step q[cur] -> q[1 - cur]; dt from dt_ptr (device) or self.dt.
@@ -107,8 +138,8 @@ class PatchSolver:
         (a retaken step still above the limit is flagged CFL_EXCEEDED)."""
         qi, qo = self.q[self.cur].data_ptr(), self.q[1 - self.cur].data_ptr()
         dt = dt_ptr if dt_ptr is not None else self.dt.data_ptr()
-        L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt, self.smax.data_ptr(),
-                         self.status.data_ptr(), self.stream)
+        self.launch_step(qi, qo, dt)
+        self.after_step()
         if cfl:
             rt = self.retake.data_ptr() if retake else 0
             L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),

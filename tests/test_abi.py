@@ -97,3 +97,29 @@ def test_argument_errors_are_reported_on_the_host(L):
                               fake, fake, fake, fake, None) == L.SWE_EINVAL
     with pytest.raises(L.SweError):
         L.swe_patch_step(p, bad, 0x1000, 0x9000000, 0x1000, 0x1000, 0x1000, 0x1000)
+
+
+def test_patch_tasks_counts_the_strip_tasks(L):
+    # strips of 60 updated columns, chunks of 32 rows (ragged ends included)
+    assert L.swe_patch_tasks(L.patch(4096, 4096, 4112, 250.0, 250.0)) == 69 * 128
+    assert L.swe_patch_tasks(L.patch(70, 70, 80, 1.0, 1.0)) == 2 * 3
+    assert L.swe_patch_tasks(L.patch(60, 32, 64, 1.0, 1.0)) == 1
+    assert L.swe_patch_tasks(L.patch(61, 33, 80, 1.0, 1.0)) == 4
+    assert L.lib().swe_patch_tasks(ctypes.byref(L.patch(10, 10, 12, 1.0, 1.0))) == L.SWE_EINVAL
+    with pytest.raises(L.SweError):
+        L.swe_patch_tasks(L.patch(10, 10, 12, 1.0, 1.0))
+
+
+def test_sched_step_rejects_a_null_schedule(L):
+    lib = L.lib()
+    p = L.params()
+    pt = L.patch(10, 10, 14, 1.0, 1.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), fake,
+                                    ctypes.c_void_p(0x9000000), fake, fake, fake, fake, None,
+                                    None) == L.SWE_EINVAL
+    assert b"schedule" in lib.swe_last_error()
+    assert lib.swe_patch_order(ctypes.byref(pt), None, None) == L.SWE_EINVAL
+    assert b"schedule" in lib.swe_last_error()
+    bad = L.patch(10, 10, 12, 1.0, 1.0)
+    assert lib.swe_patch_order(ctypes.byref(bad), ctypes.c_void_p(0x1000), None) == L.SWE_EINVAL
