@@ -54,6 +54,21 @@ __device__ __forceinline__ Src map_cell(int R, int c, int mx, int my, int pitch,
     return s;
 }
 
+// map_cell when the caller's wave-wide vote found every lane's cell inside
+// its patch: such a cell is stored where it lies (the vote keeps the branch
+// uniform, so interior rows skip the boundary cases).
+__device__ __forceinline__ Src map_cell_voted(bool all_inside, int R, int c, int mx, int my,
+                                              int pitch, int64_t off, const int8_t* bc) {
+    if (all_inside) {
+        Src s;
+        s.idx = off + (int64_t)R * pitch + c;
+        s.sx = 1.0;
+        s.sy = 1.0;
+        return s;
+    }
+    return map_cell(R, c, mx, my, pitch, off, bc);
+}
+
 // Lane moves within a segment of SEG lanes (SEG = 64: the whole wave):
 // up(x) gives lane k the value of lane k - 1, down(x) the value of lane k + 1.
 // What the first lane of a segment receives from up(), and the last from

@@ -162,15 +162,87 @@ struct MarchOut {
     uint32_t work;  // row sweeps (x or y) that needed Riemann solves
 };
 
+// ---- LDS row ring: rows of the strip loaded RING rows ahead of their use by
+// direct global-to-LDS loads, which occupy no vector registers while in
+// flight.  Each wave owns RING slots of 4 planes x kWave elements (h or eta',
+// hu, hv, b).  A dword load writes lane i's dword to LDS at M0 + 4 i; an FP64
+// plane row (kWave doubles) therefore takes two loads, each lane fetching one
+// half of a double.  Every element's address comes from map_cell, so ghost
+// cells of physical boundaries are synthesised as in the register path
+// (mirrored momenta change sign when read).  The loads are issued as inline
+// assembly, so the compiler does not track them: the march waits for them
+// itself (vector-memory loads complete in issue order, so "at most N
+// outstanding" with N = the loads issued after a row's guarantees that row).
+
+template <int N>
+__device__ __forceinline__ void wait_vmem_at_most() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+__device__ __forceinline__ void lds_dword_load(const void* src, uint32_t lds_addr) {
+    asm volatile("global_load_lds_dword %0, off" ::"v"(src), "{m0}"(lds_addr) : "memory");
+}
+
+template <typename S>
+struct RingRow;
+template <>
+struct RingRow<double> {
+    static constexpr int kLoads = 8;  // dword loads per row: 4 planes x 2 halves
+};
+template <>
+struct RingRow<float> {
+    static constexpr int kLoads = 4;
+};
+
+// Issue the loads of strip row `row` into ring slot `slot`.  The slot's
+// previous contents must have been read: wait for outstanding LDS reads first.
+template <typename S>
+__device__ __forceinline__ void ring_issue(const Task& tk, int row, int lane, uint32_t slot_lds,
+                                           bool cols_in) {
+    const S* qin = static_cast<const S*>(tk.qin);
+    const S* bpl = static_cast<const S*>(tk.b);
+    const bool inside = __all(cols_in && row >= 2 && row <= tk.my + 1);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    constexpr uint32_t kPlane = kWave * sizeof(S);
+    if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            int ce = tk.c0 + k * (kWave / 2) + (lane >> 1);
+            ce = ce < tk.mx + 3 ? ce : tk.mx + 3;
+            const Src sr = map_cell_voted(inside, row, ce, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+            const int half = 4 * (lane & 1);
+            const uint32_t m = slot_lds + k * (kWave * 4);
+            lds_dword_load(reinterpret_cast<const char*>(qin + sr.idx) + half, m);
+            lds_dword_load(reinterpret_cast<const char*>(qin + sr.idx + tk.ps) + half, m + kPlane);
+            lds_dword_load(reinterpret_cast<const char*>(qin + sr.idx + 2 * tk.ps) + half,
+                           m + 2 * kPlane);
+            lds_dword_load(reinterpret_cast<const char*>(bpl + sr.idx) + half, m + 3 * kPlane);
+        }
+    } else {
+        int ce = tk.c0 + lane;
+        ce = ce < tk.mx + 3 ? ce : tk.mx + 3;
+        const Src sr = map_cell_voted(inside, row, ce, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+        lds_dword_load(qin + sr.idx, slot_lds);
+        lds_dword_load(qin + sr.idx + tk.ps, slot_lds + kPlane);
+        lds_dword_load(qin + sr.idx + 2 * tk.ps, slot_lds + 2 * kPlane);
+        lds_dword_load(bpl + sr.idx, slot_lds + 3 * kPlane);
+    }
+}
+
 // March one strip task.  `steps` is the number of row iterations every lane
 // of the wave executes (the largest over the wave's segments); a lane whose
 // own strip is shorter repeats its last row with writes and reports masked.
 // FRIC: the Manning friction step is compiled in (the caller picks it when
 // the friction coefficient is positive), so the step without friction
 // carries none of its registers.
-template <bool DEV, int SEG, bool FRIC>
+// RING > 0: rows come through an LDS ring of RING slots at `ring` (this
+// wave's RING x 4 x kWave elements; SEG must be kWave); RING = 0: each row is
+// loaded into registers one iteration ahead.
+template <bool DEV, int SEG, bool FRIC, int RING = 0>
 __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, int lane_in_seg,
-                                          int steps) {
+                                          int steps, typename Prec<DEV>::S* ring = nullptr) {
+    static_assert(RING == 0 || SEG == kWave, "the row ring serves whole-wave strips");
+    static_assert((RING & (RING - 1)) == 0, "ring depth is a power of two");
     using S = typename Prec<DEV>::S;
     const S* __restrict__ qin = static_cast<const S*>(tk.qin);
     S* __restrict__ qout = static_cast<S*>(tk.qout);
@@ -184,6 +256,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     const S lamx = S(tk.dt / tk.dx), lamy = S(tk.dt / tk.dy);
     const bool second = P.order >= 2;
     const int tlast = U1 - U0 + 4;
+    // the segment's columns all lie inside the patch (no ghost column)
+    const bool cols_in = tk.c0 >= 2 && tk.c0 + SEG - 1 <= tk.mx + 1;
 
     S smx = S(0), smy = S(0);
     uint32_t clamps = 0, flags = 0;
@@ -214,7 +288,15 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     // the loads before then.
     S nq0, nhu, nhv, nbb;
     bool nfx, nfy;
-    {
+    uint32_t ring_lds = 0;
+    if constexpr (RING > 0) {
+        ring_lds = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(
+            reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) S*)ring)));
+#pragma unroll
+        for (int k = 0; k < RING; ++k)
+            ring_issue<S>(tk, U0 - 2 + (k <= tlast ? k : tlast), lane,
+                          ring_lds + k * (4 * kWave * sizeof(S)), cols_in);
+    } else {
         const Src s0 = map_cell(U0 - 2, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
         nq0 = qin[s0.idx];
         nhu = qin[s0.idx + tk.ps];
@@ -231,10 +313,26 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 
         // ---- row R (ghosts synthesised for physical boundaries), loaded one
         // iteration ago; then issue the loads of the next row
-        const S q0 = nq0;
-        const S hu = nfx ? -nhu : nhu;
-        const S hv = nfy ? -nhv : nhv;
-        const S bb = nbb;
+        S q0, hu, hv, bb;
+        if constexpr (RING > 0) {
+            // row t is complete once at most the loads of rows t + 1 ..
+            // t + RING - 1 are outstanding
+            wait_vmem_at_most<(RING - 1) * RingRow<S>::kLoads>();
+            const S* rs = ring + (t & (RING - 1)) * (4 * kWave);
+            const Src sg = map_cell_voted(__all(cols_in && R >= 2 && R <= tk.my + 1), R, cc,
+                                          tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
+            q0 = rs[lane];
+            const S rhu = rs[kWave + lane];
+            const S rhv = rs[2 * kWave + lane];
+            bb = rs[3 * kWave + lane];
+            hu = sg.sx < 0.0 ? -rhu : rhu;
+            hv = sg.sy < 0.0 ? -rhv : rhv;
+        } else {
+            q0 = nq0;
+            hu = nfx ? -nhu : nhu;
+            hv = nfy ? -nhv : nhv;
+            bb = nbb;
+        }
         if (po_wr) {
             const int64_t o = tk.off + (int64_t)po_row * tk.pitch + c;
             qout[o] = po[0];
@@ -242,7 +340,12 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             qout[o + 2 * tk.ps] = po[2];
         }
         po_wr = false;
-        {
+        if constexpr (RING > 0) {
+            // row t + RING into the slot just read
+            const int ta = t + RING;
+            ring_issue<S>(tk, U0 - 2 + (ta <= tlast ? ta : tlast), lane,
+                          ring_lds + (t & (RING - 1)) * (4 * kWave * sizeof(S)), cols_in);
+        } else {
             const int Rn = U0 - 2 + (t + 1 <= tlast ? t + 1 : tlast);
             const Src sn = map_cell(Rn, cc, tk.mx, tk.my, tk.pitch, tk.off, tk.bc);
             nq0 = qin[sn.idx];
@@ -399,6 +502,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         qout[o + tk.ps] = po[1];
         qout[o + 2 * tk.ps] = po[2];
     }
+    // no ring load may still be writing LDS when the wave moves on
+    if constexpr (RING > 0) wait_vmem_at_most<0>();
     MarchOut o;
     o.smx = double(smx);
     o.smy = double(smy);
