@@ -478,9 +478,9 @@ def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0, budget_gb: f
     srv = ScenarioServer(L.params(precision=L.F32_DEV), hbm_budget=int(budget_gb * (1 << 30)),
                          max_slots=max_slots, steps_per_round=steps_per_round)
     # warm the kernels outside the measured stream
-    srv.serve([Scenario(-1, 0.0, W.scenario(0, n=256, nsteps=50), 50)])
+    srv.serve([Scenario(-1, 0.0, W.scenario(0, n=256, nsteps=50), 50)], label="serve warm-up")
     log(f"[bench] serving: {nreq} requests at {rate}/s, budget {budget_gb} GB")
-    out = srv.serve(reqs, warmup=warmup)
+    out = srv.serve(reqs, warmup=warmup, label=f"serve {budget_gb:g} GB")
     done = out.pop("done")
     waits = [sc.admitted - sc.arrival for sc in done if sc.rid >= warmup]
     out.update({"rate_per_s": rate, "steps_per_request": steps, "warmup_requests": warmup,

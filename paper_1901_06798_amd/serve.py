@@ -28,6 +28,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from .timeline import markers
 from .solver import _round_up, patch_table
 from .workloads import Problem
 
@@ -254,8 +255,14 @@ class ScenarioServer:
 
     # -- one round ---------------------------------------------------------------
     def round(self, steps: int) -> None:
+        mk = markers()
         if self.table_dirty:
-            self._rebuild()
+            with mk.range("host: plan"):
+                self._rebuild()
+        with mk.range("host: enqueue"):
+            self._enqueue_round(steps)
+
+    def _enqueue_round(self, steps: int) -> None:
         # a scenario's smax pair lives at its table index during the round
         n = len(self.active)
         smax = torch.zeros(2 * n, dtype=torch.float64, device=self.dev)
@@ -282,9 +289,16 @@ class ScenarioServer:
         for sc in self.active:
             sc.steps_done += steps
 
-    def serve(self, requests, warmup: int = 0, log=None):
+    def serve(self, requests, warmup: int = 0, log=None, label: str = "serve"):
         """Run the request stream.  requests: list of Scenario with arrival
-        times in seconds from the start.  Returns a summary dict."""
+        times in seconds from the start.  Returns a summary dict.  The run is
+        one ROCTx range named `label`, its host work ranges named "host: ..."
+        (see timeline.py)."""
+        with markers().range(label):
+            return self._serve(requests, warmup, log)
+
+    def _serve(self, requests, warmup: int, log):
+        mk = markers()
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: list[Scenario] = []
         done: list[Scenario] = []
@@ -302,7 +316,9 @@ class ScenarioServer:
             inflight.popleft()
             for pool, buf in held:
                 pool.put(buf)
-            for sc in self._finish(results, t0):
+            with mk.range("host: finish"):
+                finished = self._finish(results, t0)
+            for sc in finished:
                 done.append(sc)
                 if log:
                     log(f"[serve] request {sc.rid} ({sc.problem.mx}^2) done, latency "
@@ -314,9 +330,10 @@ class ScenarioServer:
                 queue.append(pending[i])
                 i += 1
             # admit in arrival order while slots and memory allow
-            while queue and self.try_admit(queue[0]):
-                queue[0].admitted = time.perf_counter() - t0
-                queue.pop(0)
+            with mk.range("host: admit"):
+                while queue and self.try_admit(queue[0]):
+                    queue[0].admitted = time.perf_counter() - t0
+                    queue.pop(0)
             if queue and not self.active and not inflight:
                 raise L.SweError(f"request {queue[0].rid} needs "
                                  f"{self.footprint_bytes(queue[0].problem)} bytes of HBM, more "
@@ -325,8 +342,9 @@ class ScenarioServer:
                 steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
                 self.round(steps)
                 cells += steps * sum(sc.problem.mx * sc.problem.my for sc in self.active)
-                results = [self._retire(sc) for sc in
-                           [sc for sc in self.active if sc.steps_done >= sc.nsteps]]
+                with mk.range("host: retire"):
+                    results = [self._retire(sc) for sc in
+                               [sc for sc in self.active if sc.steps_done >= sc.nsteps]]
                 ev = torch.cuda.Event()
                 ev.record(torch.cuda.current_stream(self.dev))
                 inflight.append((ev, results, self.hold))
