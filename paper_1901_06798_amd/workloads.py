@@ -259,3 +259,88 @@ def request_stream(count: int = 1200, rate: float = 20.0, seed: int = 5, nsteps:
     t = np.cumsum(gaps)
     sizes = [int(np.random.default_rng(5000 + k).integers(n_lo, n_hi + 1)) for k in range(count)]
     return [(k, float(t[k]), sizes[k]) for k in range(count)]
+
+
+# --------------------------------------------------------------------------
+# Nested AMR hierarchies (levels coupled by ghost filling and averaging).
+
+@dataclass
+class AmrPatch:
+    """One patch of a hierarchy: interior cells i0 .. i0 + mx - 1, j0 .. j0 + my - 1
+    in its level's global cell index (level l has n1 r^(l-1) cells a side);
+    initial interior state, and the bed on the whole frame with two ghost
+    layers, shape (my + 4, mx + 4)."""
+    level: int
+    i0: int
+    j0: int
+    mx: int
+    my: int
+    h: np.ndarray
+    hu: np.ndarray
+    hv: np.ndarray
+    b_frame: np.ndarray
+
+
+@dataclass
+class AmrHierarchy:
+    n1: int            # level-1 cells a side (the domain)
+    dx1: float
+    ratio: int         # refinement ratio in space and time between levels
+    bc: tuple          # physical boundary codes of the domain (level 1)
+    patches: list
+
+    def dx(self, level: int) -> float:
+        return self.dx1 / self.ratio ** (level - 1)
+
+    def levels(self) -> int:
+        return max(p.level for p in self.patches)
+
+
+def _bed(kind: str, xc, yc, L, depth):
+    X, Y = np.meshgrid(xc, yc)
+    if kind == "flat":
+        return np.full(X.shape, -depth)
+    if kind == "bowl":  # deep everywhere, smooth, all wet
+        return -depth + 0.25 * depth * np.cos(2 * np.pi * X / L) * np.cos(2 * np.pi * Y / L)
+    # "shelf": the tanh shelf along x with a dry coast past 0.8 L
+    return shelf_profile(X, 0.7 * L, 0.05 * L, deep=-depth)
+
+
+def amr_hierarchy(rects, n1: int = 48, dx1: float = 2000.0, ratio: int = 2,
+                  bed: str = "shelf", depth: float = 2000.0, amp: float = 1.0,
+                  sigma_frac: float = 0.08, src=(0.4, 0.5), u0: float = 0.0,
+                  bc=(BC_EXTRAP,) * 4) -> AmrHierarchy:
+    """A hierarchy from patch rectangles.  rects[l - 1] lists the (i0, j0, mx,
+    my) of level l in that level's global index (level 1 normally one patch
+    covering 0 .. n1 - 1).  Bed and initial surface are sampled at each
+    level's own cell centres (ghost frame included for the bed); the surface
+    is a Gaussian hump of amplitude amp at src (fractions of the domain),
+    momenta u0 h in x.  The nesting is not checked here."""
+    L = n1 * dx1
+    patches = []
+    for lev, lst in enumerate(rects, start=1):
+        d = dx1 / ratio ** (lev - 1)
+        for (i0, j0, mx, my) in lst:
+            xf = cell_centres(mx + 4, d, (i0 - 2) * d)
+            yf = cell_centres(my + 4, d, (j0 - 2) * d)
+            bf = _bed(bed, xf, yf, L, depth)
+            eta = gaussian(xf[2:-2], yf[2:-2], amp, sigma_frac * L, src[0] * L, src[1] * L)
+            h = depth_from_surface(eta, bf[2:-2, 2:-2])
+            hu = u0 * h
+            patches.append(AmrPatch(lev, i0, j0, mx, my, h, hu, np.zeros_like(h), bf))
+    return AmrHierarchy(n1, dx1, ratio, tuple(bc), patches)
+
+
+def amr_three_levels(ratio: int = 2, bed: str = "shelf", amp: float = 1.0, u0: float = 0.0,
+                     n1: int = 48) -> AmrHierarchy:
+    """Small three-level test hierarchy: one level-1 patch, two level-2
+    patches that abut (their shared side fills from each other), and two
+    level-3 patches inside them, one straddling the level-2 seam.  Extents
+    are multiples of the ratio, and every fine ghost cell lies over the
+    interior of the level below."""
+    r = ratio
+    m = 2 if r == 1 else 1  # margin, in cells of the level below
+    l2 = [((m + 3) * r, (m + 4) * r, 14 * r, 16 * r), ((m + 17) * r, (m + 4) * r, 10 * r, 20 * r)]
+    l3 = [((m + 5) * r * r, (m + 7) * r * r, 6 * r * r, 6 * r * r),
+          ((m + 14) * r * r, (m + 9) * r * r, 8 * r * r, 5 * r * r)]
+    return amr_hierarchy([[(0, 0, n1, n1)], l2, l3], n1=n1, ratio=r, bed=bed, amp=amp, u0=u0)

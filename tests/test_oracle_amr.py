@@ -1,0 +1,152 @@
+"""Pins of the reference AMR level coupling (oracle/amr.py): a sea at rest
+stays bitwise at rest across levels; with refinement ratio 1 the hierarchy
+reproduces the single-level run cell for cell; averaging takes a linear
+surface and linear momenta to the coarse cell-centre values; the ghost fill
+takes the level below's cell under each ghost (checked on a field whose every
+cell differs), the same level's cell where one exists, and interpolates
+linearly in time."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import amr as A
+from paper_1901_06798_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def P():
+    O.lib()
+    return O.params()
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_sea_at_rest_stays_bitwise_at_rest(P, ratio):
+    H = W.amr_three_levels(ratio, bed="bowl", amp=0.0)
+    h = A.Hierarchy(H, P)
+    h.run(15.0, 2)
+    for lev in (1, 2, 3):
+        for p in h.levels[lev - 1]:
+            q = p.q[2:-2, 2:-2]
+            assert np.all(q[..., 1] == 0.0) and np.all(q[..., 2] == 0.0)
+            assert np.all(q[..., 0] + p.b[2:-2, 2:-2] == 0.0)
+
+
+def single_level(H, P, dt, n):
+    p = [x for x in H.patches if x.level == 1][0]
+    g = O.grid(p.mx, p.my, H.dx1, H.dx1, H.bc)
+    q, b = O.new_state(p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2])
+    O.ghost_fill_b(g, b)
+    for _ in range(n):
+        O.ghost_fill(g, q)
+        out, _, _, nf = O.step(P, g, q, b, dt)
+        assert nf == 0
+        q[2:-2, 2:-2] = out[2:-2, 2:-2]
+    return q
+
+
+def test_ratio_one_reproduces_the_single_level_run(P):
+    # a moving hump over the shelf: every level covers cells of the same
+    # size, so fine patches are windows of the coarse grid; the values agree
+    # up to the rounding of (h + b) - b in the fill and the average
+    H = W.amr_three_levels(1, bed="shelf", amp=2.0, u0=0.3)
+    h = A.Hierarchy(H, P)
+    dt, n = 60.0, 6
+    h.run(dt, n)
+    ref = single_level(H, P, dt, n)
+    scale = np.abs(ref[2:-2, 2:-2]).max(axis=(0, 1))
+    for lev in (1, 2, 3):
+        for p in h.levels[lev - 1]:
+            r0, c0 = p.j0 + 2, p.i0 + 2
+            want = ref[r0: r0 + p.my, c0: c0 + p.mx]
+            got = p.q[2:-2, 2:-2]
+            err = (np.abs(got - want).max(axis=(0, 1)) / scale).max()
+            assert err <= 1e-12, (lev, err)
+    # and the run moved water: not a trivially static state
+    assert np.abs(ref[2:-2, 2:-2, 1]).max() > 1.0
+
+
+def test_average_of_linear_fields_is_the_centre_value(P):
+    r = 4
+    H = W.amr_three_levels(r, bed="flat", amp=0.0)
+    h = A.Hierarchy(H, P)
+    f = h.levels[1][0]
+    dxf = H.dx(2)
+    xs = (np.arange(f.mx) + f.i0 + 0.5) * dxf
+    ys = (np.arange(f.my) + f.j0 + 0.5) * dxf
+    X, Y = np.meshgrid(xs, ys)
+    eta = 0.25 + 1e-5 * X - 2e-5 * Y
+    f.q[2:-2, 2:-2, 0] = eta - f.b[2:-2, 2:-2]
+    f.q[2:-2, 2:-2, 1] = 3.0 + 1e-4 * X
+    f.q[2:-2, 2:-2, 2] = -1.0 + 2e-4 * Y
+    h.average(1)
+    c = h.levels[0][0]
+    dxc = H.dx(1)
+    for Jc in range(f.j0 // r, (f.j0 + f.my) // r):
+        for Ic in range(f.i0 // r, (f.i0 + f.mx) // r):
+            xc, yc = (Ic + 0.5) * dxc, (Jc + 0.5) * dxc
+            rc, cc = c.cell(Ic, Jc)
+            assert c.q[rc, cc, 0] + c.b[rc, cc] == pytest.approx(0.25 + 1e-5 * xc - 2e-5 * yc,
+                                                                abs=1e-10)
+            assert c.q[rc, cc, 1] == pytest.approx(3.0 + 1e-4 * xc, rel=1e-13)
+            assert c.q[rc, cc, 2] == pytest.approx(-1.0 + 2e-4 * yc, rel=1e-12)
+
+
+def test_fill_takes_the_cell_under_each_ghost_and_interpolates_in_time(P):
+    r = 2
+    H = W.amr_three_levels(r, bed="flat", amp=0.0)
+    h = A.Hierarchy(H, P)
+    c = h.levels[0][0]
+    n = c.q.shape[0]
+    # every coarse cell different: depth 1000 + I + 100 J, momenta I - J and I J
+    J, I = np.meshgrid(np.arange(n) - 2, np.arange(n) - 2, indexing="ij")
+    old = [c.q.copy()]
+    old[0][..., 0] = 1000.0 + I + 100.0 * J
+    old[0][..., 1] = I - J
+    old[0][..., 2] = I * J
+    c.q[..., 0] = 2000.0 + I + 100.0 * J
+    c.q[..., 1] = 2.0 * (I - J)
+    c.q[..., 2] = 3.0 * I * J
+    for alpha in (0.0, 0.5):
+        h.fill(2, old, alpha)
+        for f in h.levels[1]:
+            other = [s for s in h.levels[1] if s is not f][0]
+            for row in range(f.my + 4):
+                for col in range(f.mx + 4):
+                    if 2 <= row < f.my + 2 and 2 <= col < f.mx + 2:
+                        continue
+                    If, Jf = f.i0 + col - 2, f.j0 + row - 2
+                    if other.covers(If, Jf):
+                        assert np.array_equal(f.q[row, col], other.q[other.cell(If, Jf)])
+                        continue
+                    Ic, Jc = If // r, Jf // r
+                    want = ((1 - alpha) * (1000.0 + Ic + 100.0 * Jc)
+                            + alpha * (2000.0 + Ic + 100.0 * Jc),
+                            (1 - alpha) * (Ic - Jc) + alpha * 2.0 * (Ic - Jc),
+                            (1 - alpha) * (Ic * Jc) + alpha * 3.0 * Ic * Jc)
+                    assert f.q[row, col] == pytest.approx(want, rel=1e-13, abs=1e-12)
+
+
+def test_fill_and_average_keep_dry_land_dry(P):
+    # a fully dry level below gives dry ghosts; fully dry fine cells average
+    # to a dry coarse cell
+    r = 2
+    H = W.amr_three_levels(r, bed="flat", amp=0.0)
+    h = A.Hierarchy(H, P)
+    c = h.levels[0][0]
+    c.q[...] = 0.0
+    h.fill(2, [c.q.copy()], 0.5)
+    for f in h.levels[1]:
+        other = [s for s in h.levels[1] if s is not f][0]
+        for row in range(f.my + 4):
+            for col in range(f.mx + 4):
+                inner = 2 <= row < f.my + 2 and 2 <= col < f.mx + 2
+                if not inner and not other.covers(f.i0 + col - 2, f.j0 + row - 2):
+                    assert np.all(f.q[row, col] == 0.0)
+    for s in h.levels[1]:
+        s.q[...] = 0.0
+    c.q[...] = 7.0
+    h.average(1)
+    for s in h.levels[1]:
+        for Jc in range(s.j0 // r, (s.j0 + s.my) // r):
+            for Ic in range(s.i0 // r, (s.i0 + s.mx) // r):
+                assert np.all(c.q[c.cell(Ic, Jc)] == 0.0)
