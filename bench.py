@@ -70,15 +70,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# sources of the single-patch step kernels (k_split, k_unsplit) that the
+# counter records describe
+STEP_SOURCES = ("swe_common.hpp", "swe_march.hpp", "swe_math.hpp", "swe_step.hip",
+                "swe_unsplit.hpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; measured traffic is used only for this hash."""
+    """Hash of the step kernels' HIP sources; a counter record is used only
+    while it carries this hash."""
     import hashlib
     d = os.path.join(ROOT, "paper_1901_06798_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in STEP_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 

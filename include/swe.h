@@ -290,6 +290,63 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
                        uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                        const uint32_t *retake, int32_t ngroups, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Coupling of AMR levels (Sec. 3: a finer level's ghost cells come from an
+ * adjacent patch of the same level or, where none exists, from the level
+ * below, interpolated in space and time; after the finer level's r substeps
+ * the cells of the level below that it covers take averages of the fine
+ * cells, the updating process; refluxing is left out, as in the paper's GPU
+ * code).  Both keep a sea at rest at rest: they interpolate and average the
+ * surface h + b and recover h from the bed of the cell written.  FP64 planes
+ * only.  Each level keeps its patches in one plane set (layout as above; all
+ * patches of a level share its plane stride); a host plan lists every entry
+ * once, so an entry's writes never collide with another's and its reads
+ * touch only interior cells, which no entry writes.
+ */
+#define SWE_AMR_COPY 0   /* ghost cell over another patch of the same level */
+#define SWE_AMR_COARSE 1 /* ghost cell filled from the cell of the level below */
+
+typedef struct swe_amr_fill_op {
+    int64_t dst;      /* element offset of the fine ghost cell in the fine planes */
+    int64_t src;      /* SWE_AMR_COPY: element offset of the same-level interior
+                         cell (fine planes); SWE_AMR_COARSE: element offset of the
+                         coarse cell under the ghost cell (coarse planes) */
+    int32_t kind;     /* SWE_AMR_COPY or SWE_AMR_COARSE */
+    int32_t reserved;
+} swe_amr_fill_op;
+
+typedef struct swe_amr_avg_op {
+    int64_t dst;      /* element offset of the coarse cell (coarse planes) */
+    int64_t src;      /* element offset of the fine cell over its lowest row and
+                         column (fine planes) */
+    int32_t pitch;    /* fine patch pitch: elements between the fine rows */
+    int32_t reserved;
+} swe_amr_avg_op;
+
+/* Fill the ghost cells of a finer level at time t_n + alpha dt_coarse,
+ * 0 <= alpha <= 1 (alpha = k / r before substep k).  ops: device array of
+ * nops entries.  q_fine, b_fine: the finer level's planes (written: the dst
+ * cells of all three planes).  q_coarse_old, q_coarse_new: the coarser
+ * level's planes before and after its step (read only), b_coarse its bed.
+ * SWE_AMR_COPY: q_fine[dst] = q_fine[src] (three planes).  SWE_AMR_COARSE,
+ * with ho, hn the coarse depths, b_c = b_coarse[src], b_f = b_fine[dst]:
+ * both ho, hn <= drytol gives (0, 0, 0); else
+ *   eta = (1 - alpha)(ho + b_c) + alpha (hn + b_c),  h = max(eta - b_f, 0),
+ *   (hu, hv) = (1 - alpha)(hu, hv)_old + alpha (hu, hv)_new, or 0 if h <= drytol. */
+int swe_amr_fill(const swe_params *p, const swe_amr_fill_op *ops, int64_t nops, void *q_fine,
+                 int64_t fine_plane_stride, const void *b_fine, const void *q_coarse_old,
+                 const void *q_coarse_new, int64_t coarse_plane_stride, const void *b_coarse,
+                 double alpha, void *stream);
+
+/* Replace the coarse cells listed in ops by averages of the r x r fine cells
+ * over each (ratio = r): with the wet fine cells (h > drytol) W,
+ * W empty gives (0, 0, 0); else h = max(mean over W of (h + b_f) - b_c, 0),
+ * (hu, hv) = mean over all r x r fine cells, or 0 if h <= drytol. */
+int swe_amr_average(const swe_params *p, const swe_amr_avg_op *ops, int64_t nops, int32_t ratio,
+                    const void *q_fine, int64_t fine_plane_stride, const void *b_fine,
+                    void *q_coarse, int64_t coarse_plane_stride, const void *b_coarse,
+                    void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);
 

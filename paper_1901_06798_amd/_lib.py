@@ -19,6 +19,7 @@ STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED, STATUS_RETAKEN = 1, 2, 
 SPLIT, UNSPLIT = 0, 1
 F64, F32_DEV = 0, 1
 BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
+SWE_AMR_COPY, SWE_AMR_COARSE = 0, 1
 
 
 class SweError(RuntimeError):
@@ -105,6 +106,9 @@ def lib():
         L.swe_patch_step_sched.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                            _P, _P]
         L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, _P]
+        i64, dbl = ctypes.c_int64, ctypes.c_double
+        L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
+        L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
@@ -116,7 +120,8 @@ def lib():
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
                      "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
-                     "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order"):
+                     "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
+                     "swe_amr_fill", "swe_amr_average"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -153,6 +158,22 @@ def swe_patch_step_sched(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b:
 
 def swe_patch_order(pt: swe_patch, sched: int, stream: int = 0) -> None:
     _check(lib().swe_patch_order(ctypes.byref(pt), sched, stream), "swe_patch_order")
+
+
+def swe_amr_fill(p: swe_params, ops: int, nops: int, q_fine: int, fine_plane_stride: int,
+                 b_fine: int, q_coarse_old: int, q_coarse_new: int, coarse_plane_stride: int,
+                 b_coarse: int, alpha: float, stream: int = 0) -> None:
+    _check(lib().swe_amr_fill(ctypes.byref(p), ops, nops, q_fine, fine_plane_stride, b_fine,
+                              q_coarse_old, q_coarse_new, coarse_plane_stride, b_coarse,
+                              float(alpha), stream), "swe_amr_fill")
+
+
+def swe_amr_average(p: swe_params, ops: int, nops: int, ratio: int, q_fine: int,
+                    fine_plane_stride: int, b_fine: int, q_coarse: int,
+                    coarse_plane_stride: int, b_coarse: int, stream: int = 0) -> None:
+    _check(lib().swe_amr_average(ctypes.byref(p), ops, nops, ratio, q_fine, fine_plane_stride,
+                                 b_fine, q_coarse, coarse_plane_stride, b_coarse, stream),
+           "swe_amr_average")
 
 
 def swe_ghost_fill(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,

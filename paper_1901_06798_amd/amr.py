@@ -1,0 +1,229 @@
+"""A nested AMR hierarchy advanced on the device (Qin, LeVeque & Motley,
+Sec. 3: levels refined by an integer ratio r in space and time, the recursive
+time integration, ghost cells of a finer level from the same level or from
+the level below, the updating process; refluxing is left out, as in the
+paper's GPU code).
+
+Each level is one BatchedSolver: its patches live in one pool (two state
+buffers and the bed), and a level step is one swe_batched_step.  Patches of
+level 2 and finer have user boundaries on every side: their ghost cells are
+written by swe_amr_fill before each of their substeps.  The host computes the
+fill and averaging plans once (which cell each ghost cell or covered coarse
+cell reads); a coarse step is then a fixed sequence of launches, with the
+step sizes in device memory, that can be captured into a HIP graph.
+
+Nesting required (not checked cell by cell): every ghost cell of a level-l
+patch (l >= 2) lies over an interior cell of the same level or of level
+l - 1; patches of one level do not overlap; a finer patch's extents are
+multiples of r in its level's index.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .batched import BatchedSolver
+from .workloads import BC_USER, AmrHierarchy, Problem
+
+FILL_DTYPE = np.dtype([("dst", "<i8"), ("src", "<i8"), ("kind", "<i4"), ("reserved", "<i4")])
+AVG_DTYPE = np.dtype([("dst", "<i8"), ("src", "<i8"), ("pitch", "<i4"), ("reserved", "<i4")])
+
+
+class _Geo:
+    """Where a level's patches sit: global index origin and pool layout."""
+
+    def __init__(self, patches, bs: BatchedSolver):
+        self.i0 = np.array([p.i0 for p in patches])
+        self.j0 = np.array([p.j0 for p in patches])
+        self.mx = np.array([p.mx for p in patches])
+        self.my = np.array([p.my for p in patches])
+        self.off = np.array(bs.offs, dtype=np.int64)
+        self.pitch = np.array([lay[0] for lay in bs.layout], dtype=np.int64)
+
+    def covering(self, I, J, skip: int = -1):
+        """Index of the first patch whose interior holds (I, J), else -1."""
+        out = np.full(I.shape, -1, dtype=np.int64)
+        for k in range(len(self.i0)):
+            if k == skip:
+                continue
+            m = ((out < 0) & (I >= self.i0[k]) & (I < self.i0[k] + self.mx[k])
+                 & (J >= self.j0[k]) & (J < self.j0[k] + self.my[k]))
+            out[m] = k
+        return out
+
+    def elem(self, k, I, J):
+        """Element offset of global cell (I, J) in patch k's planes."""
+        return (self.off[k] + (J - self.j0[k] + 2) * self.pitch[k] + (I - self.i0[k] + 2))
+
+
+def fill_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
+    ops = []
+    for k in range(len(fine.i0)):
+        rows, cols = np.meshgrid(np.arange(fine.my[k] + 4), np.arange(fine.mx[k] + 4),
+                                 indexing="ij")
+        ghost = ~((rows >= 2) & (rows < fine.my[k] + 2) & (cols >= 2) & (cols < fine.mx[k] + 2))
+        rows, cols = rows[ghost], cols[ghost]
+        I = fine.i0[k] + cols - 2
+        J = fine.j0[k] + rows - 2
+        dst = fine.off[k] + rows * fine.pitch[k] + cols
+        same = fine.covering(I, J, skip=k)
+        Ic, Jc = I // r, J // r
+        below = coarse.covering(Ic, Jc)
+        if np.any((same < 0) & (below < 0)):
+            raise L.SweError(f"patch {k}: a ghost cell lies over no cell of its level or the "
+                             f"level below")
+        op = np.zeros(dst.size, dtype=FILL_DTYPE)
+        op["dst"] = dst
+        cp = same >= 0
+        for s in np.unique(same[cp]):
+            m = same == s
+            op["src"][m] = fine.elem(s, I[m], J[m])
+        op["kind"][cp] = L.SWE_AMR_COPY
+        for c in np.unique(below[~cp]):
+            m = (~cp) & (below == c)
+            op["src"][m] = coarse.elem(c, Ic[m], Jc[m])
+        op["kind"][~cp] = L.SWE_AMR_COARSE
+        ops.append(op)
+    return np.concatenate(ops) if ops else np.zeros(0, dtype=FILL_DTYPE)
+
+
+def average_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
+    ops = []
+    for k in range(len(fine.i0)):
+        jc = np.arange(fine.j0[k] // r, (fine.j0[k] + fine.my[k]) // r)
+        ic = np.arange(fine.i0[k] // r, (fine.i0[k] + fine.mx[k]) // r)
+        Jc, Ic = np.meshgrid(jc, ic, indexing="ij")
+        Jc, Ic = Jc.ravel(), Ic.ravel()
+        below = coarse.covering(Ic, Jc)
+        if np.any(below < 0):
+            raise L.SweError(f"patch {k}: not over the level below")
+        op = np.zeros(Ic.size, dtype=AVG_DTYPE)
+        for c in np.unique(below):
+            m = below == c
+            op["dst"][m] = coarse.elem(c, Ic[m], Jc[m])
+        op["src"] = fine.elem(k, Ic * r, Jc * r)
+        op["pitch"] = fine.pitch[k]
+        ops.append(op)
+    return np.concatenate(ops) if ops else np.zeros(0, dtype=AVG_DTYPE)
+
+
+class AmrSolver:
+    def __init__(self, H: AmrHierarchy, params: L.swe_params | None = None,
+                 device: str = "cuda:0"):
+        self.H = H
+        self.p = params or L.params()
+        if self.p.precision != L.F64:
+            raise L.SweError("AmrSolver: FP64 only")
+        self.r = H.ratio
+        self.dev = torch.device(device)
+        self.nlev = H.levels()
+        self.levels, self.geo, self.lpatches = [], [], []
+        for lev in range(1, self.nlev + 1):
+            ps = [p for p in H.patches if p.level == lev]
+            bc = H.bc if lev == 1 else (BC_USER,) * 4
+            d = H.dx(lev)
+            probs = [Problem(f"l{lev}p{k}", p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2], d, d, bc,
+                             meta={"level": lev}) for k, p in enumerate(ps)]
+            bs = BatchedSolver(probs, self.p, sched=L.schedule(seg=64), device=device)
+            if lev > 1:  # the bed of the ghost frame (user sides are read from memory)
+                for k, p in enumerate(ps):
+                    bs._view(bs.b, k, 1)[0][:, : p.mx + 4] = torch.from_numpy(
+                        np.ascontiguousarray(p.b_frame)).to(self.dev)
+            self.levels.append(bs)
+            self.lpatches.append(ps)
+            self.geo.append(_Geo(ps, bs))
+        self.fill_ops, self.avg_ops, self.nfill, self.navg = [None], [], [0], []
+        for lev in range(1, self.nlev):
+            f = fill_plan(self.geo[lev], self.geo[lev - 1], self.r)
+            a = average_plan(self.geo[lev], self.geo[lev - 1], self.r)
+            self.fill_ops.append(torch.from_numpy(f.view(np.uint8).copy()).to(self.dev))
+            self.avg_ops.append(torch.from_numpy(a.view(np.uint8).copy()).to(self.dev))
+            self.nfill.append(f.size)
+            self.navg.append(a.size)
+        self.dts = torch.zeros(self.nlev, dtype=torch.float64, device=self.dev)
+        self.graph = None
+
+    @property
+    def stream(self) -> int:
+        return torch.cuda.current_stream(self.dev).cuda_stream
+
+    def set_dt(self, dt1: float) -> None:
+        """Level step sizes dt_l = dt_{l-1} / r."""
+        dts = [float(dt1)]
+        for _ in range(1, self.nlev):
+            dts.append(dts[-1] / self.r)
+        self.dts.copy_(torch.tensor(dts, dtype=torch.float64))
+
+    def _advance(self, lev: int) -> None:
+        bs = self.levels[lev - 1]
+        old = bs.pools[bs.cur]
+        bs.enqueue_step(cfl=False, dt_ptr=self.dts.data_ptr() + 8 * (lev - 1))
+        new = bs.pools[bs.cur]
+        if lev == self.nlev:
+            return
+        fine = self.levels[lev]
+        for k in range(self.r):
+            L.swe_amr_fill(self.p, self.fill_ops[lev].data_ptr(), self.nfill[lev],
+                           fine.pools[fine.cur].data_ptr(), fine.plane, fine.b.data_ptr(),
+                           old.data_ptr(), new.data_ptr(), bs.plane, bs.b.data_ptr(),
+                           k / self.r, self.stream)
+            self._advance(lev + 1)
+        L.swe_amr_average(self.p, self.avg_ops[lev - 1].data_ptr(), self.navg[lev - 1], self.r,
+                          fine.pools[fine.cur].data_ptr(), fine.plane, fine.b.data_ptr(),
+                          new.data_ptr(), bs.plane, bs.b.data_ptr(), self.stream)
+
+    def enqueue_coarse_step(self) -> None:
+        self._advance(1)
+
+    def run(self, ncoarse: int) -> None:
+        for _ in range(ncoarse):
+            self._advance(1)
+
+    def capture(self, ncoarse: int = 2) -> None:
+        """Capture ncoarse coarse steps into a HIP graph (every level's state
+        buffer must come back to where it started: level 1 flips once per
+        coarse step, level l r^(l-1) times)."""
+        flips = [ncoarse * self.r ** (lev - 1) for lev in range(1, self.nlev + 1)]
+        if any(f % 2 for f in flips):
+            raise ValueError("capture a number of coarse steps that returns every buffer")
+        s = torch.cuda.Stream(self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            torch.cuda.synchronize(self.dev)
+            with torch.cuda.graph(g, stream=s):
+                self.run(ncoarse)
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        self.graph = g
+        self.graph_steps = ncoarse
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    # -- results ---------------------------------------------------------------
+    def state(self, lev: int, k: int):
+        """Interior (h, hu, hv) of patch k of level lev."""
+        return self.levels[lev - 1].state(k)
+
+    def courant(self) -> float:
+        """Largest Courant number over the levels' steps so far (from the speed
+        maxima the steps max-combined)."""
+        worst = 0.0
+        dts = self.dts.cpu().numpy()
+        for lev, bs in enumerate(self.levels, start=1):
+            sm = bs.smax.cpu().numpy().reshape(-1, 2)
+            d = self.H.dx(lev)
+            worst = max(worst, float(dts[lev - 1] * max(sm[:, 0].max(), sm[:, 1].max()) / d))
+        return worst
+
+    def flags(self):
+        f, c = 0, 0
+        for bs in self.levels:
+            a, b = bs.flags()
+            f |= a
+            c += b
+        return f, c
+
+    def cells_per_coarse_step(self) -> int:
+        return sum(p.mx * p.my * self.r ** (p.level - 1) for p in self.H.patches)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["swe_step.hip", "swe_batched.hip"]
+SOURCES = ["swe_step.hip", "swe_batched.hip", "swe_amr.hip"]
 OUT = os.path.join(HERE, "libswe.so")
 
 # -ffp-contract=off: every product and sum rounds as written, so a cell's

@@ -123,3 +123,80 @@ def test_sched_step_rejects_a_null_schedule(L):
     assert b"schedule" in lib.swe_last_error()
     bad = L.patch(10, 10, 12, 1.0, 1.0)
     assert lib.swe_patch_order(ctypes.byref(bad), ctypes.c_void_p(0x1000), None) == L.SWE_EINVAL
+
+
+def test_amr_struct_layout_and_argument_errors(L, tmp_path):
+    src = tmp_path / "amr_layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "swe.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %d %d\n", sizeof(swe_amr_fill_op), offsetof(swe_amr_fill_op, kind),
+         sizeof(swe_amr_avg_op), offsetof(swe_amr_avg_op, src), offsetof(swe_amr_avg_op, pitch),
+         SWE_AMR_COPY, SWE_AMR_COARSE);
+  return 0;
+}
+''')
+    exe = tmp_path / "amr_layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    from paper_1901_06798_amd import amr
+    assert vals == [amr.FILL_DTYPE.itemsize, amr.FILL_DTYPE.fields["kind"][1],
+                    amr.AVG_DTYPE.itemsize, amr.AVG_DTYPE.fields["src"][1],
+                    amr.AVG_DTYPE.fields["pitch"][1], L.SWE_AMR_COPY, L.SWE_AMR_COARSE]
+    lib = L.lib()
+    p = L.params()
+    fake = ctypes.c_void_p(0x1000)
+    other = ctypes.c_void_p(0x2000)
+    # FP64 planes only; alpha in [0, 1]; distinct fine and coarse planes
+    q32 = L.params(precision=L.F32_DEV)
+    assert lib.swe_amr_fill(ctypes.byref(q32), fake, 1, fake, 8, fake, other, other, 8, fake,
+                            0.5, None) == L.SWE_EINVAL
+    assert lib.swe_amr_fill(ctypes.byref(p), fake, 1, fake, 8, fake, other, other, 8, fake,
+                            1.5, None) == L.SWE_EINVAL
+    assert lib.swe_amr_fill(ctypes.byref(p), fake, 1, fake, 8, fake, fake, other, 8, fake,
+                            0.5, None) == L.SWE_EINVAL
+    assert lib.swe_amr_fill(ctypes.byref(p), fake, 0, fake, 8, fake, other, other, 8, fake,
+                            0.5, None) == L.SWE_OK
+    assert lib.swe_amr_average(ctypes.byref(p), fake, 1, 0, fake, 8, fake, other, 8, fake,
+                               None) == L.SWE_EINVAL
+    assert lib.swe_amr_average(ctypes.byref(p), fake, 1, 2, fake, 8, fake, fake, 8, fake,
+                               None) == L.SWE_EINVAL
+    assert lib.swe_amr_average(ctypes.byref(p), None, 3, 2, fake, 8, fake, other, 8, fake,
+                               None) == L.SWE_EINVAL
+
+
+def test_amr_plans_match_the_hierarchy(L):
+    # host plans only (no GPU): every ghost cell of a fine patch listed once,
+    # copies where a same-level patch covers it, the level below elsewhere;
+    # every coarse cell under a fine patch averaged once
+    import numpy as np
+    from paper_1901_06798_amd import amr, workloads as W
+
+    class Lay:  # the pool layout a BatchedSolver would make
+        def __init__(self, ps):
+            self.offs, self.layout, t = [], [], 0
+            for p in ps:
+                pitch = -(-(p.mx + 4) // 16) * 16
+                size = -(-(pitch * (p.my + 4)) // 64) * 64
+                self.offs.append(t)
+                self.layout.append((pitch, size))
+                t += size
+
+    for r in (1, 2, 4):
+        H = W.amr_three_levels(r)
+        byl = [[p for p in H.patches if p.level == lev] for lev in (1, 2, 3)]
+        geo = [amr._Geo(ps, Lay(ps)) for ps in byl]
+        for lev in (1, 2):
+            f = amr.fill_plan(geo[lev], geo[lev - 1], r)
+            nghost = sum((p.mx + 4) * (p.my + 4) - p.mx * p.my for p in byl[lev])
+            assert f.size == nghost and np.unique(f["dst"]).size == nghost
+            # the two level-2 patches abut (copies across the seam); level 3's do not
+            kinds = {L.SWE_AMR_COPY, L.SWE_AMR_COARSE} if lev == 1 else {L.SWE_AMR_COARSE}
+            assert set(int(k) for k in np.unique(f["kind"])) == kinds
+            a = amr.average_plan(geo[lev], geo[lev - 1], r)
+            assert a.size == sum(p.mx * p.my for p in byl[lev]) // (r * r)
+            assert np.unique(a["dst"]).size == a.size
