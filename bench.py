@@ -57,6 +57,8 @@ def parse():
                     help="write the VALU counter records from a rocprofv3 --pmc run and exit")
     ap.add_argument("--make-traffic-record", nargs=2, metavar=("PMC_ROOT", "OUT"), default=None,
                     help="write the traffic record from rocprofv3 --pmc runs and exit")
+    ap.add_argument("--amr", action="store_true",
+                    help="only the coupled three-level AMR hierarchy (one JSON line)")
     ap.add_argument("--serve", type=int, default=0,
                     help="only run the serving stream with this many requests")
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -372,6 +374,44 @@ def time_batched(precision: int, steps: int = 10):
             "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0], "autotune": tuned}
 
 
+def time_amr(ncoarse: int = 10, dt1: float = 8.0):
+    """The seeded three-level hierarchy coupled on the device: eager coarse
+    steps, then replays of two captured coarse steps."""
+    import torch
+
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.amr import AmrSolver
+
+    H = W.amr_nested()
+    s = AmrSolver(H, L.params())
+    s.set_dt(dt1)
+    s.run(2)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    s.run(4)
+    t1.record()
+    torch.cuda.synchronize()
+    eager_ms = t0.elapsed_time(t1) / 4
+    s.capture(2)
+    t0.record()
+    for _ in range(ncoarse // 2):
+        s.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / (2 * (ncoarse // 2))
+    upd = s.cells_per_coarse_step()
+    npatch = [sum(1 for p in H.patches if p.level == lev) for lev in (1, 2, 3)]
+    return {"patches_per_level": npatch, "ratio": H.ratio, "level1_cells": H.n1 * H.n1,
+            "cell_updates_per_coarse_step": upd, "ms_per_coarse_step": ms,
+            "ms_per_coarse_step_eager": eager_ms, "cups": upd / (ms * 1e-3),
+            "ghost_fill_cells_per_substep": s.nfill[1:], "averaged_cells": s.navg,
+            "max_courant": s.courant(), "flags": s.flags()[0],
+            "dt_level1_s": dt1, "coarse_steps_timed": 2 * (ncoarse // 2)}
+
+
 def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
     """FP32 surface deviation vs FP64 on the walled shelf.  Both runs advance
     in lockstep (FP32 driven by the FP64 step sizes); at every checkpoint the
@@ -529,6 +569,9 @@ def main():
     if args.calib_copy > 0:
         calib_copy(args.calib_copy)
         return
+    if args.amr:
+        print(json.dumps({"amr_coupled_fp64": time_amr()}), flush=True)
+        return
     if args.serve > 0:
         out = serving_pair(args.serve, args.serve_steps)
         out["metric"] = "scenario latency p50/p99 (ms) and cell-updates/s"
@@ -613,6 +656,9 @@ def main():
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")
                 out["variants"][name] = time_batched(prec)
+            log("[bench] coupled AMR hierarchy (three levels, FP64)")
+            torch.cuda.empty_cache()
+            out["variants"]["amr_coupled_fp64"] = time_amr()
         if not args.no_serving:
             torch.cuda.empty_cache()
             out["serving"] = serving_pair(args.serve_requests, args.serve_steps)

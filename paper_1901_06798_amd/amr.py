@@ -110,7 +110,7 @@ def average_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
 
 class AmrSolver:
     def __init__(self, H: AmrHierarchy, params: L.swe_params | None = None,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", rows=None):
         self.H = H
         self.p = params or L.params()
         if self.p.precision != L.F64:
@@ -125,7 +125,12 @@ class AmrSolver:
             d = H.dx(lev)
             probs = [Problem(f"l{lev}p{k}", p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2], d, d, bc,
                              meta={"level": lev}) for k, p in enumerate(ps)]
-            bs = BatchedSolver(probs, self.p, sched=L.schedule(seg=64), device=device)
+            # 8-row tasks: a level's launch then holds enough waves to fill the
+            # device (32-row tasks left most wave slots idle and were 1.6 x
+            # slower on the bench hierarchy)
+            H_rows = rows[lev - 1] if rows is not None else 8
+            bs = BatchedSolver(probs, self.p, sched=L.schedule(seg=64, rows_per_task=H_rows),
+                               device=device)
             if lev > 1:  # the bed of the ghost frame (user sides are read from memory)
                 for k, p in enumerate(ps):
                     bs._view(bs.b, k, 1)[0][:, : p.mx + 4] = torch.from_numpy(

@@ -344,3 +344,44 @@ def amr_three_levels(ratio: int = 2, bed: str = "shelf", amp: float = 1.0, u0: f
     l3 = [((m + 5) * r * r, (m + 7) * r * r, 6 * r * r, 6 * r * r),
           ((m + 14) * r * r, (m + 9) * r * r, 8 * r * r, 5 * r * r)]
     return amr_hierarchy([[(0, 0, n1, n1)], l2, l3], n1=n1, ratio=r, bed=bed, amp=amp, u0=u0)
+
+
+def amr_nested(n1: int = 1024, dx1: float = 2000.0, ratio: int = 4, counts=(64, 128),
+               sizes=(96, 160), seed: int = 11, amp: float = 2.0,
+               depth: float = 2000.0) -> AmrHierarchy:
+    """Seeded three-level hierarchy over the shelf: level 1 one n1 x n1 patch;
+    counts[0] level-2 patches in the band 0.55 L .. 0.9 L across the shelf
+    break and the coast, counts[1] level-3 patches inside them.  Side lengths
+    are uniform in `sizes` (fine cells, multiples of the ratio); patches of a
+    level do not overlap, and every patch's ghost cells lie over the interior
+    of its parent."""
+    rng = np.random.default_rng(seed)
+    r = ratio
+    rects = [[(0, 0, n1, n1)]]
+    for lev, count in zip((2, 3), counts):
+        parents = rects[-1]
+        placed = []
+        tries = 0
+        while len(placed) < count and tries < 200 * count:
+            tries += 1
+            pi0, pj0, pmx, pmy = parents[int(rng.integers(len(parents)))]
+            mx = int(rng.integers(sizes[0] // r, sizes[1] // r + 1)) * r
+            my = int(rng.integers(sizes[0] // r, sizes[1] // r + 1)) * r
+            lo_i = (pi0 * r + 2 + r - 1) // r  # ghost cells inside the parent
+            hi_i = ((pi0 + pmx) * r - 2 - mx) // r
+            lo_j = (pj0 * r + 2 + r - 1) // r
+            hi_j = ((pj0 + pmy) * r - 2 - my) // r
+            if lev == 2:  # the band across the shelf break and the coast
+                lo_i = max(lo_i, int(0.55 * n1))
+                hi_i = min(hi_i, int(0.9 * n1 * r - mx) // r)
+            if hi_i < lo_i or hi_j < lo_j:
+                continue
+            i0 = int(rng.integers(lo_i, hi_i + 1)) * r
+            j0 = int(rng.integers(lo_j, hi_j + 1)) * r
+            if any(i0 < a + w and a < i0 + mx and j0 < b + h and b < j0 + my
+                   for a, b, w, h in placed):
+                continue
+            placed.append((i0, j0, mx, my))
+        rects.append(placed)
+    return amr_hierarchy(rects, n1=n1, dx1=dx1, ratio=r, bed="shelf", depth=depth, amp=amp,
+                         sigma_frac=0.04, src=(0.5, 0.5))
