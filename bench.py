@@ -374,7 +374,7 @@ def time_batched(precision: int, steps: int = 10):
             "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0], "autotune": tuned}
 
 
-def time_amr(ncoarse: int = 10, dt1: float = 8.0):
+def time_amr(ncoarse: int = 10, dt1: float = 8.0, precision: int = 0):
     """The seeded three-level hierarchy coupled on the device: eager coarse
     steps, then replays of two captured coarse steps."""
     import torch
@@ -384,7 +384,7 @@ def time_amr(ncoarse: int = 10, dt1: float = 8.0):
     from paper_1901_06798_amd.amr import AmrSolver
 
     H = W.amr_nested()
-    s = AmrSolver(H, L.params())
+    s = AmrSolver(H, L.params(precision=precision))
     s.set_dt(dt1)
     s.run(2)
     torch.cuda.synchronize()
@@ -570,7 +570,11 @@ def main():
         calib_copy(args.calib_copy)
         return
     if args.amr:
-        print(json.dumps({"amr_coupled_fp64": time_amr()}), flush=True)
+        out = {"amr_coupled_fp64": time_amr()}
+        import torch
+        torch.cuda.empty_cache()
+        out["amr_coupled_fp32_dev"] = time_amr(precision=1)
+        print(json.dumps(out), flush=True)
         return
     if args.serve > 0:
         out = serving_pair(args.serve, args.serve_steps)
@@ -659,6 +663,8 @@ def main():
             log("[bench] coupled AMR hierarchy (three levels, FP64)")
             torch.cuda.empty_cache()
             out["variants"]["amr_coupled_fp64"] = time_amr()
+            torch.cuda.empty_cache()
+            out["variants"]["amr_coupled_fp32_dev"] = time_amr(precision=1)
         if not args.no_serving:
             torch.cuda.empty_cache()
             out["serving"] = serving_pair(args.serve_requests, args.serve_steps)

@@ -297,8 +297,10 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
  * the cells of the level below that it covers take averages of the fine
  * cells, the updating process; refluxing is left out, as in the paper's GPU
  * code).  Both keep a sea at rest at rest: they interpolate and average the
- * surface h + b and recover h from the bed of the cell written.  FP64 planes
- * only.  Each level keeps its patches in one plane set (layout as above; all
+ * surface h + b and recover h from the bed of the cell written.  FP64 planes,
+ * or FP32 surface-deviation planes (eta' = h + b - sea_level; read into FP64,
+ * combined there and rounded once; a dry cell stores eta' = b - sea_level).
+ * Each level keeps its patches in one plane set (layout as above; all
  * patches of a level share its plane stride); a host plan lists every entry
  * once, so an entry's writes never collide with another's and its reads
  * touch only interior cells, which no entry writes.

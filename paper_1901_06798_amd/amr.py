@@ -113,8 +113,6 @@ class AmrSolver:
                  device: str = "cuda:0", rows=None):
         self.H = H
         self.p = params or L.params()
-        if self.p.precision != L.F64:
-            raise L.SweError("AmrSolver: FP64 only")
         self.r = H.ratio
         self.dev = torch.device(device)
         self.nlev = H.levels()

@@ -151,9 +151,10 @@ int main(void) {
     p = L.params()
     fake = ctypes.c_void_p(0x1000)
     other = ctypes.c_void_p(0x2000)
-    # FP64 planes only; alpha in [0, 1]; distinct fine and coarse planes
-    q32 = L.params(precision=L.F32_DEV)
-    assert lib.swe_amr_fill(ctypes.byref(q32), fake, 1, fake, 8, fake, other, other, 8, fake,
+    # known precision; alpha in [0, 1]; distinct fine and coarse planes
+    q9 = L.params()
+    q9.precision = 9
+    assert lib.swe_amr_fill(ctypes.byref(q9), fake, 1, fake, 8, fake, other, other, 8, fake,
                             0.5, None) == L.SWE_EINVAL
     assert lib.swe_amr_fill(ctypes.byref(p), fake, 1, fake, 8, fake, other, other, 8, fake,
                             1.5, None) == L.SWE_EINVAL

@@ -91,3 +91,47 @@ def test_captured_coarse_steps_replay_to_the_eager_result(gpu):
             b = g.state(lev, k)
             for c in range(3):
                 assert np.array_equal(a[c], b[c]), (lev, k, c)
+
+
+def rounded_to_fp32(H):
+    """The hierarchy as the FP32 surface-deviation path stores it: bed and
+    surface deviation rounded to FP32 (sea level 0), depth from them."""
+    import copy
+    R = copy.deepcopy(H)
+    for p in R.patches:
+        b64 = p.b_frame
+        b32 = b64.astype(np.float32).astype(np.float64)
+        inner = b64[2:-2, 2:-2]
+        eta = np.where(p.h > 0.0, p.h + inner, inner).astype(np.float32).astype(np.float64)
+        p.b_frame = b32
+        p.h = np.where(p.h > 0.0, np.maximum(eta - b32[2:-2, 2:-2], 0.0), 0.0)
+        p.hu = p.hu.astype(np.float32).astype(np.float64)
+        p.hv = p.hv.astype(np.float32).astype(np.float64)
+    return R
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_fp32_deviation_hierarchy_within_1e5_m(gpu, ratio):
+    L, AmrSolver, torch = gpu
+    H = W.amr_three_levels(ratio, bed="shelf", amp=2.0, u0=0.3)
+    print(f"case amr three levels fp32 deviation ratio={ratio}", flush=True)
+    s = AmrSolver(H, L.params(precision=L.F32_DEV))
+    s.set_dt(6.0)
+    s.run(3)
+    torch.cuda.synchronize()
+    ref = run_oracle(rounded_to_fp32(H), 6.0, 3)
+    assert s.flags() == (0, 0)
+    worst = 0.0
+    for lev in range(1, 4):
+        pats = ref.levels[lev - 1]
+        mom = max(np.abs(p.q[2:-2, 2:-2, 1]).max() for p in pats)
+        for k, p in enumerate(pats):
+            h, hu, hv = s.state(lev, k)
+            b = p.b[2:-2, 2:-2]
+            want = p.q[2:-2, 2:-2]
+            wet = (want[..., 0] > 1e-2) & (h > 1e-2)
+            err = np.abs((h + b) - (want[..., 0] + b))[wet].max() if wet.any() else 0.0
+            worst = max(worst, err)
+            assert err <= 1e-5, (lev, k, err)
+            assert np.abs(hu - want[..., 1]).max() <= 1e-4 * mom, (lev, k)
+    print(f"fp32 deviation hierarchy: max surface difference {worst:.3e} m", flush=True)
