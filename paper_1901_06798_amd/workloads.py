@@ -288,12 +288,23 @@ class AmrHierarchy:
     ratio: int         # refinement ratio in space and time between levels
     bc: tuple          # physical boundary codes of the domain (level 1)
     patches: list
+    bed_kind: str = "shelf"
+    depth: float = 2000.0
 
     def dx(self, level: int) -> float:
         return self.dx1 / self.ratio ** (level - 1)
 
     def levels(self) -> int:
         return max(p.level for p in self.patches)
+
+    def bed_frame(self, level: int, i0: int, j0: int, mx: int, my: int) -> np.ndarray:
+        """Bed of a patch of `level` with interior i0 .. i0 + mx - 1, j0 .. j0 +
+        my - 1, on its frame with two ghost layers (the bathymetry a regridded
+        patch is given)."""
+        d = self.dx(level)
+        xf = cell_centres(mx + 4, d, (i0 - 2) * d)
+        yf = cell_centres(my + 4, d, (j0 - 2) * d)
+        return _bed(self.bed_kind, xf, yf, self.n1 * self.dx1, self.depth)
 
 
 def _bed(kind: str, xc, yc, L, depth):
@@ -328,7 +339,7 @@ def amr_hierarchy(rects, n1: int = 48, dx1: float = 2000.0, ratio: int = 2,
             h = depth_from_surface(eta, bf[2:-2, 2:-2])
             hu = u0 * h
             patches.append(AmrPatch(lev, i0, j0, mx, my, h, hu, np.zeros_like(h), bf))
-    return AmrHierarchy(n1, dx1, ratio, tuple(bc), patches)
+    return AmrHierarchy(n1, dx1, ratio, tuple(bc), patches, bed, depth)
 
 
 def amr_three_levels(ratio: int = 2, bed: str = "shelf", amp: float = 1.0, u0: float = 0.0,
