@@ -349,6 +349,51 @@ int swe_amr_average(const swe_params *p, const swe_amr_avg_op *ops, int64_t nops
                     void *q_coarse, int64_t coarse_plane_stride, const void *b_coarse,
                     void *stream);
 
+/* Regridding (Sec. 3: cells are flagged where the sea surface departs from
+ * rest, a buffer of cells around them too, the flags are clustered into
+ * rectangles that balance their number against the unflagged cells they
+ * cover, and the new patches take values from old patches of their level
+ * where those overlap, else from the level below).
+ *
+ * swe_amr_flag: flags of the interior cells of n level-l patches (device
+ * table `patches`, the level's planes q and bed b) into `flags`, a device
+ * uint8 plane with the state planes' layout (element offsets as q): 1 where
+ * a cell lies within `buffer` cells (max norm, same patch) of a wet cell
+ * (h > drytol) with |h + b - sea_level| > tol, and not within `margin`
+ * cells of the patch's edge; else 0.  max_mx, max_my bound the patch sizes. */
+int swe_amr_flag(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
+                 int32_t max_my, const void *q, const void *b, double tol, int32_t buffer,
+                 int32_t margin, uint8_t *flags, void *stream);
+
+/* swe_amr_cluster (HOST pointers, no device work): boxes covering the set
+ * flags of an mx x my field (flags[j * pitch + i] != 0), written as (i0, j0,
+ * i1, j1) inclusive to boxes[4 k ..], at most max_boxes; *nboxes = the count
+ * (also when it exceeds max_boxes, which is an error).  Recursive, on a box
+ * (first: the whole field): shrink it to the bounding box of its flags (none:
+ * no box); accept it if flagged / area >= efficiency or if neither side is
+ * at least 2 min_side long; else split it, in order of preference, at a zero
+ * of a signature (flags per column or per row) nearest the box centre, in
+ * the longer splittable dimension first (x on ties), then the smaller index;
+ * else at the strongest sign change of the signature's second difference,
+ * D(k) = sig(k - 1) - 2 sig(k) + sig(k + 1), with strength |D(s + 1) - D(s)|
+ * (ties: dimension order, nearest the centre, smaller index); else at the
+ * middle of the first splittable dimension.  A split at s keeps [lo, s] and
+ * [s + 1, hi] and needs both at least min_side long.  Boxes come in the
+ * order of the recursion (the lower part first). */
+int swe_amr_cluster(const uint8_t *flags, int32_t mx, int32_t my, int32_t pitch,
+                    double efficiency, int32_t min_side, int32_t *boxes, int32_t max_boxes,
+                    int32_t *nboxes);
+
+/* swe_amr_init: the interior cells of new patches of a level, as listed in
+ * ops: SWE_AMR_COPY entries take q_old[src] (an old patch of the same level
+ * that covers the cell; q_old may be NULL when there are none), SWE_AMR_COARSE
+ * entries the rule of swe_amr_fill with alpha = 1 and the one coarse state
+ * q_coarse.  q_new must differ from both sources. */
+int swe_amr_init(const swe_params *p, const swe_amr_fill_op *ops, int64_t nops, void *q_new,
+                 int64_t new_plane_stride, const void *b_new, const void *q_old,
+                 int64_t old_plane_stride, const void *q_coarse, int64_t coarse_plane_stride,
+                 const void *b_coarse, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);
 

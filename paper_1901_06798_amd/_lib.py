@@ -9,6 +9,8 @@ built, importing the binding fails loudly: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+
+import numpy as np
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -109,6 +111,10 @@ def lib():
         i64, dbl = ctypes.c_int64, ctypes.c_double
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
         L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
+        L.swe_amr_flag.argtypes = [pp, _P, i32, i32, i32, _P, _P, dbl, i32, i32, _P, _P]
+        L.swe_amr_cluster.argtypes = [_P, i32, i32, i32, dbl, i32, _P, i32,
+                                      ctypes.POINTER(i32)]
+        L.swe_amr_init.argtypes = [pp, _P, i64, _P, i64, _P, _P, i64, _P, i64, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
@@ -121,7 +127,8 @@ def lib():
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
                      "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
-                     "swe_amr_fill", "swe_amr_average"):
+                     "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
+                     "swe_amr_init"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -174,6 +181,37 @@ def swe_amr_average(p: swe_params, ops: int, nops: int, ratio: int, q_fine: int,
     _check(lib().swe_amr_average(ctypes.byref(p), ops, nops, ratio, q_fine, fine_plane_stride,
                                  b_fine, q_coarse, coarse_plane_stride, b_coarse, stream),
            "swe_amr_average")
+
+
+def swe_amr_flag(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int, b: int,
+                 tol: float, buffer: int, margin: int, flags: int, stream: int = 0) -> None:
+    _check(lib().swe_amr_flag(ctypes.byref(p), patches, n, max_mx, max_my, q, b, float(tol),
+                              buffer, margin, flags, stream), "swe_amr_flag")
+
+
+def swe_amr_cluster(flags, efficiency: float = 0.7, min_side: int = 2):
+    """Boxes (i0, j0, i1, j1) of a host uint8 array flags[j, i] (C order)."""
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    my, mx = f.shape
+    n = ctypes.c_int32(0)
+    cap = 64
+    while True:
+        out = np.zeros(4 * cap, dtype=np.int32)
+        rc = lib().swe_amr_cluster(f.ctypes.data, mx, my, mx, float(efficiency), min_side,
+                                   out.ctypes.data, cap, ctypes.byref(n))
+        if rc == SWE_OK:
+            return [tuple(int(v) for v in out[4 * k: 4 * k + 4]) for k in range(n.value)]
+        if n.value <= cap:
+            _check(rc, "swe_amr_cluster")
+        cap = n.value
+
+
+def swe_amr_init(p: swe_params, ops: int, nops: int, q_new: int, new_plane_stride: int,
+                 b_new: int, q_old: int, old_plane_stride: int, q_coarse: int,
+                 coarse_plane_stride: int, b_coarse: int, stream: int = 0) -> None:
+    _check(lib().swe_amr_init(ctypes.byref(p), ops, nops, q_new, new_plane_stride, b_new, q_old,
+                              old_plane_stride, q_coarse, coarse_plane_stride, b_coarse, stream),
+           "swe_amr_init")
 
 
 def swe_ghost_fill(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,

@@ -108,6 +108,36 @@ def average_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
     return np.concatenate(ops) if ops else np.zeros(0, dtype=AVG_DTYPE)
 
 
+def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
+    """Interior cells of new patches: copies from old patches of the level
+    where they cover the cell, else the cell of the level below."""
+    ops = []
+    for k in range(len(new.i0)):
+        rows, cols = np.meshgrid(np.arange(2, new.my[k] + 2), np.arange(2, new.mx[k] + 2),
+                                 indexing="ij")
+        rows, cols = rows.ravel(), cols.ravel()
+        I = new.i0[k] + cols - 2
+        J = new.j0[k] + rows - 2
+        same = old.covering(I, J) if old is not None else np.full(I.shape, -1)
+        Ic, Jc = I // r, J // r
+        below = coarse.covering(Ic, Jc)
+        if np.any((same < 0) & (below < 0)):
+            raise L.SweError(f"new patch {k} is not over the level below")
+        op = np.zeros(I.size, dtype=FILL_DTYPE)
+        op["dst"] = new.off[k] + rows * new.pitch[k] + cols
+        cp = same >= 0
+        for s in np.unique(same[cp]):
+            m = same == s
+            op["src"][m] = old.elem(s, I[m], J[m])
+        op["kind"][cp] = L.SWE_AMR_COPY
+        for c in np.unique(below[~cp]):
+            m = (~cp) & (below == c)
+            op["src"][m] = coarse.elem(c, Ic[m], Jc[m])
+        op["kind"][~cp] = L.SWE_AMR_COARSE
+        ops.append(op)
+    return np.concatenate(ops) if ops else np.zeros(0, dtype=FILL_DTYPE)
+
+
 class AmrSolver:
     def __init__(self, H: AmrHierarchy, params: L.swe_params | None = None,
                  device: str = "cuda:0", rows=None):
@@ -116,26 +146,36 @@ class AmrSolver:
         self.r = H.ratio
         self.dev = torch.device(device)
         self.nlev = H.levels()
+        # 8-row tasks: a level's launch then holds enough waves to fill the
+        # device (32-row tasks left most wave slots idle and were 1.6 x slower
+        # on the bench hierarchy)
+        self.rows = list(rows) if rows is not None else [8] * self.nlev
         self.levels, self.geo, self.lpatches = [], [], []
         for lev in range(1, self.nlev + 1):
             ps = [p for p in H.patches if p.level == lev]
-            bc = H.bc if lev == 1 else (BC_USER,) * 4
-            d = H.dx(lev)
-            probs = [Problem(f"l{lev}p{k}", p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2], d, d, bc,
-                             meta={"level": lev}) for k, p in enumerate(ps)]
-            # 8-row tasks: a level's launch then holds enough waves to fill the
-            # device (32-row tasks left most wave slots idle and were 1.6 x
-            # slower on the bench hierarchy)
-            H_rows = rows[lev - 1] if rows is not None else 8
-            bs = BatchedSolver(probs, self.p, sched=L.schedule(seg=64, rows_per_task=H_rows),
-                               device=device)
-            if lev > 1:  # the bed of the ghost frame (user sides are read from memory)
-                for k, p in enumerate(ps):
-                    bs._view(bs.b, k, 1)[0][:, : p.mx + 4] = torch.from_numpy(
-                        np.ascontiguousarray(p.b_frame)).to(self.dev)
+            bs = self._level_solver(lev, ps)
             self.levels.append(bs)
             self.lpatches.append(ps)
             self.geo.append(_Geo(ps, bs))
+        self._plans()
+        self.dts = torch.zeros(self.nlev, dtype=torch.float64, device=self.dev)
+        self.graph = None
+
+    def _level_solver(self, lev: int, ps) -> BatchedSolver:
+        bc = self.H.bc if lev == 1 else (BC_USER,) * 4
+        d = self.H.dx(lev)
+        probs = [Problem(f"l{lev}p{k}", p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2], d, d, bc,
+                         meta={"level": lev}) for k, p in enumerate(ps)]
+        bs = BatchedSolver(probs, self.p,
+                           sched=L.schedule(seg=64, rows_per_task=self.rows[lev - 1]),
+                           device=self.dev)
+        if lev > 1:  # the bed of the ghost frame (user sides are read from memory)
+            for k, p in enumerate(ps):
+                bs._view(bs.b, k, 1)[0][:, : p.mx + 4] = torch.from_numpy(
+                    np.ascontiguousarray(p.b_frame)).to(self.dev)
+        return bs
+
+    def _plans(self) -> None:
         self.fill_ops, self.avg_ops, self.nfill, self.navg = [None], [], [0], []
         for lev in range(1, self.nlev):
             f = fill_plan(self.geo[lev], self.geo[lev - 1], self.r)
@@ -144,8 +184,63 @@ class AmrSolver:
             self.avg_ops.append(torch.from_numpy(a.view(np.uint8).copy()).to(self.dev))
             self.nfill.append(f.size)
             self.navg.append(a.size)
-        self.dts = torch.zeros(self.nlev, dtype=torch.float64, device=self.dev)
+
+    # -- regridding --------------------------------------------------------------
+    def refine_flags(self, lev: int, tol: float = 5e-3, buffer: int = 2) -> torch.Tensor:
+        """Refinement flags of level lev (device uint8 plane, the level's layout)."""
+        bs = self.levels[lev - 1]
+        margin = 2 if self.r == 1 else 1
+        out = torch.zeros(bs.plane, dtype=torch.uint8, device=self.dev)
+        L.swe_amr_flag(self.p, bs.table.data_ptr(), bs.n, bs.max_mx, bs.max_my,
+                       bs.pools[bs.cur].data_ptr(), bs.b.data_ptr(), tol, buffer, margin,
+                       out.data_ptr(), self.stream)
+        return out
+
+    def regrid(self, tol: float = 5e-3, buffer: int = 2, efficiency: float = 0.7,
+               min_side: int = 2) -> list:
+        """Regrid levels 2 and finer from the current (synchronised) state:
+        flags on the device, clustering on the host, new patches filled on the
+        device from the old ones of their level where those overlap, else from
+        the level below (which is regridded first).  Host work; returns the
+        new rectangles (i0, j0, mx, my) per level."""
+        from .workloads import AmrPatch
+        r = self.r
+        for lev in range(2, self.nlev + 1):
+            parent, pps = self.levels[lev - 2], self.lpatches[lev - 2]
+            fh = self.refine_flags(lev - 1, tol, buffer).cpu().numpy()
+            rects = []
+            for k, p in enumerate(pps):
+                pitch, off = parent.layout[k][0], parent.offs[k]
+                F = fh[off: off + pitch * (p.my + 4)].reshape(p.my + 4, pitch)
+                for (a, b_, c, d) in L.swe_amr_cluster(F[2: p.my + 2, 2: p.mx + 2],
+                                                       efficiency, min_side):
+                    rects.append(((p.i0 + a) * r, (p.j0 + b_) * r, (c - a + 1) * r,
+                                  (d - b_ + 1) * r))
+            if not rects:  # nothing to refine: this level and the finer ones end
+                self.nlev = lev - 1
+                del self.levels[lev - 1:], self.geo[lev - 1:], self.lpatches[lev - 1:]
+                del self.rows[lev - 1:]
+                break
+            new_ps = []
+            for (i0, j0, mx, my) in rects:
+                z = np.zeros((my, mx))
+                new_ps.append(AmrPatch(lev, i0, j0, mx, my, z, z, z,
+                                       self.H.bed_frame(lev, i0, j0, mx, my)))
+            bs = self._level_solver(lev, new_ps)
+            geo = _Geo(new_ps, bs)
+            old_bs, old_geo = self.levels[lev - 1], self.geo[lev - 1]
+            ops = init_plan(geo, old_geo, self.geo[lev - 2], r)
+            dev_ops = torch.from_numpy(ops.view(np.uint8).copy()).to(self.dev)
+            L.swe_amr_init(self.p, dev_ops.data_ptr(), ops.size, bs.pools[bs.cur].data_ptr(),
+                           bs.plane, bs.b.data_ptr(), old_bs.pools[old_bs.cur].data_ptr(),
+                           old_bs.plane, parent.pools[parent.cur].data_ptr(), parent.plane,
+                           parent.b.data_ptr(), self.stream)
+            torch.cuda.synchronize(self.dev)  # dev_ops and the old level are released
+            self.levels[lev - 1], self.geo[lev - 1], self.lpatches[lev - 1] = bs, geo, new_ps
+        self._plans()
+        self.dts = self.dts[: self.nlev].clone()
         self.graph = None
+        return [[(p.i0, p.j0, p.mx, p.my) for p in ps] for ps in self.lpatches]
 
     @property
     def stream(self) -> int:
@@ -229,4 +324,4 @@ class AmrSolver:
         return f, c
 
     def cells_per_coarse_step(self) -> int:
-        return sum(p.mx * p.my * self.r ** (p.level - 1) for p in self.H.patches)
+        return sum(p.mx * p.my * self.r ** (p.level - 1) for ps in self.lpatches for p in ps)

@@ -14,8 +14,11 @@
 // cells, which no entry writes.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
+#include <vector>
 
 #include "swe.h"
 
@@ -26,6 +29,8 @@ struct FillArgs {
     int64_t nops;
     void* qf;
     int64_t psf;
+    const void* qcopy;  // planes SWE_AMR_COPY entries read (qf for ghost fills)
+    int64_t pscopy;
     const void* bf;
     const void* qco;
     const void* qcn;
@@ -66,10 +71,10 @@ __global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
         const swe_amr_fill_op op = a.ops[i];
         S* q = qf + op.dst;
         if (op.kind == SWE_AMR_COPY) {
-            const S* src = qf + op.src;
+            const S* src = static_cast<const S*>(a.qcopy) + op.src;
             q[0] = src[0];
-            q[a.psf] = src[a.psf];
-            q[2 * a.psf] = src[2 * a.psf];
+            q[a.psf] = src[a.pscopy];
+            q[2 * a.psf] = src[2 * a.pscopy];
             continue;
         }
         const double ho = depth(qco, bc, op.src, a.sea), hn = depth(qcn, bc, op.src, a.sea);
@@ -158,6 +163,43 @@ __global__ void __launch_bounds__(256) k_amr_average(AvgArgs a) {
     }
 }
 
+// Refinement flags of the interior cells of level-l patches (one block row
+// per patch): a wet cell whose surface departs from rest by more than tol
+// flags itself and every cell within `buffer` cells (max norm) of the same
+// patch; cells within `margin` cells of the patch's edge are never flagged.
+// A cell gathers its window rather than flagged cells scattering theirs, so
+// every flag is written once.
+template <typename S>
+__global__ void __launch_bounds__(256) k_amr_flag(const swe_patch* __restrict__ patches,
+                                                  const S* __restrict__ q,
+                                                  const S* __restrict__ b,
+                                                  uint8_t* __restrict__ flags, double tol,
+                                                  double drytol, double sea, int buffer,
+                                                  int margin) {
+    const swe_patch p = patches[blockIdx.y];
+    const int64_t ncell = (int64_t)p.mx * p.my;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % p.mx), j = (int)(c / p.mx);
+        const int64_t at = p.off + (int64_t)(j + 2) * p.pitch + (i + 2);
+        bool f = false;
+        if (i >= margin && i < p.mx - margin && j >= margin && j < p.my - margin) {
+            const int j0 = j - buffer > 0 ? j - buffer : 0;
+            const int j1 = j + buffer < p.my - 1 ? j + buffer : p.my - 1;
+            const int i0 = i - buffer > 0 ? i - buffer : 0;
+            const int i1 = i + buffer < p.mx - 1 ? i + buffer : p.mx - 1;
+            for (int jj = j0; jj <= j1 && !f; ++jj)
+                for (int ii = i0; ii <= i1 && !f; ++ii) {
+                    const int64_t k = p.off + (int64_t)(jj + 2) * p.pitch + (ii + 2);
+                    const double h = depth(q, b, k, sea);
+                    const double dev = h + double(b[k]) - sea;
+                    f = h > drytol && (dev > tol || -dev > tol);
+                }
+        }
+        flags[at] = f ? 1 : 0;
+    }
+}
+
 }  // namespace swe
 
 extern "C" __attribute__((visibility("hidden"))) int swe_internal_set_error(int code,
@@ -172,6 +214,114 @@ int check_launch(const char* what) {
     if (e != hipSuccess) return afail(SWE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     return SWE_OK;
 }
+
+// Flag clustering on the host (the recursive reading stated in swe.h).
+struct Box {
+    int i0, j0, i1, j1;
+};
+
+class Clusterer {
+  public:
+    Clusterer(const uint8_t* f, int64_t pitch, double eff, int min_side)
+        : f_(f), pitch_(pitch), eff_(eff), min_side_(min_side) {}
+    std::vector<Box> boxes;
+
+    void run(Box bx) {
+        int i0 = INT_MAX, j0 = INT_MAX, i1 = -1, j1 = -1;
+        long n = 0;
+        for (int j = bx.j0; j <= bx.j1; ++j)
+            for (int i = bx.i0; i <= bx.i1; ++i)
+                if (on(i, j)) {
+                    ++n;
+                    i0 = i < i0 ? i : i0;
+                    i1 = i > i1 ? i : i1;
+                    j0 = j < j0 ? j : j0;
+                    j1 = j > j1 ? j : j1;
+                }
+        if (n == 0) return;
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        const bool can[2] = {w >= 2 * min_side_, h >= 2 * min_side_};
+        if ((double)n / ((double)w * (double)h) >= eff_ || !(can[0] || can[1])) {
+            boxes.push_back(Box{i0, j0, i1, j1});
+            return;
+        }
+        // signatures: flags per column (dimension 0) and per row (dimension 1)
+        std::vector<long> sig[2] = {std::vector<long>(w, 0), std::vector<long>(h, 0)};
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i)
+                if (on(i, j)) {
+                    ++sig[0][i - i0];
+                    ++sig[1][j - j0];
+                }
+        const int lo[2] = {i0, j0}, hi[2] = {i1, j1};
+        int order[2], nd = 0;  // splittable dimensions, longer side first (x on ties)
+        const int first = w >= h ? 0 : 1;
+        if (can[first]) order[nd++] = first;
+        if (can[1 - first]) order[nd++] = 1 - first;
+        int dim = -1, cut = 0;
+        // a hole nearest the centre, in the first dimension that has one
+        for (int r = 0; r < nd && dim < 0; ++r) {
+            const int d = order[r];
+            long best = -1;
+            for (int s = lo[d]; s <= hi[d]; ++s) {
+                if (sig[d][s - lo[d]] != 0 || !allowed(lo[d], hi[d], s)) continue;
+                const long dist = std::labs(2L * s - (lo[d] + hi[d]));
+                if (best < 0 || dist < best) {
+                    best = dist;
+                    dim = d;
+                    cut = s;
+                }
+            }
+        }
+        // the strongest inflection over the dimensions
+        if (dim < 0) {
+            long bs = -1, bdist = 0;
+            int brank = 0;
+            for (int r = 0; r < nd; ++r) {
+                const int d = order[r];
+                const std::vector<long>& g = sig[d];
+                auto lap = [&](int k) { return g[k - 1 - lo[d]] - 2 * g[k - lo[d]] + g[k + 1 - lo[d]]; };
+                for (int s = lo[d] + 1; s <= hi[d] - 2; ++s) {
+                    const long a = lap(s), c = lap(s + 1);
+                    if (!((a < 0 && c > 0) || (a > 0 && c < 0)) || !allowed(lo[d], hi[d], s))
+                        continue;
+                    const long strength = std::labs(c - a);
+                    const long dist = std::labs(2L * s - (lo[d] + hi[d]));
+                    const bool better =
+                        bs < 0 || strength > bs ||
+                        (strength == bs &&
+                         (r < brank || (r == brank && (dist < bdist || (dist == bdist && s < cut)))));
+                    if (better) {
+                        bs = strength;
+                        brank = r;
+                        bdist = dist;
+                        dim = d;
+                        cut = s;
+                    }
+                }
+            }
+        }
+        if (dim < 0) {  // bisect the first dimension
+            dim = order[0];
+            cut = (lo[dim] + hi[dim]) / 2;
+        }
+        if (dim == 0) {
+            run(Box{i0, j0, cut, j1});
+            run(Box{cut + 1, j0, i1, j1});
+        } else {
+            run(Box{i0, j0, i1, cut});
+            run(Box{i0, cut + 1, i1, j1});
+        }
+    }
+
+  private:
+    bool on(int i, int j) const { return f_[(int64_t)j * pitch_ + i] != 0; }
+    bool allowed(int lo, int hi, int s) const { return lo + min_side_ - 1 <= s && s <= hi - min_side_; }
+    const uint8_t* f_;
+    int64_t pitch_;
+    double eff_;
+    int min_side_;
+};
 
 int grid_for(int64_t n) {
     const int64_t blocks = (n + 255) / 256;
@@ -202,6 +352,8 @@ int swe_amr_fill(const swe_params* p, const swe_amr_fill_op* ops, int64_t nops, 
     a.nops = nops;
     a.qf = q_fine;
     a.psf = fine_plane_stride;
+    a.qcopy = q_fine;
+    a.pscopy = fine_plane_stride;
     a.bf = b_fine;
     a.qco = q_coarse_old;
     a.qcn = q_coarse_new;
@@ -250,6 +402,89 @@ int swe_amr_average(const swe_params* p, const swe_amr_avg_op* ops, int64_t nops
     else
         hipLaunchKernelGGL(swe::k_amr_average<float>, dim3(grid_for(nops)), dim3(256), 0, st, a);
     return check_launch("swe_amr_average");
+}
+
+int swe_amr_cluster(const uint8_t* flags, int32_t mx, int32_t my, int32_t pitch,
+                    double efficiency, int32_t min_side, int32_t* boxes, int32_t max_boxes,
+                    int32_t* nboxes) {
+    if (!flags || !nboxes || mx < 1 || my < 1 || pitch < mx || min_side < 1 ||
+        !(efficiency > 0.0) || !(efficiency <= 1.0) || max_boxes < 0 || (max_boxes > 0 && !boxes))
+        return afail(SWE_EINVAL, "swe_amr_cluster: bad arguments");
+    Clusterer c(flags, pitch, efficiency, min_side);
+    c.run(Box{0, 0, mx - 1, my - 1});
+    *nboxes = (int32_t)c.boxes.size();
+    if ((int32_t)c.boxes.size() > max_boxes)
+        return afail(SWE_EINVAL, "swe_amr_cluster: more boxes than max_boxes (count in *nboxes)");
+    for (size_t k = 0; k < c.boxes.size(); ++k) {
+        boxes[4 * k] = c.boxes[k].i0;
+        boxes[4 * k + 1] = c.boxes[k].j0;
+        boxes[4 * k + 2] = c.boxes[k].i1;
+        boxes[4 * k + 3] = c.boxes[k].j1;
+    }
+    return SWE_OK;
+}
+
+int swe_amr_init(const swe_params* p, const swe_amr_fill_op* ops, int64_t nops, void* q_new,
+                 int64_t new_plane_stride, const void* b_new, const void* q_old,
+                 int64_t old_plane_stride, const void* q_coarse, int64_t coarse_plane_stride,
+                 const void* b_coarse, void* stream) {
+    if (!p) return afail(SWE_EINVAL, "params is NULL");
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+        return afail(SWE_EINVAL, "swe_amr_init: unknown precision");
+    if (nops < 0 || new_plane_stride < 1 || coarse_plane_stride < 1 ||
+        (q_old && old_plane_stride < 1))
+        return afail(SWE_EINVAL, "swe_amr_init: bad count or plane stride");
+    if (nops == 0) return SWE_OK;
+    if (!ops || !q_new || !b_new || !q_coarse || !b_coarse)
+        return afail(SWE_EINVAL, "swe_amr_init: null pointer");
+    if (q_new == q_coarse || q_new == q_old)
+        return afail(SWE_EINVAL, "swe_amr_init: the new planes must differ from the sources");
+    swe::FillArgs a;
+    a.ops = ops;
+    a.nops = nops;
+    a.qf = q_new;
+    a.psf = new_plane_stride;
+    a.qcopy = q_old ? q_old : q_new;
+    a.pscopy = q_old ? old_plane_stride : new_plane_stride;
+    a.bf = b_new;
+    a.qco = q_coarse;
+    a.qcn = q_coarse;
+    a.psc = coarse_plane_stride;
+    a.bc = b_coarse;
+    a.alpha = 1.0;
+    a.drytol = p->drytol;
+    a.sea = p->sea_level;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_amr_fill<double>, dim3(grid_for(nops)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(swe::k_amr_fill<float>, dim3(grid_for(nops)), dim3(256), 0, st, a);
+    return check_launch("swe_amr_init");
+}
+
+int swe_amr_flag(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
+                 int32_t max_my, const void* q, const void* b, double tol, int32_t buffer,
+                 int32_t margin, uint8_t* flags, void* stream) {
+    if (!p) return afail(SWE_EINVAL, "params is NULL");
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+        return afail(SWE_EINVAL, "swe_amr_flag: unknown precision");
+    if (n < 0 || max_mx < 1 || max_my < 1 || buffer < 0 || margin < 0 || !(tol >= 0.0))
+        return afail(SWE_EINVAL, "swe_amr_flag: bad count, size, buffer, margin or tol");
+    if (n == 0) return SWE_OK;
+    if (!patches || !q || !b || !flags) return afail(SWE_EINVAL, "swe_amr_flag: null pointer");
+    const int64_t ncell = (int64_t)max_mx * max_my;
+    const int64_t bx64 = (ncell + 255) / 256;
+    const dim3 grid((unsigned)(bx64 < 1024 ? bx64 : 1024), (unsigned)n);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_amr_flag<double>, grid, dim3(256), 0, st, patches,
+                           static_cast<const double*>(q), static_cast<const double*>(b), flags,
+                           tol, p->drytol, p->sea_level, buffer, margin);
+    else
+        hipLaunchKernelGGL(swe::k_amr_flag<float>, grid, dim3(256), 0, st, patches,
+                           static_cast<const float*>(q), static_cast<const float*>(b), flags,
+                           tol, p->drytol, p->sea_level, buffer, margin);
+    return check_launch("swe_amr_flag");
 }
 
 }  // extern "C"
