@@ -404,10 +404,26 @@ def time_amr(ncoarse: int = 10, dt1: float = 8.0, precision: int = 0):
     ms = t0.elapsed_time(t1) / (2 * (ncoarse // 2))
     upd = s.cells_per_coarse_step()
     npatch = [sum(1 for p in H.patches if p.level == lev) for lev in (1, 2, 3)]
-    return {"patches_per_level": npatch, "ratio": H.ratio, "level1_cells": H.n1 * H.n1,
+    nfill, navg = list(s.nfill[1:]), list(s.navg)
+    # regrid from the current state (flag |eta| > 0.5 m, buffer 2, efficiency
+    # 0.7), then eager coarse steps on the new hierarchy
+    rects = s.regrid(tol=0.5, buffer=2, efficiency=0.7)
+    regrid = {"tol_m": 0.5, "patches_per_level": [len(x) for x in rects],
+              "wall_ms": s.last_regrid_ms,
+              "cell_updates_per_coarse_step": s.cells_per_coarse_step()}
+    torch.cuda.synchronize()
+    t0.record()
+    s.run(4)
+    t1.record()
+    torch.cuda.synchronize()
+    regrid["ms_per_coarse_step_after"] = t0.elapsed_time(t1) / 4
+    regrid["cups_after"] = regrid["cell_updates_per_coarse_step"] / (
+        regrid["ms_per_coarse_step_after"] * 1e-3)
+    regrid["flags_after"] = s.flags()[0]
+    return {"regrid": regrid, "patches_per_level": npatch, "ratio": H.ratio, "level1_cells": H.n1 * H.n1,
             "cell_updates_per_coarse_step": upd, "ms_per_coarse_step": ms,
             "ms_per_coarse_step_eager": eager_ms, "cups": upd / (ms * 1e-3),
-            "ghost_fill_cells_per_substep": s.nfill[1:], "averaged_cells": s.navg,
+            "ghost_fill_cells_per_substep": nfill, "averaged_cells": navg,
             "max_courant": s.courant(), "flags": s.flags()[0],
             "dt_level1_s": dt1, "coarse_steps_timed": 2 * (ncoarse // 2)}
 

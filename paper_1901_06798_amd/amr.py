@@ -108,33 +108,46 @@ def average_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
     return np.concatenate(ops) if ops else np.zeros(0, dtype=AVG_DTYPE)
 
 
+def cover_block(geo: _Geo, i0: int, j0: int, nx: int, ny: int, r: int = 1) -> np.ndarray:
+    """Patch of `geo` whose interior holds cell (I // r, J // r), for the cells
+    I in [i0, i0 + nx), J in [j0, j0 + ny) of a level r times finer (-1: none);
+    by rectangle intersection, first patch in order."""
+    out = np.full((ny, nx), -1, dtype=np.int64)
+    for k in range(len(geo.i0)):
+        a = max(i0, geo.i0[k] * r)
+        b = min(i0 + nx, (geo.i0[k] + geo.mx[k]) * r)
+        c = max(j0, geo.j0[k] * r)
+        d = min(j0 + ny, (geo.j0[k] + geo.my[k]) * r)
+        if a < b and c < d:
+            blk = out[c - j0: d - j0, a - i0: b - i0]
+            blk[blk < 0] = k
+    return out
+
+
 def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
     """Interior cells of new patches: copies from old patches of the level
     where they cover the cell, else the cell of the level below."""
     ops = []
     for k in range(len(new.i0)):
-        rows, cols = np.meshgrid(np.arange(2, new.my[k] + 2), np.arange(2, new.mx[k] + 2),
-                                 indexing="ij")
-        rows, cols = rows.ravel(), cols.ravel()
-        I = new.i0[k] + cols - 2
-        J = new.j0[k] + rows - 2
-        same = old.covering(I, J) if old is not None else np.full(I.shape, -1)
-        Ic, Jc = I // r, J // r
-        below = coarse.covering(Ic, Jc)
+        mx, my = int(new.mx[k]), int(new.my[k])
+        J, I = np.mgrid[new.j0[k]: new.j0[k] + my, new.i0[k]: new.i0[k] + mx]
+        same = (cover_block(old, new.i0[k], new.j0[k], mx, my) if old is not None
+                else np.full((my, mx), -1, dtype=np.int64))
+        below = cover_block(coarse, new.i0[k], new.j0[k], mx, my, r)
         if np.any((same < 0) & (below < 0)):
             raise L.SweError(f"new patch {k} is not over the level below")
-        op = np.zeros(I.size, dtype=FILL_DTYPE)
-        op["dst"] = new.off[k] + rows * new.pitch[k] + cols
+        op = np.zeros((my, mx), dtype=FILL_DTYPE)
+        op["dst"] = (new.off[k] + (J - new.j0[k] + 2) * new.pitch[k] + (I - new.i0[k] + 2))
         cp = same >= 0
-        for s in np.unique(same[cp]):
-            m = same == s
-            op["src"][m] = old.elem(s, I[m], J[m])
+        for s_ in np.unique(same[cp]):
+            m = same == s_
+            op["src"][m] = old.elem(s_, I[m], J[m])
         op["kind"][cp] = L.SWE_AMR_COPY
         for c in np.unique(below[~cp]):
             m = (~cp) & (below == c)
-            op["src"][m] = coarse.elem(c, Ic[m], Jc[m])
+            op["src"][m] = coarse.elem(c, I[m] // r, J[m] // r)
         op["kind"][~cp] = L.SWE_AMR_COARSE
-        ops.append(op)
+        ops.append(op.ravel())
     return np.concatenate(ops) if ops else np.zeros(0, dtype=FILL_DTYPE)
 
 
@@ -203,11 +216,17 @@ class AmrSolver:
         device from the old ones of their level where those overlap, else from
         the level below (which is regridded first).  Host work; returns the
         new rectangles (i0, j0, mx, my) per level."""
+        import time
+
         from .workloads import AmrPatch
         r = self.r
+        t_start = time.perf_counter()
+        t_flag = t_cluster = t_pool = 0.0
         for lev in range(2, self.nlev + 1):
             parent, pps = self.levels[lev - 2], self.lpatches[lev - 2]
+            t0 = time.perf_counter()
             fh = self.refine_flags(lev - 1, tol, buffer).cpu().numpy()
+            t1 = time.perf_counter()
             rects = []
             for k, p in enumerate(pps):
                 pitch, off = parent.layout[k][0], parent.offs[k]
@@ -216,11 +235,14 @@ class AmrSolver:
                                                        efficiency, min_side):
                     rects.append(((p.i0 + a) * r, (p.j0 + b_) * r, (c - a + 1) * r,
                                   (d - b_ + 1) * r))
+            t_flag += t1 - t0
+            t_cluster += time.perf_counter() - t1
             if not rects:  # nothing to refine: this level and the finer ones end
                 self.nlev = lev - 1
                 del self.levels[lev - 1:], self.geo[lev - 1:], self.lpatches[lev - 1:]
                 del self.rows[lev - 1:]
                 break
+            t2 = time.perf_counter()
             new_ps = []
             for (i0, j0, mx, my) in rects:
                 z = np.zeros((my, mx))
@@ -229,6 +251,8 @@ class AmrSolver:
             bs = self._level_solver(lev, new_ps)
             geo = _Geo(new_ps, bs)
             old_bs, old_geo = self.levels[lev - 1], self.geo[lev - 1]
+            t3 = time.perf_counter()
+            t_pool += t3 - t2
             ops = init_plan(geo, old_geo, self.geo[lev - 2], r)
             dev_ops = torch.from_numpy(ops.view(np.uint8).copy()).to(self.dev)
             L.swe_amr_init(self.p, dev_ops.data_ptr(), ops.size, bs.pools[bs.cur].data_ptr(),
@@ -240,6 +264,14 @@ class AmrSolver:
         self._plans()
         self.dts = self.dts[: self.nlev].clone()
         self.graph = None
+        torch.cuda.synchronize(self.dev)
+        total = time.perf_counter() - t_start
+        # wall-clock phases of this regrid: flags (device, with the copy to the
+        # host), clustering (host), new pools with their bed, and the fill of
+        # the new cells with the coupling plans
+        self.last_regrid_ms = {"total": 1e3 * total, "flags": 1e3 * t_flag,
+                               "cluster": 1e3 * t_cluster, "pools": 1e3 * t_pool,
+                               "fill_and_plans": 1e3 * (total - t_flag - t_cluster - t_pool)}
         return [[(p.i0, p.j0, p.mx, p.my) for p in ps] for ps in self.lpatches]
 
     @property
