@@ -86,6 +86,8 @@ def lib():
         L.orc_ghost_fill_b.argtypes = [G, _D]
         L.orc_step.argtypes = [P, G, _D, _D, d, _D, _D, ctypes.POINTER(i32)]
         L.orc_step.restype = i64
+        L.orc_step_sphere.argtypes = [P, G, _D, _D, d, _D, _D, _D, _D, ctypes.POINTER(i32)]
+        L.orc_step_sphere.restype = i64
         L.orc_speed_scan.argtypes = [P, G, _D, _D, _D]
         L.orc_run.argtypes = [P, G, _D, _D, i32, d, _D, _D, ctypes.POINTER(i32),
                               ctypes.POINTER(i32)]
@@ -177,6 +179,33 @@ def step(p: Params, g: Grid, q: np.ndarray, b: np.ndarray, dt: float):
     nf = ctypes.c_int32(0)
     c = lib().orc_step(ctypes.byref(p), ctypes.byref(g), _ptr(q), _ptr(b), float(dt),
                        _ptr(out), _ptr(smax), ctypes.byref(nf))
+    return out, smax, int(c), int(nf.value)
+
+
+def sphere_metric(lat0_deg: float, dlat_deg: float, my: int):
+    """Capacities kap[j] (rows j = 0 .. my + 3 of the ghost frame) and edge
+    length ratios len[e] = cos(latitude of the edge between rows e - 1 and e),
+    e = 0 .. my + 4, of a latitude-longitude patch whose first interior row
+    starts at latitude lat0_deg (rows are dlat_deg high).  The capacity is the
+    cell area over its area at the equator: (sin phi_top - sin phi_bottom) /
+    dphi."""
+    d = np.deg2rad(dlat_deg)
+    edge = np.array([np.deg2rad(lat0_deg + (j - 2) * dlat_deg) for j in range(my + 5)])
+    kap = np.array([(np.sin(edge[j + 1]) - np.sin(edge[j])) / d for j in range(my + 4)])
+    ln = np.array([np.cos(edge[e]) for e in range(my + 5)])
+    return kap, ln
+
+
+def step_sphere(p: Params, g: Grid, q: np.ndarray, b: np.ndarray, dt: float, kap, ln):
+    """One split step of a latitude-longitude patch (g.dx, g.dy: R dlon, R dlat).
+    Returns (q_out, smax, clamps, nonfinite)."""
+    out = np.empty_like(q)
+    smax = np.zeros(2)
+    nf = ctypes.c_int32(0)
+    k = np.ascontiguousarray(kap, dtype=np.float64)
+    ln_ = np.ascontiguousarray(ln, dtype=np.float64)
+    c = lib().orc_step_sphere(ctypes.byref(p), ctypes.byref(g), _ptr(q), _ptr(b), float(dt),
+                              _ptr(k), _ptr(ln_), _ptr(out), _ptr(smax), ctypes.byref(nf))
     return out, smax, int(c), int(nf.value)
 
 

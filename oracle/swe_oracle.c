@@ -328,6 +328,8 @@ void orc_ghost_fill_b(const orc_grid *G, double *b) { fill_generic(G, b, 1, 0); 
 /* One 1D line of a sweep.  line[c] = (h, normal mom., transverse mom., b) for
  * c = 0 .. n + 3 (two ghosts each side).  Cells c = 2 .. n + 1 are updated
  * into out[c][0..2].  Edge e lies between cells e - 1 and e. */
+static void friction(const orc_params *P, const orc_grid *G, double *q, double dt);
+
 typedef struct {
     orc_waves *w;       /* n + 4 */
     double (*amdq)[3];
@@ -480,6 +482,132 @@ static int64_t split_step(const orc_params *P, const orc_grid *G, const double *
     free(qs);
     smax[0] = sx;
     smax[1] = sy;
+    return clamps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Latitude-longitude patches (an extension; the paper's runs use such grids
+ * but state no formulas).  Cells are Dlon x Dlat on a sphere of radius R;
+ * the momentum equations keep the pressure gradient exact (the edge-scaled
+ * fluctuations supply its metric part) and drop the curvature terms of size
+ * u^2 / R; the mass equation is corrected to the conservative form.
+ * dx = R Dlon and dy = R Dlat are their extents at the equator.  A cell's
+ * area is kappa dx dy with the capacity kappa_j = (sin phi_{j+1/2} -
+ * sin phi_{j-1/2}) / Dlat; a meridian edge is dy long, a parallel edge at
+ * phi_{e-1/2} is len_e dx long with len_e = cos phi_{e-1/2}.  A cell changes
+ * by dt / (kappa dx dy) times the sum over its edges of edge length times
+ * what enters through the edge: in x, lam / kappa_j times the fluctuations
+ * and correction differences; in y, the same with each edge's amounts scaled
+ * by len_e.  The correction at an edge uses the edge's Courant factor lam
+ * times the mean inverse capacity of its two cells, and the speed reported
+ * for the CFL condition is |s| times that mean.  No curvature or Coriolis
+ * source terms.  The mass gets the correction described in the update. */
+static void sweep_line_metric(const orc_params *P, int n, double lam, const double (*line)[4],
+                              double (*out)[3], line_work *W, double *smax, const double *kap,
+                              const double *len)
+{
+    for (int e = 1; e <= n + 3; ++e)
+        orc_riemann(P, line[e - 1][0], line[e - 1][1], line[e - 1][2], line[e - 1][3],
+                    line[e][0], line[e][1], line[e][2], line[e][3], &W->w[e]);
+    for (int e = 2; e <= n + 2; ++e) {
+        const double a = 0.5 * (1.0 / kap[e - 1] + 1.0 / kap[e]);
+        orc_fluctuations(&W->w[e], W->amdq[e], W->apdq[e]);
+        if (P->order >= 2)
+            correction(&W->w[e - 1], &W->w[e], &W->w[e + 1], lam * a, W->F[e]);
+        else
+            W->F[e][0] = W->F[e][1] = W->F[e][2] = 0.0;
+        for (int p = 0; p < 3; ++p) {
+            double v = fabs(W->w[e].s[p]) * a;
+            if (v > *smax) *smax = v;
+        }
+    }
+    for (int c = 2; c <= n + 1; ++c) {
+        const double lc = lam / kap[c];
+        for (int k = 0; k < NQ; ++k)
+            out[c][k] = line[c][k] - lc * (len[c] * W->apdq[c][k] + len[c + 1] * W->amdq[c + 1][k])
+                                   - lc * (len[c + 1] * W->F[c + 1][k] - len[c] * W->F[c][k]);
+        /* the edge-scaled fluctuations of a cell add up to the conservative
+         * flux difference plus f(Q_c) (len_c - len_{c+1}); for the mass that
+         * term is spurious (the continuity equation has no metric source), so
+         * it is taken out: f = the normal momentum */
+        out[c][0] += lc * (line[c][1] * (len[c] - len[c + 1]));
+    }
+}
+
+/* Split step on a latitude-longitude patch: kap[j] for rows j = 0 .. my + 3,
+ * len[e] for the edge between rows e - 1 and e, e = 1 .. my + 3. */
+int64_t orc_step_sphere(const orc_params *P, const orc_grid *G, const double *q_in,
+                        const double *b, double dt, const double *kap, const double *len,
+                        double *q_out, double smax[2], int32_t *nonfinite)
+{
+    const int mx = G->mx, my = G->my;
+    const size_t ncell = (size_t)(mx + 4) * (size_t)(my + 4);
+    double *qs = malloc(ncell * NQ * sizeof(double));
+    memcpy(qs, q_in, ncell * NQ * sizeof(double));
+    int64_t clamps = 0;
+    double sx = 0.0, sy = 0.0;
+    int32_t nf = 0;
+    const double lamx = dt / G->dx, lamy = dt / G->dy;
+    line_work W;
+    line_work_alloc(&W, mx > my ? mx : my);
+    const int nmax = (mx > my ? mx : my) + 4;
+    double (*line)[4] = malloc(sizeof(*line) * (size_t)nmax);
+    double (*out)[3] = malloc(sizeof(*out) * (size_t)nmax);
+    double *kline = malloc(sizeof(double) * (size_t)nmax);
+    double *ones = malloc(sizeof(double) * (size_t)(nmax + 1));
+    for (int c = 0; c <= nmax; ++c) ones[c] = 1.0;
+    for (int j = 0; j < my + 4; ++j) {
+        for (int c = 0; c < mx + 4; ++c) {
+            const double *qc = &q_in[IDX(G, c, j) * NQ];
+            line[c][0] = qc[0];
+            line[c][1] = qc[1];
+            line[c][2] = qc[2];
+            line[c][3] = b[IDX(G, c, j)];
+            kline[c] = kap[j];
+        }
+        double s = 0.0;
+        sweep_line_metric(P, mx, lamx, (const double (*)[4])line, out, &W, &s, kline, ones);
+        int interior = j >= 2 && j < my + 2;
+        if (interior && s > sx) sx = s;
+        for (int c = 2; c <= mx + 1; ++c) {
+            double *qc = &qs[IDX(G, c, j) * NQ];
+            qc[0] = out[c][0];
+            qc[1] = out[c][1];
+            qc[2] = out[c][2];
+            int64_t cl = cleanup(P, qc, &nf);
+            if (interior) clamps += cl;
+        }
+    }
+    memcpy(q_out, q_in, ncell * NQ * sizeof(double));
+    for (int i = 2; i < mx + 2; ++i) {
+        for (int c = 0; c < my + 4; ++c) {
+            const double *qc = &qs[IDX(G, i, c) * NQ];
+            line[c][0] = qc[0];
+            line[c][1] = qc[2];
+            line[c][2] = qc[1];
+            line[c][3] = b[IDX(G, i, c)];
+        }
+        double s = 0.0;
+        sweep_line_metric(P, my, lamy, (const double (*)[4])line, out, &W, &s, kap, len);
+        if (s > sy) sy = s;
+        for (int c = 2; c <= my + 1; ++c) {
+            double *qc = &q_out[IDX(G, i, c) * NQ];
+            qc[0] = out[c][0];
+            qc[1] = out[c][2];
+            qc[2] = out[c][1];
+            clamps += cleanup(P, qc, &nf);
+        }
+    }
+    line_work_free(&W);
+    free(line);
+    free(out);
+    free(kline);
+    free(ones);
+    free(qs);
+    friction(P, G, q_out, dt);
+    smax[0] = sx;
+    smax[1] = sy;
+    if (nonfinite) *nonfinite = nf;
     return clamps;
 }
 

@@ -396,3 +396,37 @@ def amr_nested(n1: int = 1024, dx1: float = 2000.0, ratio: int = 4, counts=(64, 
         rects.append(placed)
     return amr_hierarchy(rects, n1=n1, dx1=dx1, ratio=r, bed="shelf", depth=depth, amp=amp,
                          sigma_frac=0.04, src=(0.5, 0.5))
+
+
+# --------------------------------------------------------------------------
+# Latitude-longitude patches.
+
+EARTH_RADIUS = 6.371e6
+
+
+def latlon_basin(nx: int = 256, ny: int = 256, lon0: float = 140.0, lat0: float = -30.0,
+                 dlon: float = 0.25, dlat: float = 0.25, depth: float = 4000.0,
+                 amp: float = 2.0, sigma_deg: float = 2.0, src=None, shelf: bool = True,
+                 bc=(BC_WALL,) * 4, name: str = "latlon_basin") -> Problem:
+    """A basin on a latitude-longitude patch: cells dlon x dlat degrees from
+    (lon0, lat0) at the lower-left corner; bed at -depth with, if `shelf`, a
+    tanh rise to a dry coast over the last fifth in longitude; a Gaussian hump
+    of amp metres and sigma_deg degrees (in both angles) at src (lon, lat;
+    default the centre).  dx, dy are R dlon and R dlat in metres; the
+    patch's latitudes are in meta (lat0, dlat)."""
+    lon = lon0 + (np.arange(nx) + 0.5) * dlon
+    lat = lat0 + (np.arange(ny) + 0.5) * dlat
+    LON, LAT = np.meshgrid(lon, lat)
+    if shelf:
+        x_s = lon0 + 0.85 * nx * dlon
+        b = shelf_profile(LON, x_s, 0.03 * nx * dlon, deep=-depth)
+    else:
+        b = np.full(LON.shape, -depth)
+    if src is None:
+        src = (lon0 + 0.5 * nx * dlon, lat0 + 0.5 * ny * dlat)
+    eta = amp * np.exp(-((LON - src[0]) ** 2 + (LAT - src[1]) ** 2) / (2.0 * sigma_deg ** 2))
+    h = depth_from_surface(eta, b)
+    z = np.zeros_like(h)
+    R = EARTH_RADIUS
+    return Problem(name, h, z, z.copy(), b, R * np.deg2rad(dlon), R * np.deg2rad(dlat),
+                   tuple(bc), 0, meta={"lon0": lon0, "lat0": lat0, "dlon": dlon, "dlat": dlat})
