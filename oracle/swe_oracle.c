@@ -523,8 +523,9 @@ static void sweep_line_metric(const orc_params *P, int n, double lam, const doub
     }
     for (int c = 2; c <= n + 1; ++c) {
         const double lc = lam / kap[c];
+        const double *ap = W->apdq[c], *am = W->amdq[c + 1];  /* edges c, c + 1 */
         for (int k = 0; k < NQ; ++k)
-            out[c][k] = line[c][k] - lc * (len[c] * W->apdq[c][k] + len[c + 1] * W->amdq[c + 1][k])
+            out[c][k] = line[c][k] - lc * (len[c] * ap[k] + len[c + 1] * am[k])
                                    - lc * (len[c + 1] * W->F[c + 1][k] - len[c] * W->F[c][k]);
         /* the edge-scaled fluctuations of a cell add up to the conservative
          * flux difference plus f(Q_c) (len_c - len_{c+1}); for the mass that
