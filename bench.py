@@ -283,16 +283,22 @@ def cpu_baseline(pb, seconds: float):
                       f"({el:.1f} s, {threads} OpenMP threads)"}
 
 
-def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True):
+def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere: bool = False):
     """Time `steps` steps of one patch; kernel time from HIP events around each
     step launch on the launch stream (the sort of the heaviest-first order,
-    when due, runs after the bracket, inside the timed loop)."""
+    when due, runs after the bracket, inside the timed loop).  sphere: a
+    latitude-longitude patch (SphereSolver; its CFL rule without the device
+    retake, which would redo a Cartesian step)."""
     import torch
 
     from paper_1901_06798_amd import _lib as L
     from paper_1901_06798_amd.solver import PatchSolver
+    from paper_1901_06798_amd.sphere import SphereSolver
 
-    s = PatchSolver(pb, params, "cuda:0", ordered=ordered)
+    if sphere:
+        s = SphereSolver(pb, params, "cuda:0")
+    else:
+        s = PatchSolver(pb, params, "cuda:0", ordered=ordered)
     s.initial_dt()
     for _ in range(warmup):
         s.enqueue_step()
@@ -311,6 +317,11 @@ def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True):
                       stream.cuda_stream)
         ev1[k].record(stream)
         s.after_step(stream.cuda_stream)
+        if sphere:
+            L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(),
+                             s.dt.data_ptr(), s.status.data_ptr(), 0, 0, stream.cuda_stream)
+            s.cur ^= 1
+            continue
         # CFL rule with the retake on the device (a gated launch that does
         # nothing unless the step went above cfl_max)
         L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
@@ -672,6 +683,19 @@ def main():
             "cups": ru["cups"], "ms_per_step": ru["ms_per_step"],
             "kernel_ms_avg": ru["kernel_ms_avg"], "achieved_gbs": ru["achieved_gbs"],
             "frac": ru["achieved_gbs"] / HBM_PEAK_GBS, "flags": ru["flags"]}
+        log("[bench] FP64 split step on a latitude-longitude patch")
+        torch.cuda.empty_cache()
+        ps = W.latlon_basin(n, n, lon0=120.0, lat0=-40.0, dlon=60.0 / n, dlat=60.0 / n,
+                            amp=2.0, sigma_deg=2.0, bc=(W.BC_EXTRAP,) * 4)
+        rs = time_patch(ps, L.params(), args.steps, args.warmup, sphere=True)
+        rs.pop("solver")
+        out["variants"]["sphere_fp64"] = {
+            "workload": f"latlon_basin_{n}x{n}_{60.0 / n:g}deg_lat-40..20",
+            "cups": rs["cups"], "ms_per_step": rs["ms_per_step"],
+            "kernel_ms_avg": rs["kernel_ms_avg"], "achieved_gbs": rs["achieved_gbs"],
+            "frac": rs["achieved_gbs"] / HBM_PEAK_GBS, "flags": rs["flags"],
+            "kernel": "swe::k_split_sphere<false>"}
+        del ps
         if args.batched:
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")

@@ -167,6 +167,29 @@ int swe_patch_retake(const swe_params *p, const swe_patch *patch, const void *q_
                      const void *b, const double *dt, double *smax, uint32_t *status,
                      const uint32_t *retake, void *stream);
 
+/* swe_patch_step on a latitude-longitude patch (an extension: the paper's
+ * transoceanic runs use such grids; the formulas here are derived from the
+ * cell geometry).  Cells are Dlon x Dlat on a sphere of radius R; patch->dx
+ * = R Dlon and patch->dy = R Dlat are their extents at the equator.  metric:
+ * device double[2 my + 9]: kappa_j for the rows j = 0 .. my + 3 of the ghost
+ * frame (cell area over its area at the equator, (sin phi_{j+1/2} - sin
+ * phi_{j-1/2}) / Dlat), then len_e for e = 0 .. my + 4 (cos of the latitude of
+ * the edge between rows e - 1 and e).  A cell changes by dt / (kappa dx) times
+ * the x-amounts and dt / (kappa dy) times the y-amounts weighted by their
+ * edges' len; an edge's correction uses its Courant factor times the mean
+ * inverse capacity of its two cells, and the speeds max-combined into smax
+ * are |s| times that mean (so swe_cfl_reduce keeps the Courant number); the
+ * mass update omits the term (hv)_c (len_lower - len_upper) that the
+ * edge-weighted fluctuations add; no curvature or Coriolis terms.  The
+ * ghost rows' entries are the caller's: beyond a wall side (SWE_BC_WALL at
+ * ylo or yhi) they should mirror the interior rows (kappa_1 = kappa_2,
+ * kappa_0 = kappa_3, len_1 = len_3, len_0 = len_4, likewise at the top), as
+ * the ghost state does, so that no mass crosses the wall.  FP64 split step
+ * only; other arguments as swe_patch_step. */
+int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const void *q_in,
+                          void *q_out, const void *b, const double *dt, double *smax,
+                          uint32_t *status, const double *metric, void *stream);
+
 /* Number of strip tasks (waves) of one step of `patch` (host), or SWE_EINVAL
  * for a bad patch.  Sizes the schedule buffer of swe_patch_step_sched. */
 int32_t swe_patch_tasks(const swe_patch *patch);

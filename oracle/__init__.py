@@ -182,17 +182,31 @@ def step(p: Params, g: Grid, q: np.ndarray, b: np.ndarray, dt: float):
     return out, smax, int(c), int(nf.value)
 
 
-def sphere_metric(lat0_deg: float, dlat_deg: float, my: int):
+def sphere_metric(lat0_deg: float, dlat_deg: float, my: int, bc=None):
     """Capacities kap[j] (rows j = 0 .. my + 3 of the ghost frame) and edge
     length ratios len[e] = cos(latitude of the edge between rows e - 1 and e),
     e = 0 .. my + 4, of a latitude-longitude patch whose first interior row
     starts at latitude lat0_deg (rows are dlat_deg high).  The capacity is the
     cell area over its area at the equator: (sin phi_top - sin phi_bottom) /
-    dphi."""
+    dphi.  With bc (xlo, xhi, ylo, yhi), a wall at ylo or yhi makes the two
+    ghost rows beyond it the mirror image of the interior rows inside it, in
+    geometry as in state (the reflection that defines a wall ghost cell): their
+    kap and len are the mirrored interior values.  Then the x-sweep moves a
+    ghost row exactly as its image row, the Riemann problem at the wall stays
+    symmetric, and no mass crosses the wall; with the geometric values beyond
+    the wall it would."""
     d = np.deg2rad(dlat_deg)
     edge = np.array([np.deg2rad(lat0_deg + (j - 2) * dlat_deg) for j in range(my + 5)])
     kap = np.array([(np.sin(edge[j + 1]) - np.sin(edge[j])) / d for j in range(my + 4)])
     ln = np.array([np.cos(edge[e]) for e in range(my + 5)])
+    if bc is not None and bc[2] == BC_WALL:
+        # rows 1, 0 reflect rows 2, 3 about edge 2
+        kap[1], kap[0] = kap[2], kap[3]
+        ln[1], ln[0] = ln[3], ln[4]
+    if bc is not None and bc[3] == BC_WALL:
+        # rows my + 2, my + 3 reflect rows my + 1, my about edge my + 2
+        kap[my + 2], kap[my + 3] = kap[my + 1], kap[my]
+        ln[my + 3], ln[my + 4] = ln[my + 1], ln[my]
     return kap, ln
 
 

@@ -108,6 +108,8 @@ def lib():
         L.swe_patch_step_sched.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                            _P, _P]
         L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, _P]
+        L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
+                                            _P, _P, _P]
         i64, dbl = ctypes.c_int64, ctypes.c_double
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
         L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
@@ -128,7 +130,7 @@ def lib():
                      "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
                      "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
-                     "swe_amr_init"):
+                     "swe_amr_init", "swe_patch_step_sphere"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -161,6 +163,12 @@ def swe_patch_step_sched(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b:
                          smax: int, status: int, sched: int, stream: int = 0) -> None:
     _check(lib().swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
                                       smax, status, sched, stream), "swe_patch_step_sched")
+
+
+def swe_patch_step_sphere(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                          smax: int, status: int, metric: int, stream: int = 0) -> None:
+    _check(lib().swe_patch_step_sphere(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
+                                       smax, status, metric, stream), "swe_patch_step_sphere")
 
 
 def swe_patch_order(pt: swe_patch, sched: int, stream: int = 0) -> None:

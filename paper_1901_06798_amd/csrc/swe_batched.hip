@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
                 tk.bc[2] = pt.bc[2];
                 tk.bc[3] = pt.bc[3];
                 tk.active = active;
+                tk.metric = nullptr;
                 // every lane of the wave runs the same number of row iterations
                 int steps = tsk.rows + 4;
 #pragma unroll
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
     tk.bc[2] = pt.bc[2];
     tk.bc[3] = pt.bc[3];
     tk.active = run;
+    tk.metric = nullptr;
     int steps = tsk.rows + 4;
     if (SEG != kWave) {
         const int other = __shfl_xor(steps, SEG, kWave);

@@ -118,6 +118,13 @@ template <int SEG = kWave>
 __device__ __forceinline__ float lane_down(float x) { return __shfl_down(x, 1, SEG); }
 #endif
 
+// Lane l's value, for a wave-uniform l (two scalar reads of the dwords).
+__device__ __forceinline__ double lane_read(double x, int l) {
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
 // The left neighbour's side: the fields side_base makes (velocities and
 // sqrt(h) are moved separately, once the neighbour has computed them).
 template <typename T, bool DEV = false, int SEG = kWave>

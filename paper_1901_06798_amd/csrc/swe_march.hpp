@@ -153,6 +153,9 @@ struct Task {
     int U0, U1;   // first and last row updated (ghost rows are 0, 1, my + 2, my + 3)
     int8_t bc[4];
     bool active;  // false: the lane only takes part in the cross-lane moves
+    // latitude-longitude patches: capacities of rows 0 .. my + 3, then the
+    // length ratios of the edges between rows e - 1 and e, e = 0 .. my + 4
+    const double* metric;
 };
 
 // Per-lane results of a march.
@@ -238,9 +241,18 @@ __device__ __forceinline__ void ring_issue(const Task& tk, int row, int lane, ui
 // RING > 0: rows come through an LDS ring of RING slots at `ring` (this
 // wave's RING x 4 x kWave elements; SEG must be kWave); RING = 0: each row is
 // loaded into registers one iteration ahead.
-template <bool DEV, int SEG, bool FRIC, int RING = 0>
+// SPH: a latitude-longitude patch (FP64): a row's cells have capacity kappa
+// (area over the area at the equator) and a parallel edge's length is its
+// ratio len times dx; the updates divide by kappa and weight the y-edge
+// amounts by len, the corrections and the speed maxima use the mean inverse
+// capacity of the edge's cells, and the mass update takes out the term
+// f(Q) (len_lower - len_upper) that edge-weighted fluctuations add (the
+// continuity equation has no metric source).
+template <bool DEV, int SEG, bool FRIC, int RING = 0, bool SPH = false>
 __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, int lane_in_seg,
                                           int steps, typename Prec<DEV>::S* ring = nullptr) {
+    static_assert(!SPH || !DEV, "latitude-longitude patches: FP64 only");
+    static_assert(!SPH || SEG == kWave, "per-row tables are held one row per lane");
     static_assert(RING == 0 || SEG == kWave, "the row ring serves whole-wave strips");
     static_assert((RING & (RING - 1)) == 0, "ring depth is a power of two");
     using S = typename Prec<DEV>::S;
@@ -254,6 +266,13 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     const bool xedge_own = tk.active && lane >= 2 && lane <= SEG - 2 && c >= 2 && c <= tk.mx + 2;
     const int U0 = tk.U0, U1 = tk.U1;
     const S lamx = S(tk.dt / tk.dx), lamy = S(tk.dt / tk.dy);
+    // rows U0 - 2 .. U1 + 2 of the task, one per lane (at most kWave of
+    // them): lane l holds 1 / kappa of row U0 - 2 + l; a row's value is read
+    // from its lane, so no division is left in the march
+    const int rbase = U0 - 2;
+    double ik_l = 0.0;
+    if (SPH) ik_l = 1.0 / tk.metric[min(rbase + lane, tk.my + 3)];
+    const double* lenv = SPH ? tk.metric + (tk.my + 4) : nullptr;
     const bool second = P.order >= 2;
     const int tlast = U1 - U0 + 4;
     // the segment's columns all lie inside the patch (no ghost column)
@@ -392,19 +411,25 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 }
 #pragma unroll
                 for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
-                correction(w, dl, dr, lamx, F);
+                if (SPH) {
+                    correction(w, dl, dr, S(lamx * lane_read(ik_l, R - rbase)), F);
+                } else {
+                    correction(w, dl, dr, lamx, F);
+                }
             }
             const S qc[3] = {q0, hu, hv};
+            const S lx = SPH ? S(lamx * lane_read(ik_l, R - rbase)) : lamx;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const S amr = lane_down<SEG>(am[k]);
                 const S Fr = lane_down<SEG>(F[k]);
-                qs[k] = qc[k] - lamx * (ap[k] + amr) - lamx * (Fr - F[k]);
+                qs[k] = qc[k] - lx * (ap[k] + amr) - lx * (Fr - F[k]);
             }
         }
         cleanup<DEV, S>(qs, bb, P, upd_col && live, interior_row && upd_col, clamps, flags);
         if (interior_row && xedge_own) {
-            const S s = max_speed(w);
+            S s = max_speed(w);
+            if (SPH) s = S(s * lane_read(ik_l, R - rbase));
             smx = s > smx ? s : smx;
         }
 
@@ -429,8 +454,11 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 solve_edge<DEV, S>(prev, cur, prev.m, prev.t, cur.m, cur.t, P, wy);
             }
             const int E = R;  // edge between rows R - 1 and R
+            const double a_e =
+                SPH ? 0.5 * (lane_read(ik_l, E - 1 - rbase) + lane_read(ik_l, E - rbase)) : 1.0;
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
-                const S s = max_speed(wy);
+                S s = max_speed(wy);
+                if (SPH) s = S(s * a_e);
                 smy = s > smy ? s : smy;
             }
             // with either edge quiet the dot product is a zero, and a zero
@@ -446,14 +474,31 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 S F1[3] = {S(0), S(0), S(0)};
                 if (!wprev_quiet) {
                     fluctuations(wprev, am1, ap1);
-                    if (second) correction(wprev, dprev, dcur, lamy, F1);
+                    if (second) correction(wprev, dprev, dcur,
+                                   SPH ? S(lamy * (0.5 * (lane_read(ik_l, E - 2 - rbase) +
+                                                          lane_read(ik_l, E - 1 - rbase))))
+                                       : lamy,
+                                   F1);
                 }
                 if (t >= 4) {
                     // finish row R - 2 between edges E - 2 and E - 1
                     S qn[3];
+                    if (SPH) {
+                        // cell c = R - 2 between edges c (below) and c + 1 (above)
+                        const int cr = R - 2;
+                        const S lc = lamy * lane_read(ik_l, cr - rbase);
+                        const S ll = lenv[cr], lu = lenv[cr + 1];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        qn[k] = qm2[k] - lamy * (ap_prev[k] + am1[k]) - lamy * (F1[k] - F_prev[k]);
+                        for (int k = 0; k < 3; ++k)
+                            qn[k] = qm2[k] - lc * (ll * ap_prev[k] + lu * am1[k])
+                                           - lc * (lu * F1[k] - ll * F_prev[k]);
+                        qn[0] += lc * (qm2[1] * (ll - lu));
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            qn[k] = qm2[k] - lamy * (ap_prev[k] + am1[k]) -
+                                    lamy * (F1[k] - F_prev[k]);
+                    }
                     // the y-sweep works in (h, hv, hu)
                     S out[3] = {qn[0], qn[2], qn[1]};
                     const S bo = qm2_b;

@@ -47,6 +47,7 @@ struct StepArgs {
     // order[k] - 1, or task k where order[k] is 0 or out of range
     const uint32_t* order;
     uint32_t* cost;  // per task, the march's solved row sweeps (NULL: not kept)
+    const double* metric;  // latitude-longitude patch: capacities, edge lengths
 };
 
 // Task at launch position `pos` (wave-uniform).
@@ -74,8 +75,8 @@ constexpr size_t ring_bytes(bool f64) {
 // Waves per SIMD the register budget is fitted to, without spilling: the
 // FP32 march takes four (at most 128 VGPRs), the FP64 one three (168); with
 // the friction step compiled in, one fewer.
-template <bool DEV, bool FRIC>
-__global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(StepArgs a) {
+template <bool DEV, bool FRIC, bool SPH>
+__device__ __forceinline__ void split_task(const StepArgs& a) {
     const int lane = threadIdx.x & (kWave - 1);
     // the task, and with it the row loop's trip count, is the same for the
     // whole wave: keep it in scalar registers
@@ -101,10 +102,12 @@ __global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(S
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
     tk.active = true;
+    tk.metric = a.metric;
     using S = typename Prec<DEV>::S;
     extern __shared__ __align__(16) unsigned char swe_step_lds[];
     S* ring = reinterpret_cast<S*>(swe_step_lds) + (threadIdx.x / kWave) * (kRing * 4 * kWave);
-    const MarchOut o = march<DEV, kWave, FRIC, kRing>(tk, a.P, lane, tk.U1 - tk.U0 + 5, ring);
+    const MarchOut o =
+        march<DEV, kWave, FRIC, kRing, SPH>(tk, a.P, lane, tk.U1 - tk.U0 + 5, ring);
     const double wx = wave_max_nonneg(o.smx);
     const double wy = wave_max_nonneg(o.smy);
     if (lane == 0) {
@@ -116,10 +119,23 @@ __global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(S
     if (o.flags) atomicOr(&a.status[0], o.flags);
 }
 
+template <bool DEV, bool FRIC>
+__global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(StepArgs a) {
+    split_task<DEV, FRIC, false>(a);
+}
+
+// The same on a latitude-longitude patch (FP64).
+template <bool FRIC>
+__global__ void __launch_bounds__(256, FRIC ? 2 : 3) k_split_sphere(StepArgs a) {
+    split_task<false, FRIC, true>(a);
+}
+
 template __global__ void k_split<false, false>(StepArgs);
 template __global__ void k_split<true, false>(StepArgs);
 template __global__ void k_split<false, true>(StepArgs);
 template __global__ void k_split<true, true>(StepArgs);
+template __global__ void k_split_sphere<false>(StepArgs);
+template __global__ void k_split_sphere<true>(StepArgs);
 
 // One patch, unsplit with transverse waves (FP64).
 template <bool FRIC>
@@ -147,6 +163,7 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
     tk.active = true;
+    tk.metric = nullptr;
     const MarchOut o =
         march_unsplit<kWave, FRIC>(tk, a.P, lane, tk.U1 - tk.U0 + 5, transverse_order);
     const double wx = wave_max_nonneg(o.smx);
@@ -538,11 +555,14 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 // Waves over water at rest skip their Riemann solves and finish early, so
 // short tasks (many more than the device holds at once) let the hardware
 // dispatcher balance the launch; 32 rows keeps the fill overhead at 1/8.
-// SWE_ROWS_PER_WAVE overrides.
+// SWE_ROWS_PER_WAVE overrides, up to kWave - 4: the task's rows with their
+// two ghost rows either side then fit one wave's lanes, which the
+// latitude-longitude march uses to hold its per-row values.
 int rows_per_chunk(int my) {
     const char* e = std::getenv("SWE_ROWS_PER_WAVE");
     int H = e ? std::atoi(e) : 32;
     if (H < 1) H = 32;
+    if (H > swe::kWave - 4) H = swe::kWave - 4;
     return H < my ? H : my;
 }
 
@@ -569,7 +589,8 @@ static int patch_tasks(const swe_patch* patch) {
 
 static int patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                       const void* b, const double* dt, double* smax, uint32_t* status,
-                      const uint32_t* gate, uint32_t* sched, void* stream) {
+                      const uint32_t* gate, uint32_t* sched, void* stream,
+                      const double* metric = nullptr) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_patch(patch))) return rc;
@@ -616,6 +637,7 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.gate = gate;
     a.order = sched;
     a.cost = sched ? sched + a.nitems : nullptr;
+    a.metric = metric;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid(blocks), block(64 * waves_per_block);
@@ -623,6 +645,10 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     if (p->method == SWE_UNSPLIT) {
         if (fric) hipLaunchKernelGGL(swe::k_unsplit<true>, grid, block, 0, st, a, tord);
         else hipLaunchKernelGGL(swe::k_unsplit<false>, grid, block, 0, st, a, tord);
+    } else if (f64 && metric) {
+        const size_t lds = waves_per_block * swe::ring_bytes(true);
+        if (fric) hipLaunchKernelGGL(swe::k_split_sphere<true>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(swe::k_split_sphere<false>, grid, block, lds, st, a);
     } else if (f64) {
         const size_t lds = waves_per_block * swe::ring_bytes(true);
         if (fric) hipLaunchKernelGGL((swe::k_split<false, true>), grid, block, lds, st, a);
@@ -639,6 +665,16 @@ int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in
                    const void* b, const double* dt, double* smax, uint32_t* status,
                    void* stream) {
     return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, nullptr, stream);
+}
+
+int swe_patch_step_sphere(const swe_params* p, const swe_patch* patch, const void* q_in,
+                          void* q_out, const void* b, const double* dt, double* smax,
+                          uint32_t* status, const double* metric, void* stream) {
+    if (!metric) return fail(SWE_EINVAL, "swe_patch_step_sphere: null metric");
+    if (p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
+        return fail(SWE_EINVAL, "swe_patch_step_sphere: FP64 split step only");
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, nullptr, stream,
+                      metric);
 }
 
 int32_t swe_patch_tasks(const swe_patch* patch) {

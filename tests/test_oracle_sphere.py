@@ -22,7 +22,7 @@ def setup(pb):
     q, b = O.new_state(pb.h, pb.hu, pb.hv, pb.b)
     g = O.grid(pb.mx, pb.my, pb.dx, pb.dy, pb.bc)
     O.ghost_fill_b(g, b)
-    kap, ln = O.sphere_metric(pb.meta["lat0"], pb.meta["dlat"], pb.my)
+    kap, ln = O.sphere_metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
     return q, b, g, kap, ln
 
 
@@ -55,13 +55,27 @@ def test_sea_at_rest_stays_bitwise_at_rest(P):
 
 
 def test_mass_on_the_sphere_is_conserved_with_walls(P):
+    # long enough for the waves to reach the walls at both latitudes
     pb = W.latlon_basin(48, 40, lat0=40.0, shelf=False, amp=3.0)
     q0, _, _, kap, _ = setup(pb)
     m0 = np.sum(q0[2:-2, 2:-2, 0] * kap[2:-2, None])
-    q, _, kap = run(P, pb, 20.0, 60)
+    q, _, kap = run(P, pb, 20.0, 300)
     m1 = np.sum(q[2:-2, 2:-2, 0] * kap[2:-2, None])
-    assert abs(m1 - m0) / m0 <= 1e-13
+    assert abs(m1 - m0) / m0 <= 1e-14
     assert np.abs(q[2:-2, 2:-2, 1]).max() > 1.0  # water moved
+    assert np.abs(q[2, 2:-2, 2]).max() > 1.0 and np.abs(q[-3, 2:-2, 2]).max() > 1.0
+
+
+def test_wall_ghost_rows_mirror_the_geometry():
+    my = 30
+    kap, ln = O.sphere_metric(50.0, 0.2, my, (O.BC_WALL,) * 4)
+    g_kap, g_ln = O.sphere_metric(50.0, 0.2, my)
+    assert kap[1] == kap[2] and kap[0] == kap[3] and ln[1] == ln[3] and ln[0] == ln[4]
+    assert kap[my + 2] == kap[my + 1] and kap[my + 3] == kap[my]
+    assert ln[my + 3] == ln[my + 1] and ln[my + 4] == ln[my]
+    assert np.array_equal(kap[2:my + 2], g_kap[2:my + 2]) and np.array_equal(ln[2:my + 3], g_ln[2:my + 3])
+    ekap, eln = O.sphere_metric(50.0, 0.2, my, (O.BC_EXTRAP,) * 4)
+    assert np.array_equal(ekap, g_kap) and np.array_equal(eln, g_ln)
 
 
 def test_longitude_independent_state_stays_so(P):
