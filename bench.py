@@ -685,12 +685,16 @@ def main():
             "frac": ru["achieved_gbs"] / HBM_PEAK_GBS, "flags": ru["flags"]}
         log("[bench] FP64 split step on a latitude-longitude patch")
         torch.cuda.empty_cache()
-        ps = W.latlon_basin(n, n, lon0=120.0, lat0=-40.0, dlon=60.0 / n, dlat=60.0 / n,
-                            amp=2.0, sigma_deg=2.0, bc=(W.BC_EXTRAP,) * 4)
+        # the extent of the paper's transoceanic domain (longitude -240 .. -100,
+        # latitude -31 .. 65) in square cells of 140 / n degrees
+        d = 140.0 / n
+        ny = int(round(96.0 / d))
+        ps = W.latlon_basin(n, ny, lon0=-240.0, lat0=-31.0, dlon=d, dlat=d, amp=2.0,
+                            sigma_deg=1.0, src=(-217.5, 38.0), bc=(W.BC_EXTRAP,) * 4)
         rs = time_patch(ps, L.params(), args.steps, args.warmup, sphere=True)
         rs.pop("solver")
         out["variants"]["sphere_fp64"] = {
-            "workload": f"latlon_basin_{n}x{n}_{60.0 / n:g}deg_lat-40..20",
+            "workload": f"latlon_basin_{n}x{ny}_{d * 60:.3g}arcmin_lon-240..-100_lat-31..65",
             "cups": rs["cups"], "ms_per_step": rs["ms_per_step"],
             "kernel_ms_avg": rs["kernel_ms_avg"], "achieved_gbs": rs["achieved_gbs"],
             "frac": rs["achieved_gbs"] / HBM_PEAK_GBS, "flags": rs["flags"],
