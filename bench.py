@@ -257,8 +257,45 @@ def calib_copy(mb: float) -> None:
                       "launches": 10}), flush=True)
 
 
-def cpu_baseline(pb, seconds: float):
-    """Reference solver on the same grid for a bounded number of steps."""
+def copy_sanity(mb: float = 1024.0, reps: int = 10) -> dict:
+    """A plain device copy (torch copy_, read + write) timed with HIP events:
+    the bandwidth a streaming kernel reaches on this GPU, beside the peak."""
+    import torch
+    n = int(mb * 1e6 / 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 16.0 * n / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 16 * n, "ms": ms, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
+def _host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(pb, seconds: float, single_seconds: float = 8.0):
+    """Reference solver on the same grid for a bounded number of steps, with
+    its OpenMP threads (the machine's CPU share), then on one thread."""
     import oracle as O
     O.lib()
     threads = O.get_threads()
@@ -278,9 +315,25 @@ def cpu_baseline(pb, seconds: float):
         if el >= seconds or steps >= 50:
             break
     cups = pb.mx * pb.my * steps / el
-    return {"value": cups, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} FP64 split steps of the {pb.mx}x{pb.my} grid "
-                      f"({el:.1f} s, {threads} OpenMP threads)"}
+    out = {"value": cups, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} FP64 split steps of the {pb.mx}x{pb.my} grid "
+                     f"({el:.1f} s, {threads} OpenMP threads)"}
+    O.set_threads(1)
+    try:
+        s1 = 0
+        t0 = time.perf_counter()
+        while True:
+            O.run(P, g, q, b, 1, dt0=dt)
+            s1 += 1
+            el1 = time.perf_counter() - t0
+            if el1 >= single_seconds or s1 >= 5:
+                break
+    finally:
+        O.set_threads(threads)
+    out["single_thread"] = {"value": pb.mx * pb.my * s1 / el1, "unit": "cell-updates/s",
+                            "sample": f"{s1} steps of the same grid ({el1:.1f} s, 1 thread)"}
+    out["host"] = _host_cpu()
+    return out
 
 
 def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere: bool = False):
@@ -296,7 +349,7 @@ def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere
     from paper_1901_06798_amd.sphere import SphereSolver
 
     if sphere:
-        s = SphereSolver(pb, params, "cuda:0")
+        s = SphereSolver(pb, params, "cuda:0", ordered=ordered)
     else:
         s = PatchSolver(pb, params, "cuda:0", ordered=ordered)
     s.initial_dt()
@@ -619,6 +672,8 @@ def main():
     log(f"[bench] FP64: {r64['ms_per_step']:.3f} ms/step, kernel {r64['kernel_ms_avg']:.3f} ms, "
         f"{r64['cups']:.3e} CUPS, flags={r64['flags']}")
     traffic = measured_traffic(args.traffic)
+    log("[bench] plain device copy (sanity line)")
+    copy_line = copy_sanity()
     out = {
         "metric": "cell-updates/s (FP64 split step, 4096^2 shelf)",
         "value": r64["cups"],
@@ -641,6 +696,7 @@ def main():
                      "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
                      "alg_bytes_per_launch": r64["alg_bytes"]},
         "hbm_gbs_alg_step": r64["alg_bytes"] / (r64["ms_per_step"] * 1e-3) / 1e9,
+        "copy_sanity": copy_line,
         "status_flags": r64["flags"],
         "clamps": r64["clamps"],
     }

@@ -184,11 +184,14 @@ int swe_patch_retake(const swe_params *p, const swe_patch *patch, const void *q_
  * ghost rows' entries are the caller's: beyond a wall side (SWE_BC_WALL at
  * ylo or yhi) they should mirror the interior rows (kappa_1 = kappa_2,
  * kappa_0 = kappa_3, len_1 = len_3, len_0 = len_4, likewise at the top), as
- * the ghost state does, so that no mass crosses the wall.  FP64 split step
- * only; other arguments as swe_patch_step. */
+ * the ghost state does, so that no mass crosses the wall.  sched: NULL for
+ * tasks in index order, else a schedule buffer as in swe_patch_step_sched
+ * (launch order in, work per task out; swe_patch_order sorts it).  FP64
+ * split step only; other arguments as swe_patch_step. */
 int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const void *q_in,
                           void *q_out, const void *b, const double *dt, double *smax,
-                          uint32_t *status, const double *metric, void *stream);
+                          uint32_t *status, const double *metric, uint32_t *sched,
+                          void *stream);
 
 /* Number of strip tasks (waves) of one step of `patch` (host), or SWE_EINVAL
  * for a bad patch.  Sizes the schedule buffer of swe_patch_step_sched. */

@@ -109,7 +109,7 @@ def lib():
                                            _P, _P]
         L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, _P]
         L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
-                                            _P, _P, _P]
+                                            _P, _P, _P, _P]
         i64, dbl = ctypes.c_int64, ctypes.c_double
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
         L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
@@ -166,9 +166,11 @@ def swe_patch_step_sched(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b:
 
 
 def swe_patch_step_sphere(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
-                          smax: int, status: int, metric: int, stream: int = 0) -> None:
+                          smax: int, status: int, metric: int, sched: int = 0,
+                          stream: int = 0) -> None:
     _check(lib().swe_patch_step_sphere(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
-                                       smax, status, metric, stream), "swe_patch_step_sphere")
+                                       smax, status, metric, sched, stream),
+           "swe_patch_step_sphere")
 
 
 def swe_patch_order(pt: swe_patch, sched: int, stream: int = 0) -> None:

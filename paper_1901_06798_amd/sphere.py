@@ -45,7 +45,8 @@ def metric(lat0_deg: float, dlat_deg: float, my: int, bc=None) -> np.ndarray:
 class SphereSolver(PatchSolver):
     """PatchSolver for a latitude-longitude patch (FP64 split step)."""
 
-    def __init__(self, pb: Problem, params: L.swe_params | None = None, device: str = "cuda:0"):
+    def __init__(self, pb: Problem, params: L.swe_params | None = None, device: str = "cuda:0",
+                 ordered: bool = True, order_every: int = 4):
         p = params or L.params()
         if p.precision != L.F64 or p.method != L.SPLIT:
             raise L.SweError("SphereSolver: FP64 split step only")
@@ -54,7 +55,7 @@ class SphereSolver(PatchSolver):
                 raise L.SweError(f"SphereSolver: the problem's meta needs {key!r}")
         if abs(pb.meta["lat0"]) >= 90.0 or abs(pb.meta["lat0"] + pb.my * pb.meta["dlat"]) >= 90.0:
             raise L.SweError("SphereSolver: the patch must not reach a pole")
-        super().__init__(pb, p, device, ordered=False)
+        super().__init__(pb, p, device, ordered=ordered, order_every=order_every)
         m = metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
         self.kappa_min = float(m[: pb.my + 4].min())
         self.metric = torch.from_numpy(m).to(self.dev)
@@ -69,7 +70,8 @@ class SphereSolver(PatchSolver):
         st = self.stream if stream is None else stream
         L.swe_patch_step_sphere(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                                 self.smax.data_ptr(), self.status.data_ptr(),
-                                self.metric.data_ptr(), st)
+                                self.metric.data_ptr(),
+                                self.sched.data_ptr() if self.sched is not None else 0, st)
 
     def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True,
                      retake: bool = False) -> None:

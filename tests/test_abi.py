@@ -100,11 +100,11 @@ def test_argument_errors_are_reported_on_the_host(L):
 
 
 def test_patch_tasks_counts_the_strip_tasks(L):
-    # strips of 60 updated columns, chunks of 32 rows (ragged ends included)
-    assert L.swe_patch_tasks(L.patch(4096, 4096, 4112, 250.0, 250.0)) == 69 * 128
-    assert L.swe_patch_tasks(L.patch(70, 70, 80, 1.0, 1.0)) == 2 * 3
-    assert L.swe_patch_tasks(L.patch(60, 32, 64, 1.0, 1.0)) == 1
-    assert L.swe_patch_tasks(L.patch(61, 33, 80, 1.0, 1.0)) == 4
+    # strips of 60 updated columns, chunks of 48 rows (ragged ends included)
+    assert L.swe_patch_tasks(L.patch(4096, 4096, 4112, 250.0, 250.0)) == 69 * 86
+    assert L.swe_patch_tasks(L.patch(70, 100, 80, 1.0, 1.0)) == 2 * 3
+    assert L.swe_patch_tasks(L.patch(60, 48, 64, 1.0, 1.0)) == 1
+    assert L.swe_patch_tasks(L.patch(61, 49, 80, 1.0, 1.0)) == 4
     assert L.lib().swe_patch_tasks(ctypes.byref(L.patch(10, 10, 12, 1.0, 1.0))) == L.SWE_EINVAL
     with pytest.raises(L.SweError):
         L.swe_patch_tasks(L.patch(10, 10, 12, 1.0, 1.0))

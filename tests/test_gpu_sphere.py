@@ -101,3 +101,18 @@ def test_speeds_and_cfl_rule_on_the_sphere(gpu):
     torch.cuda.synchronize()
     assert len(dts) == 30 and np.all(dts > 0)
     assert int(s.status[0].item()) & L.STATUS_CFL_EXCEEDED == 0
+
+
+def test_heaviest_first_order_on_the_sphere_is_bitwise_index_order(gpu):
+    L, SphereSolver, torch = gpu
+    pb = W.latlon_basin(301, 257, lat0=-10.0, dlon=0.05, dlat=0.05, amp=2.0, sigma_deg=0.5)
+    print("case sphere order 301x257", flush=True)
+    a = SphereSolver(pb, L.params(), ordered=True, order_every=1)
+    b = SphereSolver(pb, L.params(), ordered=False)
+    da, db = a.run(30), b.run(30)
+    torch.cuda.synchronize()
+    assert np.array_equal(da, db)
+    assert torch.equal(a.planes(), b.planes()) and torch.equal(a.status, b.status)
+    n = L.swe_patch_tasks(a.pt)
+    order = a.sched[:n].cpu().numpy()
+    assert sorted(order.tolist()) == list(range(1, n + 1))
