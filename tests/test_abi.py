@@ -201,3 +201,46 @@ def test_amr_plans_match_the_hierarchy(L):
             a = amr.average_plan(geo[lev], geo[lev - 1], r)
             assert a.size == sum(p.mx * p.my for p in byl[lev]) // (r * r)
             assert np.unique(a["dst"]).size == a.size
+
+
+def test_sphere_step_argument_errors(L):
+    lib = L.lib()
+    pt = L.patch(10, 10, 14, 1.0, 1.0)
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x9000000)
+    metric = ctypes.c_void_p(0x5000)
+
+    def call(p, patch=pt, m=metric):
+        return lib.swe_patch_step_sphere(None if p is None else ctypes.byref(p),
+                                         ctypes.byref(patch), fake, out, fake, fake, fake, fake,
+                                         m, None, None)
+    assert call(L.params(), m=None) == L.SWE_EINVAL
+    assert b"metric" in lib.swe_last_error()
+    for kw in ({"precision": L.F32_DEV}, {"method": L.UNSPLIT}):
+        assert call(L.params(**kw)) == L.SWE_EINVAL
+        assert b"FP64 split" in lib.swe_last_error()
+    assert call(None) == L.SWE_EINVAL
+    assert call(L.params(), L.patch(10, 10, 12, 1.0, 1.0)) == L.SWE_EINVAL
+    assert b"pitch" in lib.swe_last_error()
+    with pytest.raises(L.SweError):
+        L.swe_patch_step_sphere(L.params(precision=L.F32_DEV), pt, 0x1000, 0x9000000, 0x1000,
+                                0x1000, 0x1000, 0x1000, 0x5000)
+
+
+def test_sphere_metric_layout():
+    from paper_1901_06798_amd import sphere as S
+    import numpy as np
+    my = 12
+    m = S.metric(-30.0, 0.5, my)
+    assert m.shape == (2 * my + 9,)
+    kap, ln = m[: my + 4], m[my + 4:]
+    # capacities telescope: the rows' areas sum to the band's
+    d = np.deg2rad(0.5)
+    band = np.sin(np.deg2rad(-30.0 + (my + 2) * 0.5)) - np.sin(np.deg2rad(-30.0 - 2 * 0.5))
+    assert np.sum(kap) * d == pytest.approx(band, rel=1e-13)
+    assert ln[2] == pytest.approx(np.cos(np.deg2rad(-30.0)), rel=1e-15)
+    # a wall at ylo mirrors the two ghost rows and edges, nothing else
+    w = S.metric(-30.0, 0.5, my, (1, 1, 0, 1))
+    assert w[1] == m[2] and w[0] == m[3]
+    assert w[my + 4 + 1] == m[my + 4 + 3] and w[my + 4] == m[my + 4 + 4]
+    assert np.array_equal(w[2: my + 4], m[2: my + 4]) and np.array_equal(w[my + 6:], m[my + 6:])

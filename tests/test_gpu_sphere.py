@@ -23,10 +23,10 @@ def gpu():
     return L, SphereSolver, torch
 
 
-def reference(pb, dts):
+def reference(pb, dts, manning_n=0.0):
     import oracle as O
     O.lib()
-    P = O.params()
+    P = O.params(manning_n=manning_n)
     q, b = O.new_state(pb.h, pb.hu, pb.hv, pb.b)
     g = O.grid(pb.mx, pb.my, pb.dx, pb.dy, pb.bc)
     O.ghost_fill_b(g, b)
@@ -39,17 +39,18 @@ def reference(pb, dts):
     return q
 
 
-@pytest.mark.parametrize("lat0,bc", [(20.0, W.BC_WALL), (-50.0, W.BC_EXTRAP)])
-def test_sphere_step_matches_the_reference(gpu, lat0, bc):
+@pytest.mark.parametrize("lat0,bc,manning_n", [(20.0, W.BC_WALL, 0.0), (-50.0, W.BC_EXTRAP, 0.0),
+                                               (35.0, W.BC_WALL, 0.025)])
+def test_sphere_step_matches_the_reference(gpu, lat0, bc, manning_n):
     L, SphereSolver, torch = gpu
     pb = W.latlon_basin(150, 130, lat0=lat0, dlon=0.1, dlat=0.1, amp=3.0, sigma_deg=1.0,
                         bc=(bc,) * 4)
-    print(f"case sphere basin 150x130 lat0={lat0} bc={bc}", flush=True)
+    print(f"case sphere basin 150x130 lat0={lat0} bc={bc} manning_n={manning_n}", flush=True)
     dts = [30.0] * 25
-    s = SphereSolver(pb, L.params())
+    s = SphereSolver(pb, L.params(manning_n=manning_n))
     s.run_forced(dts)
     torch.cuda.synchronize()
-    ref = reference(pb, dts)
+    ref = reference(pb, dts, manning_n)
     got = s.state()
     for k in range(3):
         want = ref[2:-2, 2:-2, k]
