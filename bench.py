@@ -722,6 +722,8 @@ def main():
             "frac": r32["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r32["alg_bytes"],
             "speedup_vs_fp64": r32["cups"] / r64["cups"], "flags": r32["flags"],
             "free_running_max_surface_diff_m": float(np.abs(h32 - h64)[wet].max()),
+            "free_running_wet_cells": int(wet.sum()),
+            "free_running_cells_differing": int((h32 != h64)[wet].sum()),
             "fp64_island_edge_frac": edge_stats(d32, *st64[1:], pb.b)["fp64_island_edge_frac"]}}
         log("[bench] FP64 split step, tasks launched in index order")
         torch.cuda.empty_cache()
