@@ -691,7 +691,10 @@ def main():
                    "boundary": "extrapolation", "cfl": 0.9, "limiter": "MC"},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "swe::k_split<false, false>",
+                     "traffic": traffic,
+                     "traffic_gbs": (traffic / (r64["kernel_ms_avg"] * 1e-3) / 1e9
+                                     if traffic else None),
+                     "kernel": "swe::k_split<false, false>",
                      "kernel_ms_avg": r64["kernel_ms_avg"],
                      "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
                      "alg_bytes_per_launch": r64["alg_bytes"]},
