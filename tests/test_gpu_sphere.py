@@ -117,3 +117,27 @@ def test_heaviest_first_order_on_the_sphere_is_bitwise_index_order(gpu):
     n = L.swe_patch_tasks(a.pt)
     order = a.sched[:n].cpu().numpy()
     assert sorted(order.tolist()) == list(range(1, n + 1))
+
+
+@pytest.mark.parametrize("nx,ny,lat0,dlat", [(7, 1, 60.0, 0.5), (61, 3, -70.0, 0.25),
+                                             (125, 97, 72.0, 0.1), (64, 61, -5.0, 1.0)])
+def test_small_and_high_latitude_patches(gpu, nx, ny, lat0, dlat):
+    # one to three rows (a task shorter than its ghost frame), a ragged
+    # strip, rows near 80 degrees (small capacities, large Courant factors)
+    # and cells a degree tall across the equator
+    L, SphereSolver, torch = gpu
+    # a wall needs two cells beside it: one row takes extrapolation in y
+    bc = (W.BC_WALL,) * 4 if ny >= 2 else (W.BC_WALL, W.BC_WALL, W.BC_EXTRAP, W.BC_EXTRAP)
+    pb = W.latlon_basin(nx, ny, lat0=lat0, dlon=dlat, dlat=dlat, amp=1.5,
+                        sigma_deg=max(2 * dlat, 0.3), shelf=nx > 40, bc=bc)
+    print(f"case sphere small {nx}x{ny} lat0={lat0} dlat={dlat}", flush=True)
+    s = SphereSolver(pb, L.params(), order_every=1)
+    dts = s.run(12)
+    torch.cuda.synchronize()
+    assert int(s.status[0].item()) & (L.STATUS_NONFINITE | L.STATUS_CFL_EXCEEDED) == 0
+    ref = reference(pb, dts)
+    got = s.state()
+    for k in range(3):
+        want = ref[2:-2, 2:-2, k]
+        scale = max(np.abs(want).max(), 1e-300)
+        assert np.abs(got[k] - want).max() / scale <= 1e-12, (k,)
