@@ -118,23 +118,6 @@ template <int SEG = kWave>
 __device__ __forceinline__ float lane_down(float x) { return __shfl_down(x, 1, SEG); }
 #endif
 
-// Rank in the launch order of launch position `pos` (one wave per
-// workgroup, n positions).  Workgroups go to the eight XCDs in turn
-// (workgroup i to XCD i mod 8), each XCD with its own L2.  The ranks are dealt
-// to the XCDs in runs of G consecutive ranks, which in index order, and within
-// a cost bin of the heaviest-first order, are neighbouring strips of one row
-// chunk of a patch: the cache
-// lines two neighbouring strips share (their rows are 60 columns apart, not a
-// multiple of a 128-byte line) are then fetched into one L2.  The XCDs still
-// take ranks in turn, so the launch stays heaviest first in blocks of 8 G
-// ranks; positions past the last whole block keep their rank.
-__device__ __forceinline__ int rank_at(int pos, int n, int G) {
-    const int block = 8 * G;
-    if (G <= 1 || pos >= n / block * block) return pos;
-    const int xcd = pos & 7, slot = pos >> 3;
-    return ((slot / G) * 8 + xcd) * G + slot % G;
-}
-
 // Lane l's value, for a wave-uniform l (two scalar reads of the dwords).
 __device__ __forceinline__ double lane_read(double x, int l) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);

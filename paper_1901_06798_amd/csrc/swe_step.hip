@@ -51,6 +51,22 @@ struct StepArgs {
     int xcd_run;           // ranks dealt to an XCD in runs of this many (1: in turn)
 };
 
+// Rank in the launch order of launch position `pos` (one wave per
+// workgroup).  Workgroups go to the eight XCDs in turn (workgroup i to XCD
+// i mod 8), each XCD with its own L2.  The ranks are dealt to the XCDs in runs
+// of G consecutive ranks, which in index order, and within a cost bin of the
+// heaviest-first order, are neighbouring strips of one row chunk: the cache
+// lines two neighbouring strips share (their rows are 60 columns apart, not a
+// multiple of a 128-byte line) are then fetched into one L2.  The XCDs still
+// take ranks in turn, so the launch stays heaviest first in blocks of 8 G
+// ranks; positions past the last whole block keep their rank.
+__device__ __forceinline__ int rank_at(int pos, int n, int G) {
+    const int block = 8 * G;
+    if (G <= 1 || pos >= n / block * block) return pos;
+    const int xcd = pos & 7, slot = pos >> 3;
+    return ((slot / G) * 8 + xcd) * G + slot % G;
+}
+
 // Task at launch position `pos` (wave-uniform).
 __device__ __forceinline__ int task_at(const StepArgs& a, int pos) {
     const int k = rank_at(pos, a.nitems, a.xcd_run);
