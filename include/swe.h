@@ -116,7 +116,11 @@ typedef struct swe_patch {
  * largest wave speeds over the x- and y-edges of interior cells are
  * max-combined into smax[0], smax[1] (so it must hold 0 or an earlier value
  * on entry; swe_cfl_reduce resets it).  status: device uint32_t[2].
- * Only interior cells of q_out are written. */
+ * Only interior cells of q_out are written.
+ * Launch shape (results do not depend on it): strip tasks of 60 columns and
+ * SWE_ROWS_PER_WAVE rows (environment, default 48, at most 60), one wave
+ * per workgroup (SWE_WAVES_PER_BLOCK: 1, 2 or 4), task ranks dealt to the
+ * XCDs in runs of SWE_XCD_RUN (default 8; 1 deals them in turn). */
 int swe_patch_step(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
                    const void *b, const double *dt, double *smax, uint32_t *status,
                    void *stream);
@@ -206,8 +210,11 @@ int32_t swe_patch_tasks(const swe_patch *patch);
  * sched: device uint32_t[2 n], n = swe_patch_tasks(patch), that the caller
  * allocates once per patch, fills with zeros and passes to every step of that
  * patch; between calls the library owns its contents.  sched[0, n) is the
- * launch order: position k runs task sched[k] - 1 (task k where sched[k] is
- * 0, as after the zero fill, or out of range).  Each task writes its work
+ * launch order: rank r runs task sched[r] - 1 (task r where sched[r] is 0, as
+ * after the zero fill, or out of range).  Ranks are dealt to launch positions
+ * so that each of the eight XCDs takes runs of consecutive ranks (neighbouring
+ * strips share cache lines), which keeps the launch in rank order in blocks
+ * of 8 runs; the mapping is a permutation.  Each task writes its work
  * (row sweeps that needed solves) into sched[n + task].  NULL sched is an
  * error. */
 int swe_patch_step_sched(const swe_params *p, const swe_patch *patch, const void *q_in,
