@@ -53,8 +53,10 @@ class SphereSolver(PatchSolver):
         for key in ("lat0", "dlat"):
             if key not in pb.meta:
                 raise L.SweError(f"SphereSolver: the problem's meta needs {key!r}")
-        if abs(pb.meta["lat0"]) >= 90.0 or abs(pb.meta["lat0"] + pb.my * pb.meta["dlat"]) >= 90.0:
-            raise L.SweError("SphereSolver: the patch must not reach a pole")
+        lat0, dlat = pb.meta["lat0"], pb.meta["dlat"]
+        # the ghost frame, two rows beyond each side, must stay off the poles
+        if not (dlat > 0.0 and lat0 - 2.0 * dlat > -90.0 and lat0 + (pb.my + 2) * dlat < 90.0):
+            raise L.SweError("SphereSolver: the patch with its ghost rows must not reach a pole")
         super().__init__(pb, p, device, ordered=ordered, order_every=order_every)
         m = metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
         self.kappa_min = float(m[: pb.my + 4].min())

@@ -244,3 +244,19 @@ def test_sphere_metric_layout():
     assert w[1] == m[2] and w[0] == m[3]
     assert w[my + 4 + 1] == m[my + 4 + 3] and w[my + 4] == m[my + 4 + 4]
     assert np.array_equal(w[2: my + 4], m[2: my + 4]) and np.array_equal(w[my + 6:], m[my + 6:])
+
+
+def test_sphere_solver_rejects_polar_frames_on_the_host(L):
+    # checked before any device work (the solver needs a GPU only after them)
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.sphere import SphereSolver
+    for lat0, ny in ((89.0, 4), (-89.6, 10), (80.0, 38)):
+        pb = W.latlon_basin(8, ny, lat0=lat0, dlon=0.25, dlat=0.25, amp=0.0)
+        with pytest.raises(L.SweError, match="pole"):
+            SphereSolver(pb, L.params())
+    pb = W.latlon_basin(8, 8, lat0=10.0, dlon=0.25, dlat=0.25, amp=0.0)
+    with pytest.raises(L.SweError, match="FP64 split"):
+        SphereSolver(pb, L.params(precision=L.F32_DEV))
+    pb.meta = {}
+    with pytest.raises(L.SweError, match="meta"):
+        SphereSolver(pb, L.params())
