@@ -1,4 +1,5 @@
-"""Parity at the headline size, in the launch configuration the bench times:
+"""Parity at the headline size, in the launch configuration the bench times
+(and at the size of the bench's latitude-longitude patch):
 the 4096^2 shelf is advanced on the GPU (FP64 and FP32 surface deviation) far
 enough for the wave to run up the coast; then one more step is checked on
 sampled windows.  For each window the reference solver takes one step of the
@@ -110,3 +111,56 @@ def test_fullsize_windows_match_reference(gpu, orc, shelf, precision):
             worst = max(worst, e)
             assert e <= 1e-5, f"window ({j0}, {i0}): surface error {e:.3e} m"
     print(f"worst {'relative' if precision == 0 else 'surface (m)'} error {worst:.3e}", flush=True)
+
+
+def test_fullsize_sphere_windows_match_reference(gpu, orc):
+    # the bench's latitude-longitude patch (the paper's Pacific extent in
+    # 2.05-minute cells), heaviest first, advanced 600 steps; the windows'
+    # capacities and edge lengths are those of their own rows
+    L, _, torch = gpu
+    from paper_1901_06798_amd.sphere import SphereSolver
+    d = 140.0 / N
+    ny = int(round(96.0 / d))
+    pb = W.latlon_basin(N, ny, lon0=-240.0, lat0=-31.0, dlon=d, dlat=d, amp=2.0, sigma_deg=1.0,
+                        src=(-217.5, 38.0), bc=(W.BC_EXTRAP,) * 4)
+    print(f"case fullsize sphere {N}x{ny}", flush=True)
+    s = SphereSolver(pb, L.params())
+    s.initial_dt()
+    s.run_async(600)
+    torch.cuda.synchronize()
+    before = s.state()
+    dt = float(s.dt.item())
+    s.enqueue_step(cfl=False)
+    torch.cuda.synchronize()
+    after = s.state()
+    assert int(s.status[0].item()) & (L.STATUS_NONFINITE | L.STATUS_CFL_EXCEEDED) == 0
+    P = orc.params()
+    rng = np.random.default_rng(8)
+    wet = before[0] > 1e-3
+    edge = np.argwhere(wet[:, 1:] != wet[:, :-1])
+    src_j, src_i = int((38.0 + 31.0) / d), int((-217.5 + 240.0) / d)
+    origins = [(int(rng.integers(0, ny - WIN)), int(rng.integers(0, N - WIN))) for _ in range(16)]
+    origins += [(int(np.clip(j - WIN // 2, 0, ny - WIN)), int(np.clip(i - WIN // 2, 0, N - WIN)))
+                for j, i in edge[rng.choice(len(edge), 6, replace=False)]]
+    origins += [(src_j - WIN // 2 + dj, src_i - WIN // 2 + di)
+                for dj, di in ((0, 0), (-60, 40), (80, -70), (150, 150))]
+    origins += [(0, 0), (ny - WIN, N - WIN), (0, N // 2), (ny - WIN, 7), (ny // 2, 0)]
+    worst = 0.0
+    for j0, i0 in origins:
+        qs = [padded(f)[j0: j0 + WIN + 4, i0: i0 + WIN + 4] for f in before]
+        bw = padded(pb.b)[j0: j0 + WIN + 4, i0: i0 + WIN + 4]
+        q, bb = orc.new_state(qs[0][2:-2, 2:-2], qs[1][2:-2, 2:-2], qs[2][2:-2, 2:-2],
+                              bw[2:-2, 2:-2])
+        for k in range(3):
+            q[..., k] = qs[k]
+        bb[...] = bw
+        g = orc.grid(WIN, WIN, pb.dx, pb.dy, (orc.BC_USER,) * 4)
+        kap, ln = orc.sphere_metric(-31.0 + j0 * d, d, WIN)
+        out, _, _, nf = orc.step_sphere(P, g, q, bb, dt, kap, ln)
+        assert nf == 0
+        for k in range(3):
+            scale = max(np.abs(after[k]).max(), 1e-300)
+            e = np.abs(after[k][j0: j0 + WIN, i0: i0 + WIN] - out[2:-2, 2:-2, k]).max() / scale
+            worst = max(worst, e)
+            assert e <= 1e-12, f"window ({j0}, {i0}) field {k}: {e:.3e}"
+    print(f"worst relative error {worst:.3e}", flush=True)
