@@ -79,11 +79,13 @@ STEP_SOURCES = ("swe_common.hpp", "swe_march.hpp", "swe_math.hpp", "swe_step.hip
 
 
 def kernel_source_hash() -> str:
-    """Hash of the step kernels' HIP sources; a counter record is used only
-    while it carries this hash."""
+    """Hash of the step kernels' HIP sources and compiler flags; a counter
+    record is used only while it carries this hash."""
     import hashlib
+
+    from paper_1901_06798_amd.build import HIPFLAGS
     d = os.path.join(ROOT, "paper_1901_06798_amd", "csrc")
-    h = hashlib.sha256()
+    h = hashlib.sha256(" ".join(HIPFLAGS).encode())
     for name in STEP_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + f.read())

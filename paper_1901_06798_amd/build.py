@@ -14,8 +14,14 @@ OUT = os.path.join(HERE, "libswe.so")
 # -ffp-contract=off: every product and sum rounds as written, so a cell's
 # result does not depend on the tile or launch that computed it.
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
+# -structurizecfg-skip-uniform-regions: branches whose condition is the same
+# for the whole wave (the row loop's quiet-edge skips, the task bounds) stay
+# scalar branches instead of exec-masked regions; the FP64 step launch is 3 %
+# faster (0.368 against 0.379-0.381 ms on the 4096^2 shelf), the arithmetic
+# is unchanged.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-structurizecfg-skip-uniform-regions=1",
             "-Wall", "-Wno-unused-function"]
 
 
