@@ -126,29 +126,51 @@ def cover_block(geo: _Geo, i0: int, j0: int, nx: int, ny: int, r: int = 1) -> np
 
 def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
     """Interior cells of new patches: copies from old patches of the level
-    where they cover the cell, else the cell of the level below."""
-    ops = []
+    where they cover the cell (first in order), else the cell of the level
+    below (first in order).  Built rectangle by rectangle: each source patch
+    writes the block of the new patch it overlaps, where no earlier source
+    has, so the work is the new cells plus the overlaps; the entries are
+    written in place into one array."""
+    sizes = [int(new.mx[k]) * int(new.my[k]) for k in range(len(new.i0))]
+    out = np.empty(sum(sizes), dtype=FILL_DTYPE)
+    pos = 0
     for k in range(len(new.i0)):
+        ni0, nj0 = int(new.i0[k]), int(new.j0[k])
         mx, my = int(new.mx[k]), int(new.my[k])
-        J, I = np.mgrid[new.j0[k]: new.j0[k] + my, new.i0[k]: new.i0[k] + mx]
-        same = (cover_block(old, new.i0[k], new.j0[k], mx, my) if old is not None
-                else np.full((my, mx), -1, dtype=np.int64))
-        below = cover_block(coarse, new.i0[k], new.j0[k], mx, my, r)
-        if np.any((same < 0) & (below < 0)):
+        op = out[pos: pos + sizes[k]].reshape(my, mx)
+        pos += sizes[k]
+        op["reserved"] = 0
+        op["dst"] = (new.off[k] + (np.arange(my, dtype=np.int64)[:, None] + 2) * new.pitch[k]
+                     + (np.arange(mx, dtype=np.int64)[None, :] + 2))
+        done = np.zeros((my, mx), dtype=bool)
+        src, kind = op["src"], op["kind"]
+        for geo, rr, code in (((old, 1, L.SWE_AMR_COPY),) if old is not None else ()) + (
+                (coarse, r, L.SWE_AMR_COARSE),):
+            for s_ in range(len(geo.i0)):
+                # the source's interior in the new level's index
+                a = max(ni0, int(geo.i0[s_]) * rr)
+                b = min(ni0 + mx, (int(geo.i0[s_]) + int(geo.mx[s_])) * rr)
+                c = max(nj0, int(geo.j0[s_]) * rr)
+                d = min(nj0 + my, (int(geo.j0[s_]) + int(geo.my[s_])) * rr)
+                if a >= b or c >= d:
+                    continue
+                I = np.arange(a, b, dtype=np.int64) // rr
+                J = np.arange(c, d, dtype=np.int64) // rr
+                val = (geo.off[s_] + (J[:, None] - geo.j0[s_] + 2) * geo.pitch[s_]
+                       + (I[None, :] - geo.i0[s_] + 2))
+                blk = (slice(c - nj0, d - nj0), slice(a - ni0, b - ni0))
+                taken = done[blk]
+                if not taken.any():
+                    src[blk] = val
+                    kind[blk] = code
+                else:
+                    free = ~taken
+                    src[blk][free] = val[free]
+                    kind[blk][free] = code
+                done[blk] = True
+        if not done.all():
             raise L.SweError(f"new patch {k} is not over the level below")
-        op = np.zeros((my, mx), dtype=FILL_DTYPE)
-        op["dst"] = (new.off[k] + (J - new.j0[k] + 2) * new.pitch[k] + (I - new.i0[k] + 2))
-        cp = same >= 0
-        for s_ in np.unique(same[cp]):
-            m = same == s_
-            op["src"][m] = old.elem(s_, I[m], J[m])
-        op["kind"][cp] = L.SWE_AMR_COPY
-        for c in np.unique(below[~cp]):
-            m = (~cp) & (below == c)
-            op["src"][m] = coarse.elem(c, I[m] // r, J[m] // r)
-        op["kind"][~cp] = L.SWE_AMR_COARSE
-        ops.append(op.ravel())
-    return np.concatenate(ops) if ops else np.zeros(0, dtype=FILL_DTYPE)
+    return out
 
 
 class AmrSolver:
@@ -254,7 +276,7 @@ class AmrSolver:
             t3 = time.perf_counter()
             t_pool += t3 - t2
             ops = init_plan(geo, old_geo, self.geo[lev - 2], r)
-            dev_ops = torch.from_numpy(ops.view(np.uint8).copy()).to(self.dev)
+            dev_ops = torch.from_numpy(ops.view(np.uint8)).to(self.dev)
             L.swe_amr_init(self.p, dev_ops.data_ptr(), ops.size, bs.pools[bs.cur].data_ptr(),
                            bs.plane, bs.b.data_ptr(), old_bs.pools[old_bs.cur].data_ptr(),
                            old_bs.plane, parent.pools[parent.cur].data_ptr(), parent.plane,
