@@ -215,8 +215,9 @@ class AmrSolver:
         for lev in range(1, self.nlev):
             f = fill_plan(self.geo[lev], self.geo[lev - 1], self.r)
             a = average_plan(self.geo[lev], self.geo[lev - 1], self.r)
-            self.fill_ops.append(torch.from_numpy(f.view(np.uint8).copy()).to(self.dev))
-            self.avg_ops.append(torch.from_numpy(a.view(np.uint8).copy()).to(self.dev))
+            # contiguous plans: their bytes go to the device without a copy
+            self.fill_ops.append(torch.from_numpy(f.view(np.uint8)).to(self.dev))
+            self.avg_ops.append(torch.from_numpy(a.view(np.uint8)).to(self.dev))
             self.nfill.append(f.size)
             self.navg.append(a.size)
 
