@@ -110,6 +110,17 @@ typedef struct swe_patch {
     int32_t reserved;
 } swe_patch;
 
+/* Launch shape of the single-patch step (host struct; results never depend
+ * on it).  A zero field takes its default. */
+typedef struct swe_launch {
+    int32_t rows_per_task;   /* rows of a strip task, 1 .. 60 (default 48) */
+    int32_t waves_per_block; /* waves per workgroup: 1, 2 or 4 (default 1) */
+    int32_t xcd_run;         /* task ranks dealt to each of the eight XCDs in runs
+                                of this many (default 8; 1 deals them in turn;
+                                used with one wave per workgroup only) */
+    int32_t reserved;        /* 0 */
+} swe_launch;
+
 /* Advance one patch by one step: q_out = step(q_in, dt[0]).
  * p, patch: host.  q_in, q_out: plane sets as above, must not overlap.
  * b: bathymetry plane.  dt: device double.  smax: device double[2]; the
@@ -117,24 +128,28 @@ typedef struct swe_patch {
  * max-combined into smax[0], smax[1] (so it must hold 0 or an earlier value
  * on entry; swe_cfl_reduce resets it).  status: device uint32_t[2].
  * Only interior cells of q_out are written.
- * Launch shape (results do not depend on it): strip tasks of 60 columns and
- * SWE_ROWS_PER_WAVE rows (environment, default 48, at most 60), one wave
- * per workgroup (SWE_WAVES_PER_BLOCK: 1, 2 or 4), task ranks dealt to the
- * XCDs in runs of SWE_XCD_RUN (default 8; 1 deals them in turn). */
+ * Launch shape: the defaults of swe_launch (strip tasks of 60 columns and 48
+ * rows, one wave per workgroup, ranks dealt to the XCDs in runs of 8). */
 int swe_patch_step(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
                    const void *b, const double *dt, double *smax, uint32_t *status,
                    void *stream);
 
-/* Write the ghost cells of n patches (device array `patches`) into the
- * planes `q` (all three) and, if fill_b != 0, into `b`, by the rule above.
- * Sides with SWE_BC_USER are left untouched.  max_mx/max_my bound the
- * patch sizes (host ints) and size the launch. */
+/* Ghost cells (Sec. 3: a patch is its cells plus a frame of ghost cells that
+ * the step reads; Sec. 4 names filling them as a separate task of small
+ * parallelism; the physical boundary rules are this library's reading: the
+ * paper states none).  Writes the ghost cells of n patches (device array
+ * `patches`) into the planes `q` (all three) and, if fill_b != 0, into `b`,
+ * by the rule above.  Sides with SWE_BC_USER are left untouched.
+ * max_mx/max_my bound the patch sizes (host ints) and size the launch. */
 int swe_ghost_fill(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
                    int32_t max_my, void *q, void *b, int32_t fill_b, void *stream);
 
-/* Wave speeds of n patches without updating them: max-combines the largest
- * |s| over the x- and y-edges of each patch's interior cells into
- * smax_patch[2 k], smax_patch[2 k + 1].  Used for the first dt. */
+/* Wave speeds for the first step size (Sec. 2, CFL condition: the step
+ * follows from the largest wave speed s on the level; before the first step
+ * no step has produced speeds, so they come from the Riemann problems of the
+ * initial state).  Solves every edge of n patches without updating them and
+ * max-combines the largest |s| over the x- and y-edges of each patch's
+ * interior cells into smax_patch[2 k], smax_patch[2 k + 1]. */
 int swe_speed_scan(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
                    int32_t max_my, const void *q, const void *b, double *smax_patch,
                    void *stream);
@@ -189,17 +204,28 @@ int swe_patch_retake(const swe_params *p, const swe_patch *patch, const void *q_
  * ylo or yhi) they should mirror the interior rows (kappa_1 = kappa_2,
  * kappa_0 = kappa_3, len_1 = len_3, len_0 = len_4, likewise at the top), as
  * the ghost state does, so that no mass crosses the wall.  sched: NULL for
- * tasks in index order, else a schedule buffer as in swe_patch_step_sched
- * (launch order in, work per task out; swe_patch_order sorts it).  FP64
- * split step only; other arguments as swe_patch_step. */
+ * tasks in index order, else a schedule buffer of sched_len entries as in
+ * swe_patch_step_sched (launch order in, work per task out; swe_patch_order
+ * sorts it); launch: host, NULL = defaults.  FP64 split step only; other
+ * arguments as swe_patch_step. */
 int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const void *q_in,
                           void *q_out, const void *b, const double *dt, double *smax,
                           uint32_t *status, const double *metric, uint32_t *sched,
-                          void *stream);
+                          int64_t sched_len, const swe_launch *launch, void *stream);
 
-/* Number of strip tasks (waves) of one step of `patch` (host), or SWE_EINVAL
- * for a bad patch.  Sizes the schedule buffer of swe_patch_step_sched. */
-int32_t swe_patch_tasks(const swe_patch *patch);
+/* Number of strip tasks (waves) of one step of `patch` (host) with the
+ * launch shape `launch` (host, NULL = defaults), or SWE_EINVAL for a bad
+ * patch or shape.  The schedule buffer of swe_patch_step_sched holds twice
+ * this many uint32 entries. */
+int32_t swe_patch_tasks(const swe_patch *patch, const swe_launch *launch);
+
+/* Bytes of the caller-provided schedule buffer that swe_patch_step_sched,
+ * swe_patch_order and swe_patch_step_sphere use for `patch` with `launch`
+ * (both host; 8 bytes per task), or 0 for a bad patch or shape.  It is the
+ * only device memory beyond the states that the single-patch entry points
+ * take; the batched step's queue (two uint32) and the CFL slots are sized
+ * in their own comments. */
+size_t swe_workspace_bytes(const swe_patch *patch, const swe_launch *launch);
 
 /* swe_patch_step with its tasks launched in a given order (scheduling only:
  * q_out, smax and status are bitwise those of swe_patch_step), meant for
@@ -207,9 +233,11 @@ int32_t swe_patch_tasks(const swe_patch *patch);
  * solves (Sec. 2: such edges carry no waves) and end several times sooner
  * than tasks under a moving wave; launched in index order, a few long tasks
  * start late and the launch ends on them.
- * sched: device uint32_t[2 n], n = swe_patch_tasks(patch), that the caller
- * allocates once per patch, fills with zeros and passes to every step of that
- * patch; between calls the library owns its contents.  sched[0, n) is the
+ * sched: device uint32_t[sched_len], sched_len >= 2 n with n =
+ * swe_patch_tasks(patch, launch), that the caller allocates once per patch,
+ * fills with zeros and passes to every step of that patch (with the same
+ * launch); between calls the library owns its contents.  launch: host, NULL
+ * = defaults; a shorter sched_len or a bad shape is SWE_EINVAL.  sched[0, n) is the
  * launch order: rank r runs task sched[r] - 1 (task r where sched[r] is 0, as
  * after the zero fill, or out of range).  Ranks are dealt to launch positions
  * so that each of the eight XCDs takes runs of consecutive ranks (neighbouring
@@ -219,20 +247,44 @@ int32_t swe_patch_tasks(const swe_patch *patch);
  * error. */
 int swe_patch_step_sched(const swe_params *p, const swe_patch *patch, const void *q_in,
                          void *q_out, const void *b, const double *dt, double *smax,
-                         uint32_t *status, uint32_t *sched, void *stream);
+                         uint32_t *status, uint32_t *sched, int64_t sched_len,
+                         const swe_launch *launch, void *stream);
 
 /* Launch order for the next swe_patch_step_sched of `patch` (host) from the
  * work its last one recorded: sched[0, n) = the tasks by work, largest
  * first, ties by task index (one small launch; work above 127 sorts as 127).
  * Enqueue it after the step on the same stream, every step or every few
- * steps.  NULL sched is an error. */
-int swe_patch_order(const swe_patch *patch, uint32_t *sched, void *stream);
+ * steps.  sched_len and launch as for swe_patch_step_sched; NULL sched is an
+ * error. */
+int swe_patch_order(const swe_patch *patch, uint32_t *sched, int64_t sched_len,
+                    const swe_launch *launch, void *stream);
 
-/* Water volume sum(h) dx dy over the interior of each patch, in FP64,
- * written to mass_patch[k] (deterministic order).  In SWE_F32_DEV, h is
- * eta' + sea_level - b accumulated in FP64. */
+/* Water volume (Sec. 2: the equations are conservation laws for the depth,
+ * and Sec. 3 notes where AMR gives up exact conservation of mass; this is the
+ * quantity such statements are about): sum(h) dx dy over the interior of each
+ * patch, in FP64, written to mass_patch[k] (deterministic order).  In
+ * SWE_F32_DEV, h is eta' + sea_level - b accumulated in FP64. */
 int swe_mass(const swe_params *p, const swe_patch *patches, int32_t n, const void *q,
              const void *b, double *mass_patch, void *stream);
+
+/* State in the precision's planes from FP64 data (the layout of Sec. 4's
+ * structure-of-arrays pool; the surface-deviation form is this library's
+ * FP32 storage, eta' = h + b - sea_level).  For the interior cells of n
+ * patches (device table `patches`): src holds FP64 planes (h, hu, hv) with
+ * the same element offsets, pitch and plane stride as q, src_b the FP64 bed
+ * with the offsets of b.  SWE_F64 copies them; SWE_F32_DEV stores
+ * eta' = (h > 0 ? h + b : b) - sea_level, formed in FP64 and rounded once,
+ * and hu, hv, b rounded to FP32.  Ghost cells are not written (fill them
+ * with swe_ghost_fill).  max_mx/max_my bound the patch sizes. */
+int swe_state_import(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
+                     int32_t max_my, const double *src, const double *src_b, void *q, void *b,
+                     void *stream);
+
+/* The inverse for reading results: interior (h, hu, hv) of n patches into
+ * FP64 planes dst (layout as in swe_state_import); SWE_F32_DEV gives
+ * h = max(eta' + sea_level - b, 0) in FP64. */
+int swe_state_export(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
+                     int32_t max_my, const void *q, const void *b, double *dst, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched step: many patches (e.g. the patches of an AMR hierarchy, or the
@@ -293,8 +345,10 @@ int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sc
 
 /* Advance every patch of the plan: patch k takes tref_k substeps of
  * dt_group[group_k] / tref_k from pool_in to pool_out (pool_in is not
- * modified; pool_work, same size as the pools, holds intermediate substeps of
- * patches with tref > 1; NULL is allowed when every tref is 1).  The largest
+ * modified; pool_work holds intermediate substeps of patches with tref > 1
+ * and is required when the plan has items or nsub > 1, else it may be NULL).
+ * pool_in, pool_out and pool_work hold pool_elems elements each and must not
+ * overlap.  The largest
  * speeds of all substeps are max-combined into smax_patch[2 k], [2 k + 1].
  * patches, items, tasks: device copies of the table and of the plan; plain:
  * device pointer to the plan's nplain plain tasks (tasks + ntasks - nplain),
@@ -304,7 +358,7 @@ int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sc
 int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_item *items,
                      int32_t nitems, const swe_task *tasks, const swe_task *plain,
                      int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
-                     void *pool_work,
+                     void *pool_work, int64_t pool_elems,
                      const void *pool_b, const double *dt_group, double *smax_patch,
                      uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                      void *stream);
@@ -318,7 +372,7 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
 int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_item *items,
                        int32_t nitems, const swe_task *tasks, const swe_task *plain,
                        int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
-                       void *pool_work,
+                       void *pool_work, int64_t pool_elems,
                        const void *pool_b, const double *dt_group, double *smax_patch,
                        uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                        const uint32_t *retake, int32_t ngroups, void *stream);

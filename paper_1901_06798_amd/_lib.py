@@ -54,6 +54,15 @@ class swe_schedule(ctypes.Structure):
                 ("order", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
 
 
+class swe_launch(ctypes.Structure):
+    _fields_ = [("rows_per_task", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("xcd_run", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def launch(rows_per_task=0, waves_per_block=0, xcd_run=0) -> swe_launch:
+    return swe_launch(rows_per_task, waves_per_block, xcd_run, 0)
+
+
 class swe_task(ctypes.Structure):
     _fields_ = [("patch", ctypes.c_int32), ("strip", ctypes.c_int32), ("row0", ctypes.c_int32),
                 ("rows", ctypes.c_int32)]
@@ -103,14 +112,19 @@ def lib():
         L.swe_patch_retake.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                        _P, _P]
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
-        L.swe_patch_tasks.argtypes = [ctypes.POINTER(swe_patch)]
-        L.swe_patch_tasks.restype = i32
-        L.swe_patch_step_sched.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
-                                           _P, _P]
-        L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, _P]
-        L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
-                                            _P, _P, _P, _P]
         i64, dbl = ctypes.c_int64, ctypes.c_double
+        pl = ctypes.POINTER(swe_launch)
+        L.swe_patch_tasks.argtypes = [ctypes.POINTER(swe_patch), pl]
+        L.swe_patch_tasks.restype = i32
+        L.swe_workspace_bytes.argtypes = [ctypes.POINTER(swe_patch), pl]
+        L.swe_workspace_bytes.restype = ctypes.c_size_t
+        L.swe_patch_step_sched.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
+                                           _P, i64, pl, _P]
+        L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, i64, pl, _P]
+        L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
+                                            _P, _P, _P, i64, pl, _P]
+        L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P, _P]
+        L.swe_state_export.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P]
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
         L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
         L.swe_amr_flag.argtypes = [pp, _P, i32, i32, i32, _P, _P, dbl, i32, i32, _P, _P]
@@ -120,17 +134,18 @@ def lib():
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
-        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P, _P, _P,
-                                       _P, _P, ps, _P]
-        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, _P, _P,
-                                         _P, _P, _P, ps, _P, i32, _P]
+        L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64, _P,
+                                       _P, _P, _P, _P, ps, _P]
+        L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64,
+                                         _P, _P, _P, _P, _P, ps, _P, i32, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
                      "swe_mass", "swe_batched_plan", "swe_batched_step", "swe_patch_retake",
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
                      "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
-                     "swe_amr_init", "swe_patch_step_sphere"):
+                     "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
+                     "swe_state_export"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -152,29 +167,54 @@ def swe_patch_step(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, 
                                 status, stream), "swe_patch_step")
 
 
-def swe_patch_tasks(pt: swe_patch) -> int:
-    n = lib().swe_patch_tasks(ctypes.byref(pt))
+def _lp(launch: swe_launch | None):
+    return ctypes.byref(launch) if launch is not None else None
+
+
+def swe_patch_tasks(pt: swe_patch, launch: swe_launch | None = None) -> int:
+    n = lib().swe_patch_tasks(ctypes.byref(pt), _lp(launch))
     if n < 0:
         _check(n, "swe_patch_tasks")
     return n
 
 
+def swe_workspace_bytes(pt: swe_patch, launch: swe_launch | None = None) -> int:
+    return int(lib().swe_workspace_bytes(ctypes.byref(pt), _lp(launch)))
+
+
 def swe_patch_step_sched(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
-                         smax: int, status: int, sched: int, stream: int = 0) -> None:
+                         smax: int, status: int, sched: int, sched_len: int,
+                         launch: swe_launch | None = None, stream: int = 0) -> None:
     _check(lib().swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
-                                      smax, status, sched, stream), "swe_patch_step_sched")
+                                      smax, status, sched, sched_len, _lp(launch), stream),
+           "swe_patch_step_sched")
 
 
 def swe_patch_step_sphere(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
                           smax: int, status: int, metric: int, sched: int = 0,
+                          sched_len: int = 0, launch: swe_launch | None = None,
                           stream: int = 0) -> None:
     _check(lib().swe_patch_step_sphere(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
-                                       smax, status, metric, sched, stream),
-           "swe_patch_step_sphere")
+                                       smax, status, metric, sched, sched_len, _lp(launch),
+                                       stream), "swe_patch_step_sphere")
 
 
-def swe_patch_order(pt: swe_patch, sched: int, stream: int = 0) -> None:
-    _check(lib().swe_patch_order(ctypes.byref(pt), sched, stream), "swe_patch_order")
+def swe_patch_order(pt: swe_patch, sched: int, sched_len: int,
+                    launch: swe_launch | None = None, stream: int = 0) -> None:
+    _check(lib().swe_patch_order(ctypes.byref(pt), sched, sched_len, _lp(launch), stream),
+           "swe_patch_order")
+
+
+def swe_state_import(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, src: int,
+                     src_b: int, q: int, b: int, stream: int = 0) -> None:
+    _check(lib().swe_state_import(ctypes.byref(p), patches, n, max_mx, max_my, src, src_b, q, b,
+                                  stream), "swe_state_import")
+
+
+def swe_state_export(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,
+                     b: int, dst: int, stream: int = 0) -> None:
+    _check(lib().swe_state_export(ctypes.byref(p), patches, n, max_mx, max_my, q, b, dst,
+                                  stream), "swe_state_export")
 
 
 def swe_amr_fill(p: swe_params, ops: int, nops: int, q_fine: int, fine_plane_stride: int,
@@ -293,20 +333,22 @@ SWE_TASK_BYTES = ctypes.sizeof(swe_task)
 
 def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
                      plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
-                     pool_work: int, pool_b: int, dt_group: int, smax_patch: int, status: int,
-                     queue: int, sched: swe_schedule, stream: int = 0) -> None:
+                     pool_work: int, pool_elems: int, pool_b: int, dt_group: int,
+                     smax_patch: int, status: int, queue: int, sched: swe_schedule,
+                     stream: int = 0) -> None:
     _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, plain, nplain,
-                                  nsub, pool_in, pool_out, pool_work, pool_b, dt_group,
-                                  smax_patch, status, queue, ctypes.byref(sched), stream),
-           "swe_batched_step")
+                                  nsub, pool_in, pool_out, pool_work, pool_elems, pool_b,
+                                  dt_group, smax_patch, status, queue, ctypes.byref(sched),
+                                  stream), "swe_batched_step")
 
 
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
                        plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
-                       pool_work: int, pool_b: int, dt_group: int, smax_patch: int,
-                       status: int, queue: int, sched: swe_schedule, retake: int, ngroups: int,
-                       stream: int = 0) -> None:
+                       pool_work: int, pool_elems: int, pool_b: int, dt_group: int,
+                       smax_patch: int, status: int, queue: int, sched: swe_schedule,
+                       retake: int, ngroups: int, stream: int = 0) -> None:
     _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, plain,
-                                    nplain, nsub, pool_in, pool_out, pool_work, pool_b,
-                                    dt_group, smax_patch, status, queue, ctypes.byref(sched),
-                                    retake, ngroups, stream), "swe_batched_retake")
+                                    nplain, nsub, pool_in, pool_out, pool_work, pool_elems,
+                                    pool_b, dt_group, smax_patch, status, queue,
+                                    ctypes.byref(sched), retake, ngroups, stream),
+           "swe_batched_retake")

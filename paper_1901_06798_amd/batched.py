@@ -95,23 +95,26 @@ class BatchedSolver:
         return v.reshape(nplanes, rows, pitch)
 
     def upload(self) -> None:
-        npdt = np.float32 if self.dev_path else np.float64
-        host = torch.zeros(3 * self.plane, dtype=self.dtype)
-        hb = torch.zeros(self.plane, dtype=self.dtype)
+        """Every patch's initial state from its FP64 arrays: staged in FP64 and
+        converted into the pool's precision by swe_state_import."""
+        host = torch.zeros(3 * self.plane, dtype=torch.float64)
+        hb = torch.zeros(self.plane, dtype=torch.float64)
         for k, pb in enumerate(self.problems):
             Q = self._view(host, k, 3)
             B = self._view(hb, k, 1)[0]
-            first = pb.h
-            if self.dev_path:
-                first = np.where(pb.h > 0.0, pb.h + pb.b - self.p.sea_level, pb.b - self.p.sea_level)
             inner = (slice(2, pb.my + 2), slice(2, pb.mx + 2))
-            for c, arr in enumerate((first, pb.hu, pb.hv)):
-                Q[c][inner] = torch.from_numpy(np.ascontiguousarray(arr, dtype=npdt))
-            B[inner] = torch.from_numpy(np.ascontiguousarray(pb.b, dtype=npdt))
-        self.pools[self.cur].copy_(host.to(self.dev))
-        self.b.copy_(hb.to(self.dev))
+            for c, arr in enumerate((pb.h, pb.hu, pb.hv)):
+                Q[c][inner] = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64))
+            B[inner] = torch.from_numpy(np.ascontiguousarray(pb.b, dtype=np.float64))
+        src, src_b = host.to(self.dev), hb.to(self.dev)
+        self.pools[self.cur].zero_()
+        self.b.zero_()
+        L.swe_state_import(self.p, self.table.data_ptr(), self.n, self.max_mx, self.max_my,
+                           src.data_ptr(), src_b.data_ptr(), self.pools[self.cur].data_ptr(),
+                           self.b.data_ptr(), self.stream)
         L.swe_ghost_fill(self.p, self.table.data_ptr(), self.n, self.max_mx, self.max_my,
                          self.pools[self.cur].data_ptr(), self.b.data_ptr(), 1, self.stream)
+        torch.cuda.current_stream(self.dev).synchronize()  # src, src_b are freed below
         self.status.zero_()
         self.smax.zero_()
 
@@ -135,7 +138,8 @@ class BatchedSolver:
                 self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
                 self.nplain, self.nsub, self.pools[self.cur].data_ptr(),
                 self.pools[1 - self.cur].data_ptr(),
-                self.work.data_ptr() if self.work is not None else 0, self.b.data_ptr())
+                self.work.data_ptr() if self.work is not None else 0, 3 * self.plane,
+                self.b.data_ptr())
         L.swe_batched_step(self.p, *args, dt_ptr if dt_ptr is not None else self.dt.data_ptr(),
                            self.smax.data_ptr(), self.status.data_ptr(), self.queue.data_ptr(),
                            self.sched, self.stream)

@@ -370,7 +370,7 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
 static int batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
                         int32_t nitems, const swe_task* tasks, const swe_task* plain,
                         int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
-                        void* pool_work,
+                        void* pool_work, int64_t pool_elems,
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
                         const uint32_t* retake, int32_t ngroups, void* stream) {
@@ -383,13 +383,25 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     if (p->order != 1 && p->order != 2) return bfail(SWE_EINVAL, "params: order must be 1 or 2");
     if (nitems < 0 || nplain < 0 || nsub < 0 || (nplain > 0 && nsub < 1))
         return bfail(SWE_EINVAL, "swe_batched_step: bad counts");
-    if (nsub > 1 && !pool_work)
+    // items (patches with tref > 1) and per-substep launches alternate
+    // between pool_out and pool_work
+    if ((nitems > 0 || nsub > 1) && !pool_work)
         return bfail(SWE_EINVAL, "swe_batched_step: substeps need pool_work");
     if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch || !status ||
         (nitems > 0 && (!items || !tasks || !queue)) || (nplain > 0 && !plain))
         return bfail(SWE_EINVAL, "swe_batched_step: null pointer");
-    if (pool_in == pool_out || pool_work == pool_in || pool_work == pool_out)
-        return bfail(SWE_EINVAL, "swe_batched_step: pools must be distinct");
+    if (pool_elems < 1) return bfail(SWE_EINVAL, "swe_batched_step: pool_elems must be >= 1");
+    {
+        const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
+        const size_t nb = (size_t)pool_elems * esz;
+        auto lap = [nb](const void* x, const void* y) {
+            const char* a = static_cast<const char*>(x);
+            const char* b = static_cast<const char*>(y);
+            return x && y && a < b + nb && b < a + nb;
+        };
+        if (lap(pool_in, pool_out) || lap(pool_work, pool_in) || lap(pool_work, pool_out))
+            return bfail(SWE_EINVAL, "swe_batched_step: pools overlap");
+    }
     if (nitems == 0 && nplain == 0) return SWE_OK;
     swe::BatchArgs a;
     a.patches = patches;
@@ -397,7 +409,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.tasks = tasks;
     a.pin = pool_in;
     a.pout = pool_out;
-    a.pwork = pool_work ? pool_work : pool_out;
+    a.pwork = pool_work ? pool_work : pool_out;  // unused without substeps
     a.pb = pool_b;
     a.dt_group = dt_group;
     a.smax = smax_patch;
@@ -475,26 +487,26 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
 int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
                      int32_t nitems, const swe_task* tasks, const swe_task* plain,
                      int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
-                     void* pool_work, const void* pool_b, const double* dt_group,
-                     double* smax_patch, uint32_t* status, uint32_t* queue,
-                     const swe_schedule* sched, void* stream) {
+                     void* pool_work, int64_t pool_elems, const void* pool_b,
+                     const double* dt_group, double* smax_patch, uint32_t* status,
+                     uint32_t* queue, const swe_schedule* sched, void* stream) {
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
-                        pool_out, pool_work, pool_b, dt_group, smax_patch, status, queue, sched,
-                        nullptr, 0, stream);
+                        pool_out, pool_work, pool_elems, pool_b, dt_group, smax_patch, status,
+                        queue, sched, nullptr, 0, stream);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
                        int32_t nitems, const swe_task* tasks, const swe_task* plain,
                        int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
-                       void* pool_work, const void* pool_b, const double* dt_group,
-                       double* smax_patch, uint32_t* status, uint32_t* queue,
-                       const swe_schedule* sched, const uint32_t* retake, int32_t ngroups,
-                       void* stream) {
+                       void* pool_work, int64_t pool_elems, const void* pool_b,
+                       const double* dt_group, double* smax_patch, uint32_t* status,
+                       uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
+                       int32_t ngroups, void* stream) {
     if (!retake || ngroups < 1)
         return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags or ngroups < 1");
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
-                        pool_out, pool_work, pool_b, dt_group, smax_patch, status, queue, sched,
-                        retake, ngroups, stream);
+                        pool_out, pool_work, pool_elems, pool_b, dt_group, smax_patch, status,
+                        queue, sched, retake, ngroups, stream);
 }
 
 }  // extern "C"

@@ -499,6 +499,50 @@ __global__ void __launch_bounds__(256) k_mass(const swe_patch* __restrict__ patc
     if (threadIdx.x == 0) mass[pk] = red[0] * p.dx * p.dy;
 }
 
+// Interior cells of each patch from FP64 planes into the precision's planes
+// (copy, or the surface deviation formed in FP64 and rounded once).
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_state_import(const swe_patch* __restrict__ patches,
+                                                      const double* __restrict__ src,
+                                                      const double* __restrict__ src_b,
+                                                      void* qv, void* bv, double sea_level) {
+    using S = typename Prec<DEV>::S;
+    S* __restrict__ q = static_cast<S*>(qv);
+    S* __restrict__ b = static_cast<S*>(bv);
+    const swe_patch p = patches[blockIdx.y];
+    const int64_t ncell = (int64_t)p.mx * p.my;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p.off + (2 + k / p.mx) * (int64_t)p.pitch + 2 + k % p.mx;
+        const double h = src[i], bed = src_b[i];
+        q[i] = DEV ? S((h > 0.0 ? h + bed : bed) - sea_level) : S(h);
+        q[i + p.plane_stride] = S(src[i + p.plane_stride]);
+        q[i + 2 * p.plane_stride] = S(src[i + 2 * p.plane_stride]);
+        b[i] = S(bed);
+    }
+}
+
+// Interior (h, hu, hv) of each patch as FP64 planes.
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_state_export(const swe_patch* __restrict__ patches,
+                                                      const void* qv, const void* bv,
+                                                      double* __restrict__ dst,
+                                                      double sea_level) {
+    using S = typename Prec<DEV>::S;
+    const S* __restrict__ q = static_cast<const S*>(qv);
+    const S* __restrict__ b = static_cast<const S*>(bv);
+    const swe_patch p = patches[blockIdx.y];
+    const int64_t ncell = (int64_t)p.mx * p.my;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p.off + (2 + k / p.mx) * (int64_t)p.pitch + 2 + k % p.mx;
+        const double h = DEV ? fmax((double(q[i]) + sea_level) - double(b[i]), 0.0) : double(q[i]);
+        dst[i] = h;
+        dst[i + p.plane_stride] = double(q[i + p.plane_stride]);
+        dst[i + 2 * p.plane_stride] = double(q[i + 2 * p.plane_stride]);
+    }
+}
+
 }  // namespace swe
 
 // ===========================================================================
@@ -569,21 +613,38 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-// Rows per strip task.  A wave marches H rows plus 4 rows of pipeline fill.
+// Launch shape of the patch step with the defaults filled in, or an error.
+// Rows per strip task: a wave marches H rows plus 4 rows of pipeline fill.
 // Waves over water at rest skip their Riemann solves and finish early, so
 // tasks must be many more than the device holds at once for the launch to
 // balance; in index order 32 rows did best, and with the heaviest tasks
 // launched first 40-56 rows are 7-8 % faster than 32 on the 4096^2 shelf (the
-// fill overhead drops from 1/8 to 1/12 at 48).  SWE_ROWS_PER_WAVE overrides,
-// up to kWave - 4: the task's rows with their two ghost rows either side then
-// fit one wave's lanes, which the latitude-longitude march uses to hold its
-// per-row values.
-int rows_per_chunk(int my) {
-    const char* e = std::getenv("SWE_ROWS_PER_WAVE");
-    int H = e ? std::atoi(e) : 48;
-    if (H < 1) H = 48;
-    if (H > swe::kWave - 4) H = swe::kWave - 4;
-    return H < my ? H : my;
+// fill overhead drops from 1/8 to 1/12 at 48).  At most kWave - 4 rows: the
+// task's rows with their two ghost rows either side then fit one wave's lanes,
+// which the latitude-longitude march uses to hold its per-row values.  Runs of
+// 8 ranks per XCD fetch 13 % fewer bytes on the 4096^2 FP64 step than ranks
+// dealt in turn; only one-wave workgroups map positions to XCDs one to one.
+struct Shape {
+    int H, wpb, xcd_run;
+};
+
+int launch_shape(const swe_launch* l, int my, Shape* out) {
+    int H = 48, wpb = 1, run = 8;
+    if (l) {
+        if (l->rows_per_task < 0 || l->rows_per_task > swe::kWave - 4)
+            return fail(SWE_EINVAL, "launch: rows_per_task must be 0 (default) or 1 .. 60");
+        if (l->waves_per_block != 0 && l->waves_per_block != 1 && l->waves_per_block != 2 &&
+            l->waves_per_block != 4)
+            return fail(SWE_EINVAL, "launch: waves_per_block must be 0 (default), 1, 2 or 4");
+        if (l->xcd_run < 0) return fail(SWE_EINVAL, "launch: xcd_run must be >= 0");
+        if (l->rows_per_task) H = l->rows_per_task;
+        if (l->waves_per_block) wpb = l->waves_per_block;
+        if (l->xcd_run) run = l->xcd_run;
+    }
+    out->H = H < my ? H : my;
+    out->wpb = wpb;
+    out->xcd_run = wpb == 1 && run > 1 ? run : 1;
+    return SWE_OK;
 }
 
 }  // namespace
@@ -600,20 +661,29 @@ const char* swe_last_error(void) { return g_err.c_str(); }
 
 const char* swe_version(void) { return "swe-gfx950 0.1"; }
 
-// Strip tasks of one patch step (the launch's waves).
-static int patch_tasks(const swe_patch* patch) {
-    const int H = rows_per_chunk(patch->my);
+// Strip tasks of one patch step (the launch's waves) for a given task height.
+static int patch_tasks(const swe_patch* patch, int H) {
     const int nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
     return nstrips * ((patch->my + H - 1) / H);
 }
 
 static int patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                       const void* b, const double* dt, double* smax, uint32_t* status,
-                      const uint32_t* gate, uint32_t* sched, void* stream,
-                      const double* metric = nullptr) {
+                      const uint32_t* gate, uint32_t* sched, int64_t sched_len,
+                      const swe_launch* launch, void* stream, const double* metric = nullptr) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_patch(patch))) return rc;
+    Shape sh;
+    if ((rc = launch_shape(launch, patch->my, &sh))) return rc;
+    // a gated retake launch, which mostly ends at once, takes four waves per
+    // workgroup (fewer workgroups to dispatch; results do not depend on it)
+    if (gate) {
+        sh.wpb = 4;
+        sh.xcd_run = 1;
+    }
+    if (sched && sched_len < 2 * (int64_t)patch_tasks(patch, sh.H))
+        return fail(SWE_EINVAL, "swe_patch_step: schedule buffer shorter than 2 x tasks");
     if (!q_in || !q_out || !b || !dt || !smax || !status)
         return fail(SWE_EINVAL, "swe_patch_step: null pointer");
     if (p->method == SWE_UNSPLIT && p->precision != SWE_F64)
@@ -639,16 +709,12 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.pitch = patch->pitch;
     a.mx = patch->mx;
     a.my = patch->my;
-    // one wave per workgroup: the finest unit the dispatcher can balance; a
-    // gated retake launch, which mostly ends at once, takes four (fewer
-    // workgroups to dispatch; results do not depend on the tiling)
-    const char* wpb = std::getenv("SWE_WAVES_PER_BLOCK");
-    int waves_per_block = gate ? 4 : wpb ? std::atoi(wpb) : 1;
-    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-        waves_per_block = 1;
+    // one wave per workgroup by default: the finest unit the dispatcher can
+    // balance
+    const int waves_per_block = sh.wpb;
     const bool fric = p->manning_n > 0.0;
     const bool f64 = p->precision == SWE_F64;
-    a.H = rows_per_chunk(patch->my);
+    a.H = sh.H;
     a.nstrips = (patch->mx + swe::kStripOut - 1) / swe::kStripOut;
     const int nchunks = (patch->my + a.H - 1) / a.H;
     a.nitems = a.nstrips * nchunks;
@@ -658,12 +724,7 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.order = sched;
     a.cost = sched ? sched + a.nitems : nullptr;
     a.metric = metric;
-    // runs of strips per XCD: with 8 the 4096^2 FP64 step fetches 13 % fewer
-    // bytes than with ranks dealt in turn (SWE_XCD_RUN overrides; 1 turns it off);
-    // only one-wave workgroups map positions to XCDs one to one
-    const char* xr = std::getenv("SWE_XCD_RUN");
-    const int run = xr ? std::atoi(xr) : 8;
-    a.xcd_run = waves_per_block == 1 && run > 1 ? run : 1;
+    a.xcd_run = sh.xcd_run;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid(blocks), block(64 * waves_per_block);
@@ -690,39 +751,55 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
 int swe_patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                    const void* b, const double* dt, double* smax, uint32_t* status,
                    void* stream) {
-    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, nullptr, stream);
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, nullptr, 0, nullptr,
+                      stream);
 }
 
 int swe_patch_step_sphere(const swe_params* p, const swe_patch* patch, const void* q_in,
                           void* q_out, const void* b, const double* dt, double* smax,
                           uint32_t* status, const double* metric, uint32_t* sched,
-                          void* stream) {
+                          int64_t sched_len, const swe_launch* launch, void* stream) {
     if (!metric) return fail(SWE_EINVAL, "swe_patch_step_sphere: null metric");
     if (p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
         return fail(SWE_EINVAL, "swe_patch_step_sphere: FP64 split step only");
-    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched, stream,
-                      metric);
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched, sched_len,
+                      launch, stream, metric);
 }
 
-int32_t swe_patch_tasks(const swe_patch* patch) {
-    const int rc = check_patch(patch);
-    return rc ? rc : patch_tasks(patch);
+int32_t swe_patch_tasks(const swe_patch* patch, const swe_launch* launch) {
+    int rc = check_patch(patch);
+    if (rc) return rc;
+    Shape sh;
+    if ((rc = launch_shape(launch, patch->my, &sh))) return rc;
+    return patch_tasks(patch, sh.H);
+}
+
+size_t swe_workspace_bytes(const swe_patch* patch, const swe_launch* launch) {
+    const int32_t n = swe_patch_tasks(patch, launch);
+    return n < 0 ? 0 : 2 * (size_t)n * sizeof(uint32_t);
 }
 
 int swe_patch_step_sched(const swe_params* p, const swe_patch* patch, const void* q_in,
                          void* q_out, const void* b, const double* dt, double* smax,
-                         uint32_t* status, uint32_t* sched, void* stream) {
+                         uint32_t* status, uint32_t* sched, int64_t sched_len,
+                         const swe_launch* launch, void* stream) {
     if (!sched) return fail(SWE_EINVAL, "swe_patch_step_sched: null schedule buffer");
-    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched, stream);
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched, sched_len,
+                      launch, stream);
 }
 
-int swe_patch_order(const swe_patch* patch, uint32_t* sched, void* stream) {
+int swe_patch_order(const swe_patch* patch, uint32_t* sched, int64_t sched_len,
+                    const swe_launch* launch, void* stream) {
     int rc = check_patch(patch);
     if (rc) return rc;
     if (!sched) return fail(SWE_EINVAL, "swe_patch_order: null schedule buffer");
-    const int n = patch_tasks(patch);
+    Shape sh;
+    if ((rc = launch_shape(launch, patch->my, &sh))) return rc;
+    const int n = patch_tasks(patch, sh.H);
+    if (sched_len < 2 * (int64_t)n)
+        return fail(SWE_EINVAL, "swe_patch_order: schedule buffer shorter than 2 x tasks");
     // a task marches H + 5 rows, each with an x- and a y-sweep
-    const int most = 2 * (rows_per_chunk(patch->my) + 5);
+    const int most = 2 * (sh.H + 5);
     const uint32_t width = (uint32_t)((most + swe::kOrderBins) / swe::kOrderBins);
     hipLaunchKernelGGL(swe::k_order, dim3(1), dim3(swe::kOrderThreads), 0,
                        static_cast<hipStream_t>(stream), sched, sched + n, n, width);
@@ -735,7 +812,7 @@ int swe_patch_retake(const swe_params* p, const swe_patch* patch, const void* q_
     if (!retake) return fail(SWE_EINVAL, "swe_patch_retake: null retake flags");
     if (patch && patch->group < 0) return fail(SWE_EINVAL, "swe_patch_retake: negative group");
     return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
-                      patch ? retake + patch->group : retake, nullptr, stream);
+                      patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream);
 }
 
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
@@ -809,6 +886,53 @@ int swe_mass(const swe_params* p, const swe_patch* patches, int32_t n, const voi
                            static_cast<hipStream_t>(stream), patches, q, b, mass_patch,
                            p->sea_level);
     return check_launch("swe_mass");
+}
+
+static int state_grid(int32_t n, int32_t max_mx, int32_t max_my, dim3* grid) {
+    if (n < 0 || max_mx < 1 || max_my < 1) return fail(SWE_EINVAL, "bad patch count or bounds");
+    int64_t bx = ((int64_t)max_mx * max_my + 255) / 256;
+    if (bx > 4096) bx = 4096;
+    *grid = dim3((unsigned)bx, (unsigned)n);
+    return SWE_OK;
+}
+
+int swe_state_import(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
+                     int32_t max_my, const double* src, const double* src_b, void* q, void* b,
+                     void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !src || !src_b || !q || !b)
+        return fail(SWE_EINVAL, "swe_state_import: null pointer");
+    dim3 grid;
+    if ((rc = state_grid(n, max_mx, max_my, &grid))) return rc;
+    if (n == 0) return SWE_OK;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_state_import<false>, grid, dim3(256), 0, st, patches, src,
+                           src_b, q, b, p->sea_level);
+    else
+        hipLaunchKernelGGL(swe::k_state_import<true>, grid, dim3(256), 0, st, patches, src,
+                           src_b, q, b, p->sea_level);
+    return check_launch("swe_state_import");
+}
+
+int swe_state_export(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
+                     int32_t max_my, const void* q, const void* b, double* dst, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !q || !dst || (p->precision == SWE_F32_DEV && !b))
+        return fail(SWE_EINVAL, "swe_state_export: null pointer");
+    dim3 grid;
+    if ((rc = state_grid(n, max_mx, max_my, &grid))) return rc;
+    if (n == 0) return SWE_OK;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == SWE_F64)
+        hipLaunchKernelGGL(swe::k_state_export<false>, grid, dim3(256), 0, st, patches, q, b, dst,
+                           p->sea_level);
+    else
+        hipLaunchKernelGGL(swe::k_state_export<true>, grid, dim3(256), 0, st, patches, q, b, dst,
+                           p->sea_level);
+    return check_launch("swe_state_export");
 }
 
 }  // extern "C"

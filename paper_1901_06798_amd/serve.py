@@ -271,7 +271,7 @@ class ScenarioServer:
                     self.tasks.data_ptr(),
                     self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
                     self.nplain, self.nsub, self.pools[self.cur].data_ptr(),
-                    self.pools[1 - self.cur].data_ptr(), 0, self.b.data_ptr(),
+                    self.pools[1 - self.cur].data_ptr(), 0, 3 * self.plane, self.b.data_ptr(),
                     self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
                     self.queue_ctr.data_ptr(), self.sched)
             L.swe_batched_step(self.p, *args, self.stream)

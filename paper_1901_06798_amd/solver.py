@@ -33,7 +33,7 @@ class PatchSolver:
     step's speeds, a step above cfl_max is retaken with the reduced dt)."""
 
     def __init__(self, pb: Problem, params: L.swe_params | None = None, device: str = "cuda:0",
-                 ordered: bool = True, order_every: int = 4):
+                 ordered: bool = True, order_every: int = 4, launch: L.swe_launch | None = None):
         if not torch.cuda.is_available():
             raise L.SweError("PatchSolver needs a GPU (torch.cuda is not available)")
         L.lib()
@@ -60,8 +60,12 @@ class PatchSolver:
         # launch order of the step's tasks, heaviest first from the last step
         # (re-sorted after the first step, then every order_every steps: the
         # work of a task changes slowly as the waves travel)
-        self.sched = (torch.zeros(2 * L.swe_patch_tasks(self.pt), dtype=torch.int32,
-                                  device=self.dev) if ordered else None)
+        # (launch: the step's launch shape, None = the library's defaults; a
+        # schedule buffer that is never sorted keeps the tasks in index order)
+        self.launch = launch
+        self.ordered = ordered
+        self.sched = (torch.zeros(L.swe_workspace_bytes(self.pt, launch) // 4, dtype=torch.int32,
+                                  device=self.dev) if ordered or launch is not None else None)
         self.order_every = max(1, int(order_every))
         self.steps_launched = 0
         self.upload(pb)
@@ -79,18 +83,25 @@ class PatchSolver:
         return torch.cuda.current_stream(self.dev).cuda_stream
 
     def upload(self, pb: Problem) -> None:
-        Q = self.planes()
-        Q.zero_()
+        """Initial state from FP64 arrays, converted on the device into the
+        planes' precision (swe_state_import), then the ghost frame."""
+        self.planes().zero_()
+        self.b.zero_()
         inner = (slice(2, self.my + 2), slice(2, self.mx + 2))
-        npdt = np.float32 if self.dev_path else np.float64
-        first = pb.h
-        if self.dev_path:
-            # surface deviation, formed in FP64 and rounded once
-            first = np.where(pb.h > 0.0, pb.h + pb.b - self.p.sea_level, pb.b - self.p.sea_level)
-        for k, arr in enumerate((first, pb.hu, pb.hv)):
-            Q[k][inner] = torch.from_numpy(np.ascontiguousarray(arr, dtype=npdt)).to(self.dev)
-        self.bplane()[inner] = torch.from_numpy(np.ascontiguousarray(pb.b, dtype=npdt)).to(self.dev)
+        src = torch.zeros(3, self.rows, self.pitch, dtype=torch.float64)
+        src_b = torch.zeros(self.rows, self.pitch, dtype=torch.float64)
+        for k, arr in enumerate((pb.h, pb.hu, pb.hv)):
+            src[k][inner] = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64))
+        src_b[inner] = torch.from_numpy(np.ascontiguousarray(pb.b, dtype=np.float64))
+        # the FP64 staging planes take the state planes' element layout
+        dsrc = torch.zeros(3 * self.ps, dtype=torch.float64, device=self.dev)
+        dsrc.view(3, self.ps)[:, : self.pitch * self.rows].copy_(src.view(3, -1))
+        dsrc_b = src_b.view(-1).to(self.dev)
+        L.swe_state_import(self.p, self.pt_dev.data_ptr(), 1, self.mx, self.my, dsrc.data_ptr(),
+                           dsrc_b.data_ptr(), self.q[self.cur].data_ptr(), self.b.data_ptr(),
+                           self.stream)
         self.ghost_fill(fill_b=True)
+        torch.cuda.current_stream(self.dev).synchronize()  # before the staging planes go
         self.status.zero_()
         self.smax.zero_()
 
@@ -113,15 +124,15 @@ class PatchSolver:
         if self.sched is not None:
             L.swe_patch_step_sched(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                                    self.smax.data_ptr(), self.status.data_ptr(),
-                                   self.sched.data_ptr(), st)
+                                   self.sched.data_ptr(), self.sched.numel(), self.launch, st)
         else:
             L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                              self.smax.data_ptr(), self.status.data_ptr(), st)
 
     def launch_order(self, stream: int | None = None) -> None:
         """Next step's launch order from this step's work (ordered solvers)."""
-        if self.sched is not None:
-            L.swe_patch_order(self.pt, self.sched.data_ptr(),
+        if self.ordered:
+            L.swe_patch_order(self.pt, self.sched.data_ptr(), self.sched.numel(), self.launch,
                               self.stream if stream is None else stream)
 
     def after_step(self, stream: int | None = None) -> None:

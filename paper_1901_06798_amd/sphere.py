@@ -73,7 +73,9 @@ class SphereSolver(PatchSolver):
         L.swe_patch_step_sphere(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                                 self.smax.data_ptr(), self.status.data_ptr(),
                                 self.metric.data_ptr(),
-                                self.sched.data_ptr() if self.sched is not None else 0, st)
+                                self.sched.data_ptr() if self.sched is not None else 0,
+                                self.sched.numel() if self.sched is not None else 0,
+                                self.launch, st)
 
     def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True,
                      retake: bool = False) -> None:

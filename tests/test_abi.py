@@ -105,24 +105,57 @@ def test_patch_tasks_counts_the_strip_tasks(L):
     assert L.swe_patch_tasks(L.patch(70, 100, 80, 1.0, 1.0)) == 2 * 3
     assert L.swe_patch_tasks(L.patch(60, 48, 64, 1.0, 1.0)) == 1
     assert L.swe_patch_tasks(L.patch(61, 49, 80, 1.0, 1.0)) == 4
-    assert L.lib().swe_patch_tasks(ctypes.byref(L.patch(10, 10, 12, 1.0, 1.0))) == L.SWE_EINVAL
+    assert L.lib().swe_patch_tasks(ctypes.byref(L.patch(10, 10, 12, 1.0, 1.0)), None) == L.SWE_EINVAL
     with pytest.raises(L.SweError):
         L.swe_patch_tasks(L.patch(10, 10, 12, 1.0, 1.0))
 
 
-def test_sched_step_rejects_a_null_schedule(L):
+def test_launch_shape_sets_the_task_count_and_workspace(L):
+    pt = L.patch(4096, 4096, 4112, 250.0, 250.0)
+    assert L.swe_patch_tasks(pt, L.launch()) == 69 * 86
+    assert L.swe_patch_tasks(pt, L.launch(rows_per_task=32)) == 69 * 128
+    assert L.swe_patch_tasks(pt, L.launch(rows_per_task=60, waves_per_block=4)) == 69 * 69
+    # a task never holds more rows than the patch has
+    assert L.swe_patch_tasks(L.patch(70, 5, 80, 1.0, 1.0), L.launch(rows_per_task=60)) == 2
+    assert L.swe_workspace_bytes(pt) == 8 * 69 * 86
+    assert L.swe_workspace_bytes(pt, L.launch(rows_per_task=32)) == 8 * 69 * 128
+    lib = L.lib()
+    for bad in (L.launch(rows_per_task=61), L.launch(rows_per_task=-1),
+                L.launch(waves_per_block=3), L.launch(xcd_run=-2)):
+        assert lib.swe_patch_tasks(ctypes.byref(pt), ctypes.byref(bad)) == L.SWE_EINVAL
+        assert b"launch" in lib.swe_last_error()
+        assert lib.swe_workspace_bytes(ctypes.byref(pt), ctypes.byref(bad)) == 0
+    assert lib.swe_workspace_bytes(ctypes.byref(L.patch(10, 10, 12, 1.0, 1.0)), None) == 0
+
+
+def test_sched_step_rejects_a_null_or_short_schedule(L):
     lib = L.lib()
     p = L.params()
-    pt = L.patch(10, 10, 14, 1.0, 1.0)
+    pt = L.patch(100, 100, 104, 1.0, 1.0)  # 2 strips x 3 chunks of 48 rows
     fake = ctypes.c_void_p(0x1000)
-    assert lib.swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), fake,
-                                    ctypes.c_void_p(0x9000000), fake, fake, fake, fake, None,
+    out = ctypes.c_void_p(0x90000000)
+    n = L.swe_patch_tasks(pt)
+    assert n == 6
+    assert lib.swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, fake,
+                                    fake, fake, None, 0, None, None) == L.SWE_EINVAL
+    assert b"schedule" in lib.swe_last_error()
+    # the buffer must hold 2 n entries for the launch shape it is used with
+    assert lib.swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, fake,
+                                    fake, fake, fake, 2 * n - 1, None, None) == L.SWE_EINVAL
+    assert b"shorter" in lib.swe_last_error()
+    rows32 = L.launch(rows_per_task=32)
+    assert lib.swe_patch_step_sched(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, fake,
+                                    fake, fake, fake, 2 * n, ctypes.byref(rows32),
                                     None) == L.SWE_EINVAL
+    assert lib.swe_patch_order(ctypes.byref(pt), None, 2 * n, None, None) == L.SWE_EINVAL
     assert b"schedule" in lib.swe_last_error()
-    assert lib.swe_patch_order(ctypes.byref(pt), None, None) == L.SWE_EINVAL
-    assert b"schedule" in lib.swe_last_error()
+    assert lib.swe_patch_order(ctypes.byref(pt), fake, 2 * n - 1, None, None) == L.SWE_EINVAL
+    assert b"shorter" in lib.swe_last_error()
     bad = L.patch(10, 10, 12, 1.0, 1.0)
-    assert lib.swe_patch_order(ctypes.byref(bad), ctypes.c_void_p(0x1000), None) == L.SWE_EINVAL
+    assert lib.swe_patch_order(ctypes.byref(bad), fake, 100, None, None) == L.SWE_EINVAL
+    badl = L.launch(waves_per_block=8)
+    assert lib.swe_patch_order(ctypes.byref(pt), fake, 100, ctypes.byref(badl),
+                               None) == L.SWE_EINVAL
 
 
 def test_amr_struct_layout_and_argument_errors(L, tmp_path):
@@ -213,7 +246,7 @@ def test_sphere_step_argument_errors(L):
     def call(p, patch=pt, m=metric):
         return lib.swe_patch_step_sphere(None if p is None else ctypes.byref(p),
                                          ctypes.byref(patch), fake, out, fake, fake, fake, fake,
-                                         m, None, None)
+                                         m, None, 0, None, None)
     assert call(L.params(), m=None) == L.SWE_EINVAL
     assert b"metric" in lib.swe_last_error()
     for kw in ({"precision": L.F32_DEV}, {"method": L.UNSPLIT}):
@@ -260,3 +293,55 @@ def test_sphere_solver_rejects_polar_frames_on_the_host(L):
     pb.meta = {}
     with pytest.raises(L.SweError, match="meta"):
         SphereSolver(pb, L.params())
+
+
+def test_batched_step_pool_checks(L):
+    # every call below is rejected on the host before anything is enqueued
+    lib = L.lib()
+    sched = L.schedule()
+    fake = ctypes.c_void_p(0x1000)
+    A, B, C = 0x10000000, 0x20000000, 0x30000000
+
+    def call(nitems, nplain, nsub, pin, pout, pwork, elems, p=L.params()):
+        v = lambda x: None if x is None else ctypes.c_void_p(x)
+        return lib.swe_batched_step(ctypes.byref(p), fake, fake, nitems, fake, fake, nplain,
+                                    nsub, v(pin), v(pout), v(pwork), elems, fake, fake, fake,
+                                    fake, fake, ctypes.byref(sched), None)
+
+    # items (patches with substeps) and per-substep launches need pool_work
+    assert call(3, 0, 0, A, B, None, 100) == L.SWE_EINVAL
+    assert b"pool_work" in lib.swe_last_error()
+    assert call(0, 5, 2, A, B, None, 100) == L.SWE_EINVAL
+    assert b"pool_work" in lib.swe_last_error()
+    # overlapping byte ranges are refused, not only equal pointers: 100 FP64
+    # elements are 800 bytes, 100 FP32 elements 400
+    assert call(3, 0, 0, A, A + 792, C, 100) == L.SWE_EINVAL
+    assert b"overlap" in lib.swe_last_error()
+    assert call(3, 0, 0, A, B, B + 8, 100) == L.SWE_EINVAL
+    assert call(3, 0, 0, C - 8, B, C, 100) == L.SWE_EINVAL
+    assert call(3, 0, 0, A, A + 396, C, 100, L.params(precision=L.F32_DEV)) == L.SWE_EINVAL
+    assert call(3, 0, 0, A, B, C, 0) == L.SWE_EINVAL
+    assert b"pool_elems" in lib.swe_last_error()
+    with pytest.raises(L.SweError):
+        L.swe_batched_step(L.params(), 0x1000, 0x1000, 3, 0x1000, 0x1000, 0, 0, A, B, 0, 100,
+                           0x1000, 0x1000, 0x1000, 0x1000, 0x1000, sched)
+
+
+def test_state_import_export_argument_errors(L):
+    lib = L.lib()
+    p = L.params()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 10, 10, None, fake, fake, fake,
+                                None) == L.SWE_EINVAL
+    assert lib.swe_state_import(ctypes.byref(p), fake, -1, 10, 10, fake, fake, fake, fake,
+                                None) == L.SWE_EINVAL
+    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 0, 10, fake, fake, fake, fake,
+                                None) == L.SWE_EINVAL
+    f32 = L.params(precision=L.F32_DEV)
+    assert lib.swe_state_export(ctypes.byref(f32), fake, 1, 10, 10, fake, None, fake,
+                                None) == L.SWE_EINVAL
+    assert lib.swe_state_export(ctypes.byref(p), fake, 1, 10, 10, fake, None, None,
+                                None) == L.SWE_EINVAL
+    # zero patches enqueue nothing
+    assert lib.swe_state_import(ctypes.byref(p), fake, 0, 10, 10, fake, fake, fake, fake,
+                                None) == L.SWE_OK

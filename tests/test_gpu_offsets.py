@@ -60,7 +60,8 @@ def advance(L, torch, p, pt, table, qin, qout, b, steps, batched=False, plan=Non
             plain = tasks.data_ptr() + L.SWE_TASK_BYTES * (pl.ntasks - pl.nplain)
             L.swe_batched_step(p, table.data_ptr(), items.data_ptr(), pl.nitems,
                                tasks.data_ptr(), plain, pl.nplain, pl.nsub, a.data_ptr(),
-                               c.data_ptr(), 0, b.data_ptr(), dt.data_ptr(), smax.data_ptr(),
+                               c.data_ptr(), 0, a.numel(), b.data_ptr(), dt.data_ptr(),
+                               smax.data_ptr(),
                                status.data_ptr(), queue.data_ptr(), sched, s)
         else:
             L.swe_patch_step(p, pt, a.data_ptr(), c.data_ptr(), b.data_ptr(), dt.data_ptr(),
@@ -125,7 +126,7 @@ def test_empty_batches(gpu):
     L.swe_mass(p, z.data_ptr(), 0, z.data_ptr(), z.data_ptr(), z.data_ptr(), s)
     sched = L.schedule()
     L.swe_batched_step(p, z.data_ptr(), z.data_ptr(), 0, z.data_ptr(), z.data_ptr(), 0, 0,
-                       z.data_ptr(), z[32:].data_ptr(), 0, z.data_ptr(), z.data_ptr(),
+                       z.data_ptr(), z[32:].data_ptr(), 0, 32, z.data_ptr(), z.data_ptr(),
                        z.data_ptr(), st.data_ptr(), q.data_ptr(), sched, s)
     torch.cuda.synchronize()
     assert int(st.abs().sum().item()) == 0 and int(q.abs().sum().item()) == 0

@@ -117,7 +117,7 @@ def test_order_kernel_is_a_stable_sort(gpu, mx, my):
     sched = torch.zeros(2 * n, dtype=torch.int32, device="cuda:0")
     sched[n:] = torch.from_numpy(cost).to("cuda:0")
     sched[:n] = 12345  # stale order: the sort overwrites all of it
-    L.swe_patch_order(pt, sched.data_ptr())
+    L.swe_patch_order(pt, sched.data_ptr(), sched.numel())
     torch.cuda.synchronize()
     got = sched.cpu().numpy().view(np.uint32)
     assert np.array_equal(got[n:], cost.view(np.uint32))
@@ -128,21 +128,16 @@ def test_xcd_runs_give_bitwise_the_same_step(gpu):
     # launch positions dealt to the XCDs in runs of 1, 3 and 8 ranks (the last
     # ranks past a whole block of 8 runs keep their position): any mapping is a
     # permutation of the tasks, so the results are the same bit for bit
-    import os
     L, PatchSolver, torch = gpu
     pb = shelf(601)
     print("case xcd runs shelf 601^2", flush=True)
     results = []
-    for run in ("1", "3", "8"):
-        os.environ["SWE_XCD_RUN"] = run
-        try:
-            for ordered in (True, False):
-                s = PatchSolver(pb, L.params(), ordered=ordered)
-                dts = s.run(25)
-                torch.cuda.synchronize()
-                results.append((dts, s.planes().clone(), s.dt.clone()))
-        finally:
-            os.environ.pop("SWE_XCD_RUN", None)
+    for run in (1, 3, 8):
+        for ordered in (True, False):
+            s = PatchSolver(pb, L.params(), ordered=ordered, launch=L.launch(xcd_run=run))
+            dts = s.run(25)
+            torch.cuda.synchronize()
+            results.append((dts, s.planes().clone(), s.dt.clone()))
     for dts, q, dt in results[1:]:
         assert np.array_equal(dts, results[0][0])
         assert torch.equal(q, results[0][1]) and torch.equal(dt, results[0][2])

@@ -191,16 +191,15 @@ def test_tile_shape_and_rerun_are_bitwise_identical(gpu):
     L, PatchSolver, torch = gpu
     pb = smooth_random_problem(150, 140, seed=9)
     results = []
-    # 60 is the most a task may hold (larger values are capped to it)
-    for rows in ("60", "7", "60", "33", "140"):
-        os.environ["SWE_ROWS_PER_WAVE"] = rows
-        try:
-            s = PatchSolver(pb, L.params())
-            s.run(15)
-            torch.cuda.synchronize()
-            results.append(s.state())
-        finally:
-            os.environ.pop("SWE_ROWS_PER_WAVE", None)
+    # 60 rows is the most a task may hold; 2 and 4 waves per workgroup; tasks
+    # in index order or heaviest first
+    shapes = [(60, 1, True), (7, 1, True), (60, 2, False), (33, 4, True), (48, 1, False)]
+    for rows, wpb, ordered in shapes:
+        s = PatchSolver(pb, L.params(), ordered=ordered,
+                        launch=L.launch(rows_per_task=rows, waves_per_block=wpb))
+        s.run(15)
+        torch.cuda.synchronize()
+        results.append(s.state())
     for r in results[1:]:
         for a, c in zip(results[0], r):
             assert np.array_equal(a, c)
