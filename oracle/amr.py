@@ -4,24 +4,46 @@ TEST INFRASTRUCTURE ONLY (see the package docstring): only tests/ and the
 bench's host baseline may use it.
 
 Qin, LeVeque & Motley, Sec. 3 (patches on levels refined by an integer ratio
-in space and time; the recursive time integration; the updating process;
-refluxing is dropped, as in the paper's GPU code) and its interpolation and
-averaging strategies (a sea at rest must stay at rest; away from the shore
-the surface elevation is interpolated and averaged, and the depth follows
-from it and the bed).  The paper defers the details of both strategies to
-other work; the reading here:
+in space and time; the recursive time integration, whose step 2 fills a
+finer level's ghost cells from the same level or by interpolation in space
+and time from the level below; the updating process; refluxing is dropped,
+as in the paper's GPU code) and its interpolation and averaging strategies:
+a sea at rest must stay at rest; away from the shoreline the interpolation
+is simple linear interpolation and the averaging takes the arithmetic mean
+of the surface elevation, the depth following from the surface and the bed;
+near the shoreline, where a cell is dry, no strategy keeps both the mass and
+a flat surface.  The reading here:
 
-fill (ghost cells of a level-(l+1) patch before each of its substeps k, at
-time t_n + (k / r) dt_l):
+coarse value at a fine cell (I, J) of level l + 1 from level l (ratio r),
+  at time t_n + alpha dt_l between that level's states before (old) and
+  after (new) its step:
+    the fine cell's centre lies at X = (I + 1/2) / r - 1/2,
+    Y = (J + 1/2) / r - 1/2 in level-l cell units (level-l centres at whole
+    numbers); its bilinear stencil is the level-l cells (i0 + a, j0 + c),
+    a, c in {0, 1}, i0 = floor(X), j0 = floor(Y), with weights
+    (1 - wx, wx) and (1 - wy, wy), wx = X - i0, wy = Y - j0 (exact binary
+    fractions); a stencil cell of weight 0 (ratio 1) is left out;
+    linear (away from the shore): every stencil cell lies in the interior of
+      a level-l patch and is wet (h > drytol) in both states; then per
+      stencil cell eta_k = (1 - alpha)(h_old + b_k) + alpha (h_new + b_k) and
+      momenta (1 - alpha) m_old + alpha m_new, combined as
+        v = (1 - wy) ((1 - wx) v_00 + wx v_10) + wy ((1 - wx) v_01 + wx v_11),
+      h = max(eta - b_f, 0), hu = hv = 0 if h <= drytol;
+    constant (near the shore: otherwise): the level-l cell (I // r, J // r)
+      under the fine cell alone:
+        both states dry -> h = 0, hu = hv = 0
+        else eta = (1 - alpha)(h_old + b_c) + alpha (h_new + b_c),
+             h = max(eta - b_f, 0), hu, hv linear in time, zeroed when
+             h <= drytol (b_c, b_f: bed of the coarse and of the fine cell).
+  Bilinear weights are non-negative, so the linear rule creates no new
+  extrema, reproduces a linear surface exactly and keeps a sea at rest at
+  rest; the constant rule near dry cells keeps a wet surface from being
+  interpolated toward the bed of a dry cell.
+fill (ghost cells of a level-(l+1) patch before each of its substeps k,
+  alpha = k / r):
   - a ghost cell over the interior of another patch of the same level takes
     that cell's values (the first such patch in the hierarchy's order);
-  - otherwise it takes the values of the level-l cell under it (piecewise
-    constant in space), linear in time between that cell's states before and
-    after the level-l step, alpha = k / r:
-      both states dry            -> h = 0, hu = hv = 0
-      else eta = (1 - alpha) (h_old + b_c) + alpha (h_new + b_c)
-           h = max(eta - b_f, 0); hu, hv linear in time; hu = hv = 0 if
-           h <= drytol (b_c, b_f: bed of the coarse and of the fine cell).
+  - otherwise the coarse value above.
 average (level-l cells under a level-(l+1) patch after its r substeps; the
   r x r fine cells over a coarse cell):
       no fine cell wet           -> h = 0, hu = hv = 0
@@ -34,10 +56,11 @@ advance(l, dt): step every level-l patch by dt (level 1: physical boundary
   then average it onto level l.
 
 Parity unpinned against the paper's own code (it states no formulas); the
-tests pin this reading by invariants: a sea at rest stays bitwise at rest, a
-hierarchy with ratio 1 reproduces the single-level run, averaging a linear
-surface gives the coarse cell-centre value, and the fill on a field whose
-every cell differs.
+tests pin this reading: a sea at rest stays bitwise at rest, a hierarchy with
+ratio 1 reproduces the single-level run, a linear surface and linear momenta
+are interpolated exactly away from the shore, a dry stencil cell falls back
+to the cell under the ghost, averaging a linear surface gives the coarse
+cell-centre value.
 """
 from __future__ import annotations
 
@@ -61,6 +84,62 @@ class OPatch:
         return J - self.j0 + 2, I - self.i0 + 2
 
 
+def coarse_value(coarse, old, r, drytol, alpha, I, J, bf):
+    """(h, hu, hv) at fine cell (I, J) of the level above the patches `coarse`
+    (OPatch objects, ratio r), with bed bf, at time alpha between `old` (their
+    q arrays before their step, in patch order) and their current states; the
+    reading in the module docstring."""
+
+    def states(Ic, Jc):
+        """(old, new, bed) of the coarse cell (Ic, Jc), or None where no
+        coarse patch has it in its interior."""
+        for k, c in enumerate(coarse):
+            if c.covers(Ic, Jc):
+                rc, cc = c.cell(Ic, Jc)
+                return old[k][rc, cc], c.q[rc, cc], c.b[rc, cc]
+        return None
+
+    X = (I + 0.5) / r - 0.5
+    Y = (J + 0.5) / r - 0.5
+    i0, j0 = int(np.floor(X)), int(np.floor(Y))
+    wx, wy = X - i0, Y - j0
+    # (offset, weight) along each axis; a weight of 0 (ratio 1) drops the cell
+    cols = [(0, 1.0 - wx)] + ([(1, wx)] if wx > 0.0 else [])
+    rows = [(0, 1.0 - wy)] + ([(1, wy)] if wy > 0.0 else [])
+    cells = {(a, c): states(i0 + a, j0 + c) for c, _ in rows for a, _ in cols}
+    linear = all(st is not None and st[0][0] > drytol and st[1][0] > drytol
+                 for st in cells.values())
+    if linear:
+        v = {}
+        for k, (qo, qn, bk) in cells.items():
+            v[k] = ((1.0 - alpha) * (qo[0] + bk) + alpha * (qn[0] + bk),
+                    (1.0 - alpha) * qo[1] + alpha * qn[1],
+                    (1.0 - alpha) * qo[2] + alpha * qn[2])
+
+        def combine(m):
+            total = None
+            for c, wr in rows:
+                line = None
+                for a, wc in cols:
+                    t = wc * v[a, c][m]
+                    line = t if line is None else line + t
+                t = wr * line
+                total = t if total is None else total + t
+            return total
+        eta, hu, hv = combine(0), combine(1), combine(2)
+    else:
+        qo, qn, bc_ = states(I // r, J // r)
+        if qo[0] <= drytol and qn[0] <= drytol:
+            return (0.0, 0.0, 0.0)
+        eta = (1.0 - alpha) * (qo[0] + bc_) + alpha * (qn[0] + bc_)
+        hu = (1.0 - alpha) * qo[1] + alpha * qn[1]
+        hv = (1.0 - alpha) * qo[2] + alpha * qn[2]
+    h = max(eta - bf, 0.0)
+    if h <= drytol:
+        return (h, 0.0, 0.0)
+    return (h, hu, hv)
+
+
 class Hierarchy:
     def __init__(self, H, P):
         self.r = H.ratio
@@ -80,11 +159,13 @@ class Hierarchy:
                 return p
         return None
 
+    def coarse_value(self, lev, old, alpha, I, J, bf):
+        return coarse_value(self.levels[lev - 1], old, self.r, self.P.drytol, alpha, I, J, bf)
+
     def fill(self, lev, old, alpha):
         """Ghost cells of level lev (>= 2) from the same level or from level
         lev - 1, whose states before and after its step are `old` (copies of
         that level's q arrays, in patch order) and the current ones."""
-        r, drytol = self.r, self.P.drytol
         for f in self.levels[lev - 1]:
             for row in range(f.my + 4):
                 for col in range(f.mx + 4):
@@ -95,23 +176,8 @@ class Hierarchy:
                     if s is not None:
                         f.q[row, col, :] = s.q[s.cell(I, J)]
                         continue
-                    Ic, Jc = I // r, J // r
-                    cidx = [k for k, c in enumerate(self.levels[lev - 2]) if c.covers(Ic, Jc)][0]
-                    cn = self.levels[lev - 2][cidx]
-                    rc, cc = cn.cell(Ic, Jc)
-                    qo, qn = old[cidx][rc, cc], cn.q[rc, cc]
-                    bc_ = cn.b[rc, cc]
-                    bf = f.b[row, col]
-                    if qo[0] <= drytol and qn[0] <= drytol:
-                        f.q[row, col, :] = 0.0
-                        continue
-                    eta = (1.0 - alpha) * (qo[0] + bc_) + alpha * (qn[0] + bc_)
-                    h = max(eta - bf, 0.0)
-                    if h <= drytol:
-                        f.q[row, col, :] = (h, 0.0, 0.0)
-                    else:
-                        f.q[row, col, :] = (h, (1.0 - alpha) * qo[1] + alpha * qn[1],
-                                            (1.0 - alpha) * qo[2] + alpha * qn[2])
+                    f.q[row, col, :] = self.coarse_value(lev - 1, old, alpha, I, J,
+                                                         f.b[row, col])
 
     def average(self, lev):
         """Level-lev cells under level lev + 1 patches from the fine cells."""

@@ -37,23 +37,24 @@ cluster  per level-l patch, recursively on a box of its interior (start:
          A box (in level-l cells) becomes the level-(l+1) patch of r times
          its extent.
 fill     new cell (I, J) of level l + 1: the old level-(l+1) patch that
-         covers it (first in order) gives its values; otherwise the level-l
-         cell (I // r, J // r): dry (h <= drytol) gives (0, 0, 0), else
-         h = max(h_c + b_c - b_f, 0) and the cell's momenta, zeroed when
-         h <= drytol.
+         covers it (first in order) gives its values; otherwise the coarse
+         value of oracle/amr.py (linear in space away from the shore, the
+         level-l cell under it near the shore) from the one level-l state,
+         i.e. with the old and new states equal and alpha = 1.
 order    level 2 from level 1, then level 3 from the new level 2, and so on.
 
 Parity unpinned against the paper's code (it cites the clustering algorithm
 without stating it); the tests pin the reading by invariants: every flagged
 cell is covered, patches of a level do not overlap and lie inside their
 parent's interior less the margin, every accepted box meets the efficiency
-or cannot be split, the fill copies old cells and reproduces a sea at rest.
+or cannot be split, the fill copies old cells, reproduces a sea at rest and
+interpolates a linear surface exactly.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .amr import OPatch
+from .amr import OPatch, coarse_value
 
 
 def flag_patch(q, b, tol, drytol, buffer, margin, sea=0.0):
@@ -177,16 +178,8 @@ def fill_new(rect, level, H, old_fine, coarse, r, drytol):
             if src is not None:
                 p.q[jj + 2, ii + 2] = src.q[src.cell(I, J)]
                 continue
-            c = next(o for o in coarse if o.covers(I // r, J // r))
-            rc, cc = c.cell(I // r, J // r)
-            hc = c.q[rc, cc, 0]
-            if hc <= drytol:
-                continue
-            h = max(hc + c.b[rc, cc] - p.b[jj + 2, ii + 2], 0.0)
-            if h <= drytol:
-                p.q[jj + 2, ii + 2] = (h, 0.0, 0.0)
-            else:
-                p.q[jj + 2, ii + 2] = (h, c.q[rc, cc, 1], c.q[rc, cc, 2])
+            p.q[jj + 2, ii + 2] = coarse_value(coarse, [c.q for c in coarse], r, drytol, 1.0,
+                                               I, J, p.b[jj + 2, ii + 2])
     return p
 
 

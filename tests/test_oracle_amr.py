@@ -1,10 +1,12 @@
 """Pins of the reference AMR level coupling (oracle/amr.py): a sea at rest
 stays bitwise at rest across levels; with refinement ratio 1 the hierarchy
 reproduces the single-level run cell for cell; averaging takes a linear
-surface and linear momenta to the coarse cell-centre values; the ghost fill
-takes the level below's cell under each ghost (checked on a field whose every
-cell differs), the same level's cell where one exists, and interpolates
-linearly in time."""
+surface and linear momenta to the coarse cell-centre values; away from the
+shore the ghost fill interpolates linearly in space (bilinear functions,
+every cell different, are reproduced at the fine cell centres, over a flat
+and over a varying bed) and in time, takes the same level's cell where one
+exists, and falls back to the cell under the ghost where a stencil cell is
+dry or outside the level below."""
 import numpy as np
 import pytest
 
@@ -91,13 +93,23 @@ def test_average_of_linear_fields_is_the_centre_value(P):
             assert c.q[rc, cc, 2] == pytest.approx(-1.0 + 2e-4 * yc, rel=1e-12)
 
 
-def test_fill_takes_the_cell_under_each_ghost_and_interpolates_in_time(P):
-    r = 2
+def stencil_inside(c, X, Y):
+    """True when the bilinear stencil of the point (X, Y), in coarse cell
+    units, lies in the interior of the coarse patch c."""
+    i0, j0 = int(np.floor(X)), int(np.floor(Y))
+    i1 = i0 + (1 if X > i0 else 0)
+    j1 = j0 + (1 if Y > j0 else 0)
+    return all(c.covers(i, j) for i in (i0, i1) for j in (j0, j1))
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_fill_interpolates_bilinear_fields_in_space_and_time(P, r):
     H = W.amr_three_levels(r, bed="flat", amp=0.0)
     h = A.Hierarchy(H, P)
     c = h.levels[0][0]
     n = c.q.shape[0]
-    # every coarse cell different: depth 1000 + I + 100 J, momenta I - J and I J
+    # every coarse cell different: depth 1000 + I + 100 J, momenta I - J and
+    # I J (bilinear functions, which bilinear interpolation reproduces)
     J, I = np.meshgrid(np.arange(n) - 2, np.arange(n) - 2, indexing="ij")
     old = [c.q.copy()]
     old[0][..., 0] = 1000.0 + I + 100.0 * J
@@ -106,7 +118,8 @@ def test_fill_takes_the_cell_under_each_ghost_and_interpolates_in_time(P):
     c.q[..., 0] = 2000.0 + I + 100.0 * J
     c.q[..., 1] = 2.0 * (I - J)
     c.q[..., 2] = 3.0 * I * J
-    for alpha in (0.0, 0.5):
+    checked = {"linear": 0, "constant": 0}
+    for alpha in (0.0, 0.5, 0.75):
         h.fill(2, old, alpha)
         for f in h.levels[1]:
             other = [s for s in h.levels[1] if s is not f][0]
@@ -118,12 +131,93 @@ def test_fill_takes_the_cell_under_each_ghost_and_interpolates_in_time(P):
                     if other.covers(If, Jf):
                         assert np.array_equal(f.q[row, col], other.q[other.cell(If, Jf)])
                         continue
-                    Ic, Jc = If // r, Jf // r
-                    want = ((1 - alpha) * (1000.0 + Ic + 100.0 * Jc)
-                            + alpha * (2000.0 + Ic + 100.0 * Jc),
-                            (1 - alpha) * (Ic - Jc) + alpha * 2.0 * (Ic - Jc),
-                            (1 - alpha) * (Ic * Jc) + alpha * 3.0 * Ic * Jc)
+                    X, Y = (If + 0.5) / r - 0.5, (Jf + 0.5) / r - 0.5
+                    if not stencil_inside(c, X, Y):
+                        X, Y = If // r, Jf // r
+                        checked["constant"] += 1
+                    else:
+                        checked["linear"] += 1
+                    want = ((1 - alpha) * (1000.0 + X + 100.0 * Y)
+                            + alpha * (2000.0 + X + 100.0 * Y),
+                            (1 - alpha) * (X - Y) + alpha * 2.0 * (X - Y),
+                            (1 - alpha) * (X * Y) + alpha * 3.0 * X * Y)
                     assert f.q[row, col] == pytest.approx(want, rel=1e-13, abs=1e-12)
+    assert checked["linear"] > 100
+
+
+def test_fill_reproduces_a_linear_surface_over_a_varying_bed(P):
+    # the surface, not the depth, is interpolated: a tilted surface over the
+    # bowl bed (all wet) comes out tilted at the fine cell centres, whatever
+    # the fine cells' own bed; momenta linear in x and y likewise
+    r = 4
+    H = W.amr_three_levels(r, bed="bowl", amp=0.0)
+    h = A.Hierarchy(H, P)
+    c = h.levels[0][0]
+    dxc = H.dx(1)
+    n = c.q.shape[0]
+    J, I = np.meshgrid(np.arange(n) - 2, np.arange(n) - 2, indexing="ij")
+    xc, yc = (I + 0.5) * dxc, (J + 0.5) * dxc
+    eta = 0.4 + 2e-6 * xc - 3e-6 * yc
+    c.q[..., 0] = eta - c.b
+    c.q[..., 1] = 5.0 + 1e-4 * xc
+    c.q[..., 2] = -2.0 + 3e-4 * yc
+    h.fill(2, [c.q.copy()], 1.0)
+    dxf = H.dx(2)
+    nlin = 0
+    for f in h.levels[1]:
+        other = [s for s in h.levels[1] if s is not f][0]
+        for row in range(f.my + 4):
+            for col in range(f.mx + 4):
+                if 2 <= row < f.my + 2 and 2 <= col < f.mx + 2:
+                    continue
+                If, Jf = f.i0 + col - 2, f.j0 + row - 2
+                X, Y = (If + 0.5) / r - 0.5, (Jf + 0.5) / r - 0.5
+                if other.covers(If, Jf) or not stencil_inside(c, X, Y):
+                    continue
+                x, y = (If + 0.5) * dxf, (Jf + 0.5) * dxf
+                assert f.q[row, col, 0] + f.b[row, col] == pytest.approx(
+                    0.4 + 2e-6 * x - 3e-6 * y, abs=1e-11)
+                assert f.q[row, col, 1] == pytest.approx(5.0 + 1e-4 * x, rel=1e-13)
+                assert f.q[row, col, 2] == pytest.approx(-2.0 + 3e-4 * y, rel=1e-13)
+                nlin += 1
+    assert nlin > 100
+
+
+def test_dry_stencil_cell_falls_back_to_the_cell_under_the_ghost(P):
+    # near the shore (a dry cell in the bilinear stencil, in either state)
+    # the ghost takes the coarse cell under it, constant in space
+    r = 2
+    H = W.amr_three_levels(r, bed="flat", amp=0.0)
+    h = A.Hierarchy(H, P)
+    c = h.levels[0][0]
+    n = c.q.shape[0]
+    J, I = np.meshgrid(np.arange(n) - 2, np.arange(n) - 2, indexing="ij")
+    c.q[..., 0] = 1000.0 + I + 100.0 * J
+    c.q[..., 1] = 0.0
+    c.q[..., 2] = 0.0
+    f = h.levels[1][0]
+    # the coarse cell left of the patch's first interior column, at its first row
+    Ic, Jc = f.i0 // r - 1, f.j0 // r
+    old = c.q.copy()
+    old[c.cell(Ic, Jc)] = 0.0  # dry before the step only
+    h.fill(2, [old], 0.5)
+    hit = 0
+    for row in range(f.my + 4):
+        for col in range(f.mx + 4):
+            if 2 <= row < f.my + 2 and 2 <= col < f.mx + 2:
+                continue
+            If, Jf = f.i0 + col - 2, f.j0 + row - 2
+            X, Y = (If + 0.5) / r - 0.5, (Jf + 0.5) / r - 0.5
+            i0, j0 = int(np.floor(X)), int(np.floor(Y))
+            if not (i0 <= Ic <= i0 + 1 and j0 <= Jc <= j0 + 1):
+                continue
+            under = c.cell(If // r, Jf // r)
+            want_eta = 0.5 * (old[under][0] + c.b[under]) + 0.5 * (c.q[under][0] + c.b[under])
+            if old[under][0] <= P.drytol and c.q[under][0] <= P.drytol:
+                want_eta = f.b[row, col]
+            assert f.q[row, col, 0] == max(want_eta - f.b[row, col], 0.0)
+            hit += 1
+    assert hit >= 4
 
 
 def test_fill_and_average_keep_dry_land_dry(P):

@@ -140,3 +140,31 @@ def test_sea_at_rest_needs_no_refinement_and_fill_keeps_rest():
     p = G.fill_new((40, 48, 24, 16), 2, H, [], h.levels[0], 4, P.drytol)
     q = p.q[2:-2, 2:-2]
     assert np.all(q[..., 0] + p.b[2:-2, 2:-2] == 0.0) and not q[..., 1:].any()
+
+
+def test_new_cells_interpolate_a_linear_surface():
+    # a new patch over a tilted sea (all wet, the bowl bed) takes the surface
+    # of the level below linearly at its own cell centres, and linear momenta
+    O.lib()
+    P = O.params()
+    r = 4
+    H = W.amr_three_levels(r, bed="bowl", amp=0.0)
+    h = A.Hierarchy(H, P)
+    c = h.levels[0][0]
+    dxc, dxf = H.dx(1), H.dx(2)
+    n = c.q.shape[0]
+    J, I = np.meshgrid(np.arange(n) - 2, np.arange(n) - 2, indexing="ij")
+    xc, yc = (I + 0.5) * dxc, (J + 0.5) * dxc
+    c.q[..., 0] = (0.3 - 1e-6 * xc + 4e-6 * yc) - c.b
+    c.q[..., 1] = 1.0 + 2e-4 * yc
+    c.q[..., 2] = -3.0 + 1e-4 * xc
+    i0, j0, mx, my = 40, 48, 24, 16
+    p = G.fill_new((i0, j0, mx, my), 2, H, [], h.levels[0], r, P.drytol)
+    for jj in range(my):
+        for ii in range(mx):
+            x, y = (i0 + ii + 0.5) * dxf, (j0 + jj + 0.5) * dxf
+            qf = p.q[jj + 2, ii + 2]
+            assert qf[0] + p.b[jj + 2, ii + 2] == pytest.approx(0.3 - 1e-6 * x + 4e-6 * y,
+                                                                 abs=1e-11)
+            assert qf[1] == pytest.approx(1.0 + 2e-4 * y, rel=1e-13)
+            assert qf[2] == pytest.approx(-3.0 + 1e-4 * x, rel=1e-13)
