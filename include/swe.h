@@ -384,7 +384,10 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
  * the cells of the level below that it covers take averages of the fine
  * cells, the updating process; refluxing is left out, as in the paper's GPU
  * code).  Both keep a sea at rest at rest: they interpolate and average the
- * surface h + b and recover h from the bed of the cell written.  FP64 planes,
+ * surface h + b and recover h from the bed of the cell written.  Sec. 3's
+ * interpolation strategy: away from the shoreline plain linear interpolation
+ * (here bilinear in space, linear in time); near it, where a cell of the
+ * stencil is dry, the coarse cell under the fine cell alone.  FP64 planes,
  * or FP32 surface-deviation planes (eta' = h + b - sea_level; read into FP64,
  * combined there and rounded once; a dry cell stores eta' = b - sea_level).
  * Each level keeps its patches in one plane set (layout as above; all
@@ -400,6 +403,15 @@ typedef struct swe_amr_fill_op {
     int64_t src;      /* SWE_AMR_COPY: element offset of the same-level interior
                          cell (fine planes); SWE_AMR_COARSE: element offset of the
                          coarse cell under the ghost cell (coarse planes) */
+    int64_t st[4];    /* SWE_AMR_COARSE: element offsets (coarse planes) of the
+                         bilinear stencil cells (i0, j0), (i0 + 1, j0), (i0, j0 + 1),
+                         (i0 + 1, j0 + 1), where the fine cell's centre lies at
+                         X = (I + 1/2) / r - 1/2, Y = (J + 1/2) / r - 1/2 in coarse
+                         cell units (coarse centres at whole numbers) and
+                         i0 = floor(X), j0 = floor(Y); -1 for a cell that lies in no
+                         coarse patch's interior.  A cell of weight 0 (wx == 0 drops
+                         the i0 + 1 column, wy == 0 the j0 + 1 row) is not read. */
+    double wx, wy;    /* SWE_AMR_COARSE: X - i0 and Y - j0, in [0, 1) */
     int32_t kind;     /* SWE_AMR_COPY or SWE_AMR_COARSE */
     int32_t reserved;
 } swe_amr_fill_op;
@@ -418,10 +430,18 @@ typedef struct swe_amr_avg_op {
  * cells of all three planes).  q_coarse_old, q_coarse_new: the coarser
  * level's planes before and after its step (read only), b_coarse its bed.
  * SWE_AMR_COPY: q_fine[dst] = q_fine[src] (three planes).  SWE_AMR_COARSE,
- * with ho, hn the coarse depths, b_c = b_coarse[src], b_f = b_fine[dst]:
- * both ho, hn <= drytol gives (0, 0, 0); else
- *   eta = (1 - alpha)(ho + b_c) + alpha (hn + b_c),  h = max(eta - b_f, 0),
- *   (hu, hv) = (1 - alpha)(hu, hv)_old + alpha (hu, hv)_new, or 0 if h <= drytol. */
+ * with b_f = b_fine[dst] and, for a coarse cell k, ho_k, hn_k its depths
+ * before and after the step, b_k its bed, its values at alpha
+ *   eta_k = (1 - alpha)(ho_k + b_k) + alpha (hn_k + b_k),
+ *   m_k   = (1 - alpha) m_old,k + alpha m_new,k   (m = hu, hv):
+ * linear, when every stencil cell of non-zero weight has st >= 0 and both of
+ * its depths > drytol: per value v in (eta, hu, hv), with c0..c3 the stencil
+ * cells in the order of st,
+ *   line_0 = (1 - wx) v_c0 + wx v_c1,  line_1 = (1 - wx) v_c2 + wx v_c3,
+ *   v = (1 - wy) line_0 + wy line_1   (a zero-weight term is left out);
+ * constant, otherwise: the cell src alone, and (0, 0, 0) if both its depths
+ * are <= drytol.  Then h = max(eta - b_f, 0), and hu = hv = 0 if h <= drytol.
+ * Every product and sum rounds as written (no fused multiply-add). */
 int swe_amr_fill(const swe_params *p, const swe_amr_fill_op *ops, int64_t nops, void *q_fine,
                  int64_t fine_plane_stride, const void *b_fine, const void *q_coarse_old,
                  const void *q_coarse_new, int64_t coarse_plane_stride, const void *b_coarse,

@@ -26,7 +26,8 @@ from . import _lib as L
 from .batched import BatchedSolver
 from .workloads import BC_USER, AmrHierarchy, Problem
 
-FILL_DTYPE = np.dtype([("dst", "<i8"), ("src", "<i8"), ("kind", "<i4"), ("reserved", "<i4")])
+FILL_DTYPE = np.dtype([("dst", "<i8"), ("src", "<i8"), ("st", "<i8", (4,)), ("wx", "<f8"),
+                       ("wy", "<f8"), ("kind", "<i4"), ("reserved", "<i4")])
 AVG_DTYPE = np.dtype([("dst", "<i8"), ("src", "<i8"), ("pitch", "<i4"), ("reserved", "<i4")])
 
 
@@ -57,6 +58,29 @@ class _Geo:
         return (self.off[k] + (J - self.j0[k] + 2) * self.pitch[k] + (I - self.i0[k] + 2))
 
 
+def stencil(coarse: _Geo, I: np.ndarray, J: np.ndarray, r: int):
+    """Bilinear stencil on the level below (ratio r) of the fine cells (I, J):
+    the fine centre lies at X = (I + 1/2) / r - 1/2, Y = (J + 1/2) / r - 1/2
+    in coarse cell units; the stencil is the coarse cells (i0 + a, j0 + c),
+    i0 = floor(X), j0 = floor(Y), in the order (0, 0), (1, 0), (0, 1), (1, 1),
+    with weights wx = X - i0, wy = Y - j0.  Returns (st, wx, wy): st[:, k] is
+    the element offset of stencil cell k in the first patch of `coarse` whose
+    interior holds it, -1 where none does."""
+    X = (I + 0.5) / r - 0.5
+    Y = (J + 0.5) / r - 0.5
+    i0 = np.floor(X).astype(np.int64)
+    j0 = np.floor(Y).astype(np.int64)
+    wx, wy = X - i0, Y - j0
+    st = np.full((I.size, 4), -1, dtype=np.int64)
+    for k, (a, c) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+        Ic, Jc = i0 + a, j0 + c
+        who = coarse.covering(Ic, Jc)
+        for c_ in np.unique(who[who >= 0]):
+            m = who == c_
+            st[m, k] = coarse.elem(c_, Ic[m], Jc[m])
+    return st, wx, wy
+
+
 def fill_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
     ops = []
     for k in range(len(fine.i0)):
@@ -84,6 +108,10 @@ def fill_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
             m = (~cp) & (below == c)
             op["src"][m] = coarse.elem(c, Ic[m], Jc[m])
         op["kind"][~cp] = L.SWE_AMR_COARSE
+        op["st"] = -1
+        if (~cp).any():
+            st, wx, wy = stencil(coarse, I[~cp], J[~cp], r)
+            op["st"][~cp], op["wx"][~cp], op["wy"][~cp] = st, wx, wy
         ops.append(op)
     return np.concatenate(ops) if ops else np.zeros(0, dtype=FILL_DTYPE)
 
@@ -126,8 +154,9 @@ def cover_block(geo: _Geo, i0: int, j0: int, nx: int, ny: int, r: int = 1) -> np
 
 def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
     """Interior cells of new patches: copies from old patches of the level
-    where they cover the cell (first in order), else the cell of the level
-    below (first in order).  Built rectangle by rectangle: each source patch
+    where they cover the cell (first in order), else values from the level
+    below (the cell under it, first in order, and the bilinear stencil of
+    `stencil`).  Built rectangle by rectangle: each source patch
     writes the block of the new patch it overlaps, where no earlier source
     has, so the work is the new cells plus the overlaps; the entries are
     written in place into one array."""
@@ -170,6 +199,14 @@ def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
                 done[blk] = True
         if not done.all():
             raise L.SweError(f"new patch {k} is not over the level below")
+        op["st"] = -1
+        op["wx"] = 0.0
+        op["wy"] = 0.0
+        cm = kind == L.SWE_AMR_COARSE
+        if cm.any():
+            jj, ii = np.nonzero(cm)
+            st, wx, wy = stencil(coarse, ni0 + ii.astype(np.int64), nj0 + jj.astype(np.int64), r)
+            op["st"][cm], op["wx"][cm], op["wy"][cm] = st, wx, wy
     return out
 
 

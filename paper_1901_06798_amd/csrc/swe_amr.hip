@@ -55,10 +55,25 @@ __device__ __forceinline__ S first_value(double h, double eta, double b, double 
     return S(h > 0.0 ? eta - sea : b - sea);
 }
 
+// Values of coarse cell k at time alpha between its states before (qco) and
+// after (qcn) its step: the surface (depth + bed) and the momenta, each
+// linear in time.
+template <typename S>
+__device__ __forceinline__ void coarse_at(const FillArgs& a, const S* qco, const S* qcn,
+                                          const S* bc, int64_t k, double ho, double hn,
+                                          double w0, double w1, double v[3]) {
+    const double b = double(bc[k]);
+    v[0] = w0 * (ho + b) + w1 * (hn + b);
+    v[1] = w0 * double(qco[k + a.psc]) + w1 * double(qcn[k + a.psc]);
+    v[2] = w0 * double(qco[k + 2 * a.psc]) + w1 * double(qcn[k + 2 * a.psc]);
+}
+
 // Ghost cells of the finer level.  A copy takes the same level's cell; a
-// coarse entry takes the cell below (constant in space), linear in time
-// between its states before (qco) and after (qcn) its step.  FP32 planes are
-// read into FP64, combined there and rounded once.
+// coarse entry interpolates the level below linearly in time between its
+// states before (qco) and after (qcn) its step, and in space bilinearly from
+// the four coarse centres around the fine cell when they are all wet in both
+// states (away from the shore), else takes the cell under it alone.  FP32
+// planes are read into FP64, combined there and rounded once.
 template <typename S>
 __global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
     S* qf = static_cast<S*>(a.qf);
@@ -68,8 +83,9 @@ __global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
     const S* bc = static_cast<const S*>(a.bc);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nops; i += stride) {
-        const swe_amr_fill_op op = a.ops[i];
-        S* q = qf + op.dst;
+        const swe_amr_fill_op& op = a.ops[i];
+        const int64_t dst = op.dst;
+        S* q = qf + dst;
         if (op.kind == SWE_AMR_COPY) {
             const S* src = static_cast<const S*>(a.qcopy) + op.src;
             q[0] = src[0];
@@ -77,27 +93,69 @@ __global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
             q[2 * a.psf] = src[2 * a.pscopy];
             continue;
         }
-        const double ho = depth(qco, bc, op.src, a.sea), hn = depth(qcn, bc, op.src, a.sea);
-        const double b_f = double(bf[op.dst]);
-        if (ho <= a.drytol && hn <= a.drytol) {
-            q[0] = first_value<S>(0.0, b_f, b_f, a.sea);
-            q[a.psf] = S(0);
-            q[2 * a.psf] = S(0);
-            continue;
-        }
-        const double b = double(bc[op.src]);
+        const double b_f = double(bf[dst]);
         const double w0 = 1.0 - a.alpha, w1 = a.alpha;
-        const double eta = w0 * (ho + b) + w1 * (hn + b);
-        const double d = eta - b_f;
+        const double wx = op.wx, wy = op.wy;
+        // stencil cells of non-zero weight: c0 always, c1 with wx > 0, c2 with
+        // wy > 0, c3 with both
+        const bool two_x = wx > 0.0, two_y = wy > 0.0;
+        int64_t st[4];
+        double ho[4], hn[4];
+        bool linear = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
+            st[k] = op.st[k];
+            ho[k] = hn[k] = 0.0;
+            if (!used) continue;
+            if (st[k] < 0) {
+                linear = false;
+                continue;
+            }
+            ho[k] = depth(qco, bc, st[k], a.sea);
+            hn[k] = depth(qcn, bc, st[k], a.sea);
+            linear = linear && ho[k] > a.drytol && hn[k] > a.drytol;
+        }
+        double v[3];
+        if (linear) {
+            double c[4][3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
+                if (used) coarse_at(a, qco, qcn, bc, st[k], ho[k], hn[k], w0, w1, c[k]);
+            }
+            const double ux = 1.0 - wx, uy = 1.0 - wy;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                double line0 = ux * c[0][m];
+                if (two_x) line0 = line0 + wx * c[1][m];
+                double val = uy * line0;
+                if (two_y) {
+                    double line1 = ux * c[2][m];
+                    if (two_x) line1 = line1 + wx * c[3][m];
+                    val = val + wy * line1;
+                }
+                v[m] = val;
+            }
+        } else {
+            const double h0 = depth(qco, bc, op.src, a.sea), h1 = depth(qcn, bc, op.src, a.sea);
+            if (h0 <= a.drytol && h1 <= a.drytol) {
+                q[0] = first_value<S>(0.0, b_f, b_f, a.sea);
+                q[a.psf] = S(0);
+                q[2 * a.psf] = S(0);
+                continue;
+            }
+            coarse_at(a, qco, qcn, bc, op.src, h0, h1, w0, w1, v);
+        }
+        const double d = v[0] - b_f;
         const double h = d > 0.0 ? d : 0.0;
-        q[0] = first_value<S>(h, eta, b_f, a.sea);
+        q[0] = first_value<S>(h, v[0], b_f, a.sea);
         if (h <= a.drytol) {
             q[a.psf] = S(0);
             q[2 * a.psf] = S(0);
         } else {
-            q[a.psf] = S(w0 * double(qco[op.src + a.psc]) + w1 * double(qcn[op.src + a.psc]));
-            q[2 * a.psf] =
-                S(w0 * double(qco[op.src + 2 * a.psc]) + w1 * double(qcn[op.src + 2 * a.psc]));
+            q[a.psf] = S(v[1]);
+            q[2 * a.psf] = S(v[2]);
         }
     }
 }

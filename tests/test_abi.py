@@ -165,7 +165,9 @@ def test_amr_struct_layout_and_argument_errors(L, tmp_path):
 #include <stddef.h>
 #include "swe.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %d %d\n", sizeof(swe_amr_fill_op), offsetof(swe_amr_fill_op, kind),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %d %d\n", sizeof(swe_amr_fill_op),
+         offsetof(swe_amr_fill_op, st), offsetof(swe_amr_fill_op, wx),
+         offsetof(swe_amr_fill_op, wy), offsetof(swe_amr_fill_op, kind),
          sizeof(swe_amr_avg_op), offsetof(swe_amr_avg_op, src), offsetof(swe_amr_avg_op, pitch),
          SWE_AMR_COPY, SWE_AMR_COARSE);
   return 0;
@@ -177,7 +179,9 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     from paper_1901_06798_amd import amr
-    assert vals == [amr.FILL_DTYPE.itemsize, amr.FILL_DTYPE.fields["kind"][1],
+    assert vals == [amr.FILL_DTYPE.itemsize, amr.FILL_DTYPE.fields["st"][1],
+                    amr.FILL_DTYPE.fields["wx"][1], amr.FILL_DTYPE.fields["wy"][1],
+                    amr.FILL_DTYPE.fields["kind"][1],
                     amr.AVG_DTYPE.itemsize, amr.AVG_DTYPE.fields["src"][1],
                     amr.AVG_DTYPE.fields["pitch"][1], L.SWE_AMR_COPY, L.SWE_AMR_COARSE]
     lib = L.lib()
