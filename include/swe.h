@@ -377,6 +377,28 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
                        uint32_t *status, uint32_t *queue, const swe_schedule *sched,
                        const uint32_t *retake, int32_t ngroups, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * swe_batched_step without the queue and pool_work arguments.  The item
+ * queue and the intermediate substep pool live in one static device array
+ * of the library (256 bytes of queue, then SWE_STATIC_WORK_BYTES of substep
+ * pool), which each device that the library runs on holds until the process
+ * ends; the call allocates nothing.  A plan with items or nsub > 1 needs
+ * pool_elems elements of the precision's type to fit in the substep pool,
+ * else the call fails with SWE_EINVAL before enqueueing anything.  The
+ * queue is zeroed by a small kernel at the start of every call with items.
+ * Every call on one device shares that device's array and leaves its
+ * intermediate substeps there: calls that overlap on one device (different
+ * streams without ordering between them) race and give wrong results.
+ * Results are bitwise those of swe_batched_step with the same plan. */
+#define SWE_STATIC_WORK_BYTES (32u * 1024u * 1024u)
+int swe_batched_step_static(const swe_params *p, const swe_patch *patches,
+                            const swe_item *items, int32_t nitems, const swe_task *tasks,
+                            const swe_task *plain, int32_t nplain, int32_t nsub,
+                            const void *pool_in, void *pool_out, int64_t pool_elems,
+                            const void *pool_b, const double *dt_group, double *smax_patch,
+                            uint32_t *status, const swe_schedule *sched, void *stream);
+
 /* ------------------------------------------------------------------------
  * Coupling of AMR levels (Sec. 3: a finer level's ghost cells come from an
  * adjacent patch of the same level or, where none exists, from the level

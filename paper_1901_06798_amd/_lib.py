@@ -138,6 +138,8 @@ def lib():
                                        _P, _P, _P, _P, ps, _P]
         L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64,
                                          _P, _P, _P, _P, _P, ps, _P, i32, _P]
+        L.swe_batched_step_static.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, i64,
+                                              _P, _P, _P, _P, ps, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
@@ -145,7 +147,7 @@ def lib():
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
                      "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
                      "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
-                     "swe_state_export"):
+                     "swe_state_export", "swe_batched_step_static"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -340,6 +342,19 @@ def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks
                                   nsub, pool_in, pool_out, pool_work, pool_elems, pool_b,
                                   dt_group, smax_patch, status, queue, ctypes.byref(sched),
                                   stream), "swe_batched_step")
+
+
+SWE_STATIC_WORK_BYTES = 32 * 1024 * 1024
+
+
+def swe_batched_step_static(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
+                            plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
+                            pool_elems: int, pool_b: int, dt_group: int, smax_patch: int,
+                            status: int, sched: swe_schedule, stream: int = 0) -> None:
+    _check(lib().swe_batched_step_static(ctypes.byref(p), patches, items, nitems, tasks, plain,
+                                         nplain, nsub, pool_in, pool_out, pool_elems, pool_b,
+                                         dt_group, smax_patch, status, ctypes.byref(sched),
+                                         stream), "swe_batched_step_static")
 
 
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -367,13 +368,61 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
     return SWE_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// swe_batched_step_static: the same step with its item queue and its
+// intermediate substep pool in the library's own device memory, for callers
+// that cannot allocate.  Layout of the array: the queue's two counters in the
+// first 256 bytes, the substep pool (at most SWE_STATIC_WORK_BYTES) after
+// them.  Each device holds its own copy; host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device.
+namespace {
+
+constexpr size_t kStaticQueueBytes = 256;
+__device__ __align__(256) unsigned char scratch[kStaticQueueBytes + SWE_STATIC_WORK_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return bfail(SWE_EHIP, "swe_batched_step_static: cannot query the current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return bfail(SWE_EHIP, std::string("swe_batched_step_static: hipGetSymbolAddress: ") +
+                                       hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SWE_OK;
+}
+
+// Zero the queue's two counters (a kernel rather than a memset node, so the
+// call stays safe to capture).
+__global__ void k_zero_queue(uint32_t* q) {
+    if (threadIdx.x < 2) q[threadIdx.x] = 0u;
+}
+
+}  // namespace
+
+extern "C" {
+
 static int batched_step(const swe_params* p, const swe_patch* patches, const swe_item* items,
                         int32_t nitems, const swe_task* tasks, const swe_task* plain,
                         int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
                         void* pool_work, int64_t pool_elems,
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
-                        const uint32_t* retake, int32_t ngroups, void* stream) {
+                        const uint32_t* retake, int32_t ngroups, void* stream,
+                        bool zero_queue = false) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -458,6 +507,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
         int grid = ncu * per_cu;
         if (grid > nitems) grid = nitems;
         if (grid < 1) grid = 1;
+        if (zero_queue) hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, a);
     }
     if (nplain > 0) {
@@ -493,6 +543,34 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
                         pool_out, pool_work, pool_elems, pool_b, dt_group, smax_patch, status,
                         queue, sched, nullptr, 0, stream);
+}
+
+int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
+                            const swe_item* items, int32_t nitems, const swe_task* tasks,
+                            const swe_task* plain, int32_t nplain, int32_t nsub,
+                            const void* pool_in, void* pool_out, int64_t pool_elems,
+                            const void* pool_b, const double* dt_group, double* smax_patch,
+                            uint32_t* status, const swe_schedule* sched, void* stream) {
+    if (!p) return bfail(SWE_EINVAL, "params is NULL");
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+        return bfail(SWE_EINVAL, "swe_batched_step_static: unknown precision");
+    if (pool_elems < 1) return bfail(SWE_EINVAL, "swe_batched_step_static: pool_elems must be >= 1");
+    const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
+    const bool work = nitems > 0 || nsub > 1;
+    if (work && (uint64_t)pool_elems > SWE_STATIC_WORK_BYTES / esz)
+        return bfail(SWE_EINVAL,
+                     "swe_batched_step_static: the pool (" + std::to_string(pool_elems) +
+                         " elements) exceeds the static substep pool of " +
+                         std::to_string(SWE_STATIC_WORK_BYTES) +
+                         " bytes; use swe_batched_step with a caller-provided pool_work");
+    void* base = nullptr;
+    int rc = static_scratch(&base);
+    if (rc) return rc;
+    uint32_t* queue = static_cast<uint32_t*>(base);
+    void* pwork = static_cast<unsigned char*>(base) + kStaticQueueBytes;
+    return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in, pool_out,
+                        work ? pwork : nullptr, pool_elems, pool_b, dt_group, smax_patch, status,
+                        queue, sched, nullptr, 0, stream, true);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,

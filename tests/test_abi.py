@@ -349,3 +349,28 @@ def test_state_import_export_argument_errors(L):
     # zero patches enqueue nothing
     assert lib.swe_state_import(ctypes.byref(p), fake, 0, 10, 10, fake, fake, fake, fake,
                                 None) == L.SWE_OK
+
+
+def test_static_batched_step_host_checks(L, tmp_path):
+    # the static variant's maximum matches the header, and a pool beyond it is
+    # refused on the host before any device call
+    src = tmp_path / "static_max.c"
+    src.write_text('#include <stdio.h>\n#include "swe.h"\n'
+                   'int main(void) { printf("%u\\n", SWE_STATIC_WORK_BYTES); return 0; }\n')
+    exe = tmp_path / "static_max"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    assert int(out) == L.SWE_STATIC_WORK_BYTES
+    lib = L.lib()
+    p = L.params()
+    sched = L.schedule()
+    fake = ctypes.c_void_p(0x1000)
+    out_pool = ctypes.c_void_p(0x90000000)
+    for prec, esz in ((L.F64, 8), (L.F32_DEV, 4)):
+        p.precision = prec
+        rc = lib.swe_batched_step_static(ctypes.byref(p), fake, fake, 1, fake, None, 0, 0, fake,
+                                         out_pool, L.SWE_STATIC_WORK_BYTES // esz + 1, fake, fake,
+                                         fake, fake, ctypes.byref(sched), None)
+        assert rc == L.SWE_EINVAL
+        assert b"static substep pool" in lib.swe_last_error()

@@ -1,0 +1,94 @@
+"""GPU test of swe_batched_step_static, the batched step whose item queue and
+substep pool live in the library's static device array (for callers that
+cannot allocate): called through the C ABI on AMR-shaped patch sets (three
+levels, 1/4/16 substeps), two calls in a row on one device, the second with
+a smaller set, each bitwise equal to swe_batched_step with its own queue and
+pool_work on the same inputs and plan; and a pool beyond the static maximum
+is refused before anything runs."""
+import numpy as np
+import pytest
+
+from paper_1901_06798_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd.batched import BatchedSolver
+    L.lib()
+    return L, BatchedSolver, torch
+
+
+def static_step(L, bs, steps):
+    """steps coarse steps of bs through swe_batched_step_static, fixed dt."""
+    plain = bs.tasks.data_ptr() + L.SWE_TASK_BYTES * (bs.ntasks - bs.nplain)
+    for _ in range(steps):
+        L.swe_batched_step_static(bs.p, bs.table.data_ptr(), bs.items.data_ptr(), bs.nitems,
+                                  bs.tasks.data_ptr(), plain, bs.nplain, bs.nsub,
+                                  bs.pools[bs.cur].data_ptr(), bs.pools[1 - bs.cur].data_ptr(),
+                                  3 * bs.plane, bs.b.data_ptr(), bs.dt.data_ptr(),
+                                  bs.smax.data_ptr(), bs.status.data_ptr(), bs.sched, bs.stream)
+        bs.cur ^= 1
+
+
+def compare(L, BatchedSolver, torch, seed, counts, precision, sched, steps=3):
+    specs, probs = W.amr_patch_set(npatch=counts, seed=seed)
+    trefs = [s.tref for s in specs]
+    p = L.params(precision=precision)
+    ref = BatchedSolver(probs, p, trefs=trefs, sched=sched)
+    got = BatchedSolver(probs, p, trefs=trefs, sched=sched)
+    elem = 8 if precision == L.F64 else 4
+    assert 3 * got.plane * elem <= L.SWE_STATIC_WORK_BYTES
+    ref.initial_dt()
+    torch.cuda.synchronize()
+    got.dt.copy_(ref.dt)
+    print(f"case static batched step seed={seed} patches={len(probs)} precision={precision} "
+          f"per_substep={sched.per_substep} items={got.nitems} nsub={got.nsub}", flush=True)
+    for _ in range(steps):
+        ref.enqueue_step(cfl=False)
+    static_step(L, got, steps)
+    torch.cuda.synchronize()
+    assert got.nitems > 0 or got.nsub > 1  # the static array is used
+    assert ref.flags() == got.flags() == (0, 0)
+    assert torch.equal(ref.smax, got.smax)
+    for k in range(len(probs)):
+        for a, b in zip(ref.state(k), got.state(k)):
+            assert np.array_equal(a, b), f"patch {k}"
+    return len(probs), 3 * got.plane
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_static_step_equals_the_step_with_caller_buffers(gpu, precision):
+    L, BatchedSolver, torch = gpu
+    sched = L.schedule()
+    n1, e1 = compare(L, BatchedSolver, torch, 3, (6, 10, 14), precision, sched)
+    # second call on the same device with a smaller set: the array still holds
+    # the first call's substeps
+    n2, e2 = compare(L, BatchedSolver, torch, 4, (2, 3, 4), precision, sched)
+    assert n2 < n1 and e2 < e1
+
+
+def test_static_step_per_substep_launches(gpu):
+    L, BatchedSolver, torch = gpu
+    sched = L.schedule(per_substep=1)
+    compare(L, BatchedSolver, torch, 5, (4, 6, 8), L.F64, sched)
+    compare(L, BatchedSolver, torch, 6, (1, 2, 3), L.F64, sched)
+
+
+def test_static_step_refuses_a_pool_beyond_its_maximum(gpu):
+    L, BatchedSolver, torch = gpu
+    specs, probs = W.amr_patch_set(npatch=(1, 1, 1), seed=7)
+    bs = BatchedSolver(probs, L.params(), trefs=[s.tref for s in specs])
+    too_many = L.SWE_STATIC_WORK_BYTES // 8 + 1
+    plain = bs.tasks.data_ptr() + L.SWE_TASK_BYTES * (bs.ntasks - bs.nplain)
+    with pytest.raises(L.SweError, match="static substep pool"):
+        L.swe_batched_step_static(bs.p, bs.table.data_ptr(), bs.items.data_ptr(), bs.nitems,
+                                  bs.tasks.data_ptr(), plain, bs.nplain, bs.nsub,
+                                  bs.pools[0].data_ptr(), bs.pools[1].data_ptr(), too_many,
+                                  bs.b.data_ptr(), bs.dt.data_ptr(), bs.smax.data_ptr(),
+                                  bs.status.data_ptr(), bs.sched, bs.stream)
