@@ -80,9 +80,11 @@ enum swe_bc { SWE_BC_WALL = 0, SWE_BC_EXTRAP = 1, SWE_BC_USER = 2 };
 typedef struct swe_params {
     double g;            /* gravity, 9.81 m s^-2 */
     double drytol;       /* a cell with h <= drytol is dry (1e-3 m) */
-    double h_corr;       /* an edge with a cell at or below this depth gets no
-                            limited correction (0.1 m); keeps the swash zone
-                            first order, which keeps depths non-negative */
+    double h_corr;       /* an edge with a cell at or below this depth (a film on
+                            the shore) gets no limited correction (0.1 m); the
+                            split step also limits each correction to a share of
+                            its donor cell's water, so that no correction drives
+                            a depth below 0 */
     double manning_n;    /* Manning coefficient (Sec. 2 drag term); 0 = off */
     double cfl_desired;  /* Courant number aimed at by swe_cfl_reduce (0.9) */
     double cfl_max;      /* a step above this Courant number is flagged (1.0) */

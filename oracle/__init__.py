@@ -18,6 +18,7 @@ invariants (lake at rest, mass, symmetry, convergence), not by a closed form.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -32,8 +33,14 @@ BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
 EDGE_WET, EDGE_WALL_R, EDGE_WALL_L, EDGE_DRY = 0, 1, 2, 3
 
 
+_OPC_SRC = os.path.join(_HERE, "opcount.cpp")
+_OPC_PATH = os.path.join(_HERE, "liboracle_opcount.so")
+
+
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O3, no fast-math, no FP contraction)."""
+    """Compile the oracle with gcc (plain -O3, no fast-math, no FP contraction),
+    and its operation-counting build (opcount.cpp: the same source as C++
+    with a counting real type, single-threaded)."""
     cmd = ["gcc", "-std=c11", "-O3", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
            "-Wno-unused-parameter", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
@@ -41,6 +48,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    # -fpermissive: the C source converts malloc's void * implicitly
+    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-fpermissive", "-w",
+           "-ffp-contract=off", "-fno-fast-math", _OPC_SRC, "-o", _OPC_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_OPC_PATH + ".tmp", _OPC_PATH)
     return _LIB_PATH
 
 
@@ -69,34 +83,89 @@ _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 
 
+def _bind(L):
+    P, G = ctypes.POINTER(Params), ctypes.POINTER(Grid)
+    d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+    L.orc_riemann.argtypes = [P] + [d] * 8 + [ctypes.POINTER(Waves)]
+    L.orc_riemann.restype = None
+    L.orc_fluctuations.argtypes = [ctypes.POINTER(Waves), _D, _D]
+    L.orc_mc_limiter.argtypes = [d]
+    L.orc_mc_limiter.restype = d
+    L.orc_ghost_fill.argtypes = [G, _D]
+    L.orc_ghost_fill_b.argtypes = [G, _D]
+    L.orc_step.argtypes = [P, G, _D, _D, d, _D, _D, ctypes.POINTER(i32)]
+    L.orc_step.restype = i64
+    L.orc_step_sphere.argtypes = [P, G, _D, _D, d, _D, _D, _D, _D, ctypes.POINTER(i32)]
+    L.orc_step_sphere.restype = i64
+    L.orc_speed_scan.argtypes = [P, G, _D, _D, _D]
+    L.orc_run.argtypes = [P, G, _D, _D, i32, d, _D, _D, ctypes.POINTER(i32),
+                          ctypes.POINTER(i32)]
+    L.orc_run.restype = i64
+    L.orc_mass.argtypes = [G, _D]
+    L.orc_mass.restype = d
+    L.orc_set_threads.argtypes = [i32]
+    L.orc_get_threads.restype = i32
+    return L
+
+
+_opc = None
+
+
+def opcount_lib():
+    """The operation-counting build (same functions, single-threaded, plus
+    orc_opcount_get / orc_opcount_reset)."""
+    global _opc
+    if _opc is None:
+        if not os.path.exists(_OPC_PATH):
+            build()
+        L = _bind(ctypes.CDLL(_OPC_PATH))
+        L.orc_opcount_get.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+        L.orc_opcount_get.restype = None
+        L.orc_opcount_reset.restype = None
+        _opc = L
+    return _opc
+
+
+OPCOUNT_KINDS = ("add", "mul", "div", "sqrt", "cmp", "other")
+
+
+def opcount_reset() -> None:
+    opcount_lib().orc_opcount_reset()
+
+
+def opcount_get() -> dict:
+    """Operations counted by the counting build since the last reset:
+    add (additions and subtractions), mul, div, sqrt, cmp (comparisons of
+    reals), other (sign flips, absolute values, powers); "flops" is the
+    first four summed."""
+    buf = (ctypes.c_int64 * 6)()
+    opcount_lib().orc_opcount_get(buf)
+    out = dict(zip(OPCOUNT_KINDS, (int(v) for v in buf)))
+    out["flops"] = out["add"] + out["mul"] + out["div"] + out["sqrt"]
+    return out
+
+
+@contextlib.contextmanager
+def counting():
+    """Inside the block, every call of this module runs on the counting build
+    (single-threaded; results bit for bit the plain build's); the counters
+    start at zero.  Read them with opcount_get()."""
+    global _lib
+    saved = _lib
+    _lib = opcount_lib()
+    opcount_reset()
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        P, G = ctypes.POINTER(Params), ctypes.POINTER(Grid)
-        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
-        L.orc_riemann.argtypes = [P] + [d] * 8 + [ctypes.POINTER(Waves)]
-        L.orc_riemann.restype = None
-        L.orc_fluctuations.argtypes = [ctypes.POINTER(Waves), _D, _D]
-        L.orc_mc_limiter.argtypes = [d]
-        L.orc_mc_limiter.restype = d
-        L.orc_ghost_fill.argtypes = [G, _D]
-        L.orc_ghost_fill_b.argtypes = [G, _D]
-        L.orc_step.argtypes = [P, G, _D, _D, d, _D, _D, ctypes.POINTER(i32)]
-        L.orc_step.restype = i64
-        L.orc_step_sphere.argtypes = [P, G, _D, _D, d, _D, _D, _D, _D, ctypes.POINTER(i32)]
-        L.orc_step_sphere.restype = i64
-        L.orc_speed_scan.argtypes = [P, G, _D, _D, _D]
-        L.orc_run.argtypes = [P, G, _D, _D, i32, d, _D, _D, ctypes.POINTER(i32),
-                              ctypes.POINTER(i32)]
-        L.orc_run.restype = i64
-        L.orc_mass.argtypes = [G, _D]
-        L.orc_mass.restype = d
-        L.orc_set_threads.argtypes = [i32]
-        L.orc_get_threads.restype = i32
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
 
 

@@ -1,0 +1,73 @@
+"""Algorithmic operation count per cell update of the split step, from the
+oracle's counting build (opcount.cpp).
+
+TEST INFRASTRUCTURE: writes a record that the benchmark reads for the
+arithmetic side of its roofline (operations per cell update times the cell
+updates of a launch, over the launch time).  The state counted is the 4096^2
+shelf workload advanced `--steps` steps by the plain oracle (the middle of
+the benchmark's timed steps); one more step is then taken by the counting
+build.  Counts cover everything the step computes for the patch (the x-sweep
+of the ghost rows and the edges the limiter reads included) and are divided
+by the interior cells.
+
+    python -m oracle.count_ops --steps 260 --out profiles/oracle_opcount_shelf4096.txt
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def count(n: int = 4096, steps: int = 260, order: int = 2):
+    import oracle as O
+    from paper_1901_06798_amd import workloads as W
+
+    pb = W.shelf_4096(n=n, dx=250.0 * 4096 / n)
+    P = O.params(order=order)
+    q, b = O.new_state(pb.h, pb.hu, pb.hv, pb.b)
+    g = O.grid(pb.mx, pb.my, pb.dx, pb.dy, pb.bc)
+    O.ghost_fill_b(g, b)
+    t0 = time.perf_counter()
+    r = O.run(P, g, q, b, steps) if steps > 0 else {"dt": [0.0]}
+    t_run = time.perf_counter() - t0
+    O.ghost_fill(g, q)
+    sm = O.speed_scan(P, g, q, b)
+    dt = P.cfl_desired / max(sm[0] / g.dx, sm[1] / g.dy)
+    with O.counting():
+        O.step(P, g, q, b, dt)
+        c = O.opcount_get()
+    cells = pb.mx * pb.my
+    per = {k: v / cells for k, v in c.items()}
+    return {"n": n, "steps_before": steps, "cells": cells, "counts": c, "per_cell_update": per,
+            "oracle_seconds": t_run}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=260)
+    ap.add_argument("--out", type=str, default=None)
+    a = ap.parse_args()
+    res = count(a.n, a.steps)
+    per = res["per_cell_update"]
+    lines = [f"# FP64 split step, {a.n}^2 shelf after {a.steps} steps: operations per interior "
+             f"cell update counted by the oracle's counting build (oracle/opcount.cpp)",
+             f"# command: python -m oracle.count_ops --n {a.n} --steps {a.steps} --out <this file>",
+             f"cells = {res['cells']}"]
+    for k in ("add", "mul", "div", "sqrt", "cmp", "other", "flops"):
+        lines.append(f"{k}_per_cell_update = {per[k]:.4f}")
+    text = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
+if __name__ == "__main__":
+    main()

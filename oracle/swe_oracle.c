@@ -160,15 +160,18 @@ void orc_riemann(const orc_params *P,
     double deta = (hR - hL) + db;
     double delta = -db;
     int clamped = 0;
+    int bound = 0; /* 1: the left middle depth was bounded, 3: the right one */
     if (s1 < 0.0 && s3 > 0.0) {
         double b1 = (s3 * deta - dm) / (s3 - s1);
         double b3 = (dm - s1 * deta) / (s3 - s1);
         if (hL + b1 < 0.0) {
             delta = hm * (s3 - s1) / s3;
             clamped = 1;
+            bound = 1;
         } else if (hR - b3 < 0.0) {
             delta = hm * (s3 - s1) / s1;
             clamped = 1;
+            bound = 3;
         }
     } else if (s1 >= 0.0) {
         if (delta < -hL) {
@@ -188,9 +191,24 @@ void orc_riemann(const orc_params *P,
     double dphi = (mR * uR - mL * uL) + g * hbar * deta;
     double dt = mR * vR - mL * vL;
 
-    /* decomposition */
-    double beta1 = (s3 * dh - dm) / (s3 - s1);
-    double beta3 = (dm - s1 * dh) / (s3 - s1);
+    /* decomposition.  With the jump at a bound (and a positive HLL middle
+     * depth), that side's middle depth is zero in exact arithmetic: beta1 =
+     * -h_L at the left bound, beta3 = h_R at the right one.  That coefficient
+     * is taken at its exact value (computed, it can come out a rounding error
+     * past it and drain a dry cell to a negative depth), and the other one
+     * from the mass flux, s1 beta1 + s3 beta3 = dm, as the decomposition
+     * satisfies it in exact arithmetic. */
+    double beta1, beta3;
+    if (bound == 1 && hm > 0.0) {
+        beta1 = -hL;
+        beta3 = (dm + s1 * hL) / s3;
+    } else if (bound == 3 && hm > 0.0) {
+        beta3 = hR;
+        beta1 = (dm - s3 * hR) / s1;
+    } else {
+        beta1 = (s3 * dh - dm) / (s3 - s1);
+        beta3 = (dm - s1 * dh) / (s3 - s1);
+    }
     /* the two subtracted terms are summed first so that the solve is exactly
      * symmetric under reflection x -> -x */
     double beta2 = dphi - (s1 * s1 * beta1 + s3 * s3 * beta3);
@@ -255,9 +273,11 @@ static double dot3(const double *a, const double *b)
 /* Limited second-order correction at edge e from the waves at e-1, e, e+1
  * (Sec. 2: theta against the upwind edge, MC limiter, correction flux).  The
  * waves are f-waves Z = s W, so |s| W = sign(s) Z.  An edge with a cell at or
- * below h_corr deep keeps the first-order update: near a moving shoreline the
- * limited corrections can draw more water out of a thin cell than it holds,
- * while the first-order update keeps depths non-negative. */
+ * below h_corr deep (a film of water on the shore) keeps the first-order
+ * update: there a limited momentum correction is large against the momentum
+ * the film holds, and the film's velocity m / h spikes.  Elsewhere the split
+ * mode also bounds each correction by the water of its donor cell
+ * (positivity_limit below). */
 static void correction(const orc_waves *wl, const orc_waves *w, const orc_waves *wr,
                        double lam, double F[3])
 {
@@ -337,14 +357,61 @@ typedef struct {
     double (*F)[3];
 } line_work;
 
+/* Share of a cell's water that one edge's correction may carry out of it.
+ * Sec. 2 asks the scheme to keep depths non-negative.  The first-order
+ * update of a sweep keeps them (the solver's middle depths are non-negative;
+ * with Courant numbers of the two edges of a cell summing to at most 1); the
+ * limited corrections can draw more water out of a cell than it holds, also
+ * just above h_corr.  A cell has two edges per sweep, so each correction may
+ * take at most half of its donor's first-order depth; the share sits 5e-13
+ * below a half so that the rounding of the update cannot take a drained cell
+ * below zero. */
+#define ORC_DRAIN_SHARE 0.4999999999995
+
+/* Positivity limit of the corrections of one sweep line.  For edge e the
+ * donor d is the cell the correction's mass flux F[e][0] leaves (e - 1 if it
+ * is positive, e if negative); h1 is d's depth after the first-order part of
+ * its update, and the correction takes coef * F[e][0] out of d, with coef
+ * the factor of F[e] in d's update.  If that exceeds ORC_DRAIN_SHARE * h1
+ * (0 for h1 <= 0), the whole correction F[e] is scaled down to it.
+ * kap == NULL: a Cartesian line, coef = lam, h1 = h - lam (A+dQ + A-dQ);
+ * otherwise a latitude-longitude line (see sweep_line_metric): coef =
+ * lam / kap[d] * len[e] and h1 includes the mass term of that update. */
+static void positivity_limit(int n, double lam, const double (*line)[4], line_work *W,
+                             const double *kap, const double *len)
+{
+    for (int e = 2; e <= n + 2; ++e) {
+        double f = W->F[e][0];
+        if (f == 0.0) continue;
+        int d = f > 0.0 ? e - 1 : e;
+        double h1, out;
+        if (!kap) {
+            h1 = line[d][0] - lam * (W->apdq[d][0] + W->amdq[d + 1][0]);
+            out = lam * fabs(f);
+        } else {
+            double lc = lam / kap[d];
+            h1 = (line[d][0] - lc * (len[d] * W->apdq[d][0] + len[d + 1] * W->amdq[d + 1][0]))
+                 + lc * (line[d][1] * (len[d] - len[d + 1]));
+            out = lc * (len[e] * fabs(f));
+        }
+        double cap = h1 > 0.0 ? ORC_DRAIN_SHARE * h1 : 0.0;
+        if (out > cap) {
+            double r = cap / out;
+            for (int k = 0; k < NQ; ++k) W->F[e][k] = r * W->F[e][k];
+        }
+    }
+}
+
 static void sweep_line(const orc_params *P, int n, double lam, const double (*line)[4],
                        double (*out)[3], line_work *W, double *smax)
 {
     for (int e = 1; e <= n + 3; ++e)
         orc_riemann(P, line[e - 1][0], line[e - 1][1], line[e - 1][2], line[e - 1][3],
                     line[e][0], line[e][1], line[e][2], line[e][3], &W->w[e]);
+    /* fluctuations of every solved edge: the updated cells use edges 2 .. n + 2,
+     * the donors of the positivity limit edges 1 .. n + 3 */
+    for (int e = 1; e <= n + 3; ++e) orc_fluctuations(&W->w[e], W->amdq[e], W->apdq[e]);
     for (int e = 2; e <= n + 2; ++e) {
-        orc_fluctuations(&W->w[e], W->amdq[e], W->apdq[e]);
         if (P->order >= 2)
             correction(&W->w[e - 1], &W->w[e], &W->w[e + 1], lam, W->F[e]);
         else
@@ -354,6 +421,7 @@ static void sweep_line(const orc_params *P, int n, double lam, const double (*li
             if (a > *smax) *smax = a;
         }
     }
+    if (P->order >= 2) positivity_limit(n, lam, line, W, NULL, NULL);
     for (int c = 2; c <= n + 1; ++c)
         for (int k = 0; k < NQ; ++k)
             out[c][k] = line[c][k] - lam * (W->apdq[c][k] + W->amdq[c + 1][k])
@@ -509,9 +577,9 @@ static void sweep_line_metric(const orc_params *P, int n, double lam, const doub
     for (int e = 1; e <= n + 3; ++e)
         orc_riemann(P, line[e - 1][0], line[e - 1][1], line[e - 1][2], line[e - 1][3],
                     line[e][0], line[e][1], line[e][2], line[e][3], &W->w[e]);
+    for (int e = 1; e <= n + 3; ++e) orc_fluctuations(&W->w[e], W->amdq[e], W->apdq[e]);
     for (int e = 2; e <= n + 2; ++e) {
         const double a = 0.5 * (1.0 / kap[e - 1] + 1.0 / kap[e]);
-        orc_fluctuations(&W->w[e], W->amdq[e], W->apdq[e]);
         if (P->order >= 2)
             correction(&W->w[e - 1], &W->w[e], &W->w[e + 1], lam * a, W->F[e]);
         else
@@ -521,6 +589,7 @@ static void sweep_line_metric(const orc_params *P, int n, double lam, const doub
             if (v > *smax) *smax = v;
         }
     }
+    if (P->order >= 2) positivity_limit(n, lam, line, W, kap, len);
     for (int c = 2; c <= n + 1; ++c) {
         const double lc = lam / kap[c];
         const double *ap = W->apdq[c], *am = W->amdq[c + 1];  /* edges c, c + 1 */

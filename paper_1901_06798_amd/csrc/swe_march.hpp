@@ -419,6 +419,14 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             }
             const S qc[3] = {q0, hu, hv};
             const S lx = SPH ? S(lamx * lane_read(ik_l, R - rbase)) : lamx;
+            if (second) {
+                // positivity limit: the donor of this lane's edge is the left
+                // cell (lane k - 1) for a positive mass correction, else this
+                // lane's cell; h1 = depth after the first-order part of the update
+                const S h1 = me.h - lx * (ap[0] + lane_down<SEG>(am[0]));
+                const S h1l = lane_up<SEG>(h1);
+                drain_limit(F, F[0] > S(0) ? h1l : h1, lx, S(1));
+            }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const S amr = lane_down<SEG>(am[k]);
@@ -468,17 +476,41 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 #pragma unroll
                 for (int p = 0; p < 3; ++p) dcur[p] = dot3(wprev.z[p], wy.z[p]);
             }
-            if (t >= 3) {
-                // edge E - 1: fluctuations and correction (+0 for a quiet edge)
+            if (t >= 2) {
+                // edge E - 1: fluctuations (from t = 2, so that the edge below
+                // a task's first updated row has its A+dQ for the positivity
+                // limit) and, from t = 3, the correction (+0 for a quiet edge)
                 S am1[3] = {S(0), S(0), S(0)}, ap1[3] = {S(0), S(0), S(0)};
                 S F1[3] = {S(0), S(0), S(0)};
                 if (!wprev_quiet) {
                     fluctuations(wprev, am1, ap1);
-                    if (second) correction(wprev, dprev, dcur,
+                    if (second && t >= 3) correction(wprev, dprev, dcur,
                                    SPH ? S(lamy * (0.5 * (lane_read(ik_l, E - 2 - rbase) +
                                                           lane_read(ik_l, E - 1 - rbase))))
                                        : lamy,
                                    F1);
+                }
+                if (second && t >= 3) {
+                    // positivity limit of edge E - 1's correction: its donor is
+                    // row R - 2 (below) for a positive mass correction, else row
+                    // R - 1; h1 = depth after the first-order part of the update
+                    // (between edges E - 2, E - 1, and E - 1, E)
+                    const bool up = !(F1[0] > S(0));
+                    const S hlo = DEV ? qm2[0] + S(P.sea_level) - qm2_b : qm2[0];
+                    const S hd = up ? prev.h : hlo;
+                    const S apd = up ? ap1[0] : ap_prev[0];
+                    const S amd = up ? minus_mass(wy) : am1[0];
+                    if (SPH) {
+                        const int rd = up ? R - 1 : R - 2;  // donor row
+                        const S lc = lamy * lane_read(ik_l, rd - rbase);
+                        const S ll = lenv[rd], lu = lenv[rd + 1];
+                        const S md = up ? prev.m : qm2[1];
+                        const S h1 = (hd - lc * (ll * apd + lu * amd)) + lc * (md * (ll - lu));
+                        drain_limit(F1, h1, lc, S(lenv[E - 1]));
+                    } else {
+                        const S h1 = hd - lamy * (apd + amd);
+                        drain_limit(F1, h1, lamy, S(1));
+                    }
                 }
                 if (t >= 4) {
                     // finish row R - 2 between edges E - 2 and E - 1

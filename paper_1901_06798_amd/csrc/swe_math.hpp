@@ -172,20 +172,24 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
     const T deta = DEV ? (eR - eL) : (hR - hL) + db;
     T beta1, beta3;
     bool clamped = false;
+    int bound = 0;  // 1: the left middle depth is at its bound, 3: the right one
+    T hm = T(0);
     T delta = -db;
     if (s1 < T(0) && s3 > T(0)) {
         beta1 = qdiv(s3 * deta - dm, s3 - s1);
         beta3 = qdiv(dm - s1 * deta, s3 - s1);
         if (hL + beta1 < T(0)) {
-            T hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
+            hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
             hm = hm < T(0) ? T(0) : hm;
             delta = qdiv(hm * (s3 - s1), s3);
             clamped = true;
+            bound = 1;
         } else if (hR - beta3 < T(0)) {
-            T hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
+            hm = qdiv(s3 * hR - s1 * hL - dm, s3 - s1);
             hm = hm < T(0) ? T(0) : hm;
             delta = qdiv(hm * (s3 - s1), s1);
             clamped = true;
+            bound = 3;
         }
     } else {
         if (s1 >= T(0)) {
@@ -199,9 +203,22 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
         }
     }
     if (clamped) {
-        const T dh = (hR - hL) - delta;
-        beta1 = qdiv(s3 * dh - dm, s3 - s1);
-        beta3 = qdiv(dm - s1 * dh, s3 - s1);
+        // at a bound (with a positive HLL middle depth) that side's middle
+        // depth is zero in exact arithmetic: its coefficient takes that exact
+        // value (computed, it can land a rounding error past it and drain an
+        // empty cell below zero) and the other follows from the mass flux
+        // s1 beta1 + s3 beta3 = dm
+        if (bound == 1 && hm > T(0)) {
+            beta1 = -hL;
+            beta3 = qdiv(dm + s1 * hL, s3);
+        } else if (bound == 3 && hm > T(0)) {
+            beta3 = hR;
+            beta1 = qdiv(dm - s3 * hR, s1);
+        } else {
+            const T dh = (hR - hL) - delta;
+            beta1 = qdiv(s3 * dh - dm, s3 - s1);
+            beta3 = qdiv(dm - s1 * dh, s3 - s1);
+        }
     }
 
     const T hbar = T(0.5) * (hL + hR);
@@ -306,6 +323,53 @@ __device__ __forceinline__ void correction(const Waves<T>& w, const T dl[3], con
         const T cu = use ? coef : T(0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) F[k] += cu * w.z[p][k];
+    }
+}
+
+// Mass component of A-dQ, computed exactly as fluctuations() computes am[0].
+template <typename T>
+__device__ __forceinline__ T minus_mass(const Waves<T>& w) {
+    const bool zam = w.kind == kEdgeWallL;
+    T am = T(0);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const T s = w.s[p];
+        const T m = s < T(0) ? T(1) : (s > T(0) ? T(0) : T(0.5));
+        am += (zam ? T(0) : m) * w.z[p][0];
+    }
+    return am;
+}
+
+// Share of its donor's water that one edge's correction may carry out (per
+// sweep a cell has two edges, so at most half of its depth after the
+// first-order part of its update; the FP64 share sits 5e-13 below a half so
+// that the rounding of the update cannot take a drained cell below zero, the
+// FP32 share 1e-5 below).
+template <typename T>
+struct DrainShare;
+template <>
+struct DrainShare<double> {
+    static constexpr double v = 0.4999999999995;
+};
+template <>
+struct DrainShare<float> {
+    static constexpr float v = 0.49999f;
+};
+
+// Positivity limit of a correction F (Sec. 2: depths stay non-negative): h1
+// is the depth of the donor cell, the one F's mass flux leaves, after the
+// first-order part of its update; coef * (len * |F[0]|) is what F takes out
+// of it.  If that exceeds the donor's share of h1 (0 for h1 <= 0), all of F
+// is scaled down to it.
+template <typename T>
+__device__ __forceinline__ void drain_limit(T F[3], T h1, T coef, T len) {
+    const T out = coef * (len * fabs(F[0]));
+    const T cap = h1 > T(0) ? T(DrainShare<T>::v) * h1 : T(0);
+    if (out > cap) {
+        const T r = qdiv(cap, out);
+        F[0] = r * F[0];
+        F[1] = r * F[1];
+        F[2] = r * F[2];
     }
 }
 

@@ -31,8 +31,13 @@ MUTANTS = {
     "drop_bed_source": ("double dphi = (mR * uR - mL * uL) + g * hbar * deta;",
                         "double dphi = (mR * uR - mL * uL);"),
     "bed_jump_sign": ("double db = bR - bL;", "double db = bL - bR;"),
-    "beta1_operand": ("double beta1 = (s3 * dh - dm) / (s3 - s1);",
-                      "double beta1 = (s1 * dh - dm) / (s3 - s1);"),
+    "beta1_operand": ("beta1 = (s3 * dh - dm) / (s3 - s1);",
+                      "beta1 = (s1 * dh - dm) / (s3 - s1);"),
+    "bound_beta_computed": ("beta1 = -hL;\n        beta3 = (dm + s1 * hL) / s3;",
+                            "beta1 = (s3 * dh - dm) / (s3 - s1);\n"
+                            "        beta3 = (dm - s1 * dh) / (s3 - s1);"),
+    "drain_donor": ("int d = f > 0.0 ? e - 1 : e;", "int d = f > 0.0 ? e : e - 1;"),
+    "drain_share": ("#define ORC_DRAIN_SHARE 0.4999999999995", "#define ORC_DRAIN_SHARE 1.0"),
     "s1_min_max": ("s1 = a < c ? a : c;", "s1 = a > c ? a : c;"),
     "update_index": ("W->amdq[c + 1][k])", "W->amdq[c][k])"),
     "upwind_edge": ("const orc_waves *up = s > 0.0 ? wl : wr;",
@@ -118,6 +123,29 @@ def pins(O):
         if not np.allclose(am + ap, expect, rtol=1e-12, atol=1e-12):
             failed.append("fluctuation_split")
             break
+    # an empty cell on a bank the water runs off loses no water at the bound
+    for hR in (0.3, 1.0, 2.5, 7.0):
+        for fr in np.linspace(0.5, 3.5, 13):
+            for rise in (0.05, 0.3, 0.6, 0.9):
+                uR = fr * math.sqrt(9.81 * hR)
+                left, right = (0.0, 0.0, 0.0, -3.0 + rise * hR), (hR, hR * uR, 0.0, -3.0)
+                _, _, _, clamped = O.riemann(left, right)
+                am, _ = O.fluctuations(left, right)
+                if clamped and am[0] > 0.0:
+                    failed.append("empty_bank")
+                    break
+            if failed and failed[-1] == "empty_bank":
+                break
+        if failed and failed[-1] == "empty_bank":
+            break
+    # a steep run-up: no depth reset, volume kept
+    from test_oracle_solutions import plane_beach
+    pb = plane_beach(48, amp=4.0)
+    g, q, b = oracle_setup(O, pb)
+    m0 = O.mass(g, q)
+    r = O.run(P, g, q, b, 600)
+    if r["clamps"] != 0 or abs(O.mass(g, q) - m0) / m0 > 1e-13:
+        failed.append("steep_run_up")
     if abs(O.mc_limiter(0.5) - 0.75) > 1e-15 or abs(O.mc_limiter(2.0) - 1.5) > 1e-15:
         failed.append("mc_table")
     # lake at rest with a coast stays exactly at rest

@@ -11,7 +11,10 @@ mathematics (not by retyping the solver):
 * speeds ordered s1 <= s2 <= s3;
 * a first-order Godunov update of the two cells at Courant number <= 1 keeps
   both depths non-negative (the solver's stated positivity property);
-* a wall edge against a dry bank acts like the explicit mirror state.
+* a wall edge against a dry bank acts like the explicit mirror state;
+* water running off a dry bank it can reach takes no water out of the bank's
+  empty cell: at the bound of the stationary jump that cell's middle depth is
+  exactly 0, so its left-going mass flux is 0 (also mirrored).
 """
 import math
 
@@ -194,3 +197,50 @@ def test_dry_front_speed(orc):
     c = math.sqrt(G * h)
     assert s[2] == pytest.approx(u + 2 * c, rel=1e-15)
     assert s[0] == pytest.approx(u - c, rel=1e-15)
+
+
+@settings(max_examples=400, deadline=None)
+@given(st.floats(min_value=0.05, max_value=20.0), st.floats(min_value=0.0, max_value=4.0),
+       st.floats(min_value=0.01, max_value=0.99), st.floats(min_value=-500.0, max_value=50.0))
+def test_empty_cell_on_a_bank_loses_no_water(orc, hR, fr, rise, bR):
+    # left: an empty cell on a bank whose bed lies below the right surface
+    # (the water can reach it, no wall); right: water running away from it.
+    # At the bound of the stationary jump the left middle depth is 0 in exact
+    # arithmetic, so A-dQ carries no mass out of the empty cell: its depth
+    # after a first-order update, 0 - lam * A-dQ[0], must not go below 0
+    cR = math.sqrt(G * hR)
+    uR = fr * cR
+    bL = bR + rise * hR
+    left, right = (0.0, 0.0, 0.0, bL), (hR, hR * uR, 0.0, bR)
+    Z, s, kind, clamped = orc.riemann(left, right)
+    assert kind == orc.EDGE_WET
+    am, ap = orc.fluctuations(left, right)
+    if clamped:
+        assert am[0] <= 0.0, (am[0], Z[0])
+    # the mirror image: the empty cell on the right
+    am2, ap2 = orc.fluctuations((hR, -hR * uR, 0.0, bR), (0.0, 0.0, 0.0, bL))
+    _, _, _, clamped2 = orc.riemann((hR, -hR * uR, 0.0, bR), (0.0, 0.0, 0.0, bL))
+    if clamped2:
+        assert ap2[0] <= 0.0, (ap2[0],)
+
+
+def test_empty_cell_on_a_bank_grid_hits_the_bound(orc):
+    # the same on a fixed grid of states, which reaches the bound many times
+    hits = 0
+    for hR in (0.3, 1.0, 2.5, 7.0):
+        for fr in np.linspace(0.5, 3.5, 13):
+            for rise in (0.05, 0.3, 0.6, 0.9):
+                uR = fr * math.sqrt(G * hR)
+                bR = -3.0
+                bL = bR + rise * hR
+                left, right = (0.0, 0.0, 0.0, bL), (hR, hR * uR, 0.0, bR)
+                _, _, kind, clamped = orc.riemann(left, right)
+                am, _ = orc.fluctuations(left, right)
+                if clamped:
+                    hits += 1
+                    assert am[0] <= 0.0
+                _, _, _, c2 = orc.riemann((hR, -hR * uR, 0.0, bR), (0.0, 0.0, 0.0, bL))
+                _, ap2 = orc.fluctuations((hR, -hR * uR, 0.0, bR), (0.0, 0.0, 0.0, bL))
+                if c2:
+                    assert ap2[0] <= 0.0
+    assert hits >= 20
