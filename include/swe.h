@@ -73,7 +73,13 @@ extern "C" {
 #define SWE_STATUS_RETAKEN 8u
 
 enum swe_method { SWE_SPLIT = 0, SWE_UNSPLIT = 1 };
-enum swe_precision { SWE_F64 = 0, SWE_F32_DEV = 1 };
+/* SWE_F32_STORE: the SWE_F32_DEV planes (eta', hu, hv, b in FP32) with every
+ * operation of the step in FP64, the result rounded to FP32 once per step;
+ * the single-patch split step only (it measures what FP32 storage alone
+ * costs in accuracy; the other entry points take SWE_F64 or SWE_F32_DEV,
+ * except those that only read or write the state, which treat it as
+ * SWE_F32_DEV). */
+enum swe_precision { SWE_F64 = 0, SWE_F32_DEV = 1, SWE_F32_STORE = 2 };
 enum swe_bc { SWE_BC_WALL = 0, SWE_BC_EXTRAP = 1, SWE_BC_USER = 2 };
 
 /* Physical and numerical parameters (host struct, passed by pointer). */

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("SWE_LIB_PATH", os.path.join(_HERE, "libswe.so"))
 SWE_OK, SWE_EINVAL, SWE_EHIP = 0, -1, -2
 STATUS_NEG_DEPTH, STATUS_NONFINITE, STATUS_CFL_EXCEEDED, STATUS_RETAKEN = 1, 2, 4, 8
 SPLIT, UNSPLIT = 0, 1
-F64, F32_DEV = 0, 1
+F64, F32_DEV, F32_STORE = 0, 1, 2
 BC_WALL, BC_EXTRAP, BC_USER = 0, 1, 2
 SWE_AMR_COPY, SWE_AMR_COARSE = 0, 1
 

@@ -27,7 +27,7 @@ class BatchedSolver:
             raise L.SweError("BatchedSolver needs a GPU (torch.cuda is not available)")
         L.lib()
         self.p = params or L.params()
-        self.dev_path = self.p.precision == L.F32_DEV
+        self.dev_path = self.p.precision != L.F64
         self.dev = torch.device(device)
         self.problems = list(problems)
         n = len(self.problems)

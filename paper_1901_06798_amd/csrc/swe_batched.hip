@@ -428,7 +428,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     if (rc) return rc;
     if (p->method != SWE_SPLIT) return bfail(SWE_EINVAL, "swe_batched_step: only the split step");
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
-        return bfail(SWE_EINVAL, "swe_batched_step: unknown precision");
+        return bfail(SWE_EINVAL, "swe_batched_step: precision must be SWE_F64 or SWE_F32_DEV");
     if (p->order != 1 && p->order != 2) return bfail(SWE_EINVAL, "params: order must be 1 or 2");
     if (nitems < 0 || nplain < 0 || nsub < 0 || (nplain > 0 && nsub < 1))
         return bfail(SWE_EINVAL, "swe_batched_step: bad counts");
@@ -553,7 +553,7 @@ int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
                             uint32_t* status, const swe_schedule* sched, void* stream) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
-        return bfail(SWE_EINVAL, "swe_batched_step_static: unknown precision");
+        return bfail(SWE_EINVAL, "swe_batched_step_static: precision must be SWE_F64 or SWE_F32_DEV");
     if (pool_elems < 1) return bfail(SWE_EINVAL, "swe_batched_step_static: pool_elems must be >= 1");
     const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
     const bool work = nitems > 0 || nsub > 1;

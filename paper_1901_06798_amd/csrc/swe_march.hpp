@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "swe.h"
 #include "swe_common.hpp"
@@ -59,6 +60,10 @@ __device__ __forceinline__ void solve_edge(const Side<S>& L, const Side<S>& R, S
                                            S tR, const DevParams& P, Waves<S>& w) {
     if (!DEV) {
         riemann<S, false>(L, R, P, w);
+        return;
+    }
+    if (sizeof(S) == sizeof(double)) {  // FP64 arithmetic over FP32 storage
+        riemann<S, true>(L, R, P, w);
         return;
     }
     const bool wide = L.h <= S(P.h_fp64) || R.h <= S(P.h_fp64);
@@ -248,7 +253,7 @@ __device__ __forceinline__ void ring_issue(const Task& tk, int row, int lane, ui
 // capacity of the edge's cells, and the mass update takes out the term
 // f(Q) (len_lower - len_upper) that edge-weighted fluctuations add (the
 // continuity equation has no metric source).
-template <bool DEV, int SEG, bool FRIC, int RING = 0, bool SPH = false>
+template <bool DEV, int SEG, bool FRIC, int RING = 0, bool SPH = false, bool WIDE = false>
 __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, int lane_in_seg,
                                           int steps, typename Prec<DEV>::S* ring = nullptr) {
     static_assert(!SPH || !DEV, "latitude-longitude patches: FP64 only");
@@ -256,6 +261,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     static_assert(RING == 0 || SEG == kWave, "the row ring serves whole-wave strips");
     static_assert((RING & (RING - 1)) == 0, "ring depth is a power of two");
     using S = typename Prec<DEV>::S;
+    // arithmetic type: the storage type, or FP64 over FP32 storage (WIDE)
+    using A = typename std::conditional<WIDE, double, S>::type;
     const S* __restrict__ qin = static_cast<const S*>(tk.qin);
     S* __restrict__ qout = static_cast<S*>(tk.qout);
     const S* __restrict__ bpl = static_cast<const S*>(tk.b);
@@ -265,7 +272,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     const bool upd_col = tk.active && lane >= 2 && lane <= SEG - 3 && c <= tk.mx + 1;
     const bool xedge_own = tk.active && lane >= 2 && lane <= SEG - 2 && c >= 2 && c <= tk.mx + 2;
     const int U0 = tk.U0, U1 = tk.U1;
-    const S lamx = S(tk.dt / tk.dx), lamy = S(tk.dt / tk.dy);
+    const A lamx = A(tk.dt / tk.dx), lamy = A(tk.dt / tk.dy);
     // rows U0 - 2 .. U1 + 2 of the task, one per lane (at most kWave of
     // them): lane l holds 1 / kappa of row U0 - 2 + l; a row's value is read
     // from its lane, so no division is left in the march
@@ -278,24 +285,24 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     // the segment's columns all lie inside the patch (no ghost column)
     const bool cols_in = tk.c0 >= 2 && tk.c0 + SEG - 1 <= tk.mx + 1;
 
-    S smx = S(0), smy = S(0);
+    A smx = A(0), smy = A(0);
     uint32_t clamps = 0, flags = 0;
     uint32_t work = 0;
 
     // rolling state of the y-pipeline (row R - 1, R - 2 of Q*, edge E - 1)
-    Side<S> prev;
-    prev.h = prev.m = prev.t = prev.b = prev.u = prev.v = prev.sq = prev.c = prev.eta = S(0);
+    Side<A> prev;
+    prev.h = prev.m = prev.t = prev.b = prev.u = prev.v = prev.sq = prev.c = prev.eta = A(0);
     prev.dry = true;
-    S qm2[3] = {0, 0, 0};
-    S qm2_b = S(0);
-    Waves<S> wprev;
+    A qm2[3] = {0, 0, 0};
+    A qm2_b = A(0);
+    Waves<A> wprev;
     bool wprev_quiet = false;  // wprev came from the quiet-edge path (zero f-waves)
     bool prev_full = false;    // prev carries its velocities and sqrt(h)
-    S dprev[3] = {0, 0, 0};
-    S ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
+    A dprev[3] = {0, 0, 0};
+    A ap_prev[3] = {0, 0, 0}, F_prev[3] = {0, 0, 0};
     // finished row held for one iteration: its stores are issued before the
     // next row's loads, so waiting for those loads never waits for stores
-    S po[3] = {0, 0, 0};
+    A po[3] = {0, 0, 0};
     int po_row = 0;
     bool po_wr = false;
 
@@ -332,7 +339,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 
         // ---- row R (ghosts synthesised for physical boundaries), loaded one
         // iteration ago; then issue the loads of the next row
-        S q0, hu, hv, bb;
+        A q0, hu, hv, bb;
         if constexpr (RING > 0) {
             // row t is complete once at most the loads of rows t + 1 ..
             // t + RING - 1 are outstanding
@@ -376,12 +383,12 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         }
 
         // ---- x-sweep of row R: lane k solves the edge between columns k-1, k
-        Side<S> me = side_base_from<DEV, S, S>(q0, hu, hv, bb, P);
-        Side<S> lf = side_up<S, DEV, SEG>(me, P);
-        Waves<S> w;
-        S qs[3];
+        Side<A> me = side_base_from<DEV, A, A>(q0, hu, hv, bb, P);
+        Side<A> lf = side_up<A, DEV, SEG>(me, P);
+        Waves<A> w;
+        A qs[3];
         // lane 0's edge (its left cell lies outside the segment) feeds nothing
-        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, S>(lf, me))) {
+        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, A>(lf, me))) {
             // zero f-waves: the fluctuations and corrections are +0 and the
             // update returns Q itself, as the arithmetic below would
             quiet_waves(lf, me, P, w);
@@ -394,60 +401,60 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
             lf.u = lane_up<SEG>(me.u);
             lf.v = lane_up<SEG>(me.v);
             lf.sq = lane_up<SEG>(me.sq);
-            const S lf_m = DEV ? lane_up<SEG>(hu) : S(0);
-            const S lf_t = DEV ? lane_up<SEG>(hv) : S(0);
-            solve_edge<DEV, S>(lf, me, lf_m, lf_t, hu, hv, P, w);
-            S am[3], ap[3];
+            const A lf_m = DEV ? lane_up<SEG>(hu) : A(0);
+            const A lf_t = DEV ? lane_up<SEG>(hv) : A(0);
+            solve_edge<DEV, A>(lf, me, lf_m, lf_t, hu, hv, P, w);
+            A am[3], ap[3];
             fluctuations(w, am, ap);
-            S F[3] = {S(0), S(0), S(0)};
+            A F[3] = {A(0), A(0), A(0)};
             if (second) {
-                S dr[3], dl[3];
+                A dr[3], dl[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
-                    const S zr0 = lane_down<SEG>(w.z[p][0]);
-                    const S zr1 = lane_down<SEG>(w.z[p][1]);
-                    const S zr2 = lane_down<SEG>(w.z[p][2]);
+                    const A zr0 = lane_down<SEG>(w.z[p][0]);
+                    const A zr1 = lane_down<SEG>(w.z[p][1]);
+                    const A zr2 = lane_down<SEG>(w.z[p][2]);
                     dr[p] = w.z[p][0] * zr0 + w.z[p][1] * zr1 + w.z[p][2] * zr2;
                 }
 #pragma unroll
                 for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
                 if (SPH) {
-                    correction(w, dl, dr, S(lamx * lane_read(ik_l, R - rbase)), F);
+                    correction(w, dl, dr, A(lamx * lane_read(ik_l, R - rbase)), F);
                 } else {
                     correction(w, dl, dr, lamx, F);
                 }
             }
-            const S qc[3] = {q0, hu, hv};
-            const S lx = SPH ? S(lamx * lane_read(ik_l, R - rbase)) : lamx;
+            const A qc[3] = {q0, hu, hv};
+            const A lx = SPH ? A(lamx * lane_read(ik_l, R - rbase)) : lamx;
             if (second) {
                 // positivity limit: the donor of this lane's edge is the left
                 // cell (lane k - 1) for a positive mass correction, else this
                 // lane's cell; h1 = depth after the first-order part of the update
-                const S h1 = me.h - lx * (ap[0] + lane_down<SEG>(am[0]));
-                const S h1l = lane_up<SEG>(h1);
-                drain_limit(F, F[0] > S(0) ? h1l : h1, lx, S(1));
+                const A h1 = me.h - lx * (ap[0] + lane_down<SEG>(am[0]));
+                const A h1l = lane_up<SEG>(h1);
+                drain_limit(F, F[0] > A(0) ? h1l : h1, lx, A(1));
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const S amr = lane_down<SEG>(am[k]);
-                const S Fr = lane_down<SEG>(F[k]);
+                const A amr = lane_down<SEG>(am[k]);
+                const A Fr = lane_down<SEG>(F[k]);
                 qs[k] = qc[k] - lx * (ap[k] + amr) - lx * (Fr - F[k]);
             }
         }
-        cleanup<DEV, S>(qs, bb, P, upd_col && live, interior_row && upd_col, clamps, flags);
+        cleanup<DEV, A>(qs, bb, P, upd_col && live, interior_row && upd_col, clamps, flags);
         if (interior_row && xedge_own) {
-            S s = max_speed(w);
-            if (SPH) s = S(s * lane_read(ik_l, R - rbase));
+            A s = max_speed(w);
+            if (SPH) s = A(s * lane_read(ik_l, R - rbase));
             smx = s > smx ? s : smx;
         }
 
         // ---- y-sweep pipeline on the column of Q* (normal momentum hv)
-        Side<S> cur = side_base_from<DEV, S, S>(qs[0], qs[2], qs[1], bb, P);
+        Side<A> cur = side_base_from<DEV, A, A>(qs[0], qs[2], qs[1], bb, P);
         bool cur_full = false;
         if (t >= 1) {
-            Waves<S> wy;
+            Waves<A> wy;
             // the y-sweep of a lane feeds only its own column's update
-            const bool yq = SWE_QUIET && __all(!upd_col || quiet_edge<DEV, S>(prev, cur));
+            const bool yq = SWE_QUIET && __all(!upd_col || quiet_edge<DEV, A>(prev, cur));
             if (yq) {
                 quiet_waves(prev, cur, P, wy);
             } else {
@@ -459,19 +466,19 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 cur_full = true;
                 // Q* is cleaned up, so a dry side's stored momenta are 0 and
                 // the Sides carry the stored values for the FP64 islands too
-                solve_edge<DEV, S>(prev, cur, prev.m, prev.t, cur.m, cur.t, P, wy);
+                solve_edge<DEV, A>(prev, cur, prev.m, prev.t, cur.m, cur.t, P, wy);
             }
             const int E = R;  // edge between rows R - 1 and R
             const double a_e =
                 SPH ? 0.5 * (lane_read(ik_l, E - 1 - rbase) + lane_read(ik_l, E - rbase)) : 1.0;
             if (live && E >= U0 && E <= U1 + 1 && upd_col) {
-                S s = max_speed(wy);
-                if (SPH) s = S(s * a_e);
+                A s = max_speed(wy);
+                if (SPH) s = A(s * a_e);
                 smy = s > smy ? s : smy;
             }
             // with either edge quiet the dot product is a zero, and a zero
             // numerator gives theta = +-0, whose limiter value is +0 either way
-            S dcur[3] = {S(0), S(0), S(0)};
+            A dcur[3] = {A(0), A(0), A(0)};
             if (second && t >= 2 && !yq && !wprev_quiet) {
 #pragma unroll
                 for (int p = 0; p < 3; ++p) dcur[p] = dot3(wprev.z[p], wy.z[p]);
@@ -480,12 +487,12 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 // edge E - 1: fluctuations (from t = 2, so that the edge below
                 // a task's first updated row has its A+dQ for the positivity
                 // limit) and, from t = 3, the correction (+0 for a quiet edge)
-                S am1[3] = {S(0), S(0), S(0)}, ap1[3] = {S(0), S(0), S(0)};
-                S F1[3] = {S(0), S(0), S(0)};
+                A am1[3] = {A(0), A(0), A(0)}, ap1[3] = {A(0), A(0), A(0)};
+                A F1[3] = {A(0), A(0), A(0)};
                 if (!wprev_quiet) {
                     fluctuations(wprev, am1, ap1);
                     if (second && t >= 3) correction(wprev, dprev, dcur,
-                                   SPH ? S(lamy * (0.5 * (lane_read(ik_l, E - 2 - rbase) +
+                                   SPH ? A(lamy * (0.5 * (lane_read(ik_l, E - 2 - rbase) +
                                                           lane_read(ik_l, E - 1 - rbase))))
                                        : lamy,
                                    F1);
@@ -495,31 +502,31 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                     // row R - 2 (below) for a positive mass correction, else row
                     // R - 1; h1 = depth after the first-order part of the update
                     // (between edges E - 2, E - 1, and E - 1, E)
-                    const bool up = !(F1[0] > S(0));
-                    const S hlo = DEV ? qm2[0] + S(P.sea_level) - qm2_b : qm2[0];
-                    const S hd = up ? prev.h : hlo;
-                    const S apd = up ? ap1[0] : ap_prev[0];
-                    const S amd = up ? minus_mass(wy) : am1[0];
+                    const bool up = !(F1[0] > A(0));
+                    const A hlo = DEV ? qm2[0] + A(P.sea_level) - qm2_b : qm2[0];
+                    const A hd = up ? prev.h : hlo;
+                    const A apd = up ? ap1[0] : ap_prev[0];
+                    const A amd = up ? minus_mass(wy) : am1[0];
                     if (SPH) {
                         const int rd = up ? R - 1 : R - 2;  // donor row
-                        const S lc = lamy * lane_read(ik_l, rd - rbase);
-                        const S ll = lenv[rd], lu = lenv[rd + 1];
-                        const S md = up ? prev.m : qm2[1];
-                        const S h1 = (hd - lc * (ll * apd + lu * amd)) + lc * (md * (ll - lu));
-                        drain_limit(F1, h1, lc, S(lenv[E - 1]));
+                        const A lc = lamy * lane_read(ik_l, rd - rbase);
+                        const A ll = lenv[rd], lu = lenv[rd + 1];
+                        const A md = up ? prev.m : qm2[1];
+                        const A h1 = (hd - lc * (ll * apd + lu * amd)) + lc * (md * (ll - lu));
+                        drain_limit(F1, h1, lc, A(lenv[E - 1]));
                     } else {
-                        const S h1 = hd - lamy * (apd + amd);
-                        drain_limit(F1, h1, lamy, S(1));
+                        const A h1 = hd - lamy * (apd + amd);
+                        drain_limit(F1, h1, lamy, A(1));
                     }
                 }
                 if (t >= 4) {
                     // finish row R - 2 between edges E - 2 and E - 1
-                    S qn[3];
+                    A qn[3];
                     if (SPH) {
                         // cell c = R - 2 between edges c (below) and c + 1 (above)
                         const int cr = R - 2;
-                        const S lc = lamy * lane_read(ik_l, cr - rbase);
-                        const S ll = lenv[cr], lu = lenv[cr + 1];
+                        const A lc = lamy * lane_read(ik_l, cr - rbase);
+                        const A ll = lenv[cr], lu = lenv[cr + 1];
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
                             qn[k] = qm2[k] - lc * (ll * ap_prev[k] + lu * am1[k])
@@ -532,17 +539,17 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                                     lamy * (F1[k] - F_prev[k]);
                     }
                     // the y-sweep works in (h, hv, hu)
-                    S out[3] = {qn[0], qn[2], qn[1]};
-                    const S bo = qm2_b;
+                    A out[3] = {qn[0], qn[2], qn[1]};
+                    const A bo = qm2_b;
                     const bool wr = upd_col && live;
-                    cleanup<DEV, S>(out, bo, P, wr, wr, clamps, flags);
+                    cleanup<DEV, A>(out, bo, P, wr, wr, clamps, flags);
                     if (FRIC) {
-                        const S hd = DEV ? out[0] + S(P.sea_level) - bo : out[0];
-                        if (hd > S(P.drytol)) {
-                            const S n2g = S(P.manning_n) * S(P.manning_n) * S(P.g);
-                            const S speed = sqrt(out[1] * out[1] + out[2] * out[2]) / hd;
-                            const S D = n2g * S(pow(double(hd), -7.0 / 3.0)) * speed;
-                            const S f = S(1) / (S(1) + S(tk.dt) * D);
+                        const A hd = DEV ? out[0] + A(P.sea_level) - bo : out[0];
+                        if (hd > A(P.drytol)) {
+                            const A n2g = A(P.manning_n) * A(P.manning_n) * A(P.g);
+                            const A speed = sqrt(out[1] * out[1] + out[2] * out[2]) / hd;
+                            const A D = n2g * A(pow(double(hd), -7.0 / 3.0)) * speed;
+                            const A f = A(1) / (A(1) + A(tk.dt) * D);
                             out[1] *= f;
                             out[2] *= f;
                         }

@@ -93,7 +93,7 @@ constexpr size_t ring_bytes(bool f64) {
 // Waves per SIMD the register budget is fitted to, without spilling: the
 // FP32 march takes four (at most 128 VGPRs), the FP64 one three (168); with
 // the friction step compiled in, one fewer.
-template <bool DEV, bool FRIC, bool SPH>
+template <bool DEV, bool FRIC, bool SPH, bool WIDE = false>
 __device__ __forceinline__ void split_task(const StepArgs& a) {
     const int lane = threadIdx.x & (kWave - 1);
     // the task, and with it the row loop's trip count, is the same for the
@@ -125,7 +125,7 @@ __device__ __forceinline__ void split_task(const StepArgs& a) {
     extern __shared__ __align__(16) unsigned char swe_step_lds[];
     S* ring = reinterpret_cast<S*>(swe_step_lds) + (threadIdx.x / kWave) * (kRing * 4 * kWave);
     const MarchOut o =
-        march<DEV, kWave, FRIC, kRing, SPH>(tk, a.P, lane, tk.U1 - tk.U0 + 5, ring);
+        march<DEV, kWave, FRIC, kRing, SPH, WIDE>(tk, a.P, lane, tk.U1 - tk.U0 + 5, ring);
     const double wx = wave_max_nonneg(o.smx);
     const double wy = wave_max_nonneg(o.smy);
     if (lane == 0) {
@@ -137,9 +137,11 @@ __device__ __forceinline__ void split_task(const StepArgs& a) {
     if (o.flags) atomicOr(&a.status[0], o.flags);
 }
 
-template <bool DEV, bool FRIC>
-__global__ void __launch_bounds__(256, (DEV ? 4 : 3) - (FRIC ? 1 : 0)) k_split(StepArgs a) {
-    split_task<DEV, FRIC, false>(a);
+// WIDE: FP32 surface-deviation planes, FP64 arithmetic (SWE_F32_STORE).
+template <bool DEV, bool FRIC, bool WIDE = false>
+__global__ void __launch_bounds__(256, (DEV && !WIDE ? 4 : 3) - (FRIC ? 1 : 0))
+    k_split(StepArgs a) {
+    split_task<DEV, FRIC, false, WIDE>(a);
 }
 
 // The same on a latitude-longitude patch (FP64).
@@ -152,6 +154,8 @@ template __global__ void k_split<false, false>(StepArgs);
 template __global__ void k_split<true, false>(StepArgs);
 template __global__ void k_split<false, true>(StepArgs);
 template __global__ void k_split<true, true>(StepArgs);
+template __global__ void k_split<true, false, true>(StepArgs);
+template __global__ void k_split<true, true, true>(StepArgs);
 template __global__ void k_split_sphere<false>(StepArgs);
 template __global__ void k_split_sphere<true>(StepArgs);
 
@@ -584,7 +588,7 @@ int check_params(const swe_params* p) {
     if (p->order != 1 && p->order != 2) return fail(SWE_EINVAL, "params: order must be 1 or 2");
     if (p->method != SWE_SPLIT && p->method != SWE_UNSPLIT)
         return fail(SWE_EINVAL, "params: unknown method");
-    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
+    if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV && p->precision != SWE_F32_STORE)
         return fail(SWE_EINVAL, "params: unknown precision");
     return SWE_OK;
 }
@@ -740,6 +744,10 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
         const size_t lds = waves_per_block * swe::ring_bytes(true);
         if (fric) hipLaunchKernelGGL((swe::k_split<false, true>), grid, block, lds, st, a);
         else hipLaunchKernelGGL((swe::k_split<false, false>), grid, block, lds, st, a);
+    } else if (p->precision == SWE_F32_STORE) {
+        const size_t lds = waves_per_block * swe::ring_bytes(false);
+        if (fric) hipLaunchKernelGGL((swe::k_split<true, true, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((swe::k_split<true, false, true>), grid, block, lds, st, a);
     } else {
         const size_t lds = waves_per_block * swe::ring_bytes(false);
         if (fric) hipLaunchKernelGGL((swe::k_split<true, true>), grid, block, lds, st, a);
@@ -874,7 +882,7 @@ int swe_mass(const swe_params* p, const swe_patch* patches, int32_t n, const voi
              const void* b, double* mass_patch, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
-    if (!patches || !q || !mass_patch || n < 0 || (p->precision == SWE_F32_DEV && !b))
+    if (!patches || !q || !mass_patch || n < 0 || (p->precision != SWE_F64 && !b))
         return fail(SWE_EINVAL, "swe_mass: bad arguments");
     if (n == 0) return SWE_OK;
     if (p->precision == SWE_F64)
@@ -920,7 +928,7 @@ int swe_state_export(const swe_params* p, const swe_patch* patches, int32_t n, i
                      int32_t max_my, const void* q, const void* b, double* dst, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
-    if (!patches || !q || !dst || (p->precision == SWE_F32_DEV && !b))
+    if (!patches || !q || !dst || (p->precision != SWE_F64 && !b))
         return fail(SWE_EINVAL, "swe_state_export: null pointer");
     dim3 grid;
     if ((rc = state_grid(n, max_mx, max_my, &grid))) return rc;

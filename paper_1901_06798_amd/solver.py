@@ -39,7 +39,7 @@ class PatchSolver:
         L.lib()
         self.pb = pb
         self.p = params or L.params()
-        self.dev_path = self.p.precision == L.F32_DEV
+        self.dev_path = self.p.precision != L.F64
         self.dev = torch.device(device)
         self.mx, self.my = pb.mx, pb.my
         self.pitch = _round_up(self.mx + 4, 16)

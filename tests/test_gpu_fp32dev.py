@@ -1,7 +1,8 @@
 """GPU tests of the FP32 surface-deviation path: FP32 storage of
-eta' = h + b - sea_level, FP64 solves at shallow and dry edges.  Bars: a lake
-at rest stays exactly at rest; the surface stays within 1e-5 m of the FP64
-reference (driven by the FP64 step sizes) on cells wet in both runs."""
+eta' = h + b - sea_level, FP64 solves at shallow and dry edges (SWE_F32_DEV),
+or FP64 arithmetic throughout over the same storage (SWE_F32_STORE).  Bars: a
+lake at rest stays exactly at rest; the surface stays within 1e-5 m of the
+FP64 reference (driven by the FP64 step sizes) on cells wet in both runs."""
 import numpy as np
 import pytest
 
@@ -23,11 +24,12 @@ def gpu():
     return L, PatchSolver, torch
 
 
-def test_lake_at_rest_is_exact_in_fp32(gpu):
+@pytest.mark.parametrize("prec", ["F32_DEV", "F32_STORE"])
+def test_lake_at_rest_is_exact_in_fp32(gpu, prec):
     L, PatchSolver, torch = gpu
     pb = W.shelf_grid(200, 500.0, seed=13, amp=0.0, x_s_frac=0.5, width=5e3)
     assert (pb.h == 0).any()
-    s = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    s = PatchSolver(pb, L.params(precision=getattr(L, prec)))
     s.run(40)
     torch.cuda.synchronize()
     Q = s.planes().cpu().numpy()[:, 2:-2, 2: pb.mx + 2]
@@ -42,16 +44,17 @@ def surface_error(h32, eta32, h64, eta64, wet_min=1e-2):
     return np.abs(eta32 - eta64)[both].max(), int(((h32 > 1e-3) != (h64 > 1e-3)).sum())
 
 
-def test_surface_error_against_reference(gpu, orc):
-    """Shelf with a coast, walls, 400 steps: FP32-dev vs the FP64 reference
-    solver with the same step sizes."""
+@pytest.mark.parametrize("prec", ["F32_DEV", "F32_STORE"])
+def test_surface_error_against_reference(gpu, orc, prec):
+    """Shelf with a coast, walls, 400 steps: FP32 storage vs the FP64
+    reference solver with the same step sizes."""
     L, PatchSolver, torch = gpu
     pb = W.shelf_walls(n=192, dx=2000.0, seed=4, nsteps=400)
     s64 = PatchSolver(pb, L.params())
     dts = s64.run(400)
     g, q, b = oracle_setup(orc, pb)
     orc.run(orc.params(), g, q, b, 400, dt_forced=dts)
-    s32 = PatchSolver(pb, L.params(precision=L.F32_DEV))
+    s32 = PatchSolver(pb, L.params(precision=getattr(L, prec)))
     s32.run_forced(dts)
     torch.cuda.synchronize()
     h32, _, _ = s32.state()
@@ -59,7 +62,7 @@ def test_surface_error_against_reference(gpu, orc):
     h64 = interior(q)[..., 0]
     eta64 = h64 + interior(b)
     err, mismatch = surface_error(h32, eta32, h64, eta64)
-    print(f"fp32-dev surface error {err:.3e} m, wet/dry mismatches {mismatch}", flush=True)
+    print(f"{prec} surface error {err:.3e} m, wet/dry mismatches {mismatch}", flush=True)
     assert err <= ETA_TOL
     # the FP64 GPU run itself is the reference solver's result
     for a, k in zip(s64.state(), range(3)):

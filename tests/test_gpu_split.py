@@ -216,6 +216,27 @@ def test_nonfinite_and_negative_input_are_flagged(gpu):
     assert s.flags()[0] & L.STATUS_NONFINITE
 
 
+def test_negative_input_depth_is_reset_and_counted(gpu, orc):
+    # a negative depth in the input (not made by the scheme) is treated as
+    # dry by the solves and reset to 0 by the cleanup after the sweep, with
+    # the reset counted; the result is still the reference solver's
+    L, PatchSolver, torch = gpu
+    pb = smooth_random_problem(40, 40, seed=2, coast=False)
+    pb.h = pb.h.copy()
+    pb.h[10, 10] = -0.5
+    pb.h[25, 31] = -1e-9
+    s = PatchSolver(pb, L.params())
+    s.run_forced([0.5])
+    torch.cuda.synchronize()
+    flags, clamps = s.flags()
+    g, q, b = oracle_setup(orc, pb)
+    r = orc.run(orc.params(), g, q, b, 1, dt_forced=[0.5])
+    assert flags & L.STATUS_NEG_DEPTH and not flags & L.STATUS_NONFINITE
+    assert clamps == r["clamps"] >= 1
+    compare(s.state(), interior(q))
+    assert s.state()[0].min() >= 0.0
+
+
 def test_cfl_exceeded_is_flagged_and_retaken(gpu, orc):
     L, PatchSolver, torch = gpu
     pb = W.gaussian_hump(40, 5000.0)
