@@ -44,7 +44,10 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also time the AMR patch set")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the coupled AMR hierarchy (the 3000-patch AMR set is timed "
+                         "by default)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 3000-patch AMR set")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--traffic", type=str, default=None,
                     help="counter record (key = value) with the step kernel's HBM bytes per launch")
@@ -62,8 +65,9 @@ def parse():
     ap.add_argument("--serve", type=int, default=0,
                     help="only run the serving stream with this many requests")
     ap.add_argument("--serve-steps", type=int, default=1000)
-    ap.add_argument("--serve-requests", type=int, default=36,
-                    help="requests in the serving run of the default bench")
+    ap.add_argument("--serve-requests", type=int, default=1200,
+                    help="requests in the serving run of the default bench (the first sixth "
+                         "are warm-up)")
     ap.add_argument("--no-serving", action="store_true")
     return ap.parse_args()
 
@@ -224,6 +228,70 @@ def measured_valu(kernel_ms: float, path: str | None = None):
             "lane_ops_per_s": lane_ops, "peak_lane_ops_per_s": VALU_PEAK_LANE_OPS,
             "frac": lane_ops / VALU_PEAK_LANE_OPS,
             "lane_ops_per_cell_update": 64.0 * insts / (4096.0 * 4096.0)}
+
+
+OPCOUNT_SHELF = os.path.join(ROOT, "profiles", "oracle_opcount_shelf4096.txt")
+OPCOUNT_ACTIVE = os.path.join(ROOT, "profiles", "oracle_opcount_active4096.txt")
+# FP64 vector peak of the MI355X as published (256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz x 2, an FMA counted as two operations); the step is built without
+# contraction (every product and sum rounds as written, as in the reference
+# solver), so its ceiling is half of this: one operation per lane per clock
+FP64_PEAK_TFLOPS = 78.6
+FP64_NO_FMA_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def _record(path: str) -> dict:
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                if "=" in line and not line.lstrip().startswith("#"):
+                    k, v = line.split("=", 1)
+                    rec[k.strip()] = v.strip()
+    return rec
+
+
+def alu_roofline(kernel_ms: float, record: str, cells: int):
+    """Algorithmic FP64 operations of the step (the oracle's count per cell
+    update on this workload times the cells) over the launch time."""
+    rec = _record(record)
+    if "flops_per_cell_update" not in rec:
+        return None
+    per = float(rec["flops_per_cell_update"])
+    tf = per * cells / (kernel_ms * 1e-3) / 1e12
+    return {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_PEAK_TFLOPS, "frac_of_no_fma_peak": tf / FP64_NO_FMA_TFLOPS,
+            "flops_per_cell_update": per,
+            "div_per_cell_update": float(rec.get("div_per_cell_update", "nan")),
+            "sqrt_per_cell_update": float(rec.get("sqrt_per_cell_update", "nan")),
+            "record": os.path.relpath(record, ROOT)}
+
+
+def roofline(r64: dict, traffic, valu_path, opcount: str, cells: int) -> dict:
+    """Roofline of the headline kernel.  Both bounds are computed: HBM
+    (algorithmic bytes per launch over the launch time, against 8 TB/s) and
+    ALU (algorithmic FP64 operations per launch, against the FP64 vector
+    peak); `bound` names the one the SQ counters say binds: VALU busy time
+    above the HBM fraction means the instruction stream, not memory, sets the
+    time."""
+    kms = r64["kernel_ms_avg"]
+    hbm = {"achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r64["alg_bytes"],
+           "traffic": traffic,
+           "traffic_gbs": traffic / (kms * 1e-3) / 1e9 if traffic else None}
+    alu = alu_roofline(kms, opcount, cells)
+    valu = measured_valu(kms, valu_path)
+    busy = valu["frac"] if valu else None
+    bound = "alu" if (alu is not None and busy is not None and busy > hbm["frac"]) else "hbm"
+    top = alu if bound == "alu" else hbm
+    return {"bound": bound, "achieved": top["achieved"], "peak": top["peak"],
+            "unit": top["unit"], "frac": top["frac"], "traffic": traffic,
+            "kernel": "swe::k_split<false, false>", "kernel_ms_avg": kms,
+            "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
+            "valu_busy_frac": busy, "hbm": hbm, "alu": alu,
+            "why": "VALU busy fraction (SQ counters) above the HBM fraction: the kernel is "
+                   "bound by its instruction stream" if bound == "alu" else
+                   "no current VALU record, or memory is the larger fraction"}
 
 
 def edge_stats(h, hu, hv, b, drytol: float = 1e-3, h_fp64: float = 1.0, lanes: int = 64,
@@ -437,7 +505,55 @@ def time_batched(precision: int, steps: int = 10):
     nbytes = BYTES_PER_CELL[precision] * upd
     return {"patches": len(probs), "cell_updates_per_coarse_step": upd,
             "ms_per_coarse_step": ms, "cups": upd / (ms * 1e-3),
-            "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9, "flags": bs.flags()[0], "autotune": tuned}
+            "hbm_gbs_alg": nbytes / (ms * 1e-3) / 1e9,
+            "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "flags": bs.flags()[0], "autotune": tuned,
+            "workload": "AMR patch set: 3000 patches (200/800/2000 on levels 1-3, sides "
+                        "U{16..96}, seed 3), ratios 4 and 4, 1/4/16 substeps per coarse step, "
+                        "one persistent launch per coarse step, graph replay"}
+
+
+def batched_precision(coarse_steps: int = 10) -> dict:
+    """Surface error of the batched FP32 surface-deviation step against the
+    batched FP64 step on the AMR patch set (3000 patches, three levels,
+    1/4/16 substeps), both with the FP64 run's step sizes; max over cells wet
+    (h > 1e-2 m) in both runs."""
+    import torch
+
+    from paper_1901_06798_amd import _lib as L
+    from paper_1901_06798_amd import workloads as W
+    from paper_1901_06798_amd.batched import BatchedSolver
+
+    specs, probs = W.amr_patch_set()
+    trefs = [s.tref for s in specs]
+    b64 = BatchedSolver(probs, L.params(), trefs=trefs)
+    b32 = BatchedSolver(probs, L.params(precision=L.F32_DEV), trefs=trefs)
+    b64.initial_dt()
+    dts = torch.zeros(coarse_steps, dtype=torch.float64, device=b64.dev)
+    for k in range(coarse_steps):
+        dts[k].copy_(b64.dt[0])
+        b64.enqueue_step(retake=False)
+        b32.enqueue_step(cfl=False, dt_ptr=dts.data_ptr() + 8 * k)
+        b32.smax.zero_()
+    torch.cuda.synchronize()
+    worst, worst_deep, wet_cells, moved = 0.0, 0.0, 0, 0.0
+    for k in range(len(probs)):
+        h64 = b64.state(k)[0]
+        h32 = b32.state(k)[0]
+        e64, e32 = b64.surface(k), b32.surface(k)
+        both = (h64 > 1e-2) & (h32 > 1e-2)
+        if both.any():
+            d = np.abs(e32 - e64)[both]
+            worst = max(worst, float(d.max()))
+            deep = both & (h64 > 10.0)
+            if deep.any():
+                worst_deep = max(worst_deep, float(np.abs(e32 - e64)[deep].max()))
+            wet_cells += int(both.sum())
+            moved = max(moved, float(np.abs(e64[both] - (probs[k].h + probs[k].b)[both]).max()))
+    return {"coarse_steps": coarse_steps, "max_surface_err_m": worst,
+            "max_err_deep_m": worst_deep, "bar_m": 1e-5, "within_bar": worst <= 1e-5,
+            "wet_cells_compared": wet_cells, "largest_surface_change_m": moved,
+            "flags_fp64": b64.flags(), "flags_fp32": b32.flags()}
 
 
 def time_amr(ncoarse: int = 10, dt1: float = 8.0, precision: int = 0):
@@ -596,38 +712,51 @@ def precision_study(n: int = 2048, steps: int = 2000, every: int = 250):
 
 def serving(nreq: int, warmup: int, steps: int, rate: float = 20.0, budget_gb: float = 200.0,
             max_slots: int = 64, steps_per_round: int = 50):
-    """Poisson stream of scenario requests served with continuous batching."""
+    """Poisson stream of scenario requests served with continuous batching;
+    each request arrives as its seeded parameters and its grid is built on the
+    device at admission."""
     from paper_1901_06798_amd import _lib as L
     from paper_1901_06798_amd import workloads as W
     from paper_1901_06798_amd.serve import Scenario, ScenarioServer
 
     stream = W.request_stream(count=nreq, rate=rate, nsteps=steps)
-    log(f"[bench] serving: generating {nreq} scenarios")
-    reqs = [Scenario(k, t, W.scenario(k, n=n, nsteps=steps), steps) for k, t, n in stream]
+    reqs = [Scenario(k, t, None, steps, spec=W.scenario_spec(k, n=n, nsteps=steps))
+            for k, t, n in stream]
     srv = ScenarioServer(L.params(precision=L.F32_DEV), hbm_budget=int(budget_gb * (1 << 30)),
                          max_slots=max_slots, steps_per_round=steps_per_round)
     # warm the kernels outside the measured stream
-    srv.serve([Scenario(-1, 0.0, W.scenario(0, n=256, nsteps=50), 50)], label="serve warm-up")
+    srv.serve([Scenario(-1, 0.0, None, 50, spec=W.scenario_spec(0, n=256, nsteps=50))],
+              label="serve warm-up")
     log(f"[bench] serving: {nreq} requests at {rate}/s, budget {budget_gb} GB")
     out = srv.serve(reqs, warmup=warmup, label=f"serve {budget_gb:g} GB")
     done = out.pop("done")
+    out.pop("rejected")
+    out.pop("cancelled")
     waits = [sc.admitted - sc.arrival for sc in done if sc.rid >= warmup]
+    lat = np.array([sc.finished - sc.arrival for sc in done if sc.rid >= warmup])
     out.update({"rate_per_s": rate, "steps_per_request": steps, "warmup_requests": warmup,
                 "hbm_budget_gb": budget_gb, "max_slots": max_slots,
                 "steps_per_round": steps_per_round,
+                "p90_ms": float(np.percentile(lat, 90) * 1e3) if lat.size else None,
+                "max_ms": float(lat.max() * 1e3) if lat.size else None,
                 "max_queue_wait_ms": float(max(waits) * 1e3) if waits else None,
+                "demand_cell_updates_per_s": rate * steps * float(np.mean(
+                    [n * n for _, _, n in stream])),
+                "flagged_requests": int(sum(1 for sc in done if sc.result.get("status", 0))),
                 "sizes": "n ~ U{256..2048}, dx 500 m", "precision": "fp32_dev",
-                "sample": f"first {nreq} requests of the Poisson stream (seed 5)"})
+                "sample": f"{nreq} requests of the Poisson stream (seed 5), the first "
+                          f"{warmup} not measured"})
     return out
 
 
-def serving_pair(nreq: int, steps: int) -> dict:
-    """The stream with a large HBM budget, then the first part of it with a
-    budget of about four of the largest grids, which makes requests queue."""
+def serving_pair(nreq: int, steps: int, warmup: int | None = None, small: int = 60) -> dict:
+    """The stream with a large HBM budget, then its first `small` requests
+    with a budget of about four of the largest grids, which makes requests
+    queue for memory."""
     import torch
-    out = {"budget_200gb": serving(nreq, max(1, nreq // 6), steps)}
+    out = {"budget_200gb": serving(nreq, nreq // 6 if warmup is None else warmup, steps)}
     torch.cuda.empty_cache()
-    small = max(6, nreq // 3)
+    small = min(small, nreq)
     out["budget_0.5gb"] = serving(small, max(1, small // 6), steps, budget_gb=0.5)
     return out
 
@@ -678,7 +807,7 @@ def main():
     log("[bench] plain device copy (sanity line)")
     copy_line = copy_sanity()
     out = {
-        "metric": "cell-updates/s (FP64 split step, 4096^2 shelf)",
+        "metric": "cell-updates/s + HBM GB/s, FP64 plain vs batched FP32 at \u22641e-5 m error; p99",
         "value": r64["cups"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -692,15 +821,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"shelf_{n}x{n}_dx{pb.dx:g}_fp64_split", "grid": [n, n],
                    "boundary": "extrapolation", "cfl": 0.9, "limiter": "MC"},
-        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r64["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "traffic_gbs": (traffic / (r64["kernel_ms_avg"] * 1e-3) / 1e9
-                                     if traffic else None),
-                     "kernel": "swe::k_split<false, false>",
-                     "kernel_ms_avg": r64["kernel_ms_avg"],
-                     "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
-                     "alg_bytes_per_launch": r64["alg_bytes"]},
+        "roofline": roofline(r64, traffic, args.valu, OPCOUNT_SHELF, n * n),
         "hbm_gbs_alg_step": r64["alg_bytes"] / (r64["ms_per_step"] * 1e-3) / 1e9,
         "copy_sanity": copy_line,
         "status_flags": r64["flags"],
@@ -709,6 +830,19 @@ def main():
     valu = measured_valu(r64["kernel_ms_avg"], args.valu)
     if valu:
         out["valu"] = valu
+    log("[bench] FP64 split step on a sea with no quiet edge")
+    torch.cuda.empty_cache()
+    pa = W.active_sea(n=n, dx=250.0 * 4096 / n)
+    ra = time_patch(pa, L.params(), min(args.steps, 200), args.warmup)
+    ra.pop("solver")
+    out["fully_active_fp64"] = {
+        "workload": f"active_sea_{n}x{n}: flat -4000 m, every cell wet, seeded noise in the "
+                    "surface and both velocities, so no edge is quiet",
+        "cups": ra["cups"], "ms_per_step": ra["ms_per_step"], "kernel_ms_avg": ra["kernel_ms_avg"],
+        "achieved_gbs": ra["achieved_gbs"], "hbm_frac": ra["achieved_gbs"] / HBM_PEAK_GBS,
+        "flags": ra["flags"],
+        "alu": alu_roofline(ra["kernel_ms_avg"], OPCOUNT_ACTIVE, n * n)}
+    del pa
     st64 = r64["solver"].state()
     out["edges_at_end"] = edge_stats(*st64, pb.b)
     if not args.no_variants:
@@ -764,10 +898,17 @@ def main():
             "frac": rs["achieved_gbs"] / HBM_PEAK_GBS, "flags": rs["flags"],
             "kernel": "swe::k_split_sphere<false>"}
         del ps
-        if args.batched:
+        if not args.no_batched:
             for prec, name in ((0, "batched_amr_fp64"), (1, "batched_amr_fp32_dev")):
                 log(f"[bench] {name}")
+                torch.cuda.empty_cache()
                 out["variants"][name] = time_batched(prec)
+            b64v, b32v = out["variants"]["batched_amr_fp64"], out["variants"]["batched_amr_fp32_dev"]
+            b32v["speedup_vs_fp64_batched"] = b32v["cups"] / b64v["cups"]
+            log("[bench] batched FP32 vs FP64 surface error (AMR patch set, 10 coarse steps)")
+            torch.cuda.empty_cache()
+            b32v["surface_error_vs_fp64"] = batched_precision()
+        if args.batched:
             log("[bench] coupled AMR hierarchy (three levels, FP64)")
             torch.cuda.empty_cache()
             out["variants"]["amr_coupled_fp64"] = time_amr()

@@ -278,21 +278,27 @@ int swe_mass(const swe_params *p, const swe_patch *patches, int32_t n, const voi
 /* State in the precision's planes from FP64 data (the layout of Sec. 4's
  * structure-of-arrays pool; the surface-deviation form is this library's
  * FP32 storage, eta' = h + b - sea_level).  For the interior cells of n
- * patches (device table `patches`): src holds FP64 planes (h, hu, hv) with
- * the same element offsets, pitch and plane stride as q, src_b the FP64 bed
- * with the offsets of b.  SWE_F64 copies them; SWE_F32_DEV stores
- * eta' = (h > 0 ? h + b : b) - sea_level, formed in FP64 and rounded once,
- * and hu, hv, b rounded to FP32.  Ghost cells are not written (fill them
- * with swe_ghost_fill).  max_mx/max_my bound the patch sizes. */
+ * patches (device table `patches`): element e = off + j * pitch + i of plane
+ * k of q takes src[e - src_shift + k * S] (S = src_stride, or the patch's
+ * plane_stride when src_stride is 0) and element e of b takes
+ * src_b[e - src_shift]: with src_shift = 0 and src_stride = 0, src has q's
+ * layout; a caller staging one patch alone passes src_shift = the patch's
+ * off and src_stride = its staged plane length.  SWE_F64 copies them;
+ * SWE_F32_DEV and SWE_F32_STORE store eta' = (h > 0 ? h + b : b) - sea_level,
+ * formed in FP64 and rounded once, and hu, hv, b rounded to FP32.  Ghost
+ * cells are not written (fill them with swe_ghost_fill).  max_mx/max_my
+ * bound the patch sizes. */
 int swe_state_import(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
-                     int32_t max_my, const double *src, const double *src_b, void *q, void *b,
-                     void *stream);
+                     int32_t max_my, const double *src, const double *src_b, int64_t src_shift,
+                     int64_t src_stride, void *q, void *b, void *stream);
 
 /* The inverse for reading results: interior (h, hu, hv) of n patches into
- * FP64 planes dst (layout as in swe_state_import); SWE_F32_DEV gives
- * h = max(eta' + sea_level - b, 0) in FP64. */
+ * FP64 planes dst (element e of plane k at dst[e - dst_shift + k * S], S as
+ * in swe_state_import); the FP32 planes give h = max(eta' + sea_level - b, 0)
+ * in FP64. */
 int swe_state_export(const swe_params *p, const swe_patch *patches, int32_t n, int32_t max_mx,
-                     int32_t max_my, const void *q, const void *b, double *dst, void *stream);
+                     int32_t max_my, const void *q, const void *b, double *dst, int64_t dst_shift,
+                     int64_t dst_stride, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched step: many patches (e.g. the patches of an AMR hierarchy, or the
@@ -361,6 +367,11 @@ int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sc
  * patches, items, tasks: device copies of the table and of the plan; plain:
  * device pointer to the plan's nplain plain tasks (tasks + ntasks - nplain),
  * nsub: the plan's launch count for them.
+ * group_status: NULL, or device uint32_t[2 x groups]: the status conditions
+ * and depth resets of the patches of group g are also OR-ed into
+ * group_status[2 g] and added to group_status[2 g + 1] (a caller serving
+ * independent requests, one group each, learns which request they belong
+ * to).
  * queue: device uint32_t[2], zero before the first call; the launch leaves it
  * zero again.  sched: host, the schedule the plan was built with. */
 int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_item *items,
@@ -368,8 +379,8 @@ int swe_batched_step(const swe_params *p, const swe_patch *patches, const swe_it
                      int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
                      void *pool_work, int64_t pool_elems,
                      const void *pool_b, const double *dt_group, double *smax_patch,
-                     uint32_t *status, uint32_t *queue, const swe_schedule *sched,
-                     void *stream);
+                     uint32_t *status, uint32_t *group_status, uint32_t *queue,
+                     const swe_schedule *sched, void *stream);
 
 /* Retake on the device for the batched step: redoes, from pool_in to
  * pool_out, the items of the patches whose group g has retake[g] != 0 (as
@@ -382,8 +393,9 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
                        int32_t nplain, int32_t nsub, const void *pool_in, void *pool_out,
                        void *pool_work, int64_t pool_elems,
                        const void *pool_b, const double *dt_group, double *smax_patch,
-                       uint32_t *status, uint32_t *queue, const swe_schedule *sched,
-                       const uint32_t *retake, int32_t ngroups, void *stream);
+                       uint32_t *status, uint32_t *group_status, uint32_t *queue,
+                       const swe_schedule *sched, const uint32_t *retake, int32_t ngroups,
+                       void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -405,7 +417,8 @@ int swe_batched_step_static(const swe_params *p, const swe_patch *patches,
                             const swe_task *plain, int32_t nplain, int32_t nsub,
                             const void *pool_in, void *pool_out, int64_t pool_elems,
                             const void *pool_b, const double *dt_group, double *smax_patch,
-                            uint32_t *status, const swe_schedule *sched, void *stream);
+                            uint32_t *status, uint32_t *group_status,
+                            const swe_schedule *sched, void *stream);
 
 /* ------------------------------------------------------------------------
  * Coupling of AMR levels (Sec. 3: a finer level's ghost cells come from an

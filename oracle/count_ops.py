@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE: writes a record that the benchmark reads for the
 arithmetic side of its roofline (operations per cell update times the cell
 updates of a launch, over the launch time).  The state counted is the 4096^2
 shelf workload advanced `--steps` steps by the plain oracle (the middle of
-the benchmark's timed steps); one more step is then taken by the counting
-build.  Counts cover everything the step computes for the patch (the x-sweep
+the benchmark's timed steps), or the sea with no quiet edge; one more step
+is then taken by the counting build.  Counts cover everything the step computes for the patch (the x-sweep
 of the ghost rows and the edges the limiter reads included) and are divided
 by the interior cells.
 
@@ -24,11 +24,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def count(n: int = 4096, steps: int = 260, order: int = 2):
+def count(n: int = 4096, steps: int = 260, order: int = 2, workload: str = "shelf"):
     import oracle as O
     from paper_1901_06798_amd import workloads as W
 
-    pb = W.shelf_4096(n=n, dx=250.0 * 4096 / n)
+    pb = (W.shelf_4096(n=n, dx=250.0 * 4096 / n) if workload == "shelf"
+          else W.active_sea(n=n, dx=250.0 * 4096 / n))
     P = O.params(order=order)
     q, b = O.new_state(pb.h, pb.hu, pb.hv, pb.b)
     g = O.grid(pb.mx, pb.my, pb.dx, pb.dy, pb.bc)
@@ -53,12 +54,16 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--steps", type=int, default=260)
     ap.add_argument("--out", type=str, default=None)
+    ap.add_argument("--workload", choices=("shelf", "active"), default="shelf")
     a = ap.parse_args()
-    res = count(a.n, a.steps)
+    res = count(a.n, a.steps, workload=a.workload)
     per = res["per_cell_update"]
-    lines = [f"# FP64 split step, {a.n}^2 shelf after {a.steps} steps: operations per interior "
+    what = (f"{a.n}^2 shelf" if a.workload == "shelf" else
+            f"{a.n}^2 sea with no quiet edge (workloads.active_sea)")
+    lines = [f"# FP64 split step, {what} after {a.steps} steps: operations per interior "
              f"cell update counted by the oracle's counting build (oracle/opcount.cpp)",
-             f"# command: python -m oracle.count_ops --n {a.n} --steps {a.steps} --out <this file>",
+             f"# command: python -m oracle.count_ops --n {a.n} --steps {a.steps} "
+             f"--workload {a.workload} --out <this file>",
              f"cells = {res['cells']}"]
     for k in ("add", "mul", "div", "sqrt", "cmp", "other", "flops"):
         lines.append(f"{k}_per_cell_update = {per[k]:.4f}")

@@ -123,8 +123,8 @@ def lib():
         L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, i64, pl, _P]
         L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
                                             _P, _P, _P, i64, pl, _P]
-        L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P, _P]
-        L.swe_state_export.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, _P]
+        L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, i64, i64, _P, _P, _P]
+        L.swe_state_export.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, i64, i64, _P]
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
         L.swe_amr_average.argtypes = [pp, _P, i64, i32, _P, i64, _P, _P, i64, _P, _P]
         L.swe_amr_flag.argtypes = [pp, _P, i32, i32, i32, _P, _P, dbl, i32, i32, _P, _P]
@@ -135,11 +135,11 @@ def lib():
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
         L.swe_batched_step.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64, _P,
-                                       _P, _P, _P, _P, ps, _P]
+                                       _P, _P, _P, _P, _P, ps, _P]
         L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64,
-                                         _P, _P, _P, _P, _P, ps, _P, i32, _P]
+                                         _P, _P, _P, _P, _P, _P, ps, _P, i32, _P]
         L.swe_batched_step_static.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, i64,
-                                              _P, _P, _P, _P, ps, _P]
+                                              _P, _P, _P, _P, _P, ps, _P]
         L.swe_last_error.restype = ctypes.c_char_p
         L.swe_version.restype = ctypes.c_char_p
         for name in ("swe_patch_step", "swe_ghost_fill", "swe_speed_scan", "swe_cfl_reduce",
@@ -208,15 +208,17 @@ def swe_patch_order(pt: swe_patch, sched: int, sched_len: int,
 
 
 def swe_state_import(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, src: int,
-                     src_b: int, q: int, b: int, stream: int = 0) -> None:
-    _check(lib().swe_state_import(ctypes.byref(p), patches, n, max_mx, max_my, src, src_b, q, b,
-                                  stream), "swe_state_import")
+                     src_b: int, q: int, b: int, stream: int = 0, src_shift: int = 0,
+                     src_stride: int = 0) -> None:
+    _check(lib().swe_state_import(ctypes.byref(p), patches, n, max_mx, max_my, src, src_b,
+                                  src_shift, src_stride, q, b, stream), "swe_state_import")
 
 
 def swe_state_export(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,
-                     b: int, dst: int, stream: int = 0) -> None:
+                     b: int, dst: int, stream: int = 0, dst_shift: int = 0,
+                     dst_stride: int = 0) -> None:
     _check(lib().swe_state_export(ctypes.byref(p), patches, n, max_mx, max_my, q, b, dst,
-                                  stream), "swe_state_export")
+                                  dst_shift, dst_stride, stream), "swe_state_export")
 
 
 def swe_amr_fill(p: swe_params, ops: int, nops: int, q_fine: int, fine_plane_stride: int,
@@ -337,11 +339,11 @@ def swe_batched_step(p: swe_params, patches: int, items: int, nitems: int, tasks
                      plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
                      pool_work: int, pool_elems: int, pool_b: int, dt_group: int,
                      smax_patch: int, status: int, queue: int, sched: swe_schedule,
-                     stream: int = 0) -> None:
+                     stream: int = 0, group_status: int = 0) -> None:
     _check(lib().swe_batched_step(ctypes.byref(p), patches, items, nitems, tasks, plain, nplain,
                                   nsub, pool_in, pool_out, pool_work, pool_elems, pool_b,
-                                  dt_group, smax_patch, status, queue, ctypes.byref(sched),
-                                  stream), "swe_batched_step")
+                                  dt_group, smax_patch, status, group_status, queue,
+                                  ctypes.byref(sched), stream), "swe_batched_step")
 
 
 SWE_STATIC_WORK_BYTES = 32 * 1024 * 1024
@@ -350,20 +352,22 @@ SWE_STATIC_WORK_BYTES = 32 * 1024 * 1024
 def swe_batched_step_static(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
                             plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
                             pool_elems: int, pool_b: int, dt_group: int, smax_patch: int,
-                            status: int, sched: swe_schedule, stream: int = 0) -> None:
+                            status: int, sched: swe_schedule, stream: int = 0,
+                            group_status: int = 0) -> None:
     _check(lib().swe_batched_step_static(ctypes.byref(p), patches, items, nitems, tasks, plain,
                                          nplain, nsub, pool_in, pool_out, pool_elems, pool_b,
-                                         dt_group, smax_patch, status, ctypes.byref(sched),
-                                         stream), "swe_batched_step_static")
+                                         dt_group, smax_patch, status, group_status,
+                                         ctypes.byref(sched), stream), "swe_batched_step_static")
 
 
 def swe_batched_retake(p: swe_params, patches: int, items: int, nitems: int, tasks: int,
                        plain: int, nplain: int, nsub: int, pool_in: int, pool_out: int,
                        pool_work: int, pool_elems: int, pool_b: int, dt_group: int,
                        smax_patch: int, status: int, queue: int, sched: swe_schedule,
-                       retake: int, ngroups: int, stream: int = 0) -> None:
+                       retake: int, ngroups: int, stream: int = 0,
+                       group_status: int = 0) -> None:
     _check(lib().swe_batched_retake(ctypes.byref(p), patches, items, nitems, tasks, plain,
                                     nplain, nsub, pool_in, pool_out, pool_work, pool_elems,
-                                    pool_b, dt_group, smax_patch, status, queue,
+                                    pool_b, dt_group, smax_patch, status, group_status, queue,
                                     ctypes.byref(sched), retake, ngroups, stream),
            "swe_batched_retake")

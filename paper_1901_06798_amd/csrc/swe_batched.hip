@@ -40,6 +40,7 @@ struct BatchArgs {
     const double* dt_group;
     double* smax;
     uint32_t* status;
+    uint32_t* group_status;  // per group (flags, clamps) pairs; NULL: not kept
     uint32_t* queue;  // [0] next item, [1] finished workgroups
     int nitems;
     DevParams P;
@@ -144,6 +145,8 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
         }
         if (clamps) atomicAdd(&a.status[1], clamps);
         if (flags) atomicOr(&a.status[0], flags);
+        if (a.group_status && clamps) atomicAdd(&a.group_status[2 * pt.group + 1], clamps);
+        if (a.group_status && flags) atomicOr(&a.group_status[2 * pt.group], flags);
     }
     // the last workgroup to finish rewinds the queue for the next launch
     if (threadIdx.x == 0) {
@@ -219,6 +222,8 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
     }
     if (r.clamps) atomicAdd(&a.status[1], r.clamps);
     if (r.flags) atomicOr(&a.status[0], r.flags);
+    if (a.group_status && run && r.clamps) atomicAdd(&a.group_status[2 * pt.group + 1], r.clamps);
+    if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
 }
 
 template __global__ void k_batched<false, 64, false>(BatchArgs);
@@ -421,8 +426,8 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
                         void* pool_work, int64_t pool_elems,
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
-                        const uint32_t* retake, int32_t ngroups, void* stream,
-                        bool zero_queue = false) {
+                        const uint32_t* retake, int32_t ngroups, uint32_t* group_status,
+                        void* stream, bool zero_queue = false) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -463,6 +468,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.dt_group = dt_group;
     a.smax = smax_patch;
     a.status = status;
+    a.group_status = group_status;
     a.queue = queue;
     a.nitems = nitems;
     a.P.g = p->g;
@@ -539,10 +545,11 @@ int swe_batched_step(const swe_params* p, const swe_patch* patches, const swe_it
                      int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
                      void* pool_work, int64_t pool_elems, const void* pool_b,
                      const double* dt_group, double* smax_patch, uint32_t* status,
-                     uint32_t* queue, const swe_schedule* sched, void* stream) {
+                     uint32_t* group_status, uint32_t* queue, const swe_schedule* sched,
+                     void* stream) {
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
                         pool_out, pool_work, pool_elems, pool_b, dt_group, smax_patch, status,
-                        queue, sched, nullptr, 0, stream);
+                        queue, sched, nullptr, 0, group_status, stream);
 }
 
 int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
@@ -550,7 +557,8 @@ int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
                             const swe_task* plain, int32_t nplain, int32_t nsub,
                             const void* pool_in, void* pool_out, int64_t pool_elems,
                             const void* pool_b, const double* dt_group, double* smax_patch,
-                            uint32_t* status, const swe_schedule* sched, void* stream) {
+                            uint32_t* status, uint32_t* group_status,
+                            const swe_schedule* sched, void* stream) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
         return bfail(SWE_EINVAL, "swe_batched_step_static: precision must be SWE_F64 or SWE_F32_DEV");
@@ -570,7 +578,7 @@ int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
     void* pwork = static_cast<unsigned char*>(base) + kStaticQueueBytes;
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in, pool_out,
                         work ? pwork : nullptr, pool_elems, pool_b, dt_group, smax_patch, status,
-                        queue, sched, nullptr, 0, stream, true);
+                        queue, sched, nullptr, 0, group_status, stream, true);
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,
@@ -578,13 +586,13 @@ int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_
                        int32_t nplain, int32_t nsub, const void* pool_in, void* pool_out,
                        void* pool_work, int64_t pool_elems, const void* pool_b,
                        const double* dt_group, double* smax_patch, uint32_t* status,
-                       uint32_t* queue, const swe_schedule* sched, const uint32_t* retake,
-                       int32_t ngroups, void* stream) {
+                       uint32_t* group_status, uint32_t* queue, const swe_schedule* sched,
+                       const uint32_t* retake, int32_t ngroups, void* stream) {
     if (!retake || ngroups < 1)
         return bfail(SWE_EINVAL, "swe_batched_retake: null retake flags or ngroups < 1");
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in,
                         pool_out, pool_work, pool_elems, pool_b, dt_group, smax_patch, status,
-                        queue, sched, retake, ngroups, stream);
+                        queue, sched, retake, ngroups, group_status, stream);
 }
 
 }  // extern "C"

@@ -509,19 +509,22 @@ template <bool DEV>
 __global__ void __launch_bounds__(256) k_state_import(const swe_patch* __restrict__ patches,
                                                       const double* __restrict__ src,
                                                       const double* __restrict__ src_b,
-                                                      void* qv, void* bv, double sea_level) {
+                                                      int64_t shift, int64_t stride, void* qv,
+                                                      void* bv, double sea_level) {
     using S = typename Prec<DEV>::S;
     S* __restrict__ q = static_cast<S*>(qv);
     S* __restrict__ b = static_cast<S*>(bv);
     const swe_patch p = patches[blockIdx.y];
+    const int64_t ss = stride ? stride : p.plane_stride;
     const int64_t ncell = (int64_t)p.mx * p.my;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = p.off + (2 + k / p.mx) * (int64_t)p.pitch + 2 + k % p.mx;
-        const double h = src[i], bed = src_b[i];
+        const int64_t j = i - shift;
+        const double h = src[j], bed = src_b[j];
         q[i] = DEV ? S((h > 0.0 ? h + bed : bed) - sea_level) : S(h);
-        q[i + p.plane_stride] = S(src[i + p.plane_stride]);
-        q[i + 2 * p.plane_stride] = S(src[i + 2 * p.plane_stride]);
+        q[i + p.plane_stride] = S(src[j + ss]);
+        q[i + 2 * p.plane_stride] = S(src[j + 2 * ss]);
         b[i] = S(bed);
     }
 }
@@ -530,20 +533,22 @@ __global__ void __launch_bounds__(256) k_state_import(const swe_patch* __restric
 template <bool DEV>
 __global__ void __launch_bounds__(256) k_state_export(const swe_patch* __restrict__ patches,
                                                       const void* qv, const void* bv,
-                                                      double* __restrict__ dst,
-                                                      double sea_level) {
+                                                      double* __restrict__ dst, int64_t shift,
+                                                      int64_t stride, double sea_level) {
     using S = typename Prec<DEV>::S;
     const S* __restrict__ q = static_cast<const S*>(qv);
     const S* __restrict__ b = static_cast<const S*>(bv);
     const swe_patch p = patches[blockIdx.y];
+    const int64_t ds = stride ? stride : p.plane_stride;
     const int64_t ncell = (int64_t)p.mx * p.my;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = p.off + (2 + k / p.mx) * (int64_t)p.pitch + 2 + k % p.mx;
+        const int64_t j = i - shift;
         const double h = DEV ? fmax((double(q[i]) + sea_level) - double(b[i]), 0.0) : double(q[i]);
-        dst[i] = h;
-        dst[i + p.plane_stride] = double(q[i + p.plane_stride]);
-        dst[i + 2 * p.plane_stride] = double(q[i + 2 * p.plane_stride]);
+        dst[j] = h;
+        dst[j + ds] = double(q[i + p.plane_stride]);
+        dst[j + 2 * ds] = double(q[i + 2 * p.plane_stride]);
     }
 }
 
@@ -905,41 +910,44 @@ static int state_grid(int32_t n, int32_t max_mx, int32_t max_my, dim3* grid) {
 }
 
 int swe_state_import(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
-                     int32_t max_my, const double* src, const double* src_b, void* q, void* b,
-                     void* stream) {
+                     int32_t max_my, const double* src, const double* src_b, int64_t src_shift,
+                     int64_t src_stride, void* q, void* b, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if (!patches || !src || !src_b || !q || !b)
         return fail(SWE_EINVAL, "swe_state_import: null pointer");
+    if (src_stride < 0) return fail(SWE_EINVAL, "swe_state_import: src_stride must be >= 0");
     dim3 grid;
     if ((rc = state_grid(n, max_mx, max_my, &grid))) return rc;
     if (n == 0) return SWE_OK;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->precision == SWE_F64)
         hipLaunchKernelGGL(swe::k_state_import<false>, grid, dim3(256), 0, st, patches, src,
-                           src_b, q, b, p->sea_level);
+                           src_b, src_shift, src_stride, q, b, p->sea_level);
     else
         hipLaunchKernelGGL(swe::k_state_import<true>, grid, dim3(256), 0, st, patches, src,
-                           src_b, q, b, p->sea_level);
+                           src_b, src_shift, src_stride, q, b, p->sea_level);
     return check_launch("swe_state_import");
 }
 
 int swe_state_export(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
-                     int32_t max_my, const void* q, const void* b, double* dst, void* stream) {
+                     int32_t max_my, const void* q, const void* b, double* dst, int64_t dst_shift,
+                     int64_t dst_stride, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if (!patches || !q || !dst || (p->precision != SWE_F64 && !b))
         return fail(SWE_EINVAL, "swe_state_export: null pointer");
+    if (dst_stride < 0) return fail(SWE_EINVAL, "swe_state_export: dst_stride must be >= 0");
     dim3 grid;
     if ((rc = state_grid(n, max_mx, max_my, &grid))) return rc;
     if (n == 0) return SWE_OK;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->precision == SWE_F64)
         hipLaunchKernelGGL(swe::k_state_export<false>, grid, dim3(256), 0, st, patches, q, b, dst,
-                           p->sea_level);
+                           dst_shift, dst_stride, p->sea_level);
     else
         hipLaunchKernelGGL(swe::k_state_export<true>, grid, dim3(256), 0, st, patches, q, b, dst,
-                           p->sea_level);
+                           dst_shift, dst_stride, p->sea_level);
     return check_launch("swe_state_export");
 }
 

@@ -69,17 +69,27 @@ class PoolAllocator:
 
 @dataclass
 class Scenario:
+    """One request: its grid as host arrays (`problem`) or as seeded parameters
+    built on the device at admission (`spec`, a workloads.ScenarioSpec)."""
     rid: int
     arrival: float
-    problem: Problem
+    problem: Problem | None
     nsteps: int
+    spec: object = None
     slot: int = -1
     off: int = 0
     span: int = 0
     steps_done: int = 0
     admitted: float = 0.0
     finished: float = 0.0
+    state: str = "queued"  # queued, active, done, rejected, cancelled
+    reason: str = ""
     result: dict = field(default_factory=dict)
+
+    @property
+    def grid(self):
+        """Geometry (mx, my, dx, dy, bc) of the request."""
+        return self.problem if self.problem is not None else self.spec
 
 
 class PinnedPool:
@@ -127,6 +137,8 @@ class ScenarioServer:
         self.dt = torch.zeros(max_slots, dtype=torch.float64, device=self.dev)
         self.smax = torch.zeros(2 * max_slots, dtype=torch.float64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        # per scenario slot: (status bits, depth resets) of its own steps
+        self.gstatus = torch.zeros(2 * max_slots, dtype=torch.int32, device=self.dev)
         self.group_flags = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
         self.retake = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
         self.queue_ctr = torch.zeros(2, dtype=torch.int32, device=self.dev)
@@ -135,7 +147,9 @@ class ScenarioServer:
         self.free_slots = list(range(max_slots))
         self.table_dirty = True
         self.host_state = PinnedPool(self.dtype)
+        self.host_f64 = PinnedPool(torch.float64)
         self.host_bytes = PinnedPool(torch.uint8)
+        self.host_status = PinnedPool(torch.int32)
         self.hold: list = []  # pinned buffers read by copies not yet known to be done
 
     @property
@@ -150,54 +164,69 @@ class ScenarioServer:
         return st.to(self.dev, non_blocking=True)
 
     # -- footprint and admission ----------------------------------------------
-    def footprint_elems(self, pb: Problem) -> int:
+    def footprint_elems(self, pb) -> int:
         pitch = _round_up(pb.mx + 4, 16)
         return _round_up(pitch * (pb.my + 4), 64)
 
-    def footprint_bytes(self, pb: Problem) -> int:
+    def footprint_bytes(self, pb) -> int:
         return 7 * self.footprint_elems(pb) * self.esize
+
+    def budget_bytes(self) -> int:
+        return 7 * self.plane * self.esize
 
     def try_admit(self, sc: Scenario) -> bool:
         if not self.free_slots:
             return False
-        got = self.alloc.alloc(self.footprint_elems(sc.problem))
+        got = self.alloc.alloc(self.footprint_elems(sc.grid))
         if got is None:
             return False
         sc.off, sc.span = got
         sc.slot = self.free_slots.pop(0)
         self._upload(sc)
+        sc.state = "active"
         self.active.append(sc)
         self.table_dirty = True
         return True
 
     def _patch(self, sc: Scenario) -> L.swe_patch:
-        pb = sc.problem
+        pb = sc.grid
         return L.patch(pb.mx, pb.my, _round_up(pb.mx + 4, 16), pb.dx, pb.dy, off=sc.off,
                        plane_stride=self.plane, group=sc.slot, tref=1, bc=pb.bc)
 
     def _upload(self, sc: Scenario) -> None:
-        pb = sc.problem
+        """Initial state of an admitted scenario into its pool range: FP64
+        planes staged on the device (copied from pinned host arrays, or built
+        there from the scenario's parameters), converted into the pool's
+        precision by swe_state_import; then its first dt from a speed scan."""
+        pb = sc.grid
         pitch = _round_up(pb.mx + 4, 16)
         rows = pb.my + 4
         n = pitch * rows
-        stage = self.host_state.get(4 * n)
-        stage.zero_()
-        planes = stage.view(4, rows, pitch).numpy()
-        first = pb.h
-        if self.p.precision == L.F32_DEV:
-            first = np.where(pb.h > 0.0, pb.h + pb.b - self.p.sea_level, pb.b - self.p.sea_level)
         inner = (slice(2, pb.my + 2), slice(2, pb.mx + 2))
-        planes[0][inner] = first
-        planes[1][inner] = pb.hu
-        planes[2][inner] = pb.hv
-        planes[3][inner] = pb.b
-        self.hold.append((self.host_state, stage))
-        dst = self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n]
-        dst.copy_(stage[: 3 * n].view(3, n), non_blocking=True)
-        self.b[sc.off: sc.off + n].copy_(stage[3 * n: 4 * n], non_blocking=True)
+        dev = torch.zeros(4 * n, dtype=torch.float64, device=self.dev)
+        planes = dev.view(4, rows, pitch)
+        if sc.problem is not None:
+            stage = self.host_f64.get(4 * n)
+            stage.zero_()
+            hp = stage.view(4, rows, pitch).numpy()
+            hp[0][inner] = pb.h
+            hp[1][inner] = pb.hu
+            hp[2][inner] = pb.hv
+            hp[3][inner] = pb.b
+            self.hold.append((self.host_f64, stage))
+            dev.copy_(stage, non_blocking=True)
+        else:
+            h, b = sc.spec.device_state(self.dev)
+            planes[0][inner] = h
+            planes[3][inner] = b
+        one = self._patch(sc)
+        tab_one = self._to_device(patch_table([one]))
+        L.swe_state_import(self.p, tab_one.data_ptr(), 1, pb.mx, pb.my, dev.data_ptr(),
+                           dev.data_ptr() + 8 * 3 * n, self.pools[self.cur].data_ptr(),
+                           self.b.data_ptr(), self.stream, src_shift=sc.off, src_stride=n)
+        self.gstatus[2 * sc.slot: 2 * sc.slot + 2].zero_()
         # first dt of this scenario from a speed scan of its own grid: a one-patch
         # table whose patch is group 0 of a one-group reduction into dt[slot]
-        one = self._patch(sc)
         one.group = 0
         tab = self._to_device(patch_table([one]))
         self.smax[2 * sc.slot: 2 * sc.slot + 2].zero_()
@@ -219,37 +248,48 @@ class ScenarioServer:
         self.ntasks, self.nplain, self.nsub = plan.ntasks, plan.nplain, plan.nsub
         self.table_dirty = False
 
-    def _retire(self, sc: Scenario):
-        """Queue the copy of a finished scenario's surface and free its pool
-        range and slot; returns the pinned buffer the surface lands in."""
-        pb = sc.problem
-        pitch = _round_up(pb.mx + 4, 16)
-        n = pitch * (pb.my + 4)
-        q0 = self.pools[self.cur].view(3, self.plane)[0, sc.off: sc.off + n].view(pb.my + 4, pitch)
-        eta = q0[2:-2, 2: pb.mx + 2]
-        if self.p.precision != L.F32_DEV:
-            bb = self.b[sc.off: sc.off + n].view(pb.my + 4, pitch)[2:-2, 2: pb.mx + 2]
-            eta = eta + bb
-        out = self.host_state.get(pb.mx * pb.my)
-        out.view(pb.my, pb.mx).copy_(eta, non_blocking=True)
+    def _retire(self, sc: Scenario, keep_result: bool = True):
+        """Queue the copy of a finished scenario's surface and of its status
+        pair, and free its pool range and slot; returns what _finish needs.
+        keep_result False (a cancelled scenario) copies nothing."""
+        pb = sc.grid
+        out = st = None
+        if keep_result:
+            pitch = _round_up(pb.mx + 4, 16)
+            n = pitch * (pb.my + 4)
+            q0 = self.pools[self.cur].view(3, self.plane)[0, sc.off: sc.off + n].view(pb.my + 4,
+                                                                                     pitch)
+            eta = q0[2:-2, 2: pb.mx + 2]
+            if self.p.precision == L.F64:
+                bb = self.b[sc.off: sc.off + n].view(pb.my + 4, pitch)[2:-2, 2: pb.mx + 2]
+                eta = eta + bb
+            out = self.host_state.get(pb.mx * pb.my)
+            out.view(pb.my, pb.mx).copy_(eta, non_blocking=True)
+            st = self.host_status.get(2)
+            st.copy_(self.gstatus[2 * sc.slot: 2 * sc.slot + 2], non_blocking=True)
         self.alloc.release(sc.off, sc.span)
         self.free_slots.append(sc.slot)
         self.free_slots.sort()
         self.active.remove(sc)
         self.table_dirty = True
-        return sc, out
+        return sc, out, st
 
     def _finish(self, results, t0: float) -> list:
         done = []
-        for sc, out in results:
-            pb = sc.problem
-            eta = out.view(pb.my, pb.mx).numpy().astype(np.float64)
-            if self.p.precision == L.F32_DEV:
-                eta = eta + self.p.sea_level
-            # the early-warning product: the final surface
-            sc.result = {"eta": eta}
+        for sc, out, st in results:
             sc.finished = time.perf_counter() - t0
+            if out is None:  # cancelled while active
+                continue
+            pb = sc.grid
+            eta = out.view(pb.my, pb.mx).numpy().astype(np.float64)
+            if self.p.precision != L.F64:
+                eta = eta + self.p.sea_level
+            # the early-warning product: the final surface, and what the
+            # scenario's own steps reported (status bits, depth resets)
+            sc.result = {"eta": eta, "status": int(st[0]), "clamps": int(st[1])}
+            sc.state = "done"
             self.host_state.put(out)
+            self.host_status.put(st)
             done.append(sc)
         return done
 
@@ -274,14 +314,15 @@ class ScenarioServer:
                     self.pools[1 - self.cur].data_ptr(), 0, 3 * self.plane, self.b.data_ptr(),
                     self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
                     self.queue_ctr.data_ptr(), self.sched)
-            L.swe_batched_step(self.p, *args, self.stream)
+            gs = self.gstatus.data_ptr()
+            L.swe_batched_step(self.p, *args, self.stream, group_status=gs)
             # CFL rule per scenario; a step above cfl_max is redone once on the device
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
                              self.dt.data_ptr(), self.status.data_ptr(),
                              self.group_flags.data_ptr(), 0, self.stream,
                              retake=self.retake.data_ptr())
             L.swe_batched_retake(self.p, *args, self.retake.data_ptr(), self.max_slots,
-                                 self.stream)
+                                 self.stream, group_status=gs)
             L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
                              self.dt.data_ptr(), self.status.data_ptr(),
                              self.group_flags.data_ptr(), 0, self.stream)
@@ -289,23 +330,88 @@ class ScenarioServer:
         for sc in self.active:
             sc.steps_done += steps
 
-    def serve(self, requests, warmup: int = 0, log=None, label: str = "serve"):
+    def serve(self, requests, warmup: int = 0, log=None, label: str = "serve",
+              cancel: dict | None = None, stop_after_rounds: int | None = None,
+              resume: dict | None = None, cancel_after_rounds: dict | None = None):
         """Run the request stream.  requests: list of Scenario with arrival
-        times in seconds from the start.  Returns a summary dict.  The run is
-        one ROCTx range named `label`, its host work ranges named "host: ..."
-        (see timeline.py)."""
+        times in seconds from the start.  A request whose footprint exceeds
+        the whole budget is rejected on its own (state "rejected", with the
+        reason); cancel maps request ids to times (s from the start) at which
+        the request is withdrawn: dropped if still queued, its slot and memory
+        freed at the next round boundary if active (state "cancelled");
+        cancel_after_rounds does the same after a number of rounds.
+        stop_after_rounds: stop after that many rounds and return, under
+        "checkpoint", everything needed to continue (the active scenarios'
+        stored planes and step sizes, the queue, the requests not yet
+        arrived); resume: such a checkpoint, continued in this server (its
+        pool offsets and slots may differ: results do not depend on them).
+        Returns a summary dict.  The run is one ROCTx range named `label`,
+        its host work ranges named "host: ..." (see timeline.py)."""
         with markers().range(label):
-            return self._serve(requests, warmup, log)
+            return self._serve(requests, warmup, log, cancel or {}, stop_after_rounds, resume,
+                               cancel_after_rounds or {})
 
-    def _serve(self, requests, warmup: int, log):
+    # -- checkpoint / resume -----------------------------------------------------
+    def _frame(self, sc: Scenario):
+        pb = sc.grid
+        n = _round_up(pb.mx + 4, 16) * (pb.my + 4)
+        return n
+
+    def checkpoint_active(self) -> list:
+        """Host copies of every active scenario's stored planes (state and bed,
+        in the pool's precision), step size and status pair (synchronises)."""
+        torch.cuda.synchronize(self.dev)
+        saved = []
+        for sc in self.active:
+            n = self._frame(sc)
+            planes = self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n].cpu().clone()
+            bed = self.b[sc.off: sc.off + n].cpu().clone()
+            saved.append({"scenario": sc, "planes": planes, "bed": bed,
+                          "dt": float(self.dt[sc.slot].item()),
+                          "gstatus": self.gstatus[2 * sc.slot: 2 * sc.slot + 2].cpu().clone()})
+        return saved
+
+    def restore_active(self, saved: list) -> None:
+        """Admit checkpointed scenarios with their stored planes (no speed scan:
+        their step sizes come with them)."""
+        for rec in saved:
+            sc = rec["scenario"]
+            got = self.alloc.alloc(self.footprint_elems(sc.grid))
+            if got is None or not self.free_slots:
+                raise L.SweError(f"resume: no room for request {sc.rid}")
+            sc.off, sc.span = got
+            sc.slot = self.free_slots.pop(0)
+            n = self._frame(sc)
+            self.pools[self.cur].view(3, self.plane)[:, sc.off: sc.off + n].copy_(
+                rec["planes"].to(self.dev))
+            self.b[sc.off: sc.off + n].copy_(rec["bed"].to(self.dev))
+            self.dt[sc.slot] = rec["dt"]
+            self.gstatus[2 * sc.slot: 2 * sc.slot + 2].copy_(rec["gstatus"].to(self.dev))
+            self.smax[2 * sc.slot: 2 * sc.slot + 2].zero_()
+            self.active.append(sc)
+        self.table_dirty = True
+
+    def _serve(self, requests, warmup: int, log, cancel: dict, stop_after_rounds, resume,
+               cancel_rounds: dict):
         mk = markers()
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: list[Scenario] = []
         done: list[Scenario] = []
+        rejected: list[Scenario] = []
+        cancelled: list[Scenario] = []
         inflight: deque = deque()  # (event, results, pinned buffers held)
-        t0 = time.perf_counter()
+        t_shift = 0.0
+        if resume is not None:
+            pending = sorted(resume["pending"], key=lambda r: r.arrival)
+            queue = list(resume["queue"])
+            t_shift = resume["elapsed"]
+            self.restore_active(resume["active"])
+        t0 = time.perf_counter() - t_shift
         cells = 0
+        rounds = 0
         i = 0
+        cancel_left = dict(cancel)
+        cancel_rounds_left = dict(cancel_rounds)
 
         def settle(block: bool) -> None:
             ev, results, held = inflight[0]
@@ -321,7 +427,7 @@ class ScenarioServer:
             for sc in finished:
                 done.append(sc)
                 if log:
-                    log(f"[serve] request {sc.rid} ({sc.problem.mx}^2) done, latency "
+                    log(f"[serve] request {sc.rid} ({sc.grid.mx}^2) done, latency "
                         f"{(sc.finished - sc.arrival) * 1e3:.1f} ms")
 
         while i < len(pending) or queue or self.active or inflight:
@@ -329,19 +435,45 @@ class ScenarioServer:
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 i += 1
+            # withdrawals due by now (by time, or by rounds run)
+            for rid, k in list(cancel_rounds_left.items()):
+                if rounds >= k:
+                    cancel_left[rid] = 0.0
+                    del cancel_rounds_left[rid]
+            for rid, t in list(cancel_left.items()):
+                if t > now:
+                    continue
+                hit = next((sc for sc in queue if sc.rid == rid), None)
+                if hit is not None:
+                    queue.remove(hit)
+                    hit.state, hit.finished = "cancelled", now
+                    cancelled.append(hit)
+                    del cancel_left[rid]
+                    continue
+                hit = next((sc for sc in self.active if sc.rid == rid), None)
+                if hit is not None:
+                    self._retire(hit, keep_result=False)
+                    hit.state, hit.finished = "cancelled", now
+                    cancelled.append(hit)
+                    del cancel_left[rid]
+            # a request larger than the whole budget can never be admitted:
+            # reject it alone, with the reason
+            for sc in [sc for sc in queue if self.footprint_bytes(sc.grid) > self.budget_bytes()]:
+                queue.remove(sc)
+                sc.state = "rejected"
+                sc.reason = (f"needs {self.footprint_bytes(sc.grid)} bytes of HBM, more than "
+                             f"the server's budget of {self.budget_bytes()}")
+                rejected.append(sc)
             # admit in arrival order while slots and memory allow
             with mk.range("host: admit"):
                 while queue and self.try_admit(queue[0]):
                     queue[0].admitted = time.perf_counter() - t0
                     queue.pop(0)
-            if queue and not self.active and not inflight:
-                raise L.SweError(f"request {queue[0].rid} needs "
-                                 f"{self.footprint_bytes(queue[0].problem)} bytes of HBM, more "
-                                 f"than the server's budget of {7 * self.plane * self.esize}")
             if self.active:
                 steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
                 self.round(steps)
-                cells += steps * sum(sc.problem.mx * sc.problem.my for sc in self.active)
+                rounds += 1
+                cells += steps * sum(sc.grid.mx * sc.grid.my for sc in self.active)
                 with mk.range("host: retire"):
                     results = [self._retire(sc) for sc in
                                [sc for sc in self.active if sc.steps_done >= sc.nsteps]]
@@ -349,6 +481,16 @@ class ScenarioServer:
                 ev.record(torch.cuda.current_stream(self.dev))
                 inflight.append((ev, results, self.hold))
                 self.hold = []
+                if stop_after_rounds is not None and rounds >= stop_after_rounds:
+                    while inflight:
+                        settle(block=True)
+                    ckpt = {"active": self.checkpoint_active(), "queue": list(queue),
+                            "pending": pending[i:], "elapsed": time.perf_counter() - t0}
+                    for rec in ckpt["active"]:
+                        self.active.remove(rec["scenario"])
+                    self.active = []
+                    return {"stopped": True, "checkpoint": ckpt, "done": done,
+                            "rejected": rejected, "cancelled": cancelled}
             # stay one round ahead: wait for the older of two queued rounds, or
             # for the last one when nothing else can be queued
             if inflight and (len(inflight) > 1 or not self.active):
@@ -361,11 +503,13 @@ class ScenarioServer:
             if not self.active and not inflight and not queue and i < len(pending):
                 time.sleep(max(0.0, min(0.01, pending[i].arrival - (time.perf_counter() - t0))))
         torch.cuda.synchronize(self.dev)
-        total = time.perf_counter() - t0
+        total = time.perf_counter() - t0 - t_shift
         lat = np.array([sc.finished - sc.arrival for sc in done if sc.rid >= warmup])
         flags = self.status.cpu().numpy()
         return {"requests": len(done), "measured": int(lat.size),
+                "rejected_requests": len(rejected), "cancelled_requests": len(cancelled),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
                 "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-                "cell_updates_per_s": cells / total, "wall_s": total,
-                "status_flags": int(flags[0]), "clamps": int(flags[1]), "done": done}
+                "cell_updates_per_s": cells / total if total > 0 else None, "wall_s": total,
+                "status_flags": int(flags[0]), "clamps": int(flags[1]), "done": done,
+                "rejected": rejected, "cancelled": cancelled}

@@ -143,6 +143,20 @@ def shelf_4096(n: int = 4096, dx: float = 250.0, nsteps: int = 500) -> Problem:
     return shelf_grid(n, dx, seed=2, nsteps=nsteps, name=f"shelf_{n}")
 
 
+def active_sea(n: int = 4096, dx: float = 250.0, seed: int = 6, depth: float = 4000.0) -> Problem:
+    """A state with no quiet edge: flat sea floor at -depth, every cell wet,
+    the surface and both velocities seeded uniform noise (+-0.5 m, +-0.3 m/s
+    per cell, row-major), extrapolation boundaries.  Every edge carries
+    waves, so a step can skip no Riemann solve."""
+    rng = np.random.default_rng(seed)
+    eta = rng.uniform(-0.5, 0.5, size=(n, n))
+    u = rng.uniform(-0.3, 0.3, size=(n, n))
+    v = rng.uniform(-0.3, 0.3, size=(n, n))
+    b = np.full((n, n), -depth)
+    h = eta - b
+    return Problem(f"active_sea_{n}", h, h * u, h * v, b, dx, dx, (BC_EXTRAP,) * 4)
+
+
 def shelf_walls(n: int = 2048, dx: float = 500.0, seed: int = 4, nsteps: int = 2000,
                 amp: float = 2.0) -> Problem:
     """Wall-bounded shelf (mass drift is then pure numerics), source 60 km
@@ -248,6 +262,65 @@ def scenario(k: int, n: int | None = None, dx: float = 500.0, nsteps: int = 1000
     return Problem(f"scenario{k}", h, z, z.copy(), b, dx, dx, (BC_EXTRAP,) * 4, nsteps,
                    meta={"x_s": x_s, "width": width, "amp": amp, "sigma": sigma,
                          "src": (cx, cy)})
+
+
+@dataclass
+class ScenarioSpec:
+    """Scenario k as its seeded parameters (the same draws as scenario(k)),
+    for building the initial state where it is needed (on the device)."""
+    name: str
+    n: int
+    dx: float
+    nsteps: int
+    x_s: float
+    width: float
+    amp: float
+    sigma: float
+    cx: float
+    cy: float
+    bc: tuple = (BC_EXTRAP,) * 4
+
+    @property
+    def mx(self) -> int:
+        return self.n
+
+    @property
+    def my(self) -> int:
+        return self.n
+
+    @property
+    def dy(self) -> float:
+        return self.dx
+
+    def device_state(self, device):
+        """Initial depth and bed (FP64 torch tensors on `device`, (n, n)):
+        the shelf of scenario() along x, the Gaussian source, h = max(eta - b, 0)."""
+        import torch
+        xc = (torch.arange(self.n, dtype=torch.float64, device=device) + 0.5) * self.dx
+        bx = -4000.0 + (50.0 + 4000.0) * 0.5 * (1.0 + torch.tanh((xc - self.x_s) / self.width))
+        b = bx[None, :].expand(self.n, self.n)
+        gx = torch.exp(-((xc - self.cx) ** 2) / (2.0 * self.sigma * self.sigma))
+        gy = torch.exp(-((xc - self.cy) ** 2) / (2.0 * self.sigma * self.sigma))
+        eta = self.amp * (gy[:, None] * gx[None, :])
+        return torch.clamp(eta - b, min=0.0), b
+
+
+def scenario_spec(k: int, n: int | None = None, dx: float = 500.0, nsteps: int = 1000,
+                  n_lo: int = 256, n_hi: int = 2048) -> ScenarioSpec:
+    """The parameters of scenario(k, ...) without its arrays."""
+    rng = np.random.default_rng(5000 + k)
+    if n is None:
+        n = int(rng.integers(n_lo, n_hi + 1))
+    else:
+        rng.integers(n_lo, n_hi + 1)
+    L = n * dx
+    x_s = float(rng.uniform(0.6, 0.85)) * L
+    width = float(rng.uniform(10e3, 30e3))
+    amp = float(rng.uniform(0.5, 5.0))
+    sigma = float(rng.uniform(10e3, 50e3))
+    cx = float(rng.uniform(0.2, 0.5)) * L
+    cy = float(rng.uniform(0.3, 0.7)) * L
+    return ScenarioSpec(f"scenario{k}", n, dx, nsteps, x_s, width, amp, sigma, cx, cy)
 
 
 def request_stream(count: int = 1200, rate: float = 20.0, seed: int = 5, nsteps: int = 1000,

@@ -310,7 +310,7 @@ def test_batched_step_pool_checks(L):
         v = lambda x: None if x is None else ctypes.c_void_p(x)
         return lib.swe_batched_step(ctypes.byref(p), fake, fake, nitems, fake, fake, nplain,
                                     nsub, v(pin), v(pout), v(pwork), elems, fake, fake, fake,
-                                    fake, fake, ctypes.byref(sched), None)
+                                    fake, None, fake, ctypes.byref(sched), None)
 
     # items (patches with substeps) and per-substep launches need pool_work
     assert call(3, 0, 0, A, B, None, 100) == L.SWE_EINVAL
@@ -335,19 +335,24 @@ def test_state_import_export_argument_errors(L):
     lib = L.lib()
     p = L.params()
     fake = ctypes.c_void_p(0x1000)
-    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 10, 10, None, fake, fake, fake,
+    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 10, 10, None, fake, 0, 0, fake, fake,
                                 None) == L.SWE_EINVAL
-    assert lib.swe_state_import(ctypes.byref(p), fake, -1, 10, 10, fake, fake, fake, fake,
+    assert lib.swe_state_import(ctypes.byref(p), fake, -1, 10, 10, fake, fake, 0, 0, fake, fake,
                                 None) == L.SWE_EINVAL
-    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 0, 10, fake, fake, fake, fake,
+    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 0, 10, fake, fake, 0, 0, fake, fake,
                                 None) == L.SWE_EINVAL
+    assert lib.swe_state_import(ctypes.byref(p), fake, 1, 10, 10, fake, fake, 0, -1, fake, fake,
+                                None) == L.SWE_EINVAL
+    assert b"src_stride" in lib.swe_last_error()
     f32 = L.params(precision=L.F32_DEV)
-    assert lib.swe_state_export(ctypes.byref(f32), fake, 1, 10, 10, fake, None, fake,
+    assert lib.swe_state_export(ctypes.byref(f32), fake, 1, 10, 10, fake, None, fake, 0, 0,
                                 None) == L.SWE_EINVAL
-    assert lib.swe_state_export(ctypes.byref(p), fake, 1, 10, 10, fake, None, None,
+    assert lib.swe_state_export(ctypes.byref(p), fake, 1, 10, 10, fake, None, None, 0, 0,
+                                None) == L.SWE_EINVAL
+    assert lib.swe_state_export(ctypes.byref(p), fake, 1, 10, 10, fake, None, fake, 0, -2,
                                 None) == L.SWE_EINVAL
     # zero patches enqueue nothing
-    assert lib.swe_state_import(ctypes.byref(p), fake, 0, 10, 10, fake, fake, fake, fake,
+    assert lib.swe_state_import(ctypes.byref(p), fake, 0, 10, 10, fake, fake, 0, 0, fake, fake,
                                 None) == L.SWE_OK
 
 
@@ -371,6 +376,6 @@ def test_static_batched_step_host_checks(L, tmp_path):
         p.precision = prec
         rc = lib.swe_batched_step_static(ctypes.byref(p), fake, fake, 1, fake, None, 0, 0, fake,
                                          out_pool, L.SWE_STATIC_WORK_BYTES // esz + 1, fake, fake,
-                                         fake, fake, ctypes.byref(sched), None)
+                                         fake, fake, None, ctypes.byref(sched), None)
         assert rc == L.SWE_EINVAL
         assert b"static substep pool" in lib.swe_last_error()

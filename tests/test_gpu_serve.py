@@ -42,3 +42,98 @@ def test_mix_equals_alone(gpu, precision):
         torch.cuda.synchronize()
         alone = s.surface()
         assert np.array_equal(sc.result["eta"], alone), f"request {sc.rid}"
+
+
+def alone_surface(PatchSolver, torch, p, pb, nsteps):
+    s = PatchSolver(pb, p)
+    s.initial_dt()
+    s.run_async(nsteps)
+    torch.cuda.synchronize()
+    return s.surface()
+
+
+def test_oversized_request_is_rejected_alone(gpu):
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    p = L.params(precision=L.F32_DEV)
+    reqs = [Scenario(0, 0.0, W.scenario(0, n=64), 20), Scenario(1, 0.001, W.scenario(1, n=400), 20),
+            Scenario(2, 0.002, W.scenario(2, n=80), 20)]
+    srv = ScenarioServer(p, hbm_budget=2 * 7 * 100 * 100 * 4, max_slots=2, steps_per_round=10)
+    out = srv.serve(reqs)
+    assert out["requests"] == 2 and out["rejected_requests"] == 1
+    rej = out["rejected"][0]
+    assert rej.rid == 1 and rej.state == "rejected" and "budget" in rej.reason
+    for sc in out["done"]:
+        assert sc.state == "done"
+        assert np.array_equal(sc.result["eta"], alone_surface(PatchSolver, torch, p, sc.problem,
+                                                              sc.nsteps))
+
+
+def test_cancelled_requests_leave_the_rest_unchanged(gpu):
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    p = L.params(precision=L.F32_DEV)
+    sizes = [96, 64, 128, 80, 72]
+    reqs = [Scenario(k, 0.0, W.scenario(k, n=n), 60) for k, n in enumerate(sizes)]
+    # request 1 is withdrawn at once (still queued: one slot only), request 0
+    # while it runs (after its first round)
+    srv = ScenarioServer(p, max_slots=1, steps_per_round=20)
+    out = srv.serve(reqs, cancel={1: 0.0}, cancel_after_rounds={0: 1})
+    got = {sc.rid: sc for sc in out["done"]}
+    assert sorted(sc.rid for sc in out["cancelled"]) == [0, 1]
+    assert all(sc.state == "cancelled" and not sc.result for sc in out["cancelled"])
+    assert sorted(got) == [2, 3, 4]
+    for rid, sc in got.items():
+        assert np.array_equal(sc.result["eta"], alone_surface(PatchSolver, torch, p, sc.problem,
+                                                              sc.nsteps))
+
+
+def test_per_request_status(gpu):
+    # a request with a NaN in its input reports it; the others report nothing
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    p = L.params(precision=L.F32_DEV)
+    bad = W.scenario(1, n=80)
+    bad.hu = bad.hu.copy()
+    bad.hu[40, 10] = np.nan
+    reqs = [Scenario(0, 0.0, W.scenario(0, n=64), 10), Scenario(1, 0.0, bad, 10),
+            Scenario(2, 0.0, W.scenario(2, n=72), 10)]
+    out = ScenarioServer(p, max_slots=3, steps_per_round=5).serve(reqs)
+    st = {sc.rid: sc.result["status"] for sc in out["done"]}
+    assert st[1] & L.STATUS_NONFINITE
+    assert st[0] & (L.STATUS_NONFINITE | L.STATUS_NEG_DEPTH) == 0
+    assert st[2] & (L.STATUS_NONFINITE | L.STATUS_NEG_DEPTH) == 0
+    assert out["status_flags"] & L.STATUS_NONFINITE
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_checkpoint_and_resume_is_bitwise(gpu, precision):
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    p = L.params(precision=precision)
+    sizes = [64, 150, 96, 120, 80]
+    steps = [45, 30, 60, 25, 50]
+
+    def requests():
+        return [Scenario(k, 0.0, W.scenario(k, n=n), steps[k]) for k, n in enumerate(sizes)]
+    whole = ScenarioServer(p, max_slots=3, steps_per_round=10).serve(requests())
+    first = ScenarioServer(p, max_slots=3, steps_per_round=10).serve(requests(),
+                                                                     stop_after_rounds=2)
+    assert first["stopped"] and first["checkpoint"]["active"]
+    # the rest in a new server with other slots and pool offsets
+    rest = ScenarioServer(p, max_slots=4, steps_per_round=10).serve(
+        [], resume=first["checkpoint"])
+    got = {sc.rid: sc.result["eta"] for sc in first["done"] + rest["done"]}
+    want = {sc.rid: sc.result["eta"] for sc in whole["done"]}
+    assert sorted(got) == sorted(want) == list(range(len(sizes)))
+    for rid in want:
+        assert np.array_equal(got[rid], want[rid]), rid
+
+
+def test_device_built_scenario_matches_host_arrays(gpu):
+    # a request given as parameters (the state built on the device) runs as
+    # the same request given as host arrays, to the rounding of the initial
+    # state's tanh and exp
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    p = L.params()
+    spec = W.scenario_spec(3, n=160, nsteps=30)
+    a = ScenarioServer(p, max_slots=2).serve([Scenario(0, 0.0, None, 30, spec=spec)])
+    b = ScenarioServer(p, max_slots=2).serve([Scenario(0, 0.0, W.scenario(3, n=160), 30)])
+    ea, eb = a["done"][0].result["eta"], b["done"][0].result["eta"]
+    assert np.abs(ea - eb).max() <= 1e-9
