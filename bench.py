@@ -143,7 +143,7 @@ def make_traffic_record(root: str, out: str) -> None:
     under `root`: pmc_fetch/, pmc_write/ (bench.py) and calib_fetch/,
     calib_write/ (bench.py --calib-copy 1024).  Each counter is scaled by the
     ratio of the copy kernel's known bytes to what the counter read for it."""
-    kern = "k_split<false, false>"
+    kern = "k_split<false, false, false>"
     fetch, nf = _pmc_mean(os.path.join(root, "pmc_fetch"), "FETCH_SIZE", kern, STEP_WG)
     write, nw = _pmc_mean(os.path.join(root, "pmc_write"), "WRITE_SIZE", kern, STEP_WG)
     cf, _ = _pmc_mean(os.path.join(root, "calib_fetch"), "FETCH_SIZE", "copyBuffer")
@@ -152,7 +152,7 @@ def make_traffic_record(root: str, out: str) -> None:
     sf, sw = copy_kib / cf, copy_kib / cw
     total = (fetch * sf + write * sw) * 1024.0
     lines = [
-        "# FP64 split step k_split<false, false>, 4096^2 shelf: HBM traffic per launch",
+        "# FP64 split step k_split<false, false, false>, 4096^2 shelf: HBM traffic per launch",
         "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the copy calibration",
         f"kernel_source_hash = {kernel_source_hash()}",
         f"fetch_kib_per_launch = {fetch:.1f}",
@@ -181,22 +181,27 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VAL
                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
 
 
-VALU_KERNELS = (("k_split<false, false>", "k_split_f64_shelf4096_valu.txt", "FP64 split step"),
-                ("k_split<true, false>", "k_split_f32dev_shelf4096_valu.txt",
-                 "FP32 surface-deviation split step"),
-                ("k_unsplit<false>", "k_unsplit_f64_shelf4096_valu.txt", "FP64 unsplit step"))
+# (kernel, record, what, pmc run): sq1 runs the headline step alone
+# (--no-variants), sq2 with its variants
+VALU_KERNELS = (("k_split<false, false, false>", "k_split_f64_shelf4096_valu.txt",
+                 "FP64 split step", "sq1"),
+                ("k_split<true, false, false>", "k_split_f32dev_shelf4096_valu.txt",
+                 "FP32 surface-deviation split step", "sq2"),
+                ("k_unsplit<false>", "k_unsplit_f64_shelf4096_valu.txt", "FP64 unsplit step",
+                 "sq2"))
 
 
 def make_valu_record(root: str, outdir: str) -> None:
-    """Instruction counters per dispatch of the step kernels from one
-    rocprofv3 --pmc run under root/sq1 (counters SQ_COUNTERS, bench.py with
-    its variants), one record per kernel in outdir."""
-    for kern, fname, what in VALU_KERNELS:
+    """Instruction counters per dispatch of the step kernels from rocprofv3
+    --pmc runs under root/sq1 (bench.py --no-variants: the headline step) and
+    root/sq2 (bench.py with its variants; counters SQ_COUNTERS), one record
+    per kernel in outdir."""
+    for kern, fname, what, run in VALU_KERNELS:
         lines = [f"# {what} {kern}, 4096^2 shelf: SQ counters per dispatch",
                  f"kernel_source_hash = {kernel_source_hash()}"]
         try:
             for c in SQ_COUNTERS:
-                v, n = _pmc_mean(os.path.join(root, "sq1"), c, kern, STEP_WG)
+                v, n = _pmc_mean(os.path.join(root, run), c, kern, STEP_WG)
                 lines.append(f"{c} = {v:.0f}")
         except SystemExit as e:
             print(f"skipping {kern}: {e}")
@@ -286,7 +291,7 @@ def roofline(r64: dict, traffic, valu_path, opcount: str, cells: int) -> dict:
     top = alu if bound == "alu" else hbm
     return {"bound": bound, "achieved": top["achieved"], "peak": top["peak"],
             "unit": top["unit"], "frac": top["frac"], "traffic": traffic,
-            "kernel": "swe::k_split<false, false>", "kernel_ms_avg": kms,
+            "kernel": "swe::k_split<false, false, false>", "kernel_ms_avg": kms,
             "kernel_ms_p50": r64["kernel_ms_p50"], "kernel_ms_p99": r64["kernel_ms_p99"],
             "valu_busy_frac": busy, "hbm": hbm, "alu": alu,
             "why": "VALU busy fraction (SQ counters) above the HBM fraction: the kernel is "
@@ -830,19 +835,6 @@ def main():
     valu = measured_valu(r64["kernel_ms_avg"], args.valu)
     if valu:
         out["valu"] = valu
-    log("[bench] FP64 split step on a sea with no quiet edge")
-    torch.cuda.empty_cache()
-    pa = W.active_sea(n=n, dx=250.0 * 4096 / n)
-    ra = time_patch(pa, L.params(), min(args.steps, 200), args.warmup)
-    ra.pop("solver")
-    out["fully_active_fp64"] = {
-        "workload": f"active_sea_{n}x{n}: flat -4000 m, every cell wet, seeded noise in the "
-                    "surface and both velocities, so no edge is quiet",
-        "cups": ra["cups"], "ms_per_step": ra["ms_per_step"], "kernel_ms_avg": ra["kernel_ms_avg"],
-        "achieved_gbs": ra["achieved_gbs"], "hbm_frac": ra["achieved_gbs"] / HBM_PEAK_GBS,
-        "flags": ra["flags"],
-        "alu": alu_roofline(ra["kernel_ms_avg"], OPCOUNT_ACTIVE, n * n)}
-    del pa
     st64 = r64["solver"].state()
     out["edges_at_end"] = edge_stats(*st64, pb.b)
     if not args.no_variants:
@@ -881,6 +873,19 @@ def main():
             "cups": ru["cups"], "ms_per_step": ru["ms_per_step"],
             "kernel_ms_avg": ru["kernel_ms_avg"], "achieved_gbs": ru["achieved_gbs"],
             "frac": ru["achieved_gbs"] / HBM_PEAK_GBS, "flags": ru["flags"]}
+        log("[bench] FP64 split step on a sea with no quiet edge")
+        torch.cuda.empty_cache()
+        pa = W.active_sea(n=n, dx=250.0 * 4096 / n)
+        ra = time_patch(pa, L.params(), min(args.steps, 200), args.warmup)
+        ra.pop("solver")
+        out["variants"]["fully_active_fp64"] = {
+            "workload": f"active_sea_{n}x{n}: flat -4000 m, every cell wet, seeded noise in the "
+                        "surface and both velocities, so no edge is quiet",
+            "cups": ra["cups"], "ms_per_step": ra["ms_per_step"], "kernel_ms_avg": ra["kernel_ms_avg"],
+            "achieved_gbs": ra["achieved_gbs"], "hbm_frac": ra["achieved_gbs"] / HBM_PEAK_GBS,
+            "flags": ra["flags"],
+            "alu": alu_roofline(ra["kernel_ms_avg"], OPCOUNT_ACTIVE, n * n)}
+        del pa
         log("[bench] FP64 split step on a latitude-longitude patch")
         torch.cuda.empty_cache()
         # the extent of the paper's transoceanic domain (longitude -240 .. -100,
