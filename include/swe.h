@@ -181,6 +181,16 @@ int swe_cfl_reduce(const swe_params *p, const swe_patch *patches, int32_t n, int
                    double *smax_patch, double *dt_group, uint32_t *status,
                    uint32_t *group_flags, uint32_t *retake, int32_t initial, void *stream);
 
+/* Step sizes of the levels of a hierarchy (Sec. 3: a level refined by the
+ * ratio r in space takes r steps of dt / r per step of the level below):
+ * dt_levels[0] = dt_coarse[0], dt_levels[l] = dt_levels[l - 1] / ratio for
+ * l = 1 .. nlevels - 1 (device doubles).  With the hierarchy's patches in one
+ * group of swe_cfl_reduce, each with tref = ratio^(level - 1), that reduction
+ * writes the coarse step of the CFL condition over all levels and this call
+ * the levels' steps, without a host round trip. */
+int swe_level_steps(const double *dt_coarse, int32_t ratio, int32_t nlevels, double *dt_levels,
+                    void *stream);
+
 /* Retake on the device (Sec. 2, a step above the Courant limit is redone):
  * the same step as swe_patch_step, enqueued unconditionally but carried out
  * only if retake[patch->group] != 0 as written by the swe_cfl_reduce that

@@ -53,7 +53,15 @@ average (level-l cells under a level-(l+1) patch after its r substeps; the
 advance(l, dt): step every level-l patch by dt (level 1: physical boundary
   ghosts; finer levels: the filled ghosts); then, if a finer level exists,
   r times: fill its ghosts (alpha = k / r) and advance(l + 1, dt / r);
-  then average it onto level l.
+  then average it onto level l.  With regridding every b steps, level l + 1
+  and finer are regridded (oracle/regrid.py) at the start of every b-th step
+  of level l, from level l's state then.
+integrate: dt_1 from the CFL condition (Sec. 2) of the whole hierarchy, a
+  level-l patch's rate max(sx, sy) / dx_l divided by r^(l - 1) (Sec. 3: the
+  level steps dt_1 / r^(l - 1)); the first dt_1 from a speed scan, each next
+  one cfl_desired over the largest rate of the coarse step before; a coarse
+  step above cfl_max is redone from a snapshot of every level with the
+  reduced dt_1.
 
 Parity unpinned against the paper's own code (it states no formulas); the
 tests pin this reading: a sea at rest stays bitwise at rest, a hierarchy with
@@ -144,6 +152,11 @@ class Hierarchy:
     def __init__(self, H, P):
         self.r = H.ratio
         self.P = P
+        self.H = H
+        self.regrid_every = None
+        self.regrid_kw = {}
+        self.steps_taken = {}
+        self.regrids = []  # (level whose flags drove it, its step count)
         self.levels = []
         for lev in range(1, H.levels() + 1):
             bc = H.bc if lev == 1 else (BC_USER,) * 4
@@ -207,13 +220,24 @@ class Hierarchy:
                         c.q[rc, cc, :] = (h, hu / (r * r), hv / (r * r))
 
     def advance(self, lev, dt):
+        if self.regrid_every and lev < len(self.levels):
+            # level lev + 1 and finer regridded every b steps of level lev,
+            # from level lev's state at the start of its step (the levels
+            # above it are at the same time)
+            n = self.steps_taken.get(lev, 0)
+            if n > 0 and n % self.regrid_every == 0:
+                from .regrid import regrid
+                regrid(self, self.H, base=lev, **self.regrid_kw)
+                self.regrids.append((lev, n))
         old = [p.q.copy() for p in self.levels[lev - 1]]
         for p in self.levels[lev - 1]:
             if lev == 1:
                 ghost_fill(p.g, p.q)
-            out, _, clamps, nf = step(self.P, p.g, p.q, p.b, dt)
+            out, sm, clamps, nf = step(self.P, p.g, p.q, p.b, dt)
             assert nf == 0, "non-finite value in the reference AMR run"
             p.q[2:-2, 2:-2] = out[2:-2, 2:-2]
+            p.smax = np.maximum(getattr(p, "smax", np.zeros(2)), sm)
+        self.steps_taken[lev] = self.steps_taken.get(lev, 0) + 1
         if lev < len(self.levels):
             for k in range(self.r):
                 self.fill(lev + 1, old, k / self.r)
@@ -223,6 +247,87 @@ class Hierarchy:
     def run(self, dt1, ncoarse):
         for _ in range(ncoarse):
             self.advance(1, dt1)
+
+    # -- step sizes from the CFL condition (Sec. 2; Sec. 3: dt_{l+1} = dt_l / r) ----
+    def rate(self):
+        """Largest Courant rate of the last coarse step: over the patches of
+        every level, max(sx / dx_l, sy / dx_l) / r^(l - 1) (a level-l patch
+        steps dt_1 / r^(l - 1)), with (sx, sy) its largest speeds over the
+        step's substeps."""
+        worst = 0.0
+        for lev, ps in enumerate(self.levels, start=1):
+            d, tref = self.H.dx(lev), float(self.r ** (lev - 1))
+            for p in ps:
+                sx, sy = getattr(p, "smax", np.zeros(2))
+                v = max(sx / d, sy / d) / tref
+                worst = v if v > worst else worst
+        return worst
+
+    def reset_speeds(self):
+        for ps in self.levels:
+            for p in ps:
+                p.smax = np.zeros(2)
+
+    def initial_dt(self):
+        """dt_1 from the speeds of the initial state (every level's ghost
+        cells filled first, the finer ones from the level below at alpha 0)."""
+        from . import speed_scan
+        self.reset_speeds()
+        for lev, ps in enumerate(self.levels, start=1):
+            if lev > 1:
+                self.fill(lev, [c.q.copy() for c in self.levels[lev - 2]], 0.0)
+            for p in ps:
+                if lev == 1:
+                    ghost_fill(p.g, p.q)
+                p.smax = speed_scan(self.P, p.g, p.q, p.b)
+        rate = self.rate()
+        return self.P.cfl_desired / rate if rate > 0.0 else 1.0
+
+    def snapshot(self):
+        import copy
+        return ([[copy.copy(p) for p in ps] for ps in self.levels],
+                [[p.q.copy() for p in ps] for ps in self.levels], dict(self.steps_taken),
+                len(self.regrids))
+
+    def restore(self, snap):
+        lists, qs, steps, nreg = snap
+        self.levels = [list(ps) for ps in lists]
+        for ps, qq in zip(self.levels, qs):
+            for p, q in zip(ps, qq):
+                p.q = q.copy()
+        self.steps_taken = dict(steps)
+        del self.regrids[nreg:]
+
+    def integrate(self, ncoarse, regrid_every=None, regrid_kw=None, dt0=None):
+        """ncoarse coarse steps with dt_1 from the CFL condition: the first
+        from a speed scan, each next one cfl_desired / rate of the step before;
+        a coarse step whose Courant number dt_1 rate exceeds cfl_max is redone
+        (every level restored, regridding included) with dt_1 = cfl_desired /
+        rate.  With regrid_every = b, level l + 1 and finer are regridded every
+        b steps of level l (regrid_kw: tol, buffer, efficiency, min_side).
+        dt0: the first dt_1 instead of the speed scan's.
+        Returns the accepted dt_1 sequence and the number of retakes."""
+        self.regrid_every = regrid_every
+        self.regrid_kw = dict(regrid_kw or {})
+        dt = self.initial_dt() if dt0 is None else float(dt0)
+        dts, retakes = [], 0
+        for _ in range(ncoarse):
+            snap = self.snapshot()
+            while True:
+                self.reset_speeds()
+                self.advance(1, dt)
+                rate = self.rate()
+                if rate > 0.0 and dt * rate > self.P.cfl_max:
+                    self.restore(snap)
+                    dt = self.P.cfl_desired / rate
+                    retakes += 1
+                    continue
+                break
+            dts.append(dt)
+            if rate > 0.0:
+                dt = self.P.cfl_desired / rate
+        self.regrid_every = None
+        return np.array(dts), retakes
 
     def interior(self, lev, k):
         p = self.levels[lev - 1][k]

@@ -183,13 +183,14 @@ def fill_new(rect, level, H, old_fine, coarse, r, drytol):
     return p
 
 
-def regrid(hier, H, tol=5e-3, buffer=2, efficiency=0.7, min_side=2):
-    """Regrid every level above level 1 of an oracle Hierarchy in place
-    (levels synchronised, e.g. after a coarse step)."""
+def regrid(hier, H, tol=5e-3, buffer=2, efficiency=0.7, min_side=2, base=1):
+    """Regrid every level above level `base` of an oracle Hierarchy in place
+    (those levels synchronised with level `base`): level base + 1 from the
+    flags of level base, then each finer level from the new level below."""
     from . import BC_USER, grid
     r, P = hier.r, hier.P
     margin = 2 if r == 1 else 1
-    for lev in range(2, len(hier.levels) + 1):
+    for lev in range(base + 1, len(hier.levels) + 1):
         rects = new_rects(hier.levels[lev - 2], r, tol, P.drytol, buffer, margin, efficiency,
                           min_side)
         old = hier.levels[lev - 1]

@@ -112,6 +112,7 @@ def lib():
         L.swe_patch_retake.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                        _P, _P]
         L.swe_mass.argtypes = [pp, _P, i32, _P, _P, _P, _P]
+        L.swe_level_steps.argtypes = [_P, i32, i32, _P, _P]
         i64, dbl = ctypes.c_int64, ctypes.c_double
         pl = ctypes.POINTER(swe_launch)
         L.swe_patch_tasks.argtypes = [ctypes.POINTER(swe_patch), pl]
@@ -147,7 +148,7 @@ def lib():
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
                      "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
                      "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
-                     "swe_state_export", "swe_batched_step_static"):
+                     "swe_state_export", "swe_batched_step_static", "swe_level_steps"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +206,12 @@ def swe_patch_order(pt: swe_patch, sched: int, sched_len: int,
                     launch: swe_launch | None = None, stream: int = 0) -> None:
     _check(lib().swe_patch_order(ctypes.byref(pt), sched, sched_len, _lp(launch), stream),
            "swe_patch_order")
+
+
+def swe_level_steps(dt_coarse: int, ratio: int, nlevels: int, dt_levels: int,
+                    stream: int = 0) -> None:
+    _check(lib().swe_level_steps(dt_coarse, ratio, nlevels, dt_levels, stream),
+           "swe_level_steps")
 
 
 def swe_state_import(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, src: int,

@@ -231,6 +231,14 @@ class AmrSolver:
             self.geo.append(_Geo(ps, bs))
         self._plans()
         self.dts = torch.zeros(self.nlev, dtype=torch.float64, device=self.dev)
+        self.dt1 = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.cfl_status = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        self.cfl_retake = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.steps_taken = {}
+        self.regrid_every = None
+        self.regrid_kw = {}
+        self.regrids = []
+        self._speeds()
         self.graph = None
 
     def _level_solver(self, lev: int, ps) -> BatchedSolver:
@@ -270,8 +278,9 @@ class AmrSolver:
         return out
 
     def regrid(self, tol: float = 5e-3, buffer: int = 2, efficiency: float = 0.7,
-               min_side: int = 2) -> list:
-        """Regrid levels 2 and finer from the current (synchronised) state:
+               min_side: int = 2, base: int = 1) -> list:
+        """Regrid the levels above `base` from the current state (levels base
+        and finer synchronised):
         flags on the device, clustering on the host, new patches filled on the
         device from the old ones of their level where those overlap, else from
         the level below (which is regridded first).  Host work; returns the
@@ -282,7 +291,7 @@ class AmrSolver:
         r = self.r
         t_start = time.perf_counter()
         t_flag = t_cluster = t_pool = 0.0
-        for lev in range(2, self.nlev + 1):
+        for lev in range(base + 1, self.nlev + 1):
             parent, pps = self.levels[lev - 2], self.lpatches[lev - 2]
             t0 = time.perf_counter()
             fh = self.refine_flags(lev - 1, tol, buffer).cpu().numpy()
@@ -323,6 +332,7 @@ class AmrSolver:
             self.levels[lev - 1], self.geo[lev - 1], self.lpatches[lev - 1] = bs, geo, new_ps
         self._plans()
         self.dts = self.dts[: self.nlev].clone()
+        self._speeds(keep_levels=base)
         self.graph = None
         torch.cuda.synchronize(self.dev)
         total = time.perf_counter() - t_start
@@ -333,6 +343,121 @@ class AmrSolver:
                                "cluster": 1e3 * t_cluster, "pools": 1e3 * t_pool,
                                "fill_and_plans": 1e3 * (total - t_flag - t_cluster - t_pool)}
         return [[(p.i0, p.j0, p.mx, p.my) for p in ps] for ps in self.lpatches]
+
+    # -- CFL condition over the hierarchy (Sec. 2; Sec. 3: dt_{l+1} = dt_l / r) --
+    def _speeds(self, keep_levels: int = 0) -> None:
+        """One speed array for every patch of every level (each level's
+        batched step max-combines into its slice) and a patch table of the
+        whole hierarchy for swe_cfl_reduce: one group, a level-l patch with
+        its dx and tref = r^(l - 1).  The speeds of the first keep_levels
+        levels are carried over (a regrid replaced only the finer ones)."""
+        old = [bs.smax for bs in self.levels[:keep_levels]]
+        total = sum(bs.n for bs in self.levels)
+        self.smax_all = torch.zeros(2 * max(total, 1), dtype=torch.float64, device=self.dev)
+        pts, k = [], 0
+        for lev, bs in enumerate(self.levels, start=1):
+            view = self.smax_all[2 * k: 2 * (k + bs.n)]
+            if lev <= keep_levels:
+                view.copy_(old[lev - 1])
+            bs.smax = view
+            for pt in bs.patches:
+                q = L.patch(pt.mx, pt.my, pt.pitch, pt.dx, pt.dy, off=pt.off,
+                            plane_stride=pt.plane_stride, group=0, tref=self.r ** (lev - 1),
+                            level=lev, bc=tuple(pt.bc))
+                pts.append(q)
+            k += bs.n
+        from .solver import patch_table
+        self.cfl_table = patch_table(pts).to(self.dev)
+        self.cfl_n = len(pts)
+
+    def _reduce(self, initial: bool, retake: bool) -> None:
+        """dt_1 from the speeds of the whole hierarchy, then every level's step."""
+        L.swe_cfl_reduce(self.p, self.cfl_table.data_ptr(), self.cfl_n, 1,
+                         self.smax_all.data_ptr(), self.dt1.data_ptr(),
+                         self.cfl_status.data_ptr(), 0, 1 if initial else 0, self.stream,
+                         retake=self.cfl_retake.data_ptr() if retake else 0)
+        L.swe_level_steps(self.dt1.data_ptr(), self.r, self.nlev, self.dts.data_ptr(),
+                          self.stream)
+
+    def initial_dt(self) -> float:
+        """dt_1 from the speeds of the current state: the ghost cells of every
+        finer level filled from the level below at alpha 0, then a speed scan
+        of every patch."""
+        self.smax_all.zero_()
+        for lev in range(1, self.nlev + 1):
+            bs = self.levels[lev - 1]
+            if lev > 1:
+                c = self.levels[lev - 2]
+                cur = c.pools[c.cur]
+                L.swe_amr_fill(self.p, self.fill_ops[lev - 1].data_ptr(), self.nfill[lev - 1],
+                               bs.pools[bs.cur].data_ptr(), bs.plane, bs.b.data_ptr(),
+                               cur.data_ptr(), cur.data_ptr(), c.plane, c.b.data_ptr(), 0.0,
+                               self.stream)
+            L.swe_speed_scan(self.p, bs.table.data_ptr(), bs.n, bs.max_mx, bs.max_my,
+                             bs.pools[bs.cur].data_ptr(), bs.b.data_ptr(), bs.smax.data_ptr(),
+                             self.stream)
+        self._reduce(initial=True, retake=False)
+        return float(self.dt1.item())
+
+    def _snapshot(self) -> dict:
+        return {"levels": list(self.levels), "geo": list(self.geo),
+                "lpatches": list(self.lpatches), "rows": list(self.rows), "nlev": self.nlev,
+                "cur": [bs.cur for bs in self.levels],
+                "pools": [bs.pools[bs.cur].clone() for bs in self.levels],
+                "steps_taken": dict(self.steps_taken), "nregrids": len(self.regrids)}
+
+    def _restore(self, snap: dict) -> None:
+        self.levels, self.geo = list(snap["levels"]), list(snap["geo"])
+        self.lpatches, self.rows, self.nlev = list(snap["lpatches"]), list(snap["rows"]), snap["nlev"]
+        for bs, cur, pool in zip(self.levels, snap["cur"], snap["pools"]):
+            bs.cur = cur
+            bs.pools[cur].copy_(pool)
+        self.steps_taken = dict(snap["steps_taken"])
+        del self.regrids[snap["nregrids"]:]
+        self._plans()
+        self.dts = self.dts[: self.nlev].clone() if self.dts.numel() >= self.nlev else \
+            torch.zeros(self.nlev, dtype=torch.float64, device=self.dev)
+        self._speeds()
+        self.graph = None
+
+    def integrate(self, ncoarse: int, regrid_every: int | None = None, regrid_kw=None,
+                  dt0: float | None = None, retake: bool = True) -> tuple:
+        """ncoarse coarse steps with dt_1 from the CFL condition of the whole
+        hierarchy, computed on the device after each coarse step (the first
+        from a speed scan, or dt0); with retake, a coarse step above cfl_max
+        is redone from a snapshot of every level (their states and, when a
+        regrid happened inside the step, their patches) with the reduced dt_1.
+        regrid_every = b: level l + 1 and finer are regridded at the start of
+        every b-th step of level l.  Returns the accepted dt_1 values and the
+        number of retakes."""
+        self.regrid_every = regrid_every
+        self.regrid_kw = dict(regrid_kw or {})
+        if dt0 is None:
+            self.initial_dt()
+        else:
+            self.dt1.fill_(float(dt0))
+            L.swe_level_steps(self.dt1.data_ptr(), self.r, self.nlev, self.dts.data_ptr(),
+                              self.stream)
+        dts, retakes = [], 0
+        try:
+            for _ in range(ncoarse):
+                snap = self._snapshot() if retake else None
+                while True:
+                    dt = float(self.dt1.item())
+                    self.smax_all.zero_()
+                    self._advance(1)
+                    self._reduce(initial=False, retake=retake)
+                    if retake and int(self.cfl_retake.item()):
+                        self._restore(snap)
+                        L.swe_level_steps(self.dt1.data_ptr(), self.r, self.nlev,
+                                          self.dts.data_ptr(), self.stream)
+                        retakes += 1
+                        continue
+                    break
+                dts.append(dt)
+        finally:
+            self.regrid_every = None
+        return np.array(dts), retakes
 
     @property
     def stream(self) -> int:
@@ -346,9 +471,15 @@ class AmrSolver:
         self.dts.copy_(torch.tensor(dts, dtype=torch.float64))
 
     def _advance(self, lev: int) -> None:
+        if self.regrid_every and lev < self.nlev:
+            n = self.steps_taken.get(lev, 0)
+            if n > 0 and n % self.regrid_every == 0:
+                self.regrid(base=lev, **self.regrid_kw)
+                self.regrids.append((lev, n))
         bs = self.levels[lev - 1]
         old = bs.pools[bs.cur]
         bs.enqueue_step(cfl=False, dt_ptr=self.dts.data_ptr() + 8 * (lev - 1))
+        self.steps_taken[lev] = self.steps_taken.get(lev, 0) + 1
         new = bs.pools[bs.cur]
         if lev == self.nlev:
             return

@@ -433,6 +433,18 @@ __global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict_
 }
 
 // CFL rule per group; one block per group.
+// Step sizes of the levels of a hierarchy from the coarse one, each the one
+// below divided by the refinement ratio.
+__global__ void k_level_steps(const double* dt_coarse, int ratio, int nlevels, double* dt_levels) {
+    if (threadIdx.x != 0) return;
+    double v = dt_coarse[0];
+    dt_levels[0] = v;
+    for (int l = 1; l < nlevels; ++l) {
+        v = v / (double)ratio;
+        dt_levels[l] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict__ patches, int n,
                                                     double* smax, double* dt_group,
                                                     uint32_t* status, uint32_t* group_flags,
@@ -881,6 +893,15 @@ int swe_cfl_reduce(const swe_params* p, const swe_patch* patches, int32_t n, int
                        static_cast<hipStream_t>(stream), patches, n, smax_patch, dt_group,
                        status, group_flags, retake, p->cfl_desired, p->cfl_max, initial);
     return check_launch("swe_cfl_reduce");
+}
+
+int swe_level_steps(const double* dt_coarse, int32_t ratio, int32_t nlevels, double* dt_levels,
+                    void* stream) {
+    if (!dt_coarse || !dt_levels || ratio < 1 || nlevels < 1)
+        return fail(SWE_EINVAL, "swe_level_steps: null pointer, ratio < 1 or nlevels < 1");
+    hipLaunchKernelGGL(swe::k_level_steps, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       dt_coarse, ratio, nlevels, dt_levels);
+    return check_launch("swe_level_steps");
 }
 
 int swe_mass(const swe_params* p, const swe_patch* patches, int32_t n, const void* q,

@@ -135,3 +135,71 @@ def test_fp32_deviation_hierarchy_within_1e5_m(gpu, ratio):
             assert err <= 1e-5, (lev, k, err)
             assert np.abs(hu - want[..., 1]).max() <= 1e-4 * mom, (lev, k)
     print(f"fp32 deviation hierarchy: max surface difference {worst:.3e} m", flush=True)
+
+
+def compare_hierarchies(s, ref, tol=1e-12):
+    assert s.nlev == len([lv for lv in ref.levels if lv]) or s.nlev == len(ref.levels)
+    for lev in range(1, s.nlev + 1):
+        pats = ref.levels[lev - 1]
+        assert [(p.i0, p.j0, p.mx, p.my) for p in s.lpatches[lev - 1]] == \
+            [(p.i0, p.j0, p.mx, p.my) for p in pats], lev
+        scale = [max(np.abs(p.q[2:-2, 2:-2, c]).max() for p in pats) for c in range(3)]
+        for k, p in enumerate(pats):
+            got = s.state(lev, k)
+            for c in range(3):
+                err = np.abs(got[c] - p.q[2:-2, 2:-2, c]).max() / max(scale[c], 1e-300)
+                assert err <= tol, (lev, k, c, err)
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_cfl_integration_matches_the_reference(gpu, ratio):
+    # dt_1 from the CFL condition over every level, on the device after each
+    # coarse step, against the reference hierarchy's integration
+    L, AmrSolver, torch = gpu
+    from oracle import amr as A
+    import oracle as O
+    H = W.amr_three_levels(ratio, bed="shelf", amp=2.0, u0=0.3)
+    print(f"case amr cfl integration ratio={ratio}", flush=True)
+    s = AmrSolver(H, L.params())
+    dts, rt = s.integrate(4)
+    torch.cuda.synchronize()
+    O.lib()
+    ref = A.Hierarchy(H, O.params())
+    rdts, rrt = ref.integrate(4)
+    assert rt == rrt == 0
+    np.testing.assert_allclose(dts, rdts, rtol=1e-13, atol=0)
+    assert s.flags() == (0, 0)
+    compare_hierarchies(s, ref)
+
+
+def test_cfl_retake_of_a_coarse_step(gpu):
+    L, AmrSolver, torch = gpu
+    from oracle import amr as A
+    import oracle as O
+    H = W.amr_three_levels(2, bed="shelf", amp=2.0, u0=0.3)
+    print("case amr retake from dt0 = 40 s", flush=True)
+    s = AmrSolver(H, L.params())
+    dts, rt = s.integrate(3, dt0=40.0)
+    O.lib()
+    ref = A.Hierarchy(H, O.params())
+    rdts, rrt = ref.integrate(3, dt0=40.0)
+    assert rt == rrt == 1
+    np.testing.assert_allclose(dts, rdts, rtol=1e-13, atol=0)
+    compare_hierarchies(s, ref)
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_regrid_every_b_steps_inside_the_integration(gpu, ratio):
+    L, AmrSolver, torch = gpu
+    from oracle import amr as A
+    import oracle as O
+    H = W.amr_three_levels(ratio, bed="shelf", amp=2.0, u0=0.3)
+    print(f"case amr regrid every 2 level steps ratio={ratio}", flush=True)
+    s = AmrSolver(H, L.params())
+    dts, rt = s.integrate(3, regrid_every=2)
+    O.lib()
+    ref = A.Hierarchy(H, O.params())
+    rdts, rrt = ref.integrate(3, regrid_every=2)
+    assert s.regrids == ref.regrids and len(s.regrids) >= 2
+    np.testing.assert_allclose(dts, rdts, rtol=1e-13, atol=0)
+    compare_hierarchies(s, ref)

@@ -244,3 +244,65 @@ def test_fill_and_average_keep_dry_land_dry(P):
         for Jc in range(s.j0 // r, (s.j0 + s.my) // r):
             for Ic in range(s.i0 // r, (s.i0 + s.mx) // r):
                 assert np.all(c.q[c.cell(Ic, Jc)] == 0.0)
+
+
+def test_cfl_step_of_a_sea_at_rest_is_the_closed_form(P):
+    # every level of a flat sea at rest has the same rate sqrt(g H) / dx_1
+    # (dx_l = dx_1 / r^(l-1), divided by r^(l-1)): dt_1 = 0.9 dx_1 / sqrt(g H)
+    for r in (2, 4):
+        H = W.amr_three_levels(r, bed="flat", amp=0.0)
+        h = A.Hierarchy(H, P)
+        dts, retakes = h.integrate(3)
+        want = 0.9 * H.dx1 / np.sqrt(9.81 * H.depth)
+        assert retakes == 0
+        assert np.allclose(dts, want, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_cfl_steps_keep_the_courant_number(P, ratio):
+    H = W.amr_three_levels(ratio, bed="shelf", amp=2.0, u0=0.3)
+    h = A.Hierarchy(H, P)
+    dts, retakes = h.integrate(4)
+    assert retakes == 0 and len(dts) == 4
+    # every accepted step had its rate at most cfl_max / dt
+    h2 = A.Hierarchy(H, P)
+    d = h2.initial_dt()
+    assert dts[0] == d
+    for k in range(4):
+        h2.reset_speeds()
+        h2.advance(1, dts[k])
+        rate = h2.rate()
+        assert dts[k] * rate <= P.cfl_max
+        if k + 1 < 4:
+            assert dts[k + 1] == P.cfl_desired / rate
+
+
+def test_a_coarse_step_above_the_limit_is_redone_from_the_snapshot(P):
+    H = W.amr_three_levels(2, bed="shelf", amp=2.0, u0=0.3)
+    h = A.Hierarchy(H, P)
+    dts, retakes = h.integrate(3, dt0=40.0)  # far above the CFL limit
+    assert retakes == 1 and dts[0] < 40.0
+    # the retaken run is the run started with the retake's step size
+    h2 = A.Hierarchy(H, P)
+    dts2, retakes2 = h2.integrate(3, dt0=dts[0])
+    assert retakes2 == 0 and np.array_equal(dts, dts2)
+    for lev in range(3):
+        for p, q in zip(h.levels[lev], h2.levels[lev]):
+            assert np.array_equal(p.q, q.q)
+
+
+def test_regrid_every_b_steps_of_each_level(P):
+    # level l + 1 and finer are regridded at the start of every b-th step of
+    # level l: with r = 2, b = 2, three coarse steps, level 1 steps 0..2 and
+    # level 2 steps 0..5 (two per coarse step)
+    H = W.amr_three_levels(2, bed="shelf", amp=2.0, u0=0.3)
+    h = A.Hierarchy(H, P)
+    h.integrate(3, regrid_every=2)
+    assert h.regrids == [(2, 2), (1, 2), (2, 4)]
+    # the regridded hierarchy still nests: every level-3 patch and its ghost
+    # frame lie over level-2 interiors, every level-2 patch over level 1
+    for lev in (2, 3):
+        for f in h.levels[lev - 1]:
+            for J in range(f.j0 - 2, f.j0 + f.my + 2):
+                for I in range(f.i0 - 2, f.i0 + f.mx + 2):
+                    assert any(c.covers(I // 2, J // 2) for c in h.levels[lev - 2])
