@@ -544,15 +544,41 @@ int swe_amr_cluster(const uint8_t *flags, int32_t mx, int32_t my, int32_t pitch,
                     double efficiency, int32_t min_side, int32_t *boxes, int32_t max_boxes,
                     int32_t *nboxes);
 
-/* swe_amr_init: the interior cells of new patches of a level, as listed in
- * ops: SWE_AMR_COPY entries take q_old[src] (an old patch of the same level
- * that covers the cell; q_old may be NULL when there are none), SWE_AMR_COARSE
- * entries the rule of swe_amr_fill with alpha = 1 and the one coarse state
- * q_coarse.  q_new must differ from both sources. */
-int swe_amr_init(const swe_params *p, const swe_amr_fill_op *ops, int64_t nops, void *q_new,
-                 int64_t new_plane_stride, const void *b_new, const void *q_old,
-                 int64_t old_plane_stride, const void *q_coarse, int64_t coarse_plane_stride,
-                 const void *b_coarse, void *stream);
+/* A patch of a level as swe_amr_init reads it: interior cells (i0 .. i0 +
+ * mx - 1, j0 .. j0 + my - 1) in the level's global cell index, cell (I, J)
+ * stored at element off + (J - j0 + 2) pitch + (I - i0 + 2) of each plane
+ * (two ghost cells each side, as swe_patch). */
+typedef struct swe_amr_rect {
+    int64_t off;
+    int32_t i0, j0;
+    int32_t mx, my;   /* >= 1 each */
+    int32_t pitch;    /* >= mx + 4 */
+    int32_t reserved;
+} swe_amr_rect;
+
+/* swe_amr_init: the interior cells of n_new new patches of a level (device
+ * table new_rects; planes q_new, bed b_new), built on the device from the
+ * patch tables alone.  A cell (I, J) takes, per the first rule that applies:
+ *   - the same cell of the first old patch of the level (device table
+ *     old_rects, n_old >= 0 entries, planes q_old; NULL when n_old == 0)
+ *     whose interior holds it: a copy of its three values;
+ *   - the level below (device table coarse_rects, planes q_coarse, bed
+ *     b_coarse, refinement ratio r): the rule of swe_amr_fill with alpha = 1
+ *     and q_coarse as both states, the cell under it being the coarse cell
+ *     (floor(I / r), floor(J / r)) and the stencil (i0, j0) .. (i0 + 1, j0 +
+ *     1) with i0 = floor(X), j0 = floor(Y), X = (I + 1/2) / r - 1/2,
+ *     Y = (J + 1/2) / r - 1/2, each looked up in the first coarse patch whose
+ *     interior holds it (none: that stencil cell is missing);
+ *   - else the cell is not written (a new patch must lie over the level
+ *     below: regridding builds it from flags inside a coarse patch).
+ * max_cells bounds mx my over the new patches.  q_new must differ from q_old
+ * and q_coarse; the tables are read on the device during the call's work. */
+int swe_amr_init(const swe_params *p, int32_t ratio, const swe_amr_rect *new_rects, int32_t n_new,
+                 int64_t max_cells, void *q_new, int64_t new_plane_stride, const void *b_new,
+                 const swe_amr_rect *old_rects, int32_t n_old, const void *q_old,
+                 int64_t old_plane_stride, const swe_amr_rect *coarse_rects, int32_t n_coarse,
+                 const void *q_coarse, int64_t coarse_plane_stride, const void *b_coarse,
+                 void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);

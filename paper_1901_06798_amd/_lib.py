@@ -131,7 +131,8 @@ def lib():
         L.swe_amr_flag.argtypes = [pp, _P, i32, i32, i32, _P, _P, dbl, i32, i32, _P, _P]
         L.swe_amr_cluster.argtypes = [_P, i32, i32, i32, dbl, i32, _P, i32,
                                       ctypes.POINTER(i32)]
-        L.swe_amr_init.argtypes = [pp, _P, i64, _P, i64, _P, _P, i64, _P, i64, _P, _P]
+        L.swe_amr_init.argtypes = [pp, i32, _P, i32, i64, _P, i64, _P, _P, i32, _P, i64, _P, i32,
+                                   _P, i64, _P, _P]
         ps = ctypes.POINTER(swe_schedule)
         pi32 = ctypes.POINTER(i32)
         L.swe_batched_plan.argtypes = [_P, i32, ps, _P, pi32, _P, pi32, pi32, pi32]
@@ -267,11 +268,20 @@ def swe_amr_cluster(flags, efficiency: float = 0.7, min_side: int = 2):
         cap = n.value
 
 
-def swe_amr_init(p: swe_params, ops: int, nops: int, q_new: int, new_plane_stride: int,
-                 b_new: int, q_old: int, old_plane_stride: int, q_coarse: int,
-                 coarse_plane_stride: int, b_coarse: int, stream: int = 0) -> None:
-    _check(lib().swe_amr_init(ctypes.byref(p), ops, nops, q_new, new_plane_stride, b_new, q_old,
-                              old_plane_stride, q_coarse, coarse_plane_stride, b_coarse, stream),
+# swe_amr_rect as a numpy record (the C layout: off, i0, j0, mx, my, pitch,
+# reserved)
+AMR_RECT_DTYPE = np.dtype([("off", "<i8"), ("i0", "<i4"), ("j0", "<i4"), ("mx", "<i4"),
+                           ("my", "<i4"), ("pitch", "<i4"), ("reserved", "<i4")])
+
+
+def swe_amr_init(p: swe_params, ratio: int, new_rects: int, n_new: int, max_cells: int,
+                 q_new: int, new_plane_stride: int, b_new: int, old_rects: int, n_old: int,
+                 q_old: int, old_plane_stride: int, coarse_rects: int, n_coarse: int,
+                 q_coarse: int, coarse_plane_stride: int, b_coarse: int, stream: int = 0) -> None:
+    _check(lib().swe_amr_init(ctypes.byref(p), ratio, new_rects, n_new, max_cells, q_new,
+                              new_plane_stride, b_new, old_rects, n_old, q_old,
+                              old_plane_stride, coarse_rects, n_coarse, q_coarse,
+                              coarse_plane_stride, b_coarse, stream),
            "swe_amr_init")
 
 

@@ -57,6 +57,13 @@ class _Geo:
         """Element offset of global cell (I, J) in patch k's planes."""
         return (self.off[k] + (J - self.j0[k] + 2) * self.pitch[k] + (I - self.i0[k] + 2))
 
+    def rects(self, dev) -> torch.Tensor:
+        """The level's swe_amr_rect table, on the device."""
+        t = np.zeros(len(self.i0), dtype=L.AMR_RECT_DTYPE)
+        t["off"], t["i0"], t["j0"] = self.off, self.i0, self.j0
+        t["mx"], t["my"], t["pitch"] = self.mx, self.my, self.pitch
+        return torch.from_numpy(t.view(np.uint8)).to(dev)
+
 
 def stencil(coarse: _Geo, I: np.ndarray, J: np.ndarray, r: int):
     """Bilinear stencil on the level below (ratio r) of the fine cells (I, J):
@@ -149,64 +156,6 @@ def cover_block(geo: _Geo, i0: int, j0: int, nx: int, ny: int, r: int = 1) -> np
         if a < b and c < d:
             blk = out[c - j0: d - j0, a - i0: b - i0]
             blk[blk < 0] = k
-    return out
-
-
-def init_plan(new: _Geo, old: _Geo | None, coarse: _Geo, r: int) -> np.ndarray:
-    """Interior cells of new patches: copies from old patches of the level
-    where they cover the cell (first in order), else values from the level
-    below (the cell under it, first in order, and the bilinear stencil of
-    `stencil`).  Built rectangle by rectangle: each source patch
-    writes the block of the new patch it overlaps, where no earlier source
-    has, so the work is the new cells plus the overlaps; the entries are
-    written in place into one array."""
-    sizes = [int(new.mx[k]) * int(new.my[k]) for k in range(len(new.i0))]
-    out = np.empty(sum(sizes), dtype=FILL_DTYPE)
-    pos = 0
-    for k in range(len(new.i0)):
-        ni0, nj0 = int(new.i0[k]), int(new.j0[k])
-        mx, my = int(new.mx[k]), int(new.my[k])
-        op = out[pos: pos + sizes[k]].reshape(my, mx)
-        pos += sizes[k]
-        op["reserved"] = 0
-        op["dst"] = (new.off[k] + (np.arange(my, dtype=np.int64)[:, None] + 2) * new.pitch[k]
-                     + (np.arange(mx, dtype=np.int64)[None, :] + 2))
-        done = np.zeros((my, mx), dtype=bool)
-        src, kind = op["src"], op["kind"]
-        for geo, rr, code in (((old, 1, L.SWE_AMR_COPY),) if old is not None else ()) + (
-                (coarse, r, L.SWE_AMR_COARSE),):
-            for s_ in range(len(geo.i0)):
-                # the source's interior in the new level's index
-                a = max(ni0, int(geo.i0[s_]) * rr)
-                b = min(ni0 + mx, (int(geo.i0[s_]) + int(geo.mx[s_])) * rr)
-                c = max(nj0, int(geo.j0[s_]) * rr)
-                d = min(nj0 + my, (int(geo.j0[s_]) + int(geo.my[s_])) * rr)
-                if a >= b or c >= d:
-                    continue
-                I = np.arange(a, b, dtype=np.int64) // rr
-                J = np.arange(c, d, dtype=np.int64) // rr
-                val = (geo.off[s_] + (J[:, None] - geo.j0[s_] + 2) * geo.pitch[s_]
-                       + (I[None, :] - geo.i0[s_] + 2))
-                blk = (slice(c - nj0, d - nj0), slice(a - ni0, b - ni0))
-                taken = done[blk]
-                if not taken.any():
-                    src[blk] = val
-                    kind[blk] = code
-                else:
-                    free = ~taken
-                    src[blk][free] = val[free]
-                    kind[blk][free] = code
-                done[blk] = True
-        if not done.all():
-            raise L.SweError(f"new patch {k} is not over the level below")
-        op["st"] = -1
-        op["wx"] = 0.0
-        op["wy"] = 0.0
-        cm = kind == L.SWE_AMR_COARSE
-        if cm.any():
-            jj, ii = np.nonzero(cm)
-            st, wx, wy = stencil(coarse, ni0 + ii.astype(np.int64), nj0 + jj.astype(np.int64), r)
-            op["st"][cm], op["wx"][cm], op["wy"][cm] = st, wx, wy
     return out
 
 
@@ -322,13 +271,15 @@ class AmrSolver:
             old_bs, old_geo = self.levels[lev - 1], self.geo[lev - 1]
             t3 = time.perf_counter()
             t_pool += t3 - t2
-            ops = init_plan(geo, old_geo, self.geo[lev - 2], r)
-            dev_ops = torch.from_numpy(ops.view(np.uint8)).to(self.dev)
-            L.swe_amr_init(self.p, dev_ops.data_ptr(), ops.size, bs.pools[bs.cur].data_ptr(),
-                           bs.plane, bs.b.data_ptr(), old_bs.pools[old_bs.cur].data_ptr(),
-                           old_bs.plane, parent.pools[parent.cur].data_ptr(), parent.plane,
+            cgeo = self.geo[lev - 2]
+            tn, to, tc = geo.rects(self.dev), old_geo.rects(self.dev), cgeo.rects(self.dev)
+            L.swe_amr_init(self.p, r, tn.data_ptr(), len(new_ps),
+                           int(max(p.mx * p.my for p in new_ps)), bs.pools[bs.cur].data_ptr(),
+                           bs.plane, bs.b.data_ptr(), to.data_ptr(), len(old_geo.i0),
+                           old_bs.pools[old_bs.cur].data_ptr(), old_bs.plane, tc.data_ptr(),
+                           len(cgeo.i0), parent.pools[parent.cur].data_ptr(), parent.plane,
                            parent.b.data_ptr(), self.stream)
-            torch.cuda.synchronize(self.dev)  # dev_ops and the old level are released
+            torch.cuda.synchronize(self.dev)  # the tables and the old level are released
             self.levels[lev - 1], self.geo[lev - 1], self.lpatches[lev - 1] = bs, geo, new_ps
         self._plans()
         self.dts = self.dts[: self.nlev].clone()

@@ -11,7 +11,8 @@
 // bed of the cell written.  A host plan lists every ghost cell and every
 // covered coarse cell once (swe_amr_fill_op, swe_amr_avg_op); one thread
 // handles one entry, so writes never collide, and reads touch only interior
-// cells, which no entry writes.
+// cells, which no entry writes.  The cells of patches made by regridding are
+// found on the device from the patch rectangles alone, one thread per cell.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -68,95 +69,174 @@ __device__ __forceinline__ void coarse_at(const FillArgs& a, const S* qco, const
     v[2] = w0 * double(qco[k + 2 * a.psc]) + w1 * double(qcn[k + 2 * a.psc]);
 }
 
-// Ghost cells of the finer level.  A copy takes the same level's cell; a
-// coarse entry interpolates the level below linearly in time between its
-// states before (qco) and after (qcn) its step, and in space bilinearly from
-// the four coarse centres around the fine cell when they are all wet in both
-// states (away from the shore), else takes the cell under it alone.  FP32
-// planes are read into FP64, combined there and rounded once.
+// One cell of the finer level from the level below (the rule stated for
+// swe_amr_fill): linear in time between the coarse states before (qco) and
+// after (qcn) their step, bilinear in space from the stencil cells st[0..3]
+// of weights wx, wy when every stencil cell of non-zero weight lies in a
+// coarse interior (st >= 0) and is wet in both states, else the cell under
+// it (src) alone.  FP32 planes are read into FP64, combined there and
+// rounded once.
 template <typename S>
-__global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
-    S* qf = static_cast<S*>(a.qf);
+__device__ __forceinline__ void fill_from_coarse(const FillArgs& a, S* qf, int64_t dst,
+                                                 int64_t src, const int64_t st_in[4], double wx,
+                                                 double wy) {
     const S* bf = static_cast<const S*>(a.bf);
     const S* qco = static_cast<const S*>(a.qco);
     const S* qcn = static_cast<const S*>(a.qcn);
     const S* bc = static_cast<const S*>(a.bc);
+    S* q = qf + dst;
+    const double b_f = double(bf[dst]);
+    const double w0 = 1.0 - a.alpha, w1 = a.alpha;
+    // stencil cells of non-zero weight: c0 always, c1 with wx > 0, c2 with
+    // wy > 0, c3 with both
+    const bool two_x = wx > 0.0, two_y = wy > 0.0;
+    int64_t st[4];
+    double ho[4], hn[4];
+    bool linear = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
+        st[k] = st_in[k];
+        ho[k] = hn[k] = 0.0;
+        if (!used) continue;
+        if (st[k] < 0) {
+            linear = false;
+            continue;
+        }
+        ho[k] = depth(qco, bc, st[k], a.sea);
+        hn[k] = depth(qcn, bc, st[k], a.sea);
+        linear = linear && ho[k] > a.drytol && hn[k] > a.drytol;
+    }
+    double v[3];
+    if (linear) {
+        double c[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
+            if (used) coarse_at(a, qco, qcn, bc, st[k], ho[k], hn[k], w0, w1, c[k]);
+        }
+        const double ux = 1.0 - wx, uy = 1.0 - wy;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double line0 = ux * c[0][m];
+            if (two_x) line0 = line0 + wx * c[1][m];
+            double val = uy * line0;
+            if (two_y) {
+                double line1 = ux * c[2][m];
+                if (two_x) line1 = line1 + wx * c[3][m];
+                val = val + wy * line1;
+            }
+            v[m] = val;
+        }
+    } else {
+        const double h0 = depth(qco, bc, src, a.sea), h1 = depth(qcn, bc, src, a.sea);
+        if (h0 <= a.drytol && h1 <= a.drytol) {
+            q[0] = first_value<S>(0.0, b_f, b_f, a.sea);
+            q[a.psf] = S(0);
+            q[2 * a.psf] = S(0);
+            return;
+        }
+        coarse_at(a, qco, qcn, bc, src, h0, h1, w0, w1, v);
+    }
+    const double d = v[0] - b_f;
+    const double h = d > 0.0 ? d : 0.0;
+    q[0] = first_value<S>(h, v[0], b_f, a.sea);
+    if (h <= a.drytol) {
+        q[a.psf] = S(0);
+        q[2 * a.psf] = S(0);
+    } else {
+        q[a.psf] = S(v[1]);
+        q[2 * a.psf] = S(v[2]);
+    }
+}
+
+// Ghost cells of the finer level, as listed in the plan: a copy takes the
+// same level's cell, a coarse entry fill_from_coarse.
+template <typename S>
+__global__ void __launch_bounds__(256) k_amr_fill(FillArgs a) {
+    S* qf = static_cast<S*>(a.qf);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nops; i += stride) {
         const swe_amr_fill_op& op = a.ops[i];
-        const int64_t dst = op.dst;
-        S* q = qf + dst;
         if (op.kind == SWE_AMR_COPY) {
+            S* q = qf + op.dst;
             const S* src = static_cast<const S*>(a.qcopy) + op.src;
             q[0] = src[0];
             q[a.psf] = src[a.pscopy];
             q[2 * a.psf] = src[2 * a.pscopy];
             continue;
         }
-        const double b_f = double(bf[dst]);
-        const double w0 = 1.0 - a.alpha, w1 = a.alpha;
-        const double wx = op.wx, wy = op.wy;
-        // stencil cells of non-zero weight: c0 always, c1 with wx > 0, c2 with
-        // wy > 0, c3 with both
-        const bool two_x = wx > 0.0, two_y = wy > 0.0;
+        const int64_t st[4] = {op.st[0], op.st[1], op.st[2], op.st[3]};
+        fill_from_coarse<S>(a, qf, op.dst, op.src, st, op.wx, op.wy);
+    }
+}
+
+// First rectangle of `rects` whose interior holds global cell (I, J), or -1.
+__device__ __forceinline__ int covering(const swe_amr_rect* rects, int n, int I, int J) {
+    for (int k = 0; k < n; ++k) {
+        const swe_amr_rect r = rects[k];
+        if (I >= r.i0 && I < r.i0 + r.mx && J >= r.j0 && J < r.j0 + r.my) return k;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int floor_div(int a, int r) {
+    return a >= 0 ? a / r : -((-a + r - 1) / r);
+}
+
+__device__ __forceinline__ int64_t rect_elem(const swe_amr_rect& r, int I, int J) {
+    return r.off + (int64_t)(J - r.j0 + 2) * r.pitch + (I - r.i0 + 2);
+}
+
+struct InitArgs {
+    const swe_amr_rect* nw;
+    const swe_amr_rect* old;
+    int nold;
+    const swe_amr_rect* crs;
+    int ncrs;
+    int ratio;
+};
+
+// Interior cells of new patches (one block row per new patch): the first
+// old patch of the level whose interior holds the cell gives a copy; else
+// the level below gives fill_from_coarse with alpha = 1 and one state, the
+// cell under it and the bilinear stencil of its centre X = (I + 1/2) / r -
+// 1/2, Y = (J + 1/2) / r - 1/2 each looked up in the first coarse patch that
+// holds it (the host plan of swe_amr_fill computes the same).
+template <typename S>
+__global__ void __launch_bounds__(256) k_amr_init_rects(FillArgs a, InitArgs g) {
+    S* qn = static_cast<S*>(a.qf);
+    const swe_amr_rect pn = g.nw[blockIdx.y];
+    const int64_t ncell = (int64_t)pn.mx * pn.my;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int ii = (int)(c % pn.mx), jj = (int)(c / pn.mx);
+        const int I = pn.i0 + ii, J = pn.j0 + jj;
+        const int64_t dst = rect_elem(pn, I, J);
+        const int ko = covering(g.old, g.nold, I, J);
+        if (ko >= 0) {
+            const S* src = static_cast<const S*>(a.qcopy) + rect_elem(g.old[ko], I, J);
+            qn[dst] = src[0];
+            qn[dst + a.psf] = src[a.pscopy];
+            qn[dst + 2 * a.psf] = src[2 * a.pscopy];
+            continue;
+        }
+        const int Ic = floor_div(I, g.ratio), Jc = floor_div(J, g.ratio);
+        const int kc = covering(g.crs, g.ncrs, Ic, Jc);
+        if (kc < 0) continue;  // over no coarse patch: not written
+        const double r = (double)g.ratio;
+        const double X = ((double)I + 0.5) / r - 0.5, Y = ((double)J + 0.5) / r - 0.5;
+        const double fx = floor(X), fy = floor(Y);
+        const int i0 = (int)fx, j0 = (int)fy;
+        const double wx = X - fx, wy = Y - fy;
         int64_t st[4];
-        double ho[4], hn[4];
-        bool linear = true;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
-            st[k] = op.st[k];
-            ho[k] = hn[k] = 0.0;
-            if (!used) continue;
-            if (st[k] < 0) {
-                linear = false;
-                continue;
-            }
-            ho[k] = depth(qco, bc, st[k], a.sea);
-            hn[k] = depth(qcn, bc, st[k], a.sea);
-            linear = linear && ho[k] > a.drytol && hn[k] > a.drytol;
+            const int Is = i0 + (k & 1), Js = j0 + (k >> 1);
+            const int ks = covering(g.crs, g.ncrs, Is, Js);
+            st[k] = ks >= 0 ? rect_elem(g.crs[ks], Is, Js) : -1;
         }
-        double v[3];
-        if (linear) {
-            double c[4][3];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool used = (k & 1 ? two_x : true) && (k & 2 ? two_y : true);
-                if (used) coarse_at(a, qco, qcn, bc, st[k], ho[k], hn[k], w0, w1, c[k]);
-            }
-            const double ux = 1.0 - wx, uy = 1.0 - wy;
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                double line0 = ux * c[0][m];
-                if (two_x) line0 = line0 + wx * c[1][m];
-                double val = uy * line0;
-                if (two_y) {
-                    double line1 = ux * c[2][m];
-                    if (two_x) line1 = line1 + wx * c[3][m];
-                    val = val + wy * line1;
-                }
-                v[m] = val;
-            }
-        } else {
-            const double h0 = depth(qco, bc, op.src, a.sea), h1 = depth(qcn, bc, op.src, a.sea);
-            if (h0 <= a.drytol && h1 <= a.drytol) {
-                q[0] = first_value<S>(0.0, b_f, b_f, a.sea);
-                q[a.psf] = S(0);
-                q[2 * a.psf] = S(0);
-                continue;
-            }
-            coarse_at(a, qco, qcn, bc, op.src, h0, h1, w0, w1, v);
-        }
-        const double d = v[0] - b_f;
-        const double h = d > 0.0 ? d : 0.0;
-        q[0] = first_value<S>(h, v[0], b_f, a.sea);
-        if (h <= a.drytol) {
-            q[a.psf] = S(0);
-            q[2 * a.psf] = S(0);
-        } else {
-            q[a.psf] = S(v[1]);
-            q[2 * a.psf] = S(v[2]);
-        }
+        fill_from_coarse<S>(a, qn, dst, rect_elem(g.crs[kc], Ic, Jc), st, wx, wy);
     }
 }
 
@@ -482,28 +562,30 @@ int swe_amr_cluster(const uint8_t* flags, int32_t mx, int32_t my, int32_t pitch,
     return SWE_OK;
 }
 
-int swe_amr_init(const swe_params* p, const swe_amr_fill_op* ops, int64_t nops, void* q_new,
-                 int64_t new_plane_stride, const void* b_new, const void* q_old,
-                 int64_t old_plane_stride, const void* q_coarse, int64_t coarse_plane_stride,
-                 const void* b_coarse, void* stream) {
+int swe_amr_init(const swe_params* p, int32_t ratio, const swe_amr_rect* new_rects, int32_t n_new,
+                 int64_t max_cells, void* q_new, int64_t new_plane_stride, const void* b_new,
+                 const swe_amr_rect* old_rects, int32_t n_old, const void* q_old,
+                 int64_t old_plane_stride, const swe_amr_rect* coarse_rects, int32_t n_coarse,
+                 const void* q_coarse, int64_t coarse_plane_stride, const void* b_coarse,
+                 void* stream) {
     if (!p) return afail(SWE_EINVAL, "params is NULL");
     if (p->precision != SWE_F64 && p->precision != SWE_F32_DEV)
         return afail(SWE_EINVAL, "swe_amr_init: unknown precision");
-    if (nops < 0 || new_plane_stride < 1 || coarse_plane_stride < 1 ||
-        (q_old && old_plane_stride < 1))
-        return afail(SWE_EINVAL, "swe_amr_init: bad count or plane stride");
-    if (nops == 0) return SWE_OK;
-    if (!ops || !q_new || !b_new || !q_coarse || !b_coarse)
+    if (ratio < 1 || n_new < 0 || n_old < 0 || n_coarse < 0 || max_cells < 0 ||
+        new_plane_stride < 1 || coarse_plane_stride < 1 || (n_old > 0 && old_plane_stride < 1))
+        return afail(SWE_EINVAL, "swe_amr_init: bad ratio, count, size or plane stride");
+    if (n_new == 0 || max_cells == 0) return SWE_OK;
+    if (!new_rects || !q_new || !b_new || !coarse_rects || !q_coarse || !b_coarse ||
+        (n_old > 0 && (!old_rects || !q_old)))
         return afail(SWE_EINVAL, "swe_amr_init: null pointer");
-    if (q_new == q_coarse || q_new == q_old)
+    if (q_new == q_coarse || (n_old > 0 && q_new == q_old))
         return afail(SWE_EINVAL, "swe_amr_init: the new planes must differ from the sources");
-    swe::FillArgs a;
-    a.ops = ops;
-    a.nops = nops;
+    if (n_new > 65535) return afail(SWE_EINVAL, "swe_amr_init: more than 65535 new patches");
+    swe::FillArgs a{};
     a.qf = q_new;
     a.psf = new_plane_stride;
-    a.qcopy = q_old ? q_old : q_new;
-    a.pscopy = q_old ? old_plane_stride : new_plane_stride;
+    a.qcopy = n_old > 0 ? q_old : q_new;
+    a.pscopy = n_old > 0 ? old_plane_stride : new_plane_stride;
     a.bf = b_new;
     a.qco = q_coarse;
     a.qcn = q_coarse;
@@ -512,11 +594,20 @@ int swe_amr_init(const swe_params* p, const swe_amr_fill_op* ops, int64_t nops, 
     a.alpha = 1.0;
     a.drytol = p->drytol;
     a.sea = p->sea_level;
+    swe::InitArgs g;
+    g.nw = new_rects;
+    g.old = n_old > 0 ? old_rects : nullptr;
+    g.nold = n_old;
+    g.crs = coarse_rects;
+    g.ncrs = n_coarse;
+    g.ratio = ratio;
+    const int64_t bx64 = (max_cells + 255) / 256;
+    const dim3 grid((unsigned)(bx64 < 1024 ? bx64 : 1024), (unsigned)n_new);
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->precision == SWE_F64)
-        hipLaunchKernelGGL(swe::k_amr_fill<double>, dim3(grid_for(nops)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(swe::k_amr_init_rects<double>, grid, dim3(256), 0, st, a, g);
     else
-        hipLaunchKernelGGL(swe::k_amr_fill<float>, dim3(grid_for(nops)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(swe::k_amr_init_rects<float>, grid, dim3(256), 0, st, a, g);
     return check_launch("swe_amr_init");
 }
 

@@ -381,13 +381,20 @@ class AmrHierarchy:
 
 
 def _bed(kind: str, xc, yc, L, depth):
-    X, Y = np.meshgrid(xc, yc)
+    # each kind is separable, so the transcendental terms are taken per
+    # column and per row and broadcast (the same values, cell for cell, as
+    # taking them over the whole mesh)
+    xc, yc = np.asarray(xc), np.asarray(yc)
+    shape = (yc.size, xc.size)
     if kind == "flat":
-        return np.full(X.shape, -depth)
+        return np.full(shape, -depth)
     if kind == "bowl":  # deep everywhere, smooth, all wet
-        return -depth + 0.25 * depth * np.cos(2 * np.pi * X / L) * np.cos(2 * np.pi * Y / L)
+        cx = np.cos(2 * np.pi * xc / L)[None, :]
+        cy = np.cos(2 * np.pi * yc / L)[:, None]
+        return -depth + 0.25 * depth * cx * cy
     # "shelf": the tanh shelf along x with a dry coast past 0.8 L
-    return shelf_profile(X, 0.7 * L, 0.05 * L, deep=-depth)
+    row = shelf_profile(xc, 0.7 * L, 0.05 * L, deep=-depth)
+    return np.ascontiguousarray(np.broadcast_to(row[None, :], shape))
 
 
 def amr_hierarchy(rects, n1: int = 48, dx1: float = 2000.0, ratio: int = 2,

@@ -165,6 +165,9 @@ def test_amr_struct_layout_and_argument_errors(L, tmp_path):
 #include <stddef.h>
 #include "swe.h"
 int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu ", sizeof(swe_amr_rect), offsetof(swe_amr_rect, i0),
+         offsetof(swe_amr_rect, j0), offsetof(swe_amr_rect, mx), offsetof(swe_amr_rect, my),
+         offsetof(swe_amr_rect, pitch), offsetof(swe_amr_rect, reserved));
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %d %d\n", sizeof(swe_amr_fill_op),
          offsetof(swe_amr_fill_op, st), offsetof(swe_amr_fill_op, wx),
          offsetof(swe_amr_fill_op, wy), offsetof(swe_amr_fill_op, kind),
@@ -179,6 +182,10 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     from paper_1901_06798_amd import amr
+    R = L.AMR_RECT_DTYPE
+    assert vals[:7] == [R.itemsize] + [R.fields[k][1] for k in
+                                       ("i0", "j0", "mx", "my", "pitch", "reserved")]
+    vals = vals[7:]
     assert vals == [amr.FILL_DTYPE.itemsize, amr.FILL_DTYPE.fields["st"][1],
                     amr.FILL_DTYPE.fields["wx"][1], amr.FILL_DTYPE.fields["wy"][1],
                     amr.FILL_DTYPE.fields["kind"][1],
@@ -205,6 +212,20 @@ int main(void) {
                                None) == L.SWE_EINVAL
     assert lib.swe_amr_average(ctypes.byref(p), None, 3, 2, fake, 8, fake, other, 8, fake,
                                None) == L.SWE_EINVAL
+    # swe_amr_init: ratio >= 1, the new planes differ from the sources, the
+    # old table and planes given when n_old > 0; nothing new is no work
+    third = ctypes.c_void_p(0x3000)
+
+    def init(ratio=2, n_new=1, cells=16, qn=fake, n_old=1, qo=other, qc=third):
+        return lib.swe_amr_init(ctypes.byref(p), ratio, fake, n_new, cells, qn, 8, fake, fake,
+                                n_old, qo, 8, fake, 1, qc, 8, fake, None)
+    assert init(ratio=0) == L.SWE_EINVAL
+    assert init(qo=fake) == L.SWE_EINVAL
+    assert init(qc=fake) == L.SWE_EINVAL
+    assert init(qo=None) == L.SWE_EINVAL
+    assert init(n_new=0) == L.SWE_OK
+    assert init(cells=0) == L.SWE_OK
+    assert init(n_new=70000) == L.SWE_EINVAL
 
 
 def test_amr_plans_match_the_hierarchy(L):

@@ -1,10 +1,9 @@
-"""Host checks of the AMR coupling plans (no GPU): the ghost-cell plan
-(amr.fill_plan) and the new-cell plan (amr.init_plan), each evaluated by the
-rule that swe.h states for swe_amr_fill / swe_amr_init (a plain loop over the
-entries on pool-shaped host arrays), give cell for cell what the reference
-coupling gives (oracle/amr.py fill, oracle/regrid.py fill_new).  This pins
-the plans' stencil offsets, weights and copy/coarse choices; the device
-kernels then only have to follow the stated rule, which the GPU tests check."""
+"""Host checks of the AMR ghost-cell plan (no GPU): amr.fill_plan, evaluated
+by the rule that swe.h states for swe_amr_fill (a plain loop over the entries
+on pool-shaped host arrays), gives cell for cell what the reference coupling
+gives (oracle/amr.py fill).  This pins the plan's stencil offsets, weights and
+copy/coarse choices; the device kernel then only has to follow the stated
+rule, which the GPU tests check."""
 import numpy as np
 import pytest
 
@@ -139,37 +138,3 @@ def test_ghost_plan_by_the_stated_rule_equals_the_reference_fill(P, ratio, alpha
         coarse_ops = ops[ops["kind"] == L.SWE_AMR_COARSE]
         nlin = int(np.sum(np.all(coarse_ops["st"] >= 0, axis=1)))
         assert coarse_ops.size > 0 and nlin > 0
-
-
-@pytest.mark.parametrize("ratio", [2, 4])
-def test_new_cell_plan_by_the_stated_rule_equals_the_reference_regrid(P, ratio):
-    H = W.amr_three_levels(ratio, bed="shelf", amp=2.0, u0=0.3, n1=32)
-    h = A.Hierarchy(H, P)
-    h.run(6.0, 1)
-    margin = 2 if ratio == 1 else 1
-    for lev in (2, 3):
-        coarse = h.levels[lev - 2]
-        old = h.levels[lev - 1]
-        rects = G.new_rects(coarse, ratio, 5e-3, P.drytol, 2, margin)
-        assert rects
-        new = [G.fill_new(rc, lev, H, old, coarse, ratio, P.drytol) for rc in rects]
-        pc, po, pn = Pool(coarse), Pool(old), Pool(new)
-        ops = amr.init_plan(pn.geo, po.geo, pc.geo, ratio)
-        qn = np.zeros(3 * pn.plane)
-        bn = pn.pack([p.b for p in new], 1)
-        qo = po.pack([p.q for p in old], 3)
-        qc = pc.pack([p.q for p in coarse], 3)
-        bc = pc.pack([p.b for p in coarse], 1)
-        apply_fill(ops, qn, pn.plane, bn, qo, po.plane, qc, qc, pc.plane, bc, 1.0, P.drytol)
-        for k, p in enumerate(new):
-            got = pn.unpack(qn, k)[2:-2, 2:-2]
-            assert np.array_equal(got, p.q[2:-2, 2:-2]), (ratio, lev, k)
-        h.levels[lev - 1] = [_as_patch(p, H, lev) for p in new]
-
-
-def _as_patch(p, H, lev):
-    o = A.OPatch.__new__(A.OPatch)
-    o.level, o.i0, o.j0, o.mx, o.my = p.level, p.i0, p.j0, p.mx, p.my
-    o.q, o.b = p.q, p.b
-    o.g = O.grid(p.mx, p.my, H.dx(lev), H.dx(lev), (O.BC_USER,) * 4)
-    return o
