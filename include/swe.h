@@ -327,11 +327,22 @@ int swe_state_export(const swe_params *p, const swe_patch *patches, int32_t n, i
  * launch per substep (patches are independent, so substep s of every patch
  * with tref > s can run together; the launch boundary orders a patch's
  * substeps).
+ *
+ * seg = 0 packs strips of any width side by side into the waves: every task
+ * is plain (one launch per substep, as per_substep = 1), the rows of each
+ * patch are cut into equal runs of at most rows_per_task (0: 48), and the
+ * runs of patches of one tref, tallest first, are laid into 64 lanes left to
+ * right, a run's columns cut wherever a wave fills up (a segment of c
+ * columns takes c + 4 lanes, c >= 4 unless the patch is narrower).  A pack
+ * (one wave) is returned as an item: its tasks [task_begin, task_end) lie
+ * side by side from lane 0, `substeps` is the tref of its patches, patch is
+ * -1; items are ordered by tref, largest first.
  */
 typedef struct swe_schedule {
-    int32_t seg;             /* lanes per strip: 64 or 32 */
+    int32_t seg;             /* lanes per strip: 64 or 32; 0 = packed strips */
     int32_t rows_per_task;   /* rows per task; 0 = 32 for tref == 1, else enough
-                                tasks for the workgroup (at least 8 rows) */
+                                tasks for the workgroup (at least 8 rows); with
+                                seg = 0 the largest run of rows (0 = 48) */
     int32_t waves_per_group; /* waves per workgroup: 1, 2, 4 or 8 */
     int32_t per_substep;     /* 0: patches with substeps run as items of one
                                 persistent launch; 1: every patch's tasks are
@@ -343,9 +354,13 @@ typedef struct swe_schedule {
 
 typedef struct swe_task {
     int32_t patch;  /* index into the patch table */
-    int32_t strip;  /* first column of the strip is strip * (seg - 4) (ghosts included) */
+    int32_t strip;  /* strip index within the patch's row run */
     int32_t row0;   /* first updated row (2 = first interior row) */
     int32_t rows;   /* updated rows */
+    int32_t col0;   /* column of the segment's first lane (ghosts included):
+                       strip * (seg - 4) for seg 64 or 32 */
+    int32_t lanes;  /* lanes of the segment (seg, or 5 .. 64 with seg = 0);
+                       it updates columns col0 + 2 .. col0 + lanes - 3 */
 } swe_task;
 
 typedef struct swe_item {
@@ -360,7 +375,10 @@ typedef struct swe_item {
  * plain tasks take: 1, or the largest tref with per_substep = 1; 0 without
  * plain tasks); otherwise the arrays (host, sized from a previous query) are
  * filled: the items' tasks first, then the nplain plain tasks (ordered by
- * tref, largest first).  Fails with SWE_EINVAL for a bad patch or if a
+ * tref, largest first).  With seg = 0 the items are the packs and every
+ * task is plain (nplain = ntasks, in pack order); swe_batched_step then
+ * reads the packs from `items` and their tasks from `plain`.  Fails with
+ * SWE_EINVAL for a bad patch or if a
  * SWE_BC_USER side has tref > 1 (its ghost cells are not refreshed between
  * substeps). */
 int swe_batched_plan(const swe_patch *patches, int32_t n, const swe_schedule *sched,

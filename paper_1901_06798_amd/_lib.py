@@ -65,7 +65,7 @@ def launch(rows_per_task=0, waves_per_block=0, xcd_run=0) -> swe_launch:
 
 class swe_task(ctypes.Structure):
     _fields_ = [("patch", ctypes.c_int32), ("strip", ctypes.c_int32), ("row0", ctypes.c_int32),
-                ("rows", ctypes.c_int32)]
+                ("rows", ctypes.c_int32), ("col0", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 class swe_item(ctypes.Structure):

@@ -47,6 +47,9 @@ def candidates():
                                           groups_per_cu=per_cu))
             # one launch per substep, every task one wave
             out.append(L.schedule(seg=seg, rows_per_task=rows, per_substep=1))
+    # one launch per substep, strips of any width packed side by side
+    for rows in (16, 24, 32, 0):
+        out.append(L.schedule(seg=0, rows_per_task=rows, per_substep=1))
     return out
 
 

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
                 tk.mx = pt.mx;
                 tk.my = pt.my;
                 tk.c0 = tsk.strip * (SEG - 4);
+                tk.segw = SEG;
                 tk.U0 = tsk.row0;
                 tk.U1 = tsk.row0 + tsk.rows - 1;
                 tk.bc[0] = pt.bc[0];
@@ -197,6 +198,7 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
     tk.mx = pt.mx;
     tk.my = pt.my;
     tk.c0 = tsk.strip * (SEG - 4);
+    tk.segw = SEG;
     tk.U0 = tsk.row0;
     tk.U1 = tsk.row0 + tsk.rows - 1;
     tk.bc[0] = pt.bc[0];
@@ -226,6 +228,85 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
     if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
 }
 
+// Packed tasks (seg = 0): one wave per pack (an entry of `items`), its tasks
+// side by side from lane 0, each lane marching the task whose lanes hold it
+// (lanes past the last task only take part in the cross-lane moves).  The
+// launch runs substep `sub` of the pack's patches, which share one tref;
+// buffers alternate as in k_plain.  Each task reports to its own patch: a
+// suffix maximum within the segment leaves the segment's maximum in its
+// first lane.
+template <bool DEV, bool FRIC>
+__global__ void __launch_bounds__(64, (DEV ? 3 : 2) - (FRIC ? 1 : 0)) k_pack(BatchArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const swe_item pk = a.items[blockIdx.x];
+    if (a.sub >= pk.substeps) return;
+    int tid = pk.task_begin, seg_l0 = 0, lane0 = 0, maxrows = 0;
+    bool have = false;
+    for (int j = pk.task_begin; j < pk.task_end; ++j) {
+        const int w = a.tasks[j].lanes;
+        const int rows = a.tasks[j].rows;
+        if (!have && lane < lane0 + w) {
+            tid = j;
+            seg_l0 = lane0;
+            have = true;
+        }
+        lane0 += w;
+        maxrows = rows > maxrows ? rows : maxrows;
+    }
+    const swe_task tsk = a.tasks[tid];
+    const swe_patch pt = a.patches[tsk.patch];
+    const bool run = have && (!a.retake || a.retake[pt.group] != 0);
+    if (!__any(run)) return;
+    const int last = pk.substeps - 1;
+    Task tk;
+    tk.qin = a.sub == 0 ? a.pin : ((last - (a.sub - 1)) % 2 == 0 ? a.pout : a.pwork);
+    tk.qout = (last - a.sub) % 2 == 0 ? a.pout : a.pwork;
+    tk.b = a.pb;
+    tk.off = pt.off;
+    tk.ps = pt.plane_stride;
+    tk.dt = a.dt_group[pt.group] / (double)pt.tref;
+    tk.dx = pt.dx;
+    tk.dy = pt.dy;
+    tk.pitch = pt.pitch;
+    tk.mx = pt.mx;
+    tk.my = pt.my;
+    tk.c0 = tsk.col0;
+    tk.segw = tsk.lanes;
+    tk.U0 = tsk.row0;
+    tk.U1 = tsk.row0 + tsk.rows - 1;
+    tk.bc[0] = pt.bc[0];
+    tk.bc[1] = pt.bc[1];
+    tk.bc[2] = pt.bc[2];
+    tk.bc[3] = pt.bc[3];
+    tk.active = run;
+    tk.metric = nullptr;
+    const int steps = __builtin_amdgcn_readfirstlane(maxrows + 4);
+    const MarchOut r = march<DEV, 0, FRIC>(tk, a.P, have ? lane - seg_l0 : 0, steps);
+    // suffix maximum of the bit patterns within each segment (NaN propagates)
+    unsigned long long bx = run ? static_cast<unsigned long long>(__double_as_longlong(r.smx)) : 0ull;
+    unsigned long long by = run ? static_cast<unsigned long long>(__double_as_longlong(r.smy)) : 0ull;
+    const int seg_end = have ? seg_l0 + tsk.lanes : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long ox = static_cast<unsigned long long>(
+            __shfl_down(static_cast<long long>(bx), d, kWave));
+        const unsigned long long oy = static_cast<unsigned long long>(
+            __shfl_down(static_cast<long long>(by), d, kWave));
+        const bool in = lane + d < seg_end;
+        bx = in && ox > bx ? ox : bx;
+        by = in && oy > by ? oy : by;
+    }
+    if (run && lane == seg_l0) {
+        atomic_max_nonneg(&a.smax[2 * tsk.patch], __longlong_as_double(static_cast<long long>(bx)));
+        atomic_max_nonneg(&a.smax[2 * tsk.patch + 1],
+                          __longlong_as_double(static_cast<long long>(by)));
+    }
+    if (r.clamps) atomicAdd(&a.status[1], r.clamps);
+    if (r.flags) atomicOr(&a.status[0], r.flags);
+    if (a.group_status && run && r.clamps) atomicAdd(&a.group_status[2 * pt.group + 1], r.clamps);
+    if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
+}
+
 template __global__ void k_batched<false, 64, false>(BatchArgs);
 template __global__ void k_batched<false, 32, false>(BatchArgs);
 template __global__ void k_batched<true, 64, false>(BatchArgs);
@@ -242,6 +323,10 @@ template __global__ void k_plain<false, 64, true>(BatchArgs);
 template __global__ void k_plain<false, 32, true>(BatchArgs);
 template __global__ void k_plain<true, 64, true>(BatchArgs);
 template __global__ void k_plain<true, 32, true>(BatchArgs);
+template __global__ void k_pack<false, false>(BatchArgs);
+template __global__ void k_pack<true, false>(BatchArgs);
+template __global__ void k_pack<false, true>(BatchArgs);
+template __global__ void k_pack<true, true>(BatchArgs);
 
 }  // namespace swe
 
@@ -254,7 +339,8 @@ int bfail(int code, const std::string& msg);
 
 int check_sched(const swe_schedule* s) {
     if (!s) return bfail(SWE_EINVAL, "schedule is NULL");
-    if (s->seg != 64 && s->seg != 32) return bfail(SWE_EINVAL, "schedule: seg must be 64 or 32");
+    if (s->seg != 64 && s->seg != 32 && s->seg != 0)
+        return bfail(SWE_EINVAL, "schedule: seg must be 64, 32 or 0");
     if (s->waves_per_group != 1 && s->waves_per_group != 2 && s->waves_per_group != 4 &&
         s->waves_per_group != 8)
         return bfail(SWE_EINVAL, "schedule: waves_per_group must be 1, 2, 4 or 8");
@@ -284,9 +370,10 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
     if (rc) return rc;
     if (!patches || n < 0 || !nitems || !ntasks || !nplain || !nsub)
         return bfail(SWE_EINVAL, "swe_batched_plan: bad arguments");
-    const bool per_sub = sched->per_substep != 0;
+    const bool packed = sched->seg == 0;
+    const bool per_sub = sched->per_substep != 0 || packed;
     int max_tref = 0;
-    const int seg = sched->seg;
+    const int seg = packed ? 64 : sched->seg;
     const int out_cols = seg - 4;
     const int segs_per_group = sched->waves_per_group * (64 / seg);
     struct PItem {
@@ -296,6 +383,10 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
     std::vector<PItem> its;
     std::vector<swe_task> tks;    // tasks of the substep items
     std::vector<swe_task> plain;  // tasks of single-substep patches
+    struct Run {
+        int patch, row0, rows, tref;
+    };
+    std::vector<Run> runs;  // seg = 0: row runs of every patch
     for (int k = 0; k < n; ++k) {
         const swe_patch& p = patches[k];
         if (p.mx < 1 || p.my < 1 || p.pitch < p.mx + 4 || p.tref < 1 || !(p.dx > 0) ||
@@ -311,6 +402,19 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
             return bfail(SWE_EINVAL, "swe_batched_plan: a wall in x needs mx >= 2");
         if ((p.bc[2] == SWE_BC_WALL || p.bc[3] == SWE_BC_WALL) && p.my < 2)
             return bfail(SWE_EINVAL, "swe_batched_plan: a wall in y needs my >= 2");
+        if (packed) {
+            // equal runs of at most H rows; laid into packs below
+            const int H = sched->rows_per_task > 0 ? sched->rows_per_task : 48;
+            const int nch = (p.my + H - 1) / H;
+            int row = 2;
+            for (int cidx = 0; cidx < nch; ++cidx) {
+                const int r = p.my / nch + (cidx < p.my % nch ? 1 : 0);
+                runs.push_back(Run{k, row, r, p.tref});
+                row += r;
+            }
+            if (p.tref > max_tref) max_tref = p.tref;
+            continue;
+        }
         const int nstrips = (p.mx + out_cols - 1) / out_cols;
         const bool item = p.tref > 1 && !per_sub;
         int H = sched->rows_per_task;
@@ -337,6 +441,8 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
                 t.strip = st;
                 t.row0 = 2 + cidx * H;
                 t.rows = std::min(H, p.my - cidx * H);
+                t.col0 = st * out_cols;
+                t.lanes = seg;
                 dst.push_back(t);
             }
         if (item) {
@@ -347,13 +453,57 @@ int swe_batched_plan(const swe_patch* patches, int32_t n, const swe_schedule* sc
             its.push_back(pi);
         }
     }
-    if (sched->order == 0)
+    if (packed) {
+        // runs by tref, then height, largest first; each laid left to right
+        // into 64 lanes, its columns cut where a pack fills up (a segment of
+        // c columns takes c + 4 lanes; no cut leaves fewer than kMinCols
+        // columns to a segment unless the patch is narrower)
+        constexpr int kMinCols = 4;
+        std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) {
+            if (x.tref != y.tref) return x.tref > y.tref;
+            return x.rows > y.rows;
+        });
+        int free = 0;  // lanes left in the open pack
+        for (const Run& r : runs) {
+            if (!its.empty() && its.back().it.substeps != r.tref) free = 0;  // one tref per pack
+            const int mx = patches[r.patch].mx;
+            int col = 0, piece = 0;
+            while (col < mx) {
+                const int rem = mx - col;
+                if (free < 4 + std::min(rem, kMinCols)) {
+                    PItem pi;
+                    pi.it = swe_item{(int)plain.size(), (int)plain.size(), -1, r.tref};
+                    pi.cost = 0.0;
+                    its.push_back(pi);
+                    free = 64;
+                }
+                int take = std::min(rem, free - 4);
+                if (take < rem && rem - take < kMinCols) take = rem - kMinCols;
+                if (take < 1) {
+                    free = 0;
+                    continue;
+                }
+                swe_task t;
+                t.patch = r.patch;
+                t.strip = piece++;
+                t.row0 = r.row0;
+                t.rows = r.rows;
+                t.col0 = col;
+                t.lanes = take + 4;
+                plain.push_back(t);
+                its.back().it.task_end = (int)plain.size();
+                free -= take + 4;
+                col += take;
+            }
+        }
+    } else if (sched->order == 0)
         std::stable_sort(its.begin(), its.end(),
                          [](const PItem& x, const PItem& y) { return x.cost > y.cost; });
     // plain tasks by tref, largest first (a patch's tasks stay together)
-    std::stable_sort(plain.begin(), plain.end(), [&](const swe_task& x, const swe_task& y) {
-        return patches[x.patch].tref > patches[y.patch].tref;
-    });
+    if (!packed)
+        std::stable_sort(plain.begin(), plain.end(), [&](const swe_task& x, const swe_task& y) {
+            return patches[x.patch].tref > patches[y.patch].tref;
+        });
     const int32_t nt = (int32_t)(tks.size() + plain.size());
     *nsub = plain.empty() ? 0 : max_tref;
     if (!items || !tasks) {
@@ -439,10 +589,14 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
         return bfail(SWE_EINVAL, "swe_batched_step: bad counts");
     // items (patches with tref > 1) and per-substep launches alternate
     // between pool_out and pool_work
-    if ((nitems > 0 || nsub > 1) && !pool_work)
+    const bool packed = sched->seg == 0;
+    if (((nitems > 0 && !packed) || nsub > 1) && !pool_work)
         return bfail(SWE_EINVAL, "swe_batched_step: substeps need pool_work");
+    if (packed && nitems > 0 && nsub < 1)
+        return bfail(SWE_EINVAL, "swe_batched_step: packs need nsub >= 1");
     if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch || !status ||
-        (nitems > 0 && (!items || !tasks || !queue)) || (nplain > 0 && !plain))
+        (nitems > 0 && !items) || (nitems > 0 && !packed && (!tasks || !queue)) ||
+        ((nplain > 0 || (packed && nitems > 0)) && !plain))
         return bfail(SWE_EINVAL, "swe_batched_step: null pointer");
     if (pool_elems < 1) return bfail(SWE_EINVAL, "swe_batched_step: pool_elems must be >= 1");
     {
@@ -487,6 +641,22 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     const int si = sched->seg == 64 ? 0 : 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
     using Kern = void (*)(swe::BatchArgs);
+    if (sched->seg == 0) {
+        // packs: one wave each, one launch per substep
+        const Kern table[2][2] = {{swe::k_pack<false, false>, swe::k_pack<false, true>},
+                                  {swe::k_pack<true, false>, swe::k_pack<true, true>}};
+        swe::BatchArgs b = a;
+        b.tasks = plain;
+        for (int sub = 0; sub < nsub && nitems > 0; ++sub) {
+            b.sub = sub;
+            hipLaunchKernelGGL(table[dev ? 1 : 0][fric ? 1 : 0], dim3(nitems), dim3(64), 0, st,
+                               b);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return bfail(SWE_EHIP, std::string("swe_batched_step: ") + hipGetErrorString(e));
+        return SWE_OK;
+    }
     if (nitems > 0) {
         // substep items: persistent workgroups on the item queue
         // [precision][segment 64 / 32][friction]
@@ -564,7 +734,7 @@ int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
         return bfail(SWE_EINVAL, "swe_batched_step_static: precision must be SWE_F64 or SWE_F32_DEV");
     if (pool_elems < 1) return bfail(SWE_EINVAL, "swe_batched_step_static: pool_elems must be >= 1");
     const size_t esz = p->precision == SWE_F64 ? sizeof(double) : sizeof(float);
-    const bool work = nitems > 0 || nsub > 1;
+    const bool work = (nitems > 0 && sched && sched->seg != 0) || nsub > 1;
     if (work && (uint64_t)pool_elems > SWE_STATIC_WORK_BYTES / esz)
         return bfail(SWE_EINVAL,
                      "swe_batched_step_static: the pool (" + std::to_string(pool_elems) +

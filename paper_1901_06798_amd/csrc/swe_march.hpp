@@ -1,6 +1,8 @@
 // swe_march.hpp -- the split step of one strip of a patch, marched down its
 // rows by a segment of SEG lanes (SEG = 64: a whole wave64; SEG = 32: two
-// strips, possibly of different patches, share a wave).
+// strips, possibly of different patches, share a wave; SEG = 0: the task
+// states its own width, so strips of any width, each with its own halo
+// lanes, lie side by side in one wave).
 //
 // Qin, LeVeque & Motley, Sec. 2, dimensionally split x/y forms.  A segment
 // owns SEG adjacent columns and updates the SEG - 4 inner ones over a chunk of
@@ -155,6 +157,7 @@ struct Task {
     double dt, dx, dy;
     int pitch, mx, my;
     int c0;       // column (ghosts included) of the segment's first lane
+    int segw;     // lanes of the segment (read when SEG = 0; 5 .. kWave)
     int U0, U1;   // first and last row updated (ghost rows are 0, 1, my + 2, my + 3)
     int8_t bc[4];
     bool active;  // false: the lane only takes part in the cross-lane moves
@@ -261,6 +264,9 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     static_assert(RING == 0 || SEG == kWave, "the row ring serves whole-wave strips");
     static_assert((RING & (RING - 1)) == 0, "ring depth is a power of two");
     using S = typename Prec<DEV>::S;
+    // lane moves run over the whole wave unless segments have a fixed width
+    constexpr int LS = SEG ? SEG : kWave;
+    const int segw = SEG ? SEG : tk.segw;
     // arithmetic type: the storage type, or FP64 over FP32 storage (WIDE)
     using A = typename std::conditional<WIDE, double, S>::type;
     const S* __restrict__ qin = static_cast<const S*>(tk.qin);
@@ -269,8 +275,8 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     const int lane = lane_in_seg;
     const int c = tk.c0 + lane;  // column of this lane (ghosts included)
     const int cc = c < tk.mx + 3 ? c : tk.mx + 3;
-    const bool upd_col = tk.active && lane >= 2 && lane <= SEG - 3 && c <= tk.mx + 1;
-    const bool xedge_own = tk.active && lane >= 2 && lane <= SEG - 2 && c >= 2 && c <= tk.mx + 2;
+    const bool upd_col = tk.active && lane >= 2 && lane <= segw - 3 && c <= tk.mx + 1;
+    const bool xedge_own = tk.active && lane >= 2 && lane <= segw - 2 && c >= 2 && c <= tk.mx + 2;
     const int U0 = tk.U0, U1 = tk.U1;
     const A lamx = A(tk.dt / tk.dx), lamy = A(tk.dt / tk.dy);
     // rows U0 - 2 .. U1 + 2 of the task, one per lane (at most kWave of
@@ -283,7 +289,7 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
     const bool second = P.order >= 2;
     const int tlast = U1 - U0 + 4;
     // the segment's columns all lie inside the patch (no ghost column)
-    const bool cols_in = tk.c0 >= 2 && tk.c0 + SEG - 1 <= tk.mx + 1;
+    const bool cols_in = tk.c0 >= 2 && tk.c0 + segw - 1 <= tk.mx + 1;
 
     A smx = A(0), smy = A(0);
     uint32_t clamps = 0, flags = 0;
@@ -384,11 +390,12 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
 
         // ---- x-sweep of row R: lane k solves the edge between columns k-1, k
         Side<A> me = side_base_from<DEV, A, A>(q0, hu, hv, bb, P);
-        Side<A> lf = side_up<A, DEV, SEG>(me, P);
+        Side<A> lf = side_up<A, DEV, LS>(me, P);
         Waves<A> w;
         A qs[3];
-        // lane 0's edge (its left cell lies outside the segment) feeds nothing
-        if (SWE_QUIET && __all(lane == 0 || quiet_edge<DEV, A>(lf, me))) {
+        // lane 0's edge (its left cell lies outside the segment) feeds nothing,
+        // nor does a lane outside every task
+        if (SWE_QUIET && __all(lane == 0 || !tk.active || quiet_edge<DEV, A>(lf, me))) {
             // zero f-waves: the fluctuations and corrections are +0 and the
             // update returns Q itself, as the arithmetic below would
             quiet_waves(lf, me, P, w);
@@ -398,11 +405,11 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
         } else {
             ++work;
             side_finish(me);
-            lf.u = lane_up<SEG>(me.u);
-            lf.v = lane_up<SEG>(me.v);
-            lf.sq = lane_up<SEG>(me.sq);
-            const A lf_m = DEV ? lane_up<SEG>(hu) : A(0);
-            const A lf_t = DEV ? lane_up<SEG>(hv) : A(0);
+            lf.u = lane_up<LS>(me.u);
+            lf.v = lane_up<LS>(me.v);
+            lf.sq = lane_up<LS>(me.sq);
+            const A lf_m = DEV ? lane_up<LS>(hu) : A(0);
+            const A lf_t = DEV ? lane_up<LS>(hv) : A(0);
             solve_edge<DEV, A>(lf, me, lf_m, lf_t, hu, hv, P, w);
             A am[3], ap[3];
             fluctuations(w, am, ap);
@@ -411,13 +418,13 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 A dr[3], dl[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
-                    const A zr0 = lane_down<SEG>(w.z[p][0]);
-                    const A zr1 = lane_down<SEG>(w.z[p][1]);
-                    const A zr2 = lane_down<SEG>(w.z[p][2]);
+                    const A zr0 = lane_down<LS>(w.z[p][0]);
+                    const A zr1 = lane_down<LS>(w.z[p][1]);
+                    const A zr2 = lane_down<LS>(w.z[p][2]);
                     dr[p] = w.z[p][0] * zr0 + w.z[p][1] * zr1 + w.z[p][2] * zr2;
                 }
 #pragma unroll
-                for (int p = 0; p < 3; ++p) dl[p] = lane_up<SEG>(dr[p]);
+                for (int p = 0; p < 3; ++p) dl[p] = lane_up<LS>(dr[p]);
                 if (SPH) {
                     correction(w, dl, dr, A(lamx * lane_read(ik_l, R - rbase)), F);
                 } else {
@@ -430,14 +437,14 @@ __device__ __forceinline__ MarchOut march(const Task& tk, const DevParams& P, in
                 // positivity limit: the donor of this lane's edge is the left
                 // cell (lane k - 1) for a positive mass correction, else this
                 // lane's cell; h1 = depth after the first-order part of the update
-                const A h1 = me.h - lx * (ap[0] + lane_down<SEG>(am[0]));
-                const A h1l = lane_up<SEG>(h1);
+                const A h1 = me.h - lx * (ap[0] + lane_down<LS>(am[0]));
+                const A h1l = lane_up<LS>(h1);
                 drain_limit(F, F[0] > A(0) ? h1l : h1, lx, A(1));
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const A amr = lane_down<SEG>(am[k]);
-                const A Fr = lane_down<SEG>(F[k]);
+                const A amr = lane_down<LS>(am[k]);
+                const A Fr = lane_down<LS>(F[k]);
                 qs[k] = qc[k] - lx * (ap[k] + amr) - lx * (Fr - F[k]);
             }
         }

@@ -116,6 +116,7 @@ __device__ __forceinline__ void split_task(const StepArgs& a) {
     tk.mx = a.mx;
     tk.my = a.my;
     tk.c0 = (item % a.nstrips) * kStripOut;
+    tk.segw = kWave;
     tk.U0 = 2 + (item / a.nstrips) * a.H;
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];
@@ -181,6 +182,7 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     tk.mx = a.mx;
     tk.my = a.my;
     tk.c0 = (item % a.nstrips) * kStripOut;
+    tk.segw = kWave;
     tk.U0 = 2 + (item / a.nstrips) * a.H;
     tk.U1 = min(tk.U0 + a.H - 1, a.my + 1);
     for (int s = 0; s < 4; ++s) tk.bc[s] = a.bc[s];

@@ -33,7 +33,7 @@ def mixed_problems():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("seg,rows", [(64, 0), (32, 0), (64, 7)])
+@pytest.mark.parametrize("seg,rows", [(64, 0), (32, 0), (64, 7), (0, 0), (0, 7)])
 def test_batched_equals_single_bitwise(gpu, precision, seg, rows):
     L, BatchedSolver, PatchSolver, torch = gpu
     probs = mixed_problems()
@@ -89,7 +89,7 @@ def test_amr_patch_set_matches_reference(gpu, orc):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("seg,per_substep", [(32, 0), (64, 1), (32, 1)])
+@pytest.mark.parametrize("seg,per_substep", [(32, 0), (64, 1), (32, 1), (0, 1)])
 def test_amr_substeps_equal_single_patch_bitwise(gpu, precision, seg, per_substep):
     L, BatchedSolver, PatchSolver, torch = gpu
     specs, probs, trefs = amr_set(seed=5, counts=(3, 4, 5))
@@ -113,11 +113,11 @@ def test_amr_substeps_equal_single_patch_bitwise(gpu, precision, seg, per_subste
             assert np.array_equal(a, c), f"patch {k} tref {t}"
 
 
-@pytest.mark.parametrize("per_substep", [0, 1])
-def test_graph_replay_matches_eager(gpu, per_substep):
+@pytest.mark.parametrize("seg,per_substep", [(64, 0), (64, 1), (0, 1)])
+def test_graph_replay_matches_eager(gpu, seg, per_substep):
     L, BatchedSolver, PatchSolver, torch = gpu
     specs, probs, trefs = amr_set(seed=7, counts=(4, 6, 8))
-    sched = L.schedule(per_substep=per_substep)
+    sched = L.schedule(seg=seg, per_substep=per_substep)
     eager = BatchedSolver(probs, L.params(), trefs=trefs, sched=sched)
     eager.initial_dt()
     graph = BatchedSolver(probs, L.params(), trefs=trefs, sched=sched)

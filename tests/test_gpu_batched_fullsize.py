@@ -80,7 +80,7 @@ def test_coarse_dt_follows_the_cfl_rule_over_all_patches(full_set, orc):
 
 def test_graph_replay_and_another_schedule_equal_the_eager_run(full_set):
     L, BatchedSolver, torch, specs, probs, trefs, bs, dts = full_set
-    print("case full AMR patch set: graph replay, then seg 32 per substep", flush=True)
+    print("case full AMR patch set: graph replay, seg 32 per substep, packed", flush=True)
     g = BatchedSolver(probs, L.params(), trefs=trefs, sched=L.schedule(seg=64, waves_per_group=4))
     g.initial_dt()
     g.capture(NCOARSE)
@@ -88,11 +88,14 @@ def test_graph_replay_and_another_schedule_equal_the_eager_run(full_set):
     o = BatchedSolver(probs, L.params(), trefs=trefs, sched=L.schedule(seg=32, per_substep=1))
     o.initial_dt()
     o.run(NCOARSE)
+    pk = BatchedSolver(probs, L.params(), trefs=trefs, sched=L.schedule(seg=0))
+    pk.initial_dt()
+    pk.run(NCOARSE)
     torch.cuda.synchronize()
     for k in range(len(probs)):
         want = bs.state(k)
-        for a, c, w in zip(g.state(k), o.state(k), want):
-            assert np.array_equal(a, w) and np.array_equal(c, w), k
+        for a, c, d, w in zip(g.state(k), o.state(k), pk.state(k), want):
+            assert np.array_equal(a, w) and np.array_equal(c, w) and np.array_equal(d, w), k
 
 
 def test_fp32_batched_within_1e5_m_of_fp64(full_set):

@@ -60,13 +60,15 @@ def test_device_retake_equals_host_retake(gpu, orc, precision):
             assert np.array_equal(a, ref[..., k])
 
 
-def test_batched_retake_redoes_only_the_offending_group(gpu):
+@pytest.mark.parametrize("seg", [64, 0])
+def test_batched_retake_redoes_only_the_offending_group(gpu, seg):
     L, PatchSolver, BatchedSolver, torch = gpu
     probs = [W.gaussian_hump(64 + 16 * k, 1000.0, sigma=6e3) for k in range(4)]
     p = L.params()
     factors = [1.0, 2.2, 1.0, 1.6]
-    print("case batched retake, 4 patches, groups 1 and 3 start above the limit", flush=True)
-    bs = BatchedSolver(probs, p, groups=list(range(len(probs))))
+    print(f"case batched retake seg={seg}, 4 patches, groups 1 and 3 start above the limit",
+          flush=True)
+    bs = BatchedSolver(probs, p, groups=list(range(len(probs))), sched=L.schedule(seg=seg))
     bs.initial_dt()
     bs.dt.mul_(torch.tensor(factors, dtype=torch.float64, device=bs.dev))
     bs.run(10)

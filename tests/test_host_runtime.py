@@ -55,6 +55,7 @@ def test_plan_covers_every_cell_once(L, seg, per_substep):
         t = tasks[k]
         p = pts[t.patch]
         c0 = t.strip * (seg - 4) + 2
+        assert t.col0 == t.strip * (seg - 4) and t.lanes == seg
         for r in range(t.row0, t.row0 + t.rows):
             for c in range(c0, min(c0 + seg - 4, p.mx + 2)):
                 cover[(t.patch, r, c)] = cover.get((t.patch, r, c), 0) + 1
@@ -81,6 +82,47 @@ def test_plan_covers_every_cell_once(L, seg, per_substep):
     assert trefs == sorted(trefs, reverse=True)
     # plain tasks are at most 32 rows by default
     assert all(tasks[k].rows <= 32 for k in range(nt - npl, nt))
+
+
+@pytest.mark.parametrize("rows", [0, 7, 32, 96])
+def test_packed_plan_covers_every_cell_once(L, rows):
+    # seg = 0: packs of side-by-side segments; every interior cell of every
+    # patch is updated by exactly one task, packs hold at most 64 lanes and
+    # one tref, and runs are laid tallest first within a tref
+    specs, pts = amr_patches(L, (9, 23, 41))
+    plan = L.swe_batched_plan(pts, L.schedule(seg=0, rows_per_task=rows))
+    items, ni, tasks, nt, npl = plan.items, plan.nitems, plan.tasks, plan.ntasks, plan.nplain
+    assert npl == nt and ni > 0 and plan.nsub == max(p.tref for p in pts)
+    cover = {}
+    H = rows or 48
+    prev_tref, prev_rows = None, None
+    for i in range(ni):
+        it = items[i]
+        assert it.patch == -1 and it.task_end > it.task_begin
+        if i > 0:
+            assert it.task_begin == items[i - 1].task_end
+        assert sum(tasks[k].lanes for k in range(it.task_begin, it.task_end)) <= 64
+        for k in range(it.task_begin, it.task_end):
+            t = tasks[k]
+            p = pts[t.patch]
+            assert p.tref == it.substeps
+            assert 5 <= t.lanes <= 64 and 0 <= t.col0 and t.col0 + t.lanes - 4 <= p.mx
+            assert 1 <= t.rows <= H and 2 <= t.row0 and t.row0 + t.rows <= p.my + 2
+            # runs of one patch differ by at most one row
+            assert t.rows in (-(-p.my // -(-p.my // H)), p.my // -(-p.my // H))
+            if prev_tref is not None:
+                assert (p.tref, t.rows) <= (prev_tref, prev_rows) or p.tref < prev_tref
+            prev_tref, prev_rows = p.tref, t.rows
+            # a cut leaves at least 4 columns unless the patch is narrower
+            assert t.lanes - 4 >= min(4, p.mx)
+            for r in range(t.row0, t.row0 + t.rows):
+                for c in range(t.col0 + 2, t.col0 + t.lanes - 2):
+                    cover[(t.patch, r, c)] = cover.get((t.patch, r, c), 0) + 1
+    assert items[ni - 1].task_end == nt
+    assert len(cover) == sum(p.mx * p.my for p in pts) and set(cover.values()) == {1}
+    # the packs use most of their lanes
+    used = sum(tasks[k].lanes for k in range(nt))
+    assert used / (64 * ni) > 0.85
 
 
 def test_plan_orders_longest_first(L):

@@ -73,9 +73,10 @@ def test_static_step_equals_the_step_with_caller_buffers(gpu, precision):
     assert n2 < n1 and e2 < e1
 
 
-def test_static_step_per_substep_launches(gpu):
+@pytest.mark.parametrize("seg", [64, 0])
+def test_static_step_per_substep_launches(gpu, seg):
     L, BatchedSolver, torch = gpu
-    sched = L.schedule(per_substep=1)
+    sched = L.schedule(seg=seg, per_substep=1)
     compare(L, BatchedSolver, torch, 5, (4, 6, 8), L.F64, sched)
     compare(L, BatchedSolver, torch, 6, (1, 2, 3), L.F64, sched)
 
