@@ -414,9 +414,9 @@ def cpu_baseline(pb, seconds: float, single_seconds: float = 8.0):
 def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere: bool = False):
     """Time `steps` steps of one patch; kernel time from HIP events around each
     step launch on the launch stream (the sort of the heaviest-first order,
-    when due, runs after the bracket, inside the timed loop).  sphere: a
-    latitude-longitude patch (SphereSolver; its CFL rule without the device
-    retake, which would redo a Cartesian step)."""
+    when due, runs after the bracket, inside the timed loop), then the CFL
+    rule with its gated retake on the device.  sphere: a latitude-longitude
+    patch (SphereSolver)."""
     import torch
 
     from paper_1901_06798_amd import _lib as L
@@ -445,19 +445,13 @@ def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere
                       stream.cuda_stream)
         ev1[k].record(stream)
         s.after_step(stream.cuda_stream)
-        if sphere:
-            L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(),
-                             s.dt.data_ptr(), s.status.data_ptr(), 0, 0, stream.cuda_stream)
-            s.cur ^= 1
-            continue
         # CFL rule with the retake on the device (a gated launch that does
         # nothing unless the step went above cfl_max)
         L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
                          s.status.data_ptr(), 0, 0, stream.cuda_stream,
                          retake=s.retake.data_ptr())
-        L.swe_patch_retake(s.p, s.pt, s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(),
-                           s.b.data_ptr(), s.dt.data_ptr(), s.smax.data_ptr(),
-                           s.status.data_ptr(), s.retake.data_ptr(), stream.cuda_stream)
+        s.launch_retake(s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(), s.retake.data_ptr(),
+                        stream.cuda_stream)
         L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
                          s.status.data_ptr(), 0, 0, stream.cuda_stream)
         s.cur ^= 1

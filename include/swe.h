@@ -231,6 +231,38 @@ int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const voi
                           uint32_t *status, const double *metric, uint32_t *sched,
                           int64_t sched_len, const swe_launch *launch, void *stream);
 
+/* swe_patch_retake on a latitude-longitude patch: the same gated redo of the
+ * step (Sec. 2, a step above the Courant limit is redone with a smaller
+ * step), launching swe_patch_step_sphere's step with `metric` (device, as
+ * there) in index order.  The speeds that swe_patch_step_sphere max-combines
+ * into smax are scaled by the edges' inverse capacities, so the
+ * swe_cfl_reduce between the step and this call tests the Courant number on
+ * the sphere.  Arguments otherwise as swe_patch_retake; FP64 split step
+ * only. */
+int swe_patch_retake_sphere(const swe_params *p, const swe_patch *patch, const void *q_in,
+                            void *q_out, const void *b, const double *dt, double *smax,
+                            uint32_t *status, const double *metric, const uint32_t *retake,
+                            void *stream);
+
+/* swe_speed_scan on one latitude-longitude patch (`patch`: device array of
+ * one patch; metric: device, as for swe_patch_step_sphere): each edge's
+ * largest |s| is scaled as swe_patch_step_sphere reports it, by 1 / kappa of
+ * the row for an x-edge and by the mean of the two rows' 1 / kappa for a
+ * y-edge, and the maxima over the interior cells' edges are max-combined into
+ * smax[0] (x) and smax[1] (y).  With swe_cfl_reduce (initial = 1) this gives
+ * the first step size on the sphere.  max_mx, max_my: the patch's mx, my (or
+ * larger; they size the launch).  FP64 split step only. */
+int swe_speed_scan_sphere(const swe_params *p, const swe_patch *patch, int32_t max_mx,
+                          int32_t max_my, const void *q, const void *b, const double *metric,
+                          double *smax, void *stream);
+
+/* Water volume of one latitude-longitude patch (`patch`: device array of one
+ * patch): sum over the interior of h kappa_j dx dy, kappa_j the capacity of
+ * row j from `metric` (a cell's area is kappa_j dx dy), in FP64 with the
+ * fixed reduction order of swe_mass, written to *mass (device).  FP64 only. */
+int swe_mass_sphere(const swe_params *p, const swe_patch *patch, const void *q,
+                    const double *metric, double *mass, void *stream);
+
 /* Number of strip tasks (waves) of one step of `patch` (host) with the
  * launch shape `launch` (host, NULL = defaults), or SWE_EINVAL for a bad
  * patch or shape.  The schedule buffer of swe_patch_step_sched holds twice

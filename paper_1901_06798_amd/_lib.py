@@ -124,6 +124,10 @@ def lib():
         L.swe_patch_order.argtypes = [ctypes.POINTER(swe_patch), _P, i64, pl, _P]
         L.swe_patch_step_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
                                             _P, _P, _P, i64, pl, _P]
+        L.swe_patch_retake_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
+                                              _P, _P, _P, _P]
+        L.swe_speed_scan_sphere.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, _P]
+        L.swe_mass_sphere.argtypes = [pp, _P, _P, _P, _P, _P]
         L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, i64, i64, _P, _P, _P]
         L.swe_state_export.argtypes = [pp, _P, i32, i32, i32, _P, _P, _P, i64, i64, _P]
         L.swe_amr_fill.argtypes = [pp, _P, i64, _P, i64, _P, _P, _P, i64, _P, dbl, _P]
@@ -149,7 +153,8 @@ def lib():
                      "swe_batched_retake", "swe_patch_step_sched", "swe_patch_order",
                      "swe_amr_fill", "swe_amr_average", "swe_amr_flag", "swe_amr_cluster",
                      "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
-                     "swe_state_export", "swe_batched_step_static", "swe_level_steps"):
+                     "swe_state_export", "swe_batched_step_static", "swe_level_steps",
+                     "swe_patch_retake_sphere", "swe_speed_scan_sphere", "swe_mass_sphere"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -308,6 +313,26 @@ def swe_patch_retake(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int
                      smax: int, status: int, retake: int, stream: int = 0) -> None:
     _check(lib().swe_patch_retake(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
                                   status, retake, stream), "swe_patch_retake")
+
+
+def swe_patch_retake_sphere(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int,
+                            dt: int, smax: int, status: int, metric: int, retake: int,
+                            stream: int = 0) -> None:
+    _check(lib().swe_patch_retake_sphere(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
+                                         smax, status, metric, retake, stream),
+           "swe_patch_retake_sphere")
+
+
+def swe_speed_scan_sphere(p: swe_params, patch: int, max_mx: int, max_my: int, q: int, b: int,
+                          metric: int, smax: int, stream: int = 0) -> None:
+    _check(lib().swe_speed_scan_sphere(ctypes.byref(p), patch, max_mx, max_my, q, b, metric,
+                                       smax, stream), "swe_speed_scan_sphere")
+
+
+def swe_mass_sphere(p: swe_params, patch: int, q: int, metric: int, mass: int,
+                    stream: int = 0) -> None:
+    _check(lib().swe_mass_sphere(ctypes.byref(p), patch, q, metric, mass, stream),
+           "swe_mass_sphere")
 
 
 def swe_mass(p: swe_params, patches: int, n: int, q: int, b: int, mass_patch: int,

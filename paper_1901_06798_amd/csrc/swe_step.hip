@@ -378,10 +378,13 @@ __global__ void __launch_bounds__(256) k_ghost_fill(const swe_patch* __restrict_
 }
 
 // Largest speeds over the x- and y-edges of the interior cells of each patch.
+// metric (latitude-longitude patch, FP64): each speed is scaled as the
+// split step reports it, by 1 / kappa of the row for an x-edge and by the
+// mean of its two rows' 1 / kappa for a y-edge.
 template <bool DEV>
 __global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict__ patches,
                                                     const void* qv, const void* bv, double* smax,
-                                                    DevParams P) {
+                                                    DevParams P, const double* metric) {
     using S = typename Prec<DEV>::S;
     const S* __restrict__ q = static_cast<const S*>(qv);
     const S* __restrict__ b = static_cast<const S*>(bv);
@@ -406,24 +409,35 @@ __global__ void __launch_bounds__(256) k_speed_scan(const swe_patch* __restrict_
             cl.s = side_from<DEV, S, S>(q0, cl.m, cl.t, b[s.idx], P);
             return cl;
         };
+        // 1 / kappa of rows R - 1, R, R + 1 (1 without a metric)
+        double ik[3] = {1.0, 1.0, 1.0};
+        if (metric) {
+            ik[0] = 1.0 / metric[R - 1];
+            ik[1] = 1.0 / metric[R];
+            ik[2] = 1.0 / metric[R + 1];
+        }
+        auto scaled = [&](const Waves<S>& w, double f) {
+            const double s = double(max_speed(w));
+            return metric ? s * f : s;
+        };
         Waves<S> w;
         const Cell me = load(R, c, false);
         Cell o = load(R, c - 1, false);
         solve_edge<DEV, S>(o.s, me.s, o.m, o.t, me.m, me.t, P, w);
-        sx = fmax(sx, double(max_speed(w)));
+        sx = fmax(sx, scaled(w, ik[1]));
         if (c == v.mx + 1) {
             o = load(R, c + 1, false);
             solve_edge<DEV, S>(me.s, o.s, me.m, me.t, o.m, o.t, P, w);
-            sx = fmax(sx, double(max_speed(w)));
+            sx = fmax(sx, scaled(w, ik[1]));
         }
         const Cell mey = load(R, c, true);
         o = load(R - 1, c, true);
         solve_edge<DEV, S>(o.s, mey.s, o.m, o.t, mey.m, mey.t, P, w);
-        sy = fmax(sy, double(max_speed(w)));
+        sy = fmax(sy, scaled(w, 0.5 * (ik[0] + ik[1])));
         if (R == v.my + 1) {
             o = load(R + 1, c, true);
             solve_edge<DEV, S>(mey.s, o.s, mey.m, mey.t, o.m, o.t, P, w);
-            sy = fmax(sy, double(max_speed(w)));
+            sy = fmax(sy, scaled(w, 0.5 * (ik[1] + ik[2])));
         }
     }
     sx = wave_max_nonneg(sx);
@@ -489,11 +503,13 @@ __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict_
 }
 
 // Water volume per patch, FP64, fixed reduction order.  On the deviation
-// path the depth is eta' + sea_level - b, formed in FP64.
+// path the depth is eta' + sea_level - b, formed in FP64.  metric
+// (latitude-longitude patch): each depth weighted by its row's capacity.
 template <bool DEV>
 __global__ void __launch_bounds__(256) k_mass(const swe_patch* __restrict__ patches,
                                               const void* qv, const void* bv,
-                                              double* __restrict__ mass, double sea_level) {
+                                              double* __restrict__ mass, double sea_level,
+                                              const double* metric) {
     using S = typename Prec<DEV>::S;
     const S* __restrict__ q = static_cast<const S*>(qv);
     const S* __restrict__ b = static_cast<const S*>(bv);
@@ -506,7 +522,8 @@ __global__ void __launch_bounds__(256) k_mass(const swe_patch* __restrict__ patc
         const int c = 2 + (int)(k % p.mx);
         const int R = 2 + (int)(k / p.mx);
         const int64_t i = p.off + (int64_t)R * p.pitch + c;
-        s += DEV ? (double(q[i]) + sea_level) - double(b[i]) : double(q[i]);
+        const double h = DEV ? (double(q[i]) + sea_level) - double(b[i]) : double(q[i]);
+        s += metric ? h * metric[R] : h;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -842,6 +859,21 @@ int swe_patch_retake(const swe_params* p, const swe_patch* patch, const void* q_
                       patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream);
 }
 
+int swe_patch_retake_sphere(const swe_params* p, const swe_patch* patch, const void* q_in,
+                            void* q_out, const void* b, const double* dt, double* smax,
+                            uint32_t* status, const double* metric, const uint32_t* retake,
+                            void* stream) {
+    if (!retake) return fail(SWE_EINVAL, "swe_patch_retake_sphere: null retake flags");
+    if (!metric) return fail(SWE_EINVAL, "swe_patch_retake_sphere: null metric");
+    if (patch && patch->group < 0)
+        return fail(SWE_EINVAL, "swe_patch_retake_sphere: negative group");
+    if (p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
+        return fail(SWE_EINVAL, "swe_patch_retake_sphere: FP64 split step only");
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
+                      patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream,
+                      metric);
+}
+
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,
                    int32_t max_my, void* q, void* b, int32_t fill_b, void* stream) {
     int rc = check_params(p);
@@ -876,11 +908,11 @@ int swe_speed_scan(const swe_params* p, const swe_patch* patches, int32_t n, int
     if (p->precision == SWE_F64)
         hipLaunchKernelGGL(swe::k_speed_scan<false>, dim3(bx, n), dim3(256), 0,
                            static_cast<hipStream_t>(stream), patches, q, b, smax_patch,
-                           dev_params(p));
+                           dev_params(p), nullptr);
     else
         hipLaunchKernelGGL(swe::k_speed_scan<true>, dim3(bx, n), dim3(256), 0,
                            static_cast<hipStream_t>(stream), patches, q, b, smax_patch,
-                           dev_params(p));
+                           dev_params(p), nullptr);
     return check_launch("swe_speed_scan");
 }
 
@@ -916,12 +948,47 @@ int swe_mass(const swe_params* p, const swe_patch* patches, int32_t n, const voi
     if (p->precision == SWE_F64)
         hipLaunchKernelGGL(swe::k_mass<false>, dim3(n), dim3(256), 0,
                            static_cast<hipStream_t>(stream), patches, q, b, mass_patch,
-                           p->sea_level);
+                           p->sea_level, nullptr);
     else
         hipLaunchKernelGGL(swe::k_mass<true>, dim3(n), dim3(256), 0,
                            static_cast<hipStream_t>(stream), patches, q, b, mass_patch,
-                           p->sea_level);
+                           p->sea_level, nullptr);
     return check_launch("swe_mass");
+}
+
+static int sphere_args(const swe_params* p, const char* what) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->method != SWE_SPLIT || p->precision != SWE_F64)
+        return fail(SWE_EINVAL, std::string(what) + ": FP64 split step only");
+    return SWE_OK;
+}
+
+int swe_speed_scan_sphere(const swe_params* p, const swe_patch* patch, int32_t max_mx,
+                          int32_t max_my, const void* q, const void* b, const double* metric,
+                          double* smax, void* stream) {
+    int rc = sphere_args(p, "swe_speed_scan_sphere");
+    if (rc) return rc;
+    if (!patch || !q || !b || !metric || !smax || max_mx < 1 || max_my < 1)
+        return fail(SWE_EINVAL, "swe_speed_scan_sphere: bad arguments");
+    const int64_t ncell = (int64_t)max_mx * max_my;
+    int bx = (int)((ncell + 255) / 256);
+    if (bx > 4096) bx = 4096;
+    hipLaunchKernelGGL(swe::k_speed_scan<false>, dim3(bx, 1), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), patch, q, b, smax, dev_params(p),
+                       metric);
+    return check_launch("swe_speed_scan_sphere");
+}
+
+int swe_mass_sphere(const swe_params* p, const swe_patch* patch, const void* q,
+                    const double* metric, double* mass, void* stream) {
+    int rc = sphere_args(p, "swe_mass_sphere");
+    if (rc) return rc;
+    if (!patch || !q || !metric || !mass) return fail(SWE_EINVAL, "swe_mass_sphere: bad arguments");
+    hipLaunchKernelGGL(swe::k_mass<false>, dim3(1), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), patch, q, nullptr, mass, p->sea_level,
+                       metric);
+    return check_launch("swe_mass_sphere");
 }
 
 static int state_grid(int32_t n, int32_t max_mx, int32_t max_my, dim3* grid) {

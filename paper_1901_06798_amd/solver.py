@@ -110,11 +110,15 @@ class PatchSolver:
         L.swe_ghost_fill(self.p, self.pt_dev.data_ptr(), 1, self.mx, self.my,
                          self.q[self.cur].data_ptr(), self.b.data_ptr(), int(fill_b), self.stream)
 
-    def initial_dt(self) -> None:
-        self.smax.zero_()
+    def launch_scan(self) -> None:
+        """Speeds of the current state's Riemann problems into smax."""
         L.swe_speed_scan(self.p, self.pt_dev.data_ptr(), 1, self.mx, self.my,
                          self.q[self.cur].data_ptr(), self.b.data_ptr(), self.smax.data_ptr(),
                          self.stream)
+
+    def initial_dt(self) -> None:
+        self.smax.zero_()
+        self.launch_scan()
         L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
                          self.dt.data_ptr(), self.status.data_ptr(), 0, 1, self.stream)
 
@@ -128,6 +132,12 @@ class PatchSolver:
         else:
             L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                              self.smax.data_ptr(), self.status.data_ptr(), st)
+
+    def launch_retake(self, qi: int, qo: int, retake: int, stream: int | None = None) -> None:
+        """The gated redo of the step q_in -> q_out with the reduced dt."""
+        L.swe_patch_retake(self.p, self.pt, qi, qo, self.b.data_ptr(), self.dt.data_ptr(),
+                           self.smax.data_ptr(), self.status.data_ptr(), retake,
+                           self.stream if stream is None else stream)
 
     def launch_order(self, stream: int | None = None) -> None:
         """Next step's launch order from this step's work (ordered solvers)."""
@@ -157,9 +167,7 @@ class PatchSolver:
                              self.dt.data_ptr(), self.status.data_ptr(), 0, 0, self.stream,
                              retake=rt)
             if retake:
-                L.swe_patch_retake(self.p, self.pt, qi, qo, self.b.data_ptr(),
-                                   self.dt.data_ptr(), self.smax.data_ptr(),
-                                   self.status.data_ptr(), rt, self.stream)
+                self.launch_retake(qi, qo, rt)
                 L.swe_cfl_reduce(self.p, self.pt_dev.data_ptr(), 1, 1, self.smax.data_ptr(),
                                  self.dt.data_ptr(), self.status.data_ptr(), 0, 0, self.stream)
         self.cur ^= 1

@@ -6,8 +6,9 @@ The capacities and edge length ratios come from the sphere's geometry: a row's
 cells cover R^2 dlon (sin phi_top - sin phi_bottom), so its capacity (area over
 the area of the same cells at the equator) is (sin phi_top - sin phi_bottom) /
 dlat (angles in radians), and a parallel edge is cos(phi) times as long as at
-the equator.  The CFL rule of the solver holds: the kernel reports speeds
-scaled by the edges' mean inverse capacity.
+the equator.  The CFL rule of the solver holds, on the device as for a
+Cartesian patch: the step, the retake and the first step's speed scan report
+speeds scaled by the edges' mean inverse capacity.
 """
 from __future__ import annotations
 
@@ -59,14 +60,13 @@ class SphereSolver(PatchSolver):
             raise L.SweError("SphereSolver: the patch with its ghost rows must not reach a pole")
         super().__init__(pb, p, device, ordered=ordered, order_every=order_every)
         m = metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
-        self.kappa_min = float(m[: pb.my + 4].min())
         self.metric = torch.from_numpy(m).to(self.dev)
 
-    def initial_dt(self) -> None:
-        # the scan's speeds are those of the Cartesian step; an edge's rate
-        # here is at most 1 / min(kappa) times as large
-        super().initial_dt()
-        self.dt.mul_(self.kappa_min)
+    def launch_scan(self) -> None:
+        # each edge's speed scaled by its inverse capacity, as the step reports it
+        L.swe_speed_scan_sphere(self.p, self.pt_dev.data_ptr(), self.mx, self.my,
+                                self.q[self.cur].data_ptr(), self.b.data_ptr(),
+                                self.metric.data_ptr(), self.smax.data_ptr(), self.stream)
 
     def launch_step(self, qi: int, qo: int, dt: int, stream: int | None = None) -> None:
         st = self.stream if stream is None else stream
@@ -77,14 +77,15 @@ class SphereSolver(PatchSolver):
                                 self.sched.numel() if self.sched is not None else 0,
                                 self.launch, st)
 
-    def enqueue_step(self, dt_ptr: int | None = None, cfl: bool = True,
-                     retake: bool = False) -> None:
-        # the device retake relaunches the Cartesian step: the host retake of
-        # run() is used instead
-        super().enqueue_step(dt_ptr, cfl, retake=False)
+    def launch_retake(self, qi: int, qo: int, retake: int, stream: int | None = None) -> None:
+        L.swe_patch_retake_sphere(self.p, self.pt, qi, qo, self.b.data_ptr(),
+                                  self.dt.data_ptr(), self.smax.data_ptr(),
+                                  self.status.data_ptr(), self.metric.data_ptr(), retake,
+                                  self.stream if stream is None else stream)
 
     def mass(self) -> float:
-        """Water volume: sum of h kappa_j dx dy over the interior."""
-        h = self.state()[0]
-        kap = self.metric.cpu().numpy()[2: self.my + 2]
-        return float(np.sum(h * kap[:, None]) * self.pb.dx * self.pb.dy)
+        """Water volume: sum of h kappa_j dx dy over the interior (on the device)."""
+        out = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        L.swe_mass_sphere(self.p, self.pt_dev.data_ptr(), self.q[self.cur].data_ptr(),
+                          self.metric.data_ptr(), out.data_ptr(), self.stream)
+        return float(out.item())

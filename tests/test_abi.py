@@ -283,6 +283,26 @@ def test_sphere_step_argument_errors(L):
     with pytest.raises(L.SweError):
         L.swe_patch_step_sphere(L.params(precision=L.F32_DEV), pt, 0x1000, 0x9000000, 0x1000,
                                 0x1000, 0x1000, 0x1000, 0x5000)
+    # the sphere's retake, first-step speeds and mass: FP64 split only, a
+    # metric and the retake flags required
+    rt = ctypes.c_void_p(0x7000)
+
+    def retake(p, m=metric, r=rt):
+        return lib.swe_patch_retake_sphere(ctypes.byref(p), ctypes.byref(pt), fake, out, fake,
+                                           fake, fake, fake, m, r, None)
+    assert retake(L.params(), m=None) == L.SWE_EINVAL
+    assert retake(L.params(), r=None) == L.SWE_EINVAL
+    assert retake(L.params(precision=L.F32_DEV)) == L.SWE_EINVAL
+    assert lib.swe_speed_scan_sphere(ctypes.byref(L.params()), fake, 10, 10, fake, fake, None,
+                                     fake, None) == L.SWE_EINVAL
+    assert lib.swe_speed_scan_sphere(ctypes.byref(L.params(precision=L.F32_DEV)), fake, 10, 10,
+                                     fake, fake, metric, fake, None) == L.SWE_EINVAL
+    assert lib.swe_speed_scan_sphere(ctypes.byref(L.params()), fake, 0, 10, fake, fake, metric,
+                                     fake, None) == L.SWE_EINVAL
+    assert lib.swe_mass_sphere(ctypes.byref(L.params()), fake, fake, None, fake,
+                               None) == L.SWE_EINVAL
+    assert lib.swe_mass_sphere(ctypes.byref(L.params(method=L.UNSPLIT)), fake, fake, metric,
+                               fake, None) == L.SWE_EINVAL
 
 
 def test_sphere_metric_layout():

@@ -141,3 +141,77 @@ def test_small_and_high_latitude_patches(gpu, nx, ny, lat0, dlat):
         want = ref[2:-2, 2:-2, k]
         scale = max(np.abs(want).max(), 1e-300)
         assert np.abs(got[k] - want).max() / scale <= 1e-12, (k,)
+
+
+def test_first_step_speeds_on_the_sphere(gpu):
+    # swe_speed_scan_sphere: the x-speeds are those the reference step reports
+    # for the same state (bitwise: the same solves, scaled by the same 1 /
+    # kappa); the y-speeds those of every y-edge of the initial state solved
+    # by the reference Riemann solver, scaled by the mean of its two rows'
+    # 1 / kappa; the first dt is cfl_desired over the larger Courant rate
+    L, SphereSolver, torch = gpu
+    import oracle as O
+    pb = W.latlon_basin(60, 50, lat0=48.0, dlon=0.1, dlat=0.1, amp=2.0, sigma_deg=0.6,
+                        bc=(W.BC_WALL, W.BC_EXTRAP, W.BC_WALL, W.BC_EXTRAP))
+    s = SphereSolver(pb, L.params())
+    s.smax.zero_()
+    s.launch_scan()
+    torch.cuda.synchronize()
+    got = s.smax.cpu().numpy().copy()
+    O.lib()
+    P = O.params()
+    q, b = O.new_state(pb.h, pb.hu, pb.hv, pb.b, bc=pb.bc)
+    g = O.grid(pb.mx, pb.my, pb.dx, pb.dy, pb.bc)
+    O.ghost_fill_b(g, b)
+    O.ghost_fill(g, q)
+    kap, ln = O.sphere_metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
+    _, step_speeds, _, _ = O.step_sphere(P, g, q, b, 1.0, kap, ln)
+    assert got[0] == step_speeds[0]
+    sy = 0.0
+    for j in range(2, pb.my + 3):          # edge between frame rows j - 1 and j
+        a = 0.5 * (1.0 / kap[j - 1] + 1.0 / kap[j])
+        for i in range(2, pb.mx + 2):
+            lo, hi = q[j - 1, i], q[j, i]
+            _, sp, _, _ = O.riemann((lo[0], lo[2], lo[1], b[j - 1, i]),
+                                    (hi[0], hi[2], hi[1], b[j, i]), P)
+            sy = max(sy, float(np.abs(sp).max()) * a)
+    assert got[1] == sy
+    s.initial_dt()
+    torch.cuda.synchronize()
+    rate = max(got[0] / pb.dx, got[1] / pb.dy)
+    assert float(s.dt.item()) == P.cfl_desired / rate
+
+
+def test_device_retake_on_the_sphere_equals_the_host_retake(gpu):
+    # a first step 2.5 times the CFL step: the device redoes it (gated
+    # swe_patch_retake_sphere) with the reduced dt, as the host loop does
+    L, SphereSolver, torch = gpu
+    pb = W.latlon_basin(90, 70, lat0=-30.0, dlon=0.1, dlat=0.1, amp=2.5, sigma_deg=0.8)
+    print("case sphere retake 90x70", flush=True)
+    host = SphereSolver(pb, L.params())
+    host.initial_dt()
+    big = 2.5 * float(host.dt.item())
+    host.run(10, dt0=big)
+    dev = SphereSolver(pb, L.params())
+    dev.dt.fill_(big)
+    dev.run_async(10)
+    torch.cuda.synchronize()
+    assert host.retakes >= 1
+    assert int(dev.status[0].item()) & L.STATUS_RETAKEN
+    assert not int(dev.status[0].item()) & L.STATUS_CFL_EXCEEDED
+    for a, c in zip(host.state(), dev.state()):
+        assert np.array_equal(a, c)
+
+
+def test_mass_on_the_sphere_on_the_device(gpu):
+    # swe_mass_sphere against sum(h kappa) dx dy of the same state on the host
+    L, SphereSolver, torch = gpu
+    from paper_1901_06798_amd.sphere import metric
+    pb = W.latlon_basin(77, 41, lat0=60.0, dlon=0.2, dlat=0.2, amp=2.0, sigma_deg=1.0)
+    s = SphereSolver(pb, L.params())
+    s.run_forced([40.0] * 5)
+    torch.cuda.synchronize()
+    h = s.state()[0]
+    kap = metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)[2: pb.my + 2]
+    want = float(np.sum(h * kap[:, None])) * pb.dx * pb.dy
+    assert abs(s.mass() - want) <= 1e-14 * want
