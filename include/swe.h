@@ -457,6 +457,28 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
                        const swe_schedule *sched, const uint32_t *retake, int32_t ngroups,
                        void *stream);
 
+/* nsteps coarse steps of the batched step under the CFL rule, each as
+ * swe_batched_step, then swe_cfl_reduce with the retake flags, the gated
+ * swe_batched_retake of the flagged groups and swe_cfl_reduce of the redone
+ * steps (Sec. 2: the step size follows the largest wave speed, and a step
+ * above the Courant limit is redone with a smaller one), all enqueued on
+ * `stream` by one call.  The state alternates between pool_0 and pool_1
+ * starting from pool_<first> (first = 0 or 1), so after the call it is in
+ * pool_<(first + nsteps) % 2>.  npatches, ngroups: the table's patches and
+ * the groups of dt_group, group_flags (may be NULL) and retake (device
+ * uint32_t[ngroups], required); other arguments as swe_batched_step.  For a
+ * caller that advances many steps between host decisions (a serving loop's
+ * round) this replaces four library calls per step. */
+int swe_batched_advance(const swe_params *p, const swe_patch *patches, int32_t npatches,
+                        int32_t ngroups, const swe_item *items, int32_t nitems,
+                        const swe_task *tasks, const swe_task *plain, int32_t nplain,
+                        int32_t nsub, void *pool_0, void *pool_1, int32_t first,
+                        void *pool_work, int64_t pool_elems, const void *pool_b,
+                        double *dt_group, double *smax_patch, uint32_t *status,
+                        uint32_t *group_status, uint32_t *group_flags, uint32_t *retake,
+                        uint32_t *queue, const swe_schedule *sched, int32_t nsteps,
+                        void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * swe_batched_step without the queue and pool_work arguments.  The item

@@ -335,6 +335,39 @@ template __global__ void k_pack<true, true>(BatchArgs);
 
 namespace {
 
+// Compute units of the current device and the occupancy (workgroups per
+// compute unit) of `kern` at `threads` threads, queried once per device and
+// kernel shape.
+bool launch_limits(const void* kern, int threads, int* ncu, int* occ) {
+    struct Key {
+        int dev;
+        const void* kern;
+        int threads;
+        int ncu, occ;
+    };
+    static std::mutex mu;
+    static std::vector<Key> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Key& k : cache)
+        if (k.dev == dev && k.kern == kern && k.threads == threads) {
+            *ncu = k.ncu;
+            *occ = k.occ;
+            return true;
+        }
+    int n = 0, o = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+        return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, threads, 0) != hipSuccess || o < 1)
+        o = 1;
+    cache.push_back(Key{dev, kern, threads, n, o});
+    *ncu = n;
+    *occ = o;
+    return true;
+}
+
 int bfail(int code, const std::string& msg);
 
 int check_sched(const swe_schedule* s) {
@@ -667,19 +700,10 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
              {swe::k_batched<true, 32, false>, swe::k_batched<true, 32, true>}}};
         const Kern kern = table[dev ? 1 : 0][si][fric ? 1 : 0];
         const int threads = 64 * sched->waves_per_group;
-        int dev_id = 0, ncu = 0;
-        if (hipGetDevice(&dev_id) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) !=
-                hipSuccess ||
-            ncu < 1)
+        int ncu = 0, occ = 0;
+        if (!launch_limits(reinterpret_cast<const void*>(kern), threads, &ncu, &occ))
             return bfail(SWE_EHIP, "swe_batched_step: cannot query the device");
-        int per_cu = sched->groups_per_cu;
-        if (per_cu == 0) {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void*>(kern), threads, 0) != hipSuccess ||
-                per_cu < 1)
-                per_cu = 1;
-        }
+        const int per_cu = sched->groups_per_cu ? sched->groups_per_cu : occ;
         int grid = ncu * per_cu;
         if (grid > nitems) grid = nitems;
         if (grid < 1) grid = 1;
@@ -749,6 +773,44 @@ int swe_batched_step_static(const swe_params* p, const swe_patch* patches,
     return batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool_in, pool_out,
                         work ? pwork : nullptr, pool_elems, pool_b, dt_group, smax_patch, status,
                         queue, sched, nullptr, 0, group_status, stream, true);
+}
+
+int swe_batched_advance(const swe_params* p, const swe_patch* patches, int32_t npatches,
+                        int32_t ngroups, const swe_item* items, int32_t nitems,
+                        const swe_task* tasks, const swe_task* plain, int32_t nplain,
+                        int32_t nsub, void* pool_0, void* pool_1, int32_t first,
+                        void* pool_work, int64_t pool_elems, const void* pool_b,
+                        double* dt_group, double* smax_patch, uint32_t* status,
+                        uint32_t* group_status, uint32_t* group_flags, uint32_t* retake,
+                        uint32_t* queue, const swe_schedule* sched, int32_t nsteps,
+                        void* stream) {
+    if (first != 0 && first != 1) return bfail(SWE_EINVAL, "swe_batched_advance: first must be 0 or 1");
+    if (nsteps < 0 || npatches < 0 || ngroups < 1)
+        return bfail(SWE_EINVAL, "swe_batched_advance: bad nsteps, npatches or ngroups");
+    if (!retake || !pool_0 || !pool_1)
+        return bfail(SWE_EINVAL, "swe_batched_advance: null retake flags or pool");
+    void* pool[2] = {pool_0, pool_1};
+    int cur = first;
+    for (int k = 0; k < nsteps; ++k) {
+        // the step, the CFL rule with the retake flags, the gated redo of the
+        // flagged groups, and the CFL rule of the redone steps
+        int rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
+                              pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
+                              status, queue, sched, nullptr, 0, group_status, stream);
+        if (rc) return rc;
+        rc = swe_cfl_reduce(p, patches, npatches, ngroups, smax_patch, dt_group, status,
+                            group_flags, retake, 0, stream);
+        if (rc) return rc;
+        rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
+                          pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
+                          status, queue, sched, retake, ngroups, group_status, stream);
+        if (rc) return rc;
+        rc = swe_cfl_reduce(p, patches, npatches, ngroups, smax_patch, dt_group, status,
+                            group_flags, nullptr, 0, stream);
+        if (rc) return rc;
+        cur ^= 1;
+    }
+    return SWE_OK;
 }
 
 int swe_batched_retake(const swe_params* p, const swe_patch* patches, const swe_item* items,

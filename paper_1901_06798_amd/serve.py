@@ -116,7 +116,7 @@ class PinnedPool:
 class ScenarioServer:
     def __init__(self, params: L.swe_params | None = None, hbm_budget: int = 64 << 30,
                  max_slots: int = 64, steps_per_round: int = 50, device: str = "cuda:0",
-                 sched: L.swe_schedule | None = None):
+                 sched: L.swe_schedule | None = None, graphs: bool = False):
         if not torch.cuda.is_available():
             raise L.SweError("ScenarioServer needs a GPU")
         L.lib()
@@ -151,6 +151,11 @@ class ScenarioServer:
         self.host_bytes = PinnedPool(torch.uint8)
         self.host_status = PinnedPool(torch.int32)
         self.hold: list = []  # pinned buffers read by copies not yet known to be done
+        # rounds captured as HIP graphs, per (state buffer, steps), valid until
+        # the active set changes
+        self.use_graphs = graphs
+        self.graphs: dict = {}
+        self.rsmax = None
 
     @property
     def stream(self) -> int:
@@ -246,6 +251,11 @@ class ScenarioServer:
                                                       dtype=torch.uint8))
         self.nitems = plan.nitems
         self.ntasks, self.nplain, self.nsub = plan.ntasks, plan.nplain, plan.nsub
+        # a scenario's smax pair lives at its table index (each reduction
+        # leaves the pairs at 0 for the next step)
+        self.rsmax = torch.zeros(2 * max(len(self.active), 1), dtype=torch.float64,
+                                 device=self.dev)
+        self.graphs = {}
         self.table_dirty = False
 
     def _retire(self, sc: Scenario, keep_result: bool = True):
@@ -302,31 +312,36 @@ class ScenarioServer:
         with mk.range("host: enqueue"):
             self._enqueue_round(steps)
 
+    def _advance(self, steps: int, stream: int) -> None:
+        """The round's steps, each with the CFL rule and the device retake per
+        scenario, enqueued by one library call."""
+        L.swe_batched_advance(
+            self.p, self.table.data_ptr(), len(self.active), self.max_slots,
+            self.items.data_ptr(), self.nitems, self.tasks.data_ptr(),
+            self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
+            self.nplain, self.nsub, self.pools[0].data_ptr(), self.pools[1].data_ptr(), self.cur,
+            0, 3 * self.plane, self.b.data_ptr(), self.dt.data_ptr(), self.rsmax.data_ptr(),
+            self.status.data_ptr(), self.gstatus.data_ptr(), self.group_flags.data_ptr(),
+            self.retake.data_ptr(), self.queue_ctr.data_ptr(), self.sched, steps, stream)
+
     def _enqueue_round(self, steps: int) -> None:
-        # a scenario's smax pair lives at its table index during the round
-        n = len(self.active)
-        smax = torch.zeros(2 * n, dtype=torch.float64, device=self.dev)
-        for _ in range(steps):
-            args = (self.table.data_ptr(), self.items.data_ptr(), self.nitems,
-                    self.tasks.data_ptr(),
-                    self.tasks.data_ptr() + L.SWE_TASK_BYTES * (self.ntasks - self.nplain),
-                    self.nplain, self.nsub, self.pools[self.cur].data_ptr(),
-                    self.pools[1 - self.cur].data_ptr(), 0, 3 * self.plane, self.b.data_ptr(),
-                    self.dt.data_ptr(), smax.data_ptr(), self.status.data_ptr(),
-                    self.queue_ctr.data_ptr(), self.sched)
-            gs = self.gstatus.data_ptr()
-            L.swe_batched_step(self.p, *args, self.stream, group_status=gs)
-            # CFL rule per scenario; a step above cfl_max is redone once on the device
-            L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
-                             self.dt.data_ptr(), self.status.data_ptr(),
-                             self.group_flags.data_ptr(), 0, self.stream,
-                             retake=self.retake.data_ptr())
-            L.swe_batched_retake(self.p, *args, self.retake.data_ptr(), self.max_slots,
-                                 self.stream, group_status=gs)
-            L.swe_cfl_reduce(self.p, self.table.data_ptr(), n, self.max_slots, smax.data_ptr(),
-                             self.dt.data_ptr(), self.status.data_ptr(),
-                             self.group_flags.data_ptr(), 0, self.stream)
-            self.cur ^= 1
+        # with graphs, a round is captured once per active set and state
+        # buffer, and replayed while the set stays the same
+        if self.use_graphs:
+            key = (self.cur, steps)
+            g = self.graphs.get(key)
+            if g is None:
+                g = torch.cuda.CUDAGraph()
+                side = torch.cuda.Stream(self.dev)
+                side.wait_stream(torch.cuda.current_stream(self.dev))
+                with torch.cuda.graph(g, stream=side):
+                    self._advance(steps, side.cuda_stream)
+                torch.cuda.current_stream(self.dev).wait_stream(side)
+                self.graphs[key] = g
+            g.replay()
+        else:
+            self._advance(steps, self.stream)
+        self.cur = (self.cur + steps) % 2
         for sc in self.active:
             sc.steps_done += steps
 

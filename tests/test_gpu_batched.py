@@ -142,3 +142,37 @@ def test_plan_rejects_user_boundary_with_substeps(gpu):
     probs[2].bc = (W.BC_USER,) * 4
     with pytest.raises(L.SweError):
         BatchedSolver(probs, L.params(), trefs=trefs)
+
+
+@pytest.mark.parametrize("seg", [64, 0])
+def test_advance_equals_the_step_by_step_sequence(gpu, seg):
+    # swe_batched_advance (one call for n steps with the CFL rule and the
+    # retake) against n enqueue_step calls; two groups start above the limit
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set(seed=9, counts=(3, 4, 5))
+    groups = [k % 4 for k in range(len(probs))]
+    sched = L.schedule(seg=seg, per_substep=1 if seg == 0 else 0)
+    print(f"case batched advance seg={seg}", flush=True)
+    a = BatchedSolver(probs, L.params(), trefs=trefs, groups=groups, sched=sched)
+    b = BatchedSolver(probs, L.params(), trefs=trefs, groups=groups, sched=sched)
+    for s in (a, b):
+        s.initial_dt()
+        s.dt.mul_(torch.tensor([1.0, 2.5, 1.0, 1.7], dtype=torch.float64, device=s.dev))
+    for _ in range(7):
+        a.enqueue_step()
+    args = (b.table.data_ptr(), b.n, b.ngroups, b.items.data_ptr(), b.nitems, b.tasks.data_ptr(),
+            b.tasks.data_ptr() + L.SWE_TASK_BYTES * (b.ntasks - b.nplain), b.nplain, b.nsub,
+            b.pools[0].data_ptr(), b.pools[1].data_ptr(), b.cur,
+            b.work.data_ptr() if b.work is not None else 0, 3 * b.plane, b.b.data_ptr(),
+            b.dt.data_ptr(), b.smax.data_ptr(), b.status.data_ptr(), 0,
+            b.group_flags.data_ptr(), b.retake.data_ptr(), b.queue.data_ptr(), b.sched, 7,
+            b.stream)
+    L.swe_batched_advance(b.p, *args)
+    b.cur = (b.cur + 7) % 2
+    torch.cuda.synchronize()
+    assert a.cur == b.cur
+    assert int(a.status[0].item()) & L.STATUS_RETAKEN
+    assert torch.equal(a.status, b.status) and torch.equal(a.dt, b.dt)
+    for k in range(len(probs)):
+        for x, y in zip(a.state(k), b.state(k)):
+            assert np.array_equal(x, y), k

@@ -20,8 +20,10 @@ def gpu():
     return L, ScenarioServer, Scenario, PatchSolver, torch
 
 
-@pytest.mark.parametrize("precision", [1, 0])
-def test_mix_equals_alone(gpu, precision):
+@pytest.mark.parametrize("precision,graphs", [(1, True), (0, True), (1, False)])
+def test_mix_equals_alone(gpu, precision, graphs):
+    # rounds replayed from HIP graphs (captured once per active set) or
+    # enqueued eagerly give the same bits as each scenario run alone
     L, ScenarioServer, Scenario, PatchSolver, torch = gpu
     p = L.params(precision=precision)
     sizes = [64, 150, 96, 200, 80, 128, 64]
@@ -29,7 +31,7 @@ def test_mix_equals_alone(gpu, precision):
     reqs = [Scenario(k, 0.002 * k, W.scenario(k, n=n), steps[k]) for k, n in enumerate(sizes)]
     # budget for about two of the larger grids: later requests wait for memory
     srv = ScenarioServer(p, hbm_budget=3 * 7 * 208 * 208 * (4 if precision else 8),
-                         max_slots=3, steps_per_round=10)
+                         max_slots=3, steps_per_round=10, graphs=graphs)
     out = srv.serve(reqs)
     torch.cuda.synchronize()
     assert out["requests"] == len(reqs)
