@@ -241,15 +241,18 @@ __device__ __forceinline__ void riemann(const Side<T>& L, const Side<T>& R, cons
     w.s[1] = s2;
     w.s[2] = s3;
 
-    // a wall reflects: waves running into the dry bank are removed
+    // a wall reflects: waves running into the dry bank are removed (a branch,
+    // so that a wave with no wall edge skips the selects)
     const bool wallR = w.kind == kEdgeWallR, wallL = w.kind == kEdgeWallL;
+    if (wallR || wallL) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const bool drop = (wallR && w.s[p] > T(0)) || (wallL && w.s[p] < T(0));
-        w.s[p] = drop ? T(0) : w.s[p];
-        w.z[p][0] = drop ? T(0) : w.z[p][0];
-        w.z[p][1] = drop ? T(0) : w.z[p][1];
-        w.z[p][2] = drop ? T(0) : w.z[p][2];
+        for (int p = 0; p < 3; ++p) {
+            const bool drop = (wallR && w.s[p] > T(0)) || (wallL && w.s[p] < T(0));
+            w.s[p] = drop ? T(0) : w.s[p];
+            w.z[p][0] = drop ? T(0) : w.z[p][0];
+            w.z[p][1] = drop ? T(0) : w.z[p][1];
+            w.z[p][2] = drop ? T(0) : w.z[p][2];
+        }
     }
 }
 
