@@ -413,10 +413,10 @@ def cpu_baseline(pb, seconds: float, single_seconds: float = 8.0):
 
 def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere: bool = False):
     """Time `steps` steps of one patch; kernel time from HIP events around each
-    step launch on the launch stream (the sort of the heaviest-first order,
-    when due, runs after the bracket, inside the timed loop), then the CFL
-    rule with its gated retake on the device.  sphere: a latitude-longitude
-    patch (SphereSolver)."""
+    step launch on the launch stream (the step ends with the CFL rule in its
+    last wave; the sort of the heaviest-first order, when due, and the gated
+    retake run after the bracket, inside the timed loop).  sphere: a
+    latitude-longitude patch (SphereSolver)."""
     import torch
 
     from paper_1901_06798_amd import _lib as L
@@ -440,20 +440,14 @@ def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere
     t0 = time.perf_counter()
     start.record(stream)
     for k in range(steps):
+        qi, qo = s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr()
+        # the step, whose last wave applies the CFL rule (next dt, retake flag)
         ev0[k].record(stream)
-        s.launch_step(s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(), s.dt.data_ptr(),
-                      stream.cuda_stream)
+        s.launch_step_cfl(qi, qo, stream.cuda_stream)
         ev1[k].record(stream)
         s.after_step(stream.cuda_stream)
-        # CFL rule with the retake on the device (a gated launch that does
-        # nothing unless the step went above cfl_max)
-        L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
-                         s.status.data_ptr(), 0, 0, stream.cuda_stream,
-                         retake=s.retake.data_ptr())
-        s.launch_retake(s.q[s.cur].data_ptr(), s.q[1 - s.cur].data_ptr(), s.retake.data_ptr(),
-                        stream.cuda_stream)
-        L.swe_cfl_reduce(s.p, s.pt_dev.data_ptr(), 1, 1, s.smax.data_ptr(), s.dt.data_ptr(),
-                         s.status.data_ptr(), 0, 0, stream.cuda_stream)
+        # the gated retake, which ends at once unless the step went above cfl_max
+        s.launch_retake_cfl(qi, qo, stream.cuda_stream)
         s.cur ^= 1
     end.record(stream)
     torch.cuda.synchronize()

@@ -231,6 +231,35 @@ int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const voi
                           uint32_t *status, const double *metric, uint32_t *sched,
                           int64_t sched_len, const swe_launch *launch, void *stream);
 
+/* The step and the CFL rule in one launch (Sec. 2: the step size follows the
+ * largest wave speed, and a step above the Courant limit is redone with a
+ * smaller one).  swe_patch_step_cfl is swe_patch_step_sched (sched NULL:
+ * swe_patch_step; metric not NULL: swe_patch_step_sphere's step, FP64 split
+ * only) followed, in the launch's last wave to finish, by what
+ * swe_cfl_reduce(initial = 0, retake) does for the patch's group alone:
+ * from smax[0], smax[1] and patch->dx, dy, tref the rate r; *dt * r >
+ * cfl_max sets retake[patch->group] = 1 and SWE_STATUS_RETAKEN in status[0]
+ * (else retake[group] = 0); r NaN sets SWE_STATUS_NONFINITE; *dt =
+ * cfl_desired / r when r is positive and finite; smax[0..1] = 0.
+ * swe_patch_retake_cfl is swe_patch_retake (metric as above) whose launch,
+ * when the flag is set, ends with swe_cfl_reduce(retake = NULL) for the
+ * group: the next *dt, and SWE_STATUS_CFL_EXCEEDED if the retaken step is
+ * still above cfl_max; with the flag clear it does nothing.  One step of the
+ * CFL-ruled loop is then these two launches instead of four.  counter:
+ * device uint32_t, zero before the first call; each launch that runs leaves
+ * it zero.  dt, smax, status, retake: device, as swe_cfl_reduce; the step
+ * reads *dt before any wave of the launch writes it.  Other arguments as the
+ * calls named. */
+int swe_patch_step_cfl(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
+                       const void *b, double *dt, double *smax, uint32_t *status,
+                       uint32_t *retake, uint32_t *counter, const double *metric,
+                       uint32_t *sched, int64_t sched_len, const swe_launch *launch,
+                       void *stream);
+int swe_patch_retake_cfl(const swe_params *p, const swe_patch *patch, const void *q_in,
+                         void *q_out, const void *b, double *dt, double *smax, uint32_t *status,
+                         const uint32_t *retake, uint32_t *counter, const double *metric,
+                         void *stream);
+
 /* swe_patch_retake on a latitude-longitude patch: the same gated redo of the
  * step (Sec. 2, a step above the Courant limit is redone with a smaller
  * step), launching swe_patch_step_sphere's step with `metric` (device, as

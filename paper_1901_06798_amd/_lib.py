@@ -126,6 +126,10 @@ def lib():
                                             _P, _P, _P, i64, pl, _P]
         L.swe_patch_retake_sphere.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P,
                                               _P, _P, _P, _P]
+        L.swe_patch_step_cfl.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
+                                         _P, _P, _P, _P, i64, ctypes.POINTER(swe_launch), _P]
+        L.swe_patch_retake_cfl.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
+                                           _P, _P, _P, _P]
         L.swe_speed_scan_sphere.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, _P]
         L.swe_mass_sphere.argtypes = [pp, _P, _P, _P, _P, _P]
         L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, i64, i64, _P, _P, _P]
@@ -158,7 +162,7 @@ def lib():
                      "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
                      "swe_state_export", "swe_batched_step_static", "swe_level_steps",
                      "swe_patch_retake_sphere", "swe_speed_scan_sphere", "swe_mass_sphere",
-                     "swe_batched_advance"):
+                     "swe_batched_advance", "swe_patch_step_cfl", "swe_patch_retake_cfl"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -317,6 +321,24 @@ def swe_patch_retake(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int
                      smax: int, status: int, retake: int, stream: int = 0) -> None:
     _check(lib().swe_patch_retake(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
                                   status, retake, stream), "swe_patch_retake")
+
+
+def swe_patch_step_cfl(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                       smax: int, status: int, retake: int, counter: int, metric: int = 0,
+                       sched: int = 0, sched_len: int = 0, launch: swe_launch | None = None,
+                       stream: int = 0) -> None:
+    _check(lib().swe_patch_step_cfl(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt, smax,
+                                    status, retake, counter, metric, sched, sched_len,
+                                    ctypes.byref(launch) if launch is not None else None, stream),
+           "swe_patch_step_cfl")
+
+
+def swe_patch_retake_cfl(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
+                         smax: int, status: int, retake: int, counter: int, metric: int = 0,
+                         stream: int = 0) -> None:
+    _check(lib().swe_patch_retake_cfl(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
+                                      smax, status, retake, counter, metric, stream),
+           "swe_patch_retake_cfl")
 
 
 def swe_patch_retake_sphere(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int,

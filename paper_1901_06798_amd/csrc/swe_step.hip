@@ -49,7 +49,49 @@ struct StepArgs {
     uint32_t* cost;  // per task, the march's solved row sweeps (NULL: not kept)
     const double* metric;  // latitude-longitude patch: capacities, edge lengths
     int xcd_run;           // ranks dealt to an XCD in runs of this many (1: in turn)
+    // CFL rule in the launch's last wave (NULL done: none): done counts the
+    // finished waves; the rule writes *dt_next, flags[0] (NULL: no retake
+    // flag), status
+    uint32_t* done;
+    double* dt_next;
+    uint32_t* flags;
+    double cfl_desired, cfl_max;
+    int tref;
 };
+
+// The CFL rule of one group (swe_cfl_reduce with the group's one patch) in
+// the launch's last wave to finish.  Every wave's speeds reach smax by
+// device-scope atomics, which are performed coherently across the XCDs'
+// caches; a wave waits for its atomics to complete (a workgroup-scope release
+// fence: no cache write-back) before it counts itself, so the wave that
+// counts last finds every speed in smax, and reads it with atomic exchanges.
+// The counter and smax are left at 0 for the next launch.
+__device__ __forceinline__ void cfl_tail(const StepArgs& a, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(a.done, 1u);
+    prev = __builtin_amdgcn_readfirstlane(prev);
+    if (prev + 1 != (uint32_t)a.nitems || lane != 0) return;
+    unsigned long long* sm = reinterpret_cast<unsigned long long*>(a.smax);
+    const double sx = __longlong_as_double(static_cast<long long>(atomicExch(&sm[0], 0ull)));
+    const double sy = __longlong_as_double(static_cast<long long>(atomicExch(&sm[1], 0ull)));
+    const double rx = sx / a.dx, ry = sy / a.dy;
+    double r = rx > ry ? rx : ry;
+    r = r / (double)a.tref;
+    if (isnan(rx) || isnan(ry)) r = rx + ry;
+    const double rate = (r > 0.0 || isnan(r)) ? r : 0.0;
+    const double dt = *a.dt;
+    uint32_t f = 0;
+    if (isnan(rate)) f |= SWE_STATUS_NONFINITE;
+    const bool over = rate > 0.0 && dt * rate > a.cfl_max;
+    if (over) f |= a.flags ? SWE_STATUS_RETAKEN : SWE_STATUS_CFL_EXCEEDED;
+    if (a.flags) atomicExch(a.flags, over ? 1u : 0u);
+    if (rate > 0.0 && isfinite(rate)) atomicExch(reinterpret_cast<unsigned long long*>(a.dt_next),
+                                                 static_cast<unsigned long long>(
+                                                     __double_as_longlong(a.cfl_desired / rate)));
+    if (f) atomicOr(a.status, f);
+    atomicExch(a.done, 0u);
+}
 
 // Rank in the launch order of launch position `pos` (one wave per
 // workgroup).  Workgroups go to the eight XCDs in turn (workgroup i to XCD
@@ -136,6 +178,7 @@ __device__ __forceinline__ void split_task(const StepArgs& a) {
     }
     if (o.clamps) atomicAdd(&a.status[1], o.clamps);
     if (o.flags) atomicOr(&a.status[0], o.flags);
+    if (a.done) cfl_tail(a, lane);
 }
 
 // WIDE: FP32 surface-deviation planes, FP64 arithmetic (SWE_F32_STORE).
@@ -199,6 +242,7 @@ __global__ void __launch_bounds__(256) k_unsplit(StepArgs a, int transverse_orde
     }
     if (o.clamps) atomicAdd(&a.status[1], o.clamps);
     if (o.flags) atomicOr(&a.status[0], o.flags);
+    if (a.done) cfl_tail(a, lane);
 }
 
 template __global__ void k_unsplit<false>(StepArgs, int);
@@ -707,10 +751,18 @@ static int patch_tasks(const swe_patch* patch, int H) {
     return nstrips * ((patch->my + H - 1) / H);
 }
 
+// The CFL rule fused into a launch (swe_patch_step_cfl, swe_patch_retake_cfl).
+struct FusedCfl {
+    uint32_t* counter;
+    double* dt;
+    uint32_t* flags;  // the group's retake flag to write, or NULL
+};
+
 static int patch_step(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
                       const void* b, const double* dt, double* smax, uint32_t* status,
                       const uint32_t* gate, uint32_t* sched, int64_t sched_len,
-                      const swe_launch* launch, void* stream, const double* metric = nullptr) {
+                      const swe_launch* launch, void* stream, const double* metric = nullptr,
+                      const FusedCfl* fused = nullptr) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_patch(patch))) return rc;
@@ -765,6 +817,12 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.cost = sched ? sched + a.nitems : nullptr;
     a.metric = metric;
     a.xcd_run = sh.xcd_run;
+    a.done = fused ? fused->counter : nullptr;
+    a.dt_next = fused ? fused->dt : nullptr;
+    a.flags = fused ? fused->flags : nullptr;
+    a.cfl_desired = p->cfl_desired;
+    a.cfl_max = p->cfl_max;
+    a.tref = patch->tref;
     const int blocks = (a.nitems + waves_per_block - 1) / waves_per_block;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid(blocks), block(64 * waves_per_block);
@@ -872,6 +930,38 @@ int swe_patch_retake_sphere(const swe_params* p, const swe_patch* patch, const v
     return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
                       patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream,
                       metric);
+}
+
+int swe_patch_step_cfl(const swe_params* p, const swe_patch* patch, const void* q_in, void* q_out,
+                       const void* b, double* dt, double* smax, uint32_t* status,
+                       uint32_t* retake, uint32_t* counter, const double* metric,
+                       uint32_t* sched, int64_t sched_len, const swe_launch* launch,
+                       void* stream) {
+    if (!dt || !retake || !counter)
+        return fail(SWE_EINVAL, "swe_patch_step_cfl: null dt, retake flags or counter");
+    if (patch && patch->group < 0) return fail(SWE_EINVAL, "swe_patch_step_cfl: negative group");
+    if (patch && patch->tref < 1) return fail(SWE_EINVAL, "swe_patch_step_cfl: tref < 1");
+    if (metric && p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
+        return fail(SWE_EINVAL, "swe_patch_step_cfl: a metric needs the FP64 split step");
+    const FusedCfl f{counter, dt, patch ? retake + patch->group : retake};
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, nullptr, sched,
+                      sched ? sched_len : 0, launch, stream, metric, &f);
+}
+
+int swe_patch_retake_cfl(const swe_params* p, const swe_patch* patch, const void* q_in,
+                         void* q_out, const void* b, double* dt, double* smax, uint32_t* status,
+                         const uint32_t* retake, uint32_t* counter, const double* metric,
+                         void* stream) {
+    if (!dt || !retake || !counter)
+        return fail(SWE_EINVAL, "swe_patch_retake_cfl: null dt, retake flags or counter");
+    if (patch && patch->group < 0) return fail(SWE_EINVAL, "swe_patch_retake_cfl: negative group");
+    if (patch && patch->tref < 1) return fail(SWE_EINVAL, "swe_patch_retake_cfl: tref < 1");
+    if (metric && p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
+        return fail(SWE_EINVAL, "swe_patch_retake_cfl: a metric needs the FP64 split step");
+    const FusedCfl f{counter, dt, nullptr};
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
+                      patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream, metric,
+                      &f);
 }
 
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,

@@ -57,6 +57,10 @@ class PatchSolver:
         self.smax = torch.zeros(2, dtype=f64, device=self.dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.retake = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        # finished-wave counter of the launches that end with the CFL rule
+        self.counter = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.fused = True  # the step and the CFL rule in one launch
+        self.metric_ptr = 0
         # launch order of the step's tasks, heaviest first from the last step
         # (re-sorted after the first step, then every order_every steps: the
         # work of a task changes slowly as the waves travel)
@@ -133,6 +137,23 @@ class PatchSolver:
             L.swe_patch_step(self.p, self.pt, qi, qo, self.b.data_ptr(), dt,
                              self.smax.data_ptr(), self.status.data_ptr(), st)
 
+    def launch_step_cfl(self, qi: int, qo: int, stream: int | None = None) -> None:
+        """The step with dt from self.dt, ending with the CFL rule (next dt,
+        retake flag) in its last wave."""
+        L.swe_patch_step_cfl(self.p, self.pt, qi, qo, self.b.data_ptr(), self.dt.data_ptr(),
+                             self.smax.data_ptr(), self.status.data_ptr(),
+                             self.retake.data_ptr(), self.counter.data_ptr(), self.metric_ptr,
+                             self.sched.data_ptr() if self.sched is not None else 0,
+                             self.sched.numel() if self.sched is not None else 0, self.launch,
+                             self.stream if stream is None else stream)
+
+    def launch_retake_cfl(self, qi: int, qo: int, stream: int | None = None) -> None:
+        """The gated redo of the step, ending with the CFL rule when it runs."""
+        L.swe_patch_retake_cfl(self.p, self.pt, qi, qo, self.b.data_ptr(), self.dt.data_ptr(),
+                               self.smax.data_ptr(), self.status.data_ptr(),
+                               self.retake.data_ptr(), self.counter.data_ptr(), self.metric_ptr,
+                               self.stream if stream is None else stream)
+
     def launch_retake(self, qi: int, qo: int, retake: int, stream: int | None = None) -> None:
         """The gated redo of the step q_in -> q_out with the reduced dt."""
         L.swe_patch_retake(self.p, self.pt, qi, qo, self.b.data_ptr(), self.dt.data_ptr(),
@@ -158,6 +179,12 @@ class PatchSolver:
         step above cfl_max is redone once on the device with the reduced dt
         (a retaken step still above the limit is flagged CFL_EXCEEDED)."""
         qi, qo = self.q[self.cur].data_ptr(), self.q[1 - self.cur].data_ptr()
+        if cfl and retake and dt_ptr is None and self.fused:
+            self.launch_step_cfl(qi, qo)
+            self.after_step()
+            self.launch_retake_cfl(qi, qo)
+            self.cur ^= 1
+            return
         dt = dt_ptr if dt_ptr is not None else self.dt.data_ptr()
         self.launch_step(qi, qo, dt)
         self.after_step()

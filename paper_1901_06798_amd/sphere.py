@@ -61,6 +61,7 @@ class SphereSolver(PatchSolver):
         super().__init__(pb, p, device, ordered=ordered, order_every=order_every)
         m = metric(pb.meta["lat0"], pb.meta["dlat"], pb.my, pb.bc)
         self.metric = torch.from_numpy(m).to(self.dev)
+        self.metric_ptr = self.metric.data_ptr()
 
     def launch_scan(self) -> None:
         # each edge's speed scaled by its inverse capacity, as the step reports it

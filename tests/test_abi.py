@@ -304,6 +304,23 @@ def test_sphere_step_argument_errors(L):
     assert lib.swe_mass_sphere(ctypes.byref(L.params(method=L.UNSPLIT)), fake, fake, metric,
                                fake, None) == L.SWE_EINVAL
 
+    # the step and the retake with the CFL rule fused: dt, flags and counter
+    # required; a metric only with the FP64 split step
+    cnt = ctypes.c_void_p(0x8000)
+
+    def fused(p, d=fake, r=rt, c=cnt, m=None):
+        return lib.swe_patch_step_cfl(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, d,
+                                      fake, fake, r, c, m, None, 0, None, None)
+
+    def fused_retake(p, d=fake, r=rt, c=cnt, m=None):
+        return lib.swe_patch_retake_cfl(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, d,
+                                        fake, fake, r, c, m, None)
+    for f in (fused, fused_retake):
+        assert f(L.params(), d=None) == L.SWE_EINVAL
+        assert f(L.params(), r=None) == L.SWE_EINVAL
+        assert f(L.params(), c=None) == L.SWE_EINVAL
+        assert f(L.params(precision=L.F32_DEV), m=metric) == L.SWE_EINVAL
+
 
 def test_sphere_metric_layout():
     from paper_1901_06798_amd import sphere as S

@@ -99,3 +99,47 @@ def test_retake_flags_are_cleared_each_step(gpu):
     s.run_async(1)
     torch.cuda.synchronize()
     assert int(s.retake.item()) == 0  # the next one stood
+
+
+@pytest.mark.parametrize("case", ["f64", "f32", "unsplit", "sphere", "f64-large"])
+def test_cfl_rule_fused_into_the_step_equals_the_separate_launches(gpu, case):
+    # swe_patch_step_cfl + swe_patch_retake_cfl (two launches a step) against
+    # the step, swe_cfl_reduce, swe_patch_retake and swe_cfl_reduce (four):
+    # the same states, step sizes, flags and status bits, a first step 2.4x
+    # the CFL step included; counter and speeds are left at 0
+    L, PatchSolver, _, torch = gpu
+    if case == "sphere":
+        from paper_1901_06798_amd.sphere import SphereSolver as Solver
+        pb = W.latlon_basin(130, 90, lat0=40.0, dlon=0.1, dlat=0.1, amp=2.0, sigma_deg=0.7)
+        p = L.params()
+    elif case == "f64-large":
+        # about a hundred waves on every XCD: the last one must see every speed
+        Solver = PatchSolver
+        pb = W.shelf_grid(1536, 600.0, seed=3, amp=2.0, x_s_frac=0.6, width=30e3)
+        p = L.params()
+    else:
+        Solver = PatchSolver
+        pb = W.gaussian_hump(150, 1000.0, sigma=8e3)
+    if case in ("f64", "f32", "unsplit"):
+        p = L.params(precision=1 if case == "f32" else 0,
+                     method=L.UNSPLIT if case == "unsplit" else L.SPLIT)
+    print(f"case fused CFL rule {case}", flush=True)
+    runs = []
+    for fused in (True, False):
+        s = Solver(pb, p, order_every=1)
+        s.fused = fused
+        s.initial_dt()
+        s.dt.mul_(2.4)
+        dts = []
+        for _ in range(12):
+            s.enqueue_step()
+            dts.append(s.dt.clone())
+        torch.cuda.synchronize()
+        runs.append((s, torch.stack(dts).cpu().numpy()))
+    (a, da), (b, db) = runs
+    assert np.array_equal(da, db)
+    assert int(a.status[0].item()) & L.STATUS_RETAKEN
+    assert torch.equal(a.status, b.status)
+    assert not a.counter.any() and not a.smax.any()
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
