@@ -148,6 +148,96 @@ def coarse_value(coarse, old, r, drytol, alpha, I, J, bf):
     return (h, hu, hv)
 
 
+def _locate(patches, I, J, skip=None):
+    """Index (in `patches`) of the first patch whose interior holds each of
+    the cells (I, J), -1 where none does; `skip` is left out."""
+    k = np.full(I.shape, -1, dtype=np.int64)
+    if I.size == 0:
+        return k
+    lo_i, hi_i, lo_j, hi_j = I.min(), I.max(), J.min(), J.max()
+    for n, p in enumerate(patches):
+        # a patch clear of the cells' bounding box holds none of them
+        if p is skip or p.i0 > hi_i or p.i0 + p.mx <= lo_i or p.j0 > hi_j or p.j0 + p.my <= lo_j:
+            continue
+        m = (k < 0) & (I >= p.i0) & (I < p.i0 + p.mx) & (J >= p.j0) & (J < p.j0 + p.my)
+        k[m] = n
+    return k
+
+
+def _gather(patches, arrays, k, I, J, ncomp):
+    """Values of arrays[k] (each a patch's ghost-framed array) at the cells
+    (I, J) of patch k; NaN where k < 0."""
+    out = np.full(I.shape + ((ncomp,) if ncomp else ()), np.nan)
+    for n in np.unique(k[k >= 0]):
+        p = patches[n]
+        m = k == n
+        out[m] = arrays[n][J[m] - p.j0 + 2, I[m] - p.i0 + 2]
+    return out
+
+
+def _max0(d):
+    """max(d, 0.0) as Python's max evaluates it (d unless 0.0 > d)."""
+    return np.where(0.0 > d, 0.0, d)
+
+
+def coarse_values(coarse, old, r, drytol, alpha, I, J, bf):
+    """coarse_value for arrays of fine cells (I, J) with beds bf: the same
+    reading, each value computed by the same operations in the same order
+    (numpy float64 arithmetic, element by element).  Returns (h, hu, hv)."""
+    X = (I.astype(np.float64) + 0.5) / r - 0.5
+    Y = (J.astype(np.float64) + 0.5) / r - 0.5
+    i0 = np.floor(X).astype(np.int64)
+    j0 = np.floor(Y).astype(np.int64)
+    wx, wy = X - i0, Y - j0
+    use_x, use_y = wx > 0.0, wy > 0.0
+    new = [c.q for c in coarse]
+    beds = [c.b for c in coarse]
+    v, linear = {}, np.ones(I.shape, dtype=bool)
+    for c_ in (0, 1):
+        for a in (0, 1):
+            used = np.ones(I.shape, dtype=bool)
+            if a:
+                used &= use_x
+            if c_:
+                used &= use_y
+            k = _locate(coarse, i0 + a, j0 + c_)
+            qo = _gather(coarse, old, k, i0 + a, j0 + c_, 3)
+            qn = _gather(coarse, new, k, i0 + a, j0 + c_, 3)
+            bk = _gather(coarse, beds, k, i0 + a, j0 + c_, 0)
+            ok = (k >= 0) & (qo[..., 0] > drytol) & (qn[..., 0] > drytol)
+            linear &= ~used | ok
+            v[a, c_] = ((1.0 - alpha) * (qo[..., 0] + bk) + alpha * (qn[..., 0] + bk),
+                        (1.0 - alpha) * qo[..., 1] + alpha * qn[..., 1],
+                        (1.0 - alpha) * qo[..., 2] + alpha * qn[..., 2])
+    lin = []
+    for m in range(3):
+        line0 = (1.0 - wx) * v[0, 0][m]
+        line0 = np.where(use_x, line0 + wx * v[1, 0][m], line0)
+        line1 = (1.0 - wx) * v[0, 1][m]
+        line1 = np.where(use_x, line1 + wx * v[1, 1][m], line1)
+        total = (1.0 - wy) * line0
+        lin.append(np.where(use_y, total + wy * line1, total))
+    # near the shore: the cell under the fine cell alone
+    Ic, Jc = I // r, J // r
+    k = _locate(coarse, Ic, Jc)
+    qo = _gather(coarse, old, k, Ic, Jc, 3)
+    qn = _gather(coarse, new, k, Ic, Jc, 3)
+    bc_ = _gather(coarse, beds, k, Ic, Jc, 0)
+    const = ((1.0 - alpha) * (qo[..., 0] + bc_) + alpha * (qn[..., 0] + bc_),
+             (1.0 - alpha) * qo[..., 1] + alpha * qn[..., 1],
+             (1.0 - alpha) * qo[..., 2] + alpha * qn[..., 2])
+    dry = ~linear & (qo[..., 0] <= drytol) & (qn[..., 0] <= drytol)
+    eta = np.where(linear, lin[0], const[0])
+    hu = np.where(linear, lin[1], const[1])
+    hv = np.where(linear, lin[2], const[2])
+    h = _max0(eta - bf)
+    wet = h > drytol
+    h = np.where(dry, 0.0, h)
+    hu = np.where(dry | ~wet, 0.0, hu)
+    hv = np.where(dry | ~wet, 0.0, hv)
+    return h, hu, hv
+
+
 class Hierarchy:
     def __init__(self, H, P):
         self.r = H.ratio
@@ -178,7 +268,29 @@ class Hierarchy:
     def fill(self, lev, old, alpha):
         """Ghost cells of level lev (>= 2) from the same level or from level
         lev - 1, whose states before and after its step are `old` (copies of
-        that level's q arrays, in patch order) and the current ones."""
+        that level's q arrays, in patch order) and the current ones: the rule
+        of fill_cellwise, evaluated for a patch's ghost cells at once (the
+        same operations per cell; each ghost cell reads interior cells only,
+        so the order in which they are written does not matter)."""
+        same = self.levels[lev - 1]
+        for f in same:
+            rows, cols = np.meshgrid(np.arange(f.my + 4), np.arange(f.mx + 4), indexing="ij")
+            ghost = ~((rows >= 2) & (rows < f.my + 2) & (cols >= 2) & (cols < f.mx + 2))
+            rows, cols = rows[ghost], cols[ghost]
+            I = (f.i0 + cols - 2).astype(np.int64)
+            J = (f.j0 + rows - 2).astype(np.int64)
+            k = _locate(same, I, J, skip=f)
+            cp = k >= 0
+            if cp.any():
+                f.q[rows[cp], cols[cp]] = _gather(same, [p.q for p in same], k[cp], I[cp], J[cp], 3)
+            cv = ~cp
+            if cv.any():
+                h, hu, hv = coarse_values(self.levels[lev - 2], old, self.r, self.P.drytol, alpha,
+                                          I[cv], J[cv], f.b[rows[cv], cols[cv]])
+                f.q[rows[cv], cols[cv]] = np.stack([h, hu, hv], axis=-1)
+
+    def fill_cellwise(self, lev, old, alpha):
+        """fill, one ghost cell at a time (the reading written out)."""
         for f in self.levels[lev - 1]:
             for row in range(f.my + 4):
                 for col in range(f.mx + 4):
@@ -193,7 +305,44 @@ class Hierarchy:
                                                          f.b[row, col])
 
     def average(self, lev):
-        """Level-lev cells under level lev + 1 patches from the fine cells."""
+        """Level-lev cells under level lev + 1 patches from the fine cells:
+        the rule of average_cellwise for all coarse cells under a fine patch
+        at once (the sums taken over the fine cells in the same order)."""
+        r, drytol = self.r, self.P.drytol
+        coarse = self.levels[lev - 1]
+        for f in self.levels[lev]:
+            Jc, Ic = np.meshgrid(np.arange(f.j0 // r, (f.j0 + f.my) // r),
+                                 np.arange(f.i0 // r, (f.i0 + f.mx) // r), indexing="ij")
+            Ic, Jc = Ic.ravel().astype(np.int64), Jc.ravel().astype(np.int64)
+            k = _locate(coarse, Ic, Jc)
+            seta = np.zeros(Ic.shape)
+            nwet = np.zeros(Ic.shape, dtype=np.int64)
+            hu = np.zeros(Ic.shape)
+            hv = np.zeros(Ic.shape)
+            for dj in range(r):
+                for di in range(r):
+                    rf = Jc * r + dj - f.j0 + 2
+                    cf = Ic * r + di - f.i0 + 2
+                    h = f.q[rf, cf, 0]
+                    wet = h > drytol
+                    seta = np.where(wet, seta + (h + f.b[rf, cf]), seta)
+                    nwet += wet
+                    hu = hu + f.q[rf, cf, 1]
+                    hv = hv + f.q[rf, cf, 2]
+            bc_ = _gather(coarse, [c.b for c in coarse], k, Ic, Jc, 0)
+            any_wet = nwet > 0
+            eta = seta / np.maximum(nwet, 1)
+            hc = _max0(eta - bc_)
+            keep = any_wet & (hc > drytol)
+            out = np.stack([np.where(any_wet, hc, 0.0), np.where(keep, hu / (r * r), 0.0),
+                            np.where(keep, hv / (r * r), 0.0)], axis=-1)
+            for n, c in enumerate(coarse):
+                m = k == n
+                if m.any():
+                    c.q[Jc[m] - c.j0 + 2, Ic[m] - c.i0 + 2] = out[m]
+
+    def average_cellwise(self, lev):
+        """average, one coarse cell at a time (the reading written out)."""
         r, drytol = self.r, self.P.drytol
         for f in self.levels[lev]:
             for Jc in range(f.j0 // r, (f.j0 + f.my) // r):

@@ -203,3 +203,36 @@ def test_regrid_every_b_steps_inside_the_integration(gpu, ratio):
     assert s.regrids == ref.regrids and len(s.regrids) >= 2
     np.testing.assert_allclose(dts, rdts, rtol=1e-13, atol=0)
     compare_hierarchies(s, ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bench_hierarchy_matches_the_reference(gpu, precision):
+    # the benchmark's hierarchy at its full size (one 1024^2 level-1 patch,
+    # 64 level-2 and 128 level-3 patches of 96-160 cells, ratio 4, over the
+    # shelf break and the dry coast): two coarse steps of 8 s against the
+    # reference hierarchy, every patch of every level; FP64 to 1e-12 per
+    # field, the FP32 deviation path within 1e-5 m on cells wet in both
+    L, AmrSolver, torch = gpu
+    H = W.amr_nested()
+    print(f"case amr bench hierarchy precision={precision}", flush=True)
+    s = AmrSolver(H, L.params(precision=precision))
+    s.set_dt(8.0)
+    s.run(2)
+    torch.cuda.synchronize()
+    assert s.flags() == (0, 0)
+    if precision == 0:
+        ref = run_oracle(H, 8.0, 2)
+        compare_hierarchies(s, ref)
+        return
+    ref = run_oracle(rounded_to_fp32(H), 8.0, 2)
+    worst = 0.0
+    for lev in range(1, 4):
+        for k, p in enumerate(ref.levels[lev - 1]):
+            h, hu, hv = s.state(lev, k)
+            b = p.b[2:-2, 2:-2]
+            want = p.q[2:-2, 2:-2]
+            wet = (want[..., 0] > 1e-2) & (h > 1e-2)
+            if wet.any():
+                worst = max(worst, float(np.abs((h + b) - (want[..., 0] + b))[wet].max()))
+    print(f"fp32 deviation, bench hierarchy: max surface difference {worst:.3e} m", flush=True)
+    assert worst <= 1e-5

@@ -306,3 +306,44 @@ def test_regrid_every_b_steps_of_each_level(P):
             for J in range(f.j0 - 2, f.j0 + f.my + 2):
                 for I in range(f.i0 - 2, f.i0 + f.mx + 2):
                     assert any(c.covers(I // 2, J // 2) for c in h.levels[lev - 2])
+
+
+class Cellwise(A.Hierarchy):
+    """The hierarchy with the fill and the average taken one cell at a time."""
+
+    def fill(self, lev, old, alpha):
+        self.fill_cellwise(lev, old, alpha)
+
+    def average(self, lev):
+        self.average_cellwise(lev)
+
+
+def same_bits(a, b):
+    return np.array_equal(a, b) and np.array_equal(np.signbit(a), np.signbit(b))
+
+
+@pytest.mark.parametrize("kind,ratio", [("three", 1), ("three", 2), ("three", 4),
+                                        ("nested", 2), ("nested", 4)])
+def test_whole_patch_fill_and_average_equal_the_cellwise_rule(P, kind, ratio):
+    # the array forms of fill and average against the reading written out
+    # cell by cell, bit for bit, over coarse steps of a moving hump; in the
+    # small nested hierarchy the finer levels reach over the dry coast, so
+    # ghost cells over dry land, the shoreline fallback, copies from the same
+    # level and bilinear interpolation all occur
+    if kind == "three":
+        H = W.amr_three_levels(ratio, bed="shelf", amp=3.0, u0=0.4)
+        dt = 8.0
+    else:
+        H = W.amr_nested(n1=64, ratio=ratio, counts=(3, 4), sizes=(4 * ratio, 8 * ratio),
+                         amp=3.0)
+        dt = 20.0
+    a, b = A.Hierarchy(H, P), Cellwise(H, P)
+    for h in (a, b):
+        h.run(dt, 3)
+    for lev in (1, 2, 3):
+        for pa, pb in zip(a.levels[lev - 1], b.levels[lev - 1]):
+            assert same_bits(pa.q, pb.q), lev
+    if kind == "nested":
+        for lev in (2, 3):
+            assert any((p.q[..., 0] <= P.drytol).any() for p in a.levels[lev - 1])
+            assert any((p.q[2:-2, 2:-2, 0] > 1.0).any() for p in a.levels[lev - 1])
