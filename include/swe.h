@@ -246,8 +246,10 @@ int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const voi
  * group: the next *dt, and SWE_STATUS_CFL_EXCEEDED if the retaken step is
  * still above cfl_max; with the flag clear it does nothing.  One step of the
  * CFL-ruled loop is then these two launches instead of four.  counter:
- * device uint32_t, zero before the first call; each launch that runs leaves
- * it zero.  dt, smax, status, retake: device, as swe_cfl_reduce; the step
+ * device uint32_t[3], zero before the first call; each launch that runs
+ * leaves it zero (the finished waves, then the launch's own status bits and
+ * depth resets, which join status only if its step stands: status counts
+ * accepted steps, as the unfused sequence's does not).  dt, smax, status, retake: device, as swe_cfl_reduce; the step
  * reads *dt before any wave of the launch writes it.  Other arguments as the
  * calls named. */
 int swe_patch_step_cfl(const swe_params *p, const swe_patch *patch, const void *q_in, void *q_out,
@@ -495,9 +497,14 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
  * starting from pool_<first> (first = 0 or 1), so after the call it is in
  * pool_<(first + nsteps) % 2>.  npatches, ngroups: the table's patches and
  * the groups of dt_group, group_flags (may be NULL) and retake (device
- * uint32_t[ngroups], required); other arguments as swe_batched_step.  For a
- * caller that advances many steps between host decisions (a serving loop's
- * round) this replaces four library calls per step. */
+ * uint32_t[ngroups], required).  pending: device uint32_t[2 ngroups], zero
+ * before the first call and left zero: each step's conditions (status bits,
+ * depth resets) wait there per group until the CFL rule settles them, so
+ * that status and group_status (may be NULL) count accepted steps only (a
+ * step the rule redoes reports nothing; its redo reports its own).  Other
+ * arguments as swe_batched_step.  For a caller that advances many steps
+ * between host decisions (a serving loop's round) this replaces four
+ * library calls per step. */
 int swe_batched_advance(const swe_params *p, const swe_patch *patches, int32_t npatches,
                         int32_t ngroups, const swe_item *items, int32_t nitems,
                         const swe_task *tasks, const swe_task *plain, int32_t nplain,
@@ -505,8 +512,8 @@ int swe_batched_advance(const swe_params *p, const swe_patch *patches, int32_t n
                         void *pool_work, int64_t pool_elems, const void *pool_b,
                         double *dt_group, double *smax_patch, uint32_t *status,
                         uint32_t *group_status, uint32_t *group_flags, uint32_t *retake,
-                        uint32_t *queue, const swe_schedule *sched, int32_t nsteps,
-                        void *stream);
+                        uint32_t *pending, uint32_t *queue, const swe_schedule *sched,
+                        int32_t nsteps, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):

@@ -149,8 +149,8 @@ def lib():
         L.swe_batched_retake.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, _P, i64,
                                          _P, _P, _P, _P, _P, _P, ps, _P, i32, _P]
         L.swe_batched_advance.argtypes = [pp, _P, i32, i32, _P, i32, _P, _P, i32, i32, _P, _P,
-                                          i32, _P, i64, _P, _P, _P, _P, _P, _P, _P, _P, ps,
-                                          i32, _P]
+                                          i32, _P, i64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                          ps, i32, _P]
         L.swe_batched_step_static.argtypes = [pp, _P, _P, i32, _P, _P, i32, i32, _P, _P, i64,
                                               _P, _P, _P, _P, _P, ps, _P]
         L.swe_last_error.restype = ctypes.c_char_p
@@ -407,12 +407,12 @@ def swe_batched_advance(p: swe_params, patches: int, npatches: int, ngroups: int
                         nitems: int, tasks: int, plain: int, nplain: int, nsub: int, pool_0: int,
                         pool_1: int, first: int, pool_work: int, pool_elems: int, pool_b: int,
                         dt_group: int, smax_patch: int, status: int, group_status: int,
-                        group_flags: int, retake: int, queue: int, sched: swe_schedule,
-                        nsteps: int, stream: int = 0) -> None:
+                        group_flags: int, retake: int, pending: int, queue: int,
+                        sched: swe_schedule, nsteps: int, stream: int = 0) -> None:
     _check(lib().swe_batched_advance(ctypes.byref(p), patches, npatches, ngroups, items, nitems,
                                      tasks, plain, nplain, nsub, pool_0, pool_1, first,
                                      pool_work, pool_elems, pool_b, dt_group, smax_patch,
-                                     status, group_status, group_flags, retake, queue,
+                                     status, group_status, group_flags, retake, pending, queue,
                                      ctypes.byref(sched), nsteps, stream),
            "swe_batched_advance")
 

@@ -39,7 +39,7 @@ struct BatchArgs {
     const void* pb;
     const double* dt_group;
     double* smax;
-    uint32_t* status;
+    uint32_t* status;        // (flags, clamps) of all patches; NULL: not kept
     uint32_t* group_status;  // per group (flags, clamps) pairs; NULL: not kept
     uint32_t* queue;  // [0] next item, [1] finished workgroups
     int nitems;
@@ -144,8 +144,8 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
             atomic_max_nonneg(&a.smax[2 * it.patch], wx);
             atomic_max_nonneg(&a.smax[2 * it.patch + 1], wy);
         }
-        if (clamps) atomicAdd(&a.status[1], clamps);
-        if (flags) atomicOr(&a.status[0], flags);
+        if (a.status && clamps) atomicAdd(&a.status[1], clamps);
+        if (a.status && flags) atomicOr(&a.status[0], flags);
         if (a.group_status && clamps) atomicAdd(&a.group_status[2 * pt.group + 1], clamps);
         if (a.group_status && flags) atomicOr(&a.group_status[2 * pt.group], flags);
     }
@@ -222,8 +222,8 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
         atomic_max_nonneg(&a.smax[2 * tsk.patch], wx);
         atomic_max_nonneg(&a.smax[2 * tsk.patch + 1], wy);
     }
-    if (r.clamps) atomicAdd(&a.status[1], r.clamps);
-    if (r.flags) atomicOr(&a.status[0], r.flags);
+    if (a.status && r.clamps) atomicAdd(&a.status[1], r.clamps);
+    if (a.status && r.flags) atomicOr(&a.status[0], r.flags);
     if (a.group_status && run && r.clamps) atomicAdd(&a.group_status[2 * pt.group + 1], r.clamps);
     if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
 }
@@ -301,8 +301,8 @@ __global__ void __launch_bounds__(64, (DEV ? 3 : 2) - (FRIC ? 1 : 0)) k_pack(Bat
         atomic_max_nonneg(&a.smax[2 * tsk.patch + 1],
                           __longlong_as_double(static_cast<long long>(by)));
     }
-    if (r.clamps) atomicAdd(&a.status[1], r.clamps);
-    if (r.flags) atomicOr(&a.status[0], r.flags);
+    if (a.status && r.clamps) atomicAdd(&a.status[1], r.clamps);
+    if (a.status && r.flags) atomicOr(&a.status[0], r.flags);
     if (a.group_status && run && r.clamps) atomicAdd(&a.group_status[2 * pt.group + 1], r.clamps);
     if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
 }
@@ -386,9 +386,14 @@ int check_sched(const swe_schedule* s) {
 
 }  // namespace
 
-// error slot shared with swe_step.hip (not part of the ABI)
+// error slot and the CFL rule with pending conditions, shared with
+// swe_step.hip (not part of the ABI)
 extern "C" __attribute__((visibility("hidden"))) int swe_internal_set_error(int code,
                                                                            const char* msg);
+extern "C" __attribute__((visibility("hidden"))) int swe_internal_cfl_reduce_pending(
+    const swe_params* p, const swe_patch* patches, int32_t n, int32_t ngroups,
+    double* smax_patch, double* dt_group, uint32_t* status, uint32_t* group_flags,
+    uint32_t* retake, uint32_t* pending, uint32_t* group_status, void* stream);
 
 namespace {
 int bfail(int code, const std::string& msg) { return swe_internal_set_error(code, msg.c_str()); }
@@ -610,7 +615,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
                         const uint32_t* retake, int32_t ngroups, uint32_t* group_status,
-                        void* stream, bool zero_queue = false) {
+                        void* stream, bool zero_queue = false, bool pending = false) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -627,7 +632,11 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
         return bfail(SWE_EINVAL, "swe_batched_step: substeps need pool_work");
     if (packed && nitems > 0 && nsub < 1)
         return bfail(SWE_EINVAL, "swe_batched_step: packs need nsub >= 1");
-    if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch || !status ||
+    // pending: the steps report into group_status alone (the caller's pending
+    // pairs, which the CFL rule settles)
+    if (pending && !group_status) return bfail(SWE_EINVAL, "swe_batched_step: null pending pairs");
+    if (!patches || !pool_in || !pool_out || !pool_b || !dt_group || !smax_patch ||
+        (!status && !pending) ||
         (nitems > 0 && !items) || (nitems > 0 && !packed && (!tasks || !queue)) ||
         ((nplain > 0 || (packed && nitems > 0)) && !plain))
         return bfail(SWE_EINVAL, "swe_batched_step: null pointer");
@@ -654,7 +663,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.pb = pool_b;
     a.dt_group = dt_group;
     a.smax = smax_patch;
-    a.status = status;
+    a.status = pending ? nullptr : status;
     a.group_status = group_status;
     a.queue = queue;
     a.nitems = nitems;
@@ -782,31 +791,35 @@ int swe_batched_advance(const swe_params* p, const swe_patch* patches, int32_t n
                         void* pool_work, int64_t pool_elems, const void* pool_b,
                         double* dt_group, double* smax_patch, uint32_t* status,
                         uint32_t* group_status, uint32_t* group_flags, uint32_t* retake,
-                        uint32_t* queue, const swe_schedule* sched, int32_t nsteps,
-                        void* stream) {
+                        uint32_t* pending, uint32_t* queue, const swe_schedule* sched,
+                        int32_t nsteps, void* stream) {
     if (first != 0 && first != 1) return bfail(SWE_EINVAL, "swe_batched_advance: first must be 0 or 1");
     if (nsteps < 0 || npatches < 0 || ngroups < 1)
         return bfail(SWE_EINVAL, "swe_batched_advance: bad nsteps, npatches or ngroups");
-    if (!retake || !pool_0 || !pool_1)
-        return bfail(SWE_EINVAL, "swe_batched_advance: null retake flags or pool");
+    if (!retake || !pending || !status || !pool_0 || !pool_1)
+        return bfail(SWE_EINVAL, "swe_batched_advance: null retake flags, pending pairs, status or pool");
     void* pool[2] = {pool_0, pool_1};
     int cur = first;
     for (int k = 0; k < nsteps; ++k) {
         // the step, the CFL rule with the retake flags, the gated redo of the
         // flagged groups, and the CFL rule of the redone steps
+        // the steps report their conditions as pending per group; the CFL
+        // rule settles them (a step it redoes reports nothing)
         int rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
                               pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
-                              status, queue, sched, nullptr, 0, group_status, stream);
+                              nullptr, queue, sched, nullptr, 0, pending, stream, false, true);
         if (rc) return rc;
-        rc = swe_cfl_reduce(p, patches, npatches, ngroups, smax_patch, dt_group, status,
-                            group_flags, retake, 0, stream);
+        rc = swe_internal_cfl_reduce_pending(p, patches, npatches, ngroups, smax_patch, dt_group,
+                                             status, group_flags, retake, pending, group_status,
+                                             stream);
         if (rc) return rc;
         rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
                           pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
-                          status, queue, sched, retake, ngroups, group_status, stream);
+                          nullptr, queue, sched, retake, ngroups, pending, stream, false, true);
         if (rc) return rc;
-        rc = swe_cfl_reduce(p, patches, npatches, ngroups, smax_patch, dt_group, status,
-                            group_flags, nullptr, 0, stream);
+        rc = swe_internal_cfl_reduce_pending(p, patches, npatches, ngroups, smax_patch, dt_group,
+                                             status, group_flags, nullptr, pending, group_status,
+                                             stream);
         if (rc) return rc;
         cur ^= 1;
     }

@@ -55,6 +55,8 @@ struct StepArgs {
     uint32_t* done;
     double* dt_next;
     uint32_t* flags;
+    uint32_t* status_out;  // status the settled conditions join (status then holds
+                           // the launch's pending pair)
     double cfl_desired, cfl_max;
     int tref;
 };
@@ -89,7 +91,14 @@ __device__ __forceinline__ void cfl_tail(const StepArgs& a, int lane) {
     if (rate > 0.0 && isfinite(rate)) atomicExch(reinterpret_cast<unsigned long long*>(a.dt_next),
                                                  static_cast<unsigned long long>(
                                                      __double_as_longlong(a.cfl_desired / rate)));
-    if (f) atomicOr(a.status, f);
+    if (f) atomicOr(a.status_out, f);
+    // the launch's own conditions count when its step stands; a step to be
+    // redone reports nothing (the redo reports its own)
+    const uint32_t pf = atomicExch(&a.status[0], 0u), pc = atomicExch(&a.status[1], 0u);
+    if (!(a.flags && over)) {
+        if (pf) atomicOr(a.status_out, pf);
+        if (pc) atomicAdd(&a.status_out[1], pc);
+    }
     atomicExch(a.done, 0u);
 }
 
@@ -505,11 +514,16 @@ __global__ void k_level_steps(const double* dt_coarse, int ratio, int nlevels, d
     }
 }
 
+// pending (NULL: none): per group, the (flags, clamps) the step just taken
+// reported; they join status and group_status when the step stands and are
+// dropped when it is to be redone (the redo reports its own), so only
+// accepted steps count.
 __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict__ patches, int n,
                                                     double* smax, double* dt_group,
                                                     uint32_t* status, uint32_t* group_flags,
                                                     uint32_t* retake, double cfl_desired,
-                                                    double cfl_max, int initial) {
+                                                    double cfl_max, int initial,
+                                                    uint32_t* pending, uint32_t* group_status) {
     const int g = blockIdx.x;
     __shared__ unsigned long long red[256 / kWave];
     double rate = 0.0;
@@ -542,6 +556,17 @@ __global__ void __launch_bounds__(256) k_cfl_reduce(const swe_patch* __restrict_
         if (f) {
             atomicOr(status, f);
             if (group_flags) atomicOr(&group_flags[g], f);
+        }
+        if (pending) {
+            const uint32_t pf = pending[2 * g], pc = pending[2 * g + 1];
+            pending[2 * g] = 0u;
+            pending[2 * g + 1] = 0u;
+            if (!(retake && over)) {
+                if (pf) atomicOr(status, pf);
+                if (pc) atomicAdd(&status[1], pc);
+                if (group_status && pf) atomicOr(&group_status[2 * g], pf);
+                if (group_status && pc) atomicAdd(&group_status[2 * g + 1], pc);
+            }
         }
     }
 }
@@ -820,6 +845,8 @@ static int patch_step(const swe_params* p, const swe_patch* patch, const void* q
     a.done = fused ? fused->counter : nullptr;
     a.dt_next = fused ? fused->dt : nullptr;
     a.flags = fused ? fused->flags : nullptr;
+    a.status_out = status;
+    if (fused) a.status = fused->counter + 1;  // the launch's pending (flags, clamps)
     a.cfl_desired = p->cfl_desired;
     a.cfl_max = p->cfl_max;
     a.tref = patch->tref;
@@ -1015,7 +1042,25 @@ int swe_cfl_reduce(const swe_params* p, const swe_patch* patches, int32_t n, int
         return fail(SWE_EINVAL, "swe_cfl_reduce: bad arguments");
     hipLaunchKernelGGL(swe::k_cfl_reduce, dim3(ngroups), dim3(256), 0,
                        static_cast<hipStream_t>(stream), patches, n, smax_patch, dt_group,
-                       status, group_flags, retake, p->cfl_desired, p->cfl_max, initial);
+                       status, group_flags, retake, p->cfl_desired, p->cfl_max, initial,
+                       nullptr, nullptr);
+    return check_launch("swe_cfl_reduce");
+}
+
+// swe_cfl_reduce that also settles the steps' pending conditions (for
+// swe_batched_advance; not part of the ABI).
+__attribute__((visibility("hidden"))) int swe_internal_cfl_reduce_pending(
+    const swe_params* p, const swe_patch* patches, int32_t n, int32_t ngroups,
+    double* smax_patch, double* dt_group, uint32_t* status, uint32_t* group_flags,
+    uint32_t* retake, uint32_t* pending, uint32_t* group_status, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!patches || !smax_patch || !dt_group || !status || !pending || n < 0 || ngroups < 1)
+        return fail(SWE_EINVAL, "swe_cfl_reduce: bad arguments");
+    hipLaunchKernelGGL(swe::k_cfl_reduce, dim3(ngroups), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), patches, n, smax_patch, dt_group,
+                       status, group_flags, retake, p->cfl_desired, p->cfl_max, 0, pending,
+                       group_status);
     return check_launch("swe_cfl_reduce");
 }
 

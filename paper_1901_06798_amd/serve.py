@@ -141,6 +141,8 @@ class ScenarioServer:
         self.gstatus = torch.zeros(2 * max_slots, dtype=torch.int32, device=self.dev)
         self.group_flags = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
         self.retake = torch.zeros(max_slots, dtype=torch.int32, device=self.dev)
+        # each step's conditions per slot until the CFL rule settles them
+        self.pending = torch.zeros(2 * max_slots, dtype=torch.int32, device=self.dev)
         self.queue_ctr = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.cur = 0
         self.active: list[Scenario] = []
@@ -322,7 +324,8 @@ class ScenarioServer:
             self.nplain, self.nsub, self.pools[0].data_ptr(), self.pools[1].data_ptr(), self.cur,
             0, 3 * self.plane, self.b.data_ptr(), self.dt.data_ptr(), self.rsmax.data_ptr(),
             self.status.data_ptr(), self.gstatus.data_ptr(), self.group_flags.data_ptr(),
-            self.retake.data_ptr(), self.queue_ctr.data_ptr(), self.sched, steps, stream)
+            self.retake.data_ptr(), self.pending.data_ptr(), self.queue_ctr.data_ptr(),
+            self.sched, steps, stream)
 
     def _enqueue_round(self, steps: int) -> None:
         # with graphs, a round is captured once per active set and state

@@ -58,7 +58,7 @@ class PatchSolver:
         self.status = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.retake = torch.zeros(1, dtype=torch.int32, device=self.dev)
         # finished-wave counter of the launches that end with the CFL rule
-        self.counter = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.counter = torch.zeros(3, dtype=torch.int32, device=self.dev)
         self.fused = True  # the step and the CFL rule in one launch
         self.metric_ptr = 0
         # launch order of the step's tasks, heaviest first from the last step
@@ -212,13 +212,15 @@ class PatchSolver:
         s = 0
         while s < nsteps:
             dt_now = self.dt.clone() if record_dt else None
+            before = self.status.clone()
             self.enqueue_step(retake=False)
             st = self.status.cpu()
             if int(st[0]) & L.STATUS_CFL_EXCEEDED:
                 # discard: the output buffer is dropped and the step retaken with
-                # the reduced dt that the CFL reduction just wrote
+                # the reduced dt that the CFL reduction just wrote; what the
+                # discarded step reported is dropped with it
                 self.cur ^= 1
-                self.status[0] = int(st[0]) & ~L.STATUS_CFL_EXCEEDED
+                self.status.copy_(before)
                 retakes += 1
                 continue
             if record_dt:

@@ -160,19 +160,22 @@ def test_advance_equals_the_step_by_step_sequence(gpu, seg):
         s.dt.mul_(torch.tensor([1.0, 2.5, 1.0, 1.7], dtype=torch.float64, device=s.dev))
     for _ in range(7):
         a.enqueue_step()
+    pending = torch.zeros(2 * b.ngroups, dtype=torch.int32, device=b.dev)
     args = (b.table.data_ptr(), b.n, b.ngroups, b.items.data_ptr(), b.nitems, b.tasks.data_ptr(),
             b.tasks.data_ptr() + L.SWE_TASK_BYTES * (b.ntasks - b.nplain), b.nplain, b.nsub,
             b.pools[0].data_ptr(), b.pools[1].data_ptr(), b.cur,
             b.work.data_ptr() if b.work is not None else 0, 3 * b.plane, b.b.data_ptr(),
             b.dt.data_ptr(), b.smax.data_ptr(), b.status.data_ptr(), 0,
-            b.group_flags.data_ptr(), b.retake.data_ptr(), b.queue.data_ptr(), b.sched, 7,
-            b.stream)
+            b.group_flags.data_ptr(), b.retake.data_ptr(), pending.data_ptr(),
+            b.queue.data_ptr(), b.sched, 7, b.stream)
     L.swe_batched_advance(b.p, *args)
     b.cur = (b.cur + 7) % 2
     torch.cuda.synchronize()
     assert a.cur == b.cur
     assert int(a.status[0].item()) & L.STATUS_RETAKEN
+    # the same flags (no step here resets a depth, so the counts agree too)
     assert torch.equal(a.status, b.status) and torch.equal(a.dt, b.dt)
+    assert not pending.any()
     for k in range(len(probs)):
         for x, y in zip(a.state(k), b.state(k)):
             assert np.array_equal(x, y), k

@@ -143,3 +143,35 @@ def test_cfl_rule_fused_into_the_step_equals_the_separate_launches(gpu, case):
     assert not a.counter.any() and not a.smax.any()
     for x, y in zip(a.state(), b.state()):
         assert np.array_equal(x, y)
+
+
+def test_only_accepted_steps_report_depth_resets(gpu, orc):
+    # serving scenario 45 (372^2, 1000 steps): some steps above the Courant
+    # limit reset depths before the CFL rule redoes them.  The redone steps
+    # report nothing: the fused device loop, the host loop and the batched
+    # loop (swe_batched_advance, as the server runs it) report no reset, as
+    # the reference run does, and end in the reference state bit for bit
+    L, PatchSolver, BatchedSolver, torch = gpu
+    from paper_1901_06798_amd.serve import Scenario, ScenarioServer
+    pb = W.scenario(45, n=372, nsteps=1000)
+    print("case scenario 45 accepted-step conditions", flush=True)
+    g, q, b = oracle_setup(orc, pb)
+    r = orc.run(orc.params(), g, q, b, 1000)
+    assert r["clamps"] == 0 and r["retakes"] > 0
+    dev = PatchSolver(pb, L.params())
+    dev.initial_dt()
+    dev.run_async(1000)
+    host = PatchSolver(pb, L.params())
+    host.run(1000)
+    torch.cuda.synchronize()
+    for s in (dev, host):
+        f, c = s.flags()
+        assert c == 0 and not f & L.STATUS_NEG_DEPTH, (f, c)
+        for k, a in enumerate(s.state()):
+            assert np.array_equal(a, interior(q)[..., k])
+    assert dev.flags()[0] & L.STATUS_RETAKEN
+    srv = ScenarioServer(L.params(), max_slots=2, steps_per_round=50)
+    out = srv.serve([Scenario(45, 0.0, pb, 1000), Scenario(3, 0.0, W.scenario(3, n=200), 300)])
+    got = {sc.rid: sc for sc in out["done"]}
+    assert got[45].result["clamps"] == 0 and not got[45].result["status"] & L.STATUS_NEG_DEPTH
+    assert np.array_equal(got[45].result["eta"], interior(q)[..., 0] + interior(b))
