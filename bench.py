@@ -446,8 +446,9 @@ def time_patch(pb, params, steps: int, warmup: int, ordered: bool = True, sphere
         s.launch_step_cfl(qi, qo, stream.cuda_stream)
         ev1[k].record(stream)
         s.after_step(stream.cuda_stream)
-        # the gated retake, which ends at once unless the step went above cfl_max
-        s.launch_retake_cfl(qi, qo, stream.cuda_stream)
+        # up to two gated redos, which end at once unless the step went above cfl_max
+        s.launch_retake_cfl(qi, qo, stream.cuda_stream, last=0)
+        s.launch_retake_cfl(qi, qo, stream.cuda_stream, last=1)
         s.cur ^= 1
     end.record(stream)
     torch.cuda.synchronize()

@@ -242,10 +242,13 @@ int swe_patch_step_sphere(const swe_params *p, const swe_patch *patch, const voi
  * (else retake[group] = 0); r NaN sets SWE_STATUS_NONFINITE; *dt =
  * cfl_desired / r when r is positive and finite; smax[0..1] = 0.
  * swe_patch_retake_cfl is swe_patch_retake (metric as above) whose launch,
- * when the flag is set, ends with swe_cfl_reduce(retake = NULL) for the
- * group: the next *dt, and SWE_STATUS_CFL_EXCEEDED if the retaken step is
- * still above cfl_max; with the flag clear it does nothing.  One step of the
- * CFL-ruled loop is then these two launches instead of four.  counter:
+ * when the flag is set, ends with the CFL rule for the group on the redone
+ * step: with last = 0 as the step's (a redone step still above cfl_max sets
+ * the flag again, for another redo), with last != 0 as swe_cfl_reduce(retake
+ * = NULL) (the next *dt, and SWE_STATUS_CFL_EXCEEDED if the step is still
+ * above cfl_max; it stands); with the flag clear it does nothing.  The
+ * CFL-ruled loop takes the step, a redo with last = 0 and one with last = 1:
+ * three launches instead of six, up to two redos per step.  counter:
  * device uint32_t[3], zero before the first call; each launch that runs
  * leaves it zero (the finished waves, then the launch's own status bits and
  * depth resets, which join status only if its step stands: status counts
@@ -259,7 +262,7 @@ int swe_patch_step_cfl(const swe_params *p, const swe_patch *patch, const void *
                        void *stream);
 int swe_patch_retake_cfl(const swe_params *p, const swe_patch *patch, const void *q_in,
                          void *q_out, const void *b, double *dt, double *smax, uint32_t *status,
-                         const uint32_t *retake, uint32_t *counter, const double *metric,
+                         uint32_t *retake, uint32_t *counter, const double *metric, int32_t last,
                          void *stream);
 
 /* swe_patch_retake on a latitude-longitude patch: the same gated redo of the
@@ -490,10 +493,12 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
 
 /* nsteps coarse steps of the batched step under the CFL rule, each as
  * swe_batched_step, then swe_cfl_reduce with the retake flags, the gated
- * swe_batched_retake of the flagged groups and swe_cfl_reduce of the redone
- * steps (Sec. 2: the step size follows the largest wave speed, and a step
- * above the Courant limit is redone with a smaller one), all enqueued on
- * `stream` by one call.  The state alternates between pool_0 and pool_1
+ * swe_batched_retake of the flagged groups, swe_cfl_reduce with the retake
+ * flags again, a second gated retake of the groups still above the limit
+ * and swe_cfl_reduce of the redone steps (Sec. 2: the step size follows the
+ * largest wave speed, and a step above the Courant limit is redone with a
+ * smaller one; a second redo still above it stands and is flagged
+ * SWE_STATUS_CFL_EXCEEDED), all enqueued on `stream` by one call.  The state alternates between pool_0 and pool_1
  * starting from pool_<first> (first = 0 or 1), so after the call it is in
  * pool_<(first + nsteps) % 2>.  npatches, ngroups: the table's patches and
  * the groups of dt_group, group_flags (may be NULL) and retake (device

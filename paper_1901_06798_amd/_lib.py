@@ -129,7 +129,7 @@ def lib():
         L.swe_patch_step_cfl.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                          _P, _P, _P, _P, i64, ctypes.POINTER(swe_launch), _P]
         L.swe_patch_retake_cfl.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
-                                           _P, _P, _P, _P]
+                                           _P, _P, _P, i32, _P]
         L.swe_speed_scan_sphere.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, _P]
         L.swe_mass_sphere.argtypes = [pp, _P, _P, _P, _P, _P]
         L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, i64, i64, _P, _P, _P]
@@ -335,9 +335,9 @@ def swe_patch_step_cfl(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: i
 
 def swe_patch_retake_cfl(p: swe_params, pt: swe_patch, q_in: int, q_out: int, b: int, dt: int,
                          smax: int, status: int, retake: int, counter: int, metric: int = 0,
-                         stream: int = 0) -> None:
+                         last: int = 1, stream: int = 0) -> None:
     _check(lib().swe_patch_retake_cfl(ctypes.byref(p), ctypes.byref(pt), q_in, q_out, b, dt,
-                                      smax, status, retake, counter, metric, stream),
+                                      smax, status, retake, counter, metric, last, stream),
            "swe_patch_retake_cfl")
 
 

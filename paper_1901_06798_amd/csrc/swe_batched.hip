@@ -813,14 +813,20 @@ int swe_batched_advance(const swe_params* p, const swe_patch* patches, int32_t n
                                              status, group_flags, retake, pending, group_status,
                                              stream);
         if (rc) return rc;
-        rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
-                          pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
-                          nullptr, queue, sched, retake, ngroups, pending, stream, false, true);
-        if (rc) return rc;
-        rc = swe_internal_cfl_reduce_pending(p, patches, npatches, ngroups, smax_patch, dt_group,
-                                             status, group_flags, nullptr, pending, group_status,
-                                             stream);
-        if (rc) return rc;
+        // up to two redos: a redone step still above the limit is redone once
+        // more, and only a second redo still above it stands, flagged
+        for (int redo = 0; redo < 2; ++redo) {
+            rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
+                              pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
+                              nullptr, queue, sched, retake, ngroups, pending, stream, false,
+                              true);
+            if (rc) return rc;
+            rc = swe_internal_cfl_reduce_pending(p, patches, npatches, ngroups, smax_patch,
+                                                 dt_group, status, group_flags,
+                                                 redo == 0 ? retake : nullptr, pending,
+                                                 group_status, stream);
+            if (rc) return rc;
+        }
         cur ^= 1;
     }
     return SWE_OK;

@@ -977,7 +977,7 @@ int swe_patch_step_cfl(const swe_params* p, const swe_patch* patch, const void* 
 
 int swe_patch_retake_cfl(const swe_params* p, const swe_patch* patch, const void* q_in,
                          void* q_out, const void* b, double* dt, double* smax, uint32_t* status,
-                         const uint32_t* retake, uint32_t* counter, const double* metric,
+                         uint32_t* retake, uint32_t* counter, const double* metric, int32_t last,
                          void* stream) {
     if (!dt || !retake || !counter)
         return fail(SWE_EINVAL, "swe_patch_retake_cfl: null dt, retake flags or counter");
@@ -985,10 +985,12 @@ int swe_patch_retake_cfl(const swe_params* p, const swe_patch* patch, const void
     if (patch && patch->tref < 1) return fail(SWE_EINVAL, "swe_patch_retake_cfl: tref < 1");
     if (metric && p && (p->method != SWE_SPLIT || p->precision != SWE_F64))
         return fail(SWE_EINVAL, "swe_patch_retake_cfl: a metric needs the FP64 split step");
-    const FusedCfl f{counter, dt, nullptr};
-    return patch_step(p, patch, q_in, q_out, b, dt, smax, status,
-                      patch ? retake + patch->group : retake, nullptr, 0, nullptr, stream, metric,
-                      &f);
+    // not the last redo: a redone step still above the limit sets the flag
+    // again for the next one; the last one's stands, flagged
+    uint32_t* flag = patch ? retake + patch->group : retake;
+    const FusedCfl f{counter, dt, last ? nullptr : flag};
+    return patch_step(p, patch, q_in, q_out, b, dt, smax, status, flag, nullptr, 0, nullptr,
+                      stream, metric, &f);
 }
 
 int swe_ghost_fill(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,

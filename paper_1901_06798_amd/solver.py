@@ -147,12 +147,14 @@ class PatchSolver:
                              self.sched.numel() if self.sched is not None else 0, self.launch,
                              self.stream if stream is None else stream)
 
-    def launch_retake_cfl(self, qi: int, qo: int, stream: int | None = None) -> None:
-        """The gated redo of the step, ending with the CFL rule when it runs."""
+    def launch_retake_cfl(self, qi: int, qo: int, stream: int | None = None,
+                          last: int = 1) -> None:
+        """The gated redo of the step, ending with the CFL rule when it runs
+        (last = 0: a redo still above the limit asks for one more)."""
         L.swe_patch_retake_cfl(self.p, self.pt, qi, qo, self.b.data_ptr(), self.dt.data_ptr(),
                                self.smax.data_ptr(), self.status.data_ptr(),
                                self.retake.data_ptr(), self.counter.data_ptr(), self.metric_ptr,
-                               self.stream if stream is None else stream)
+                               last, self.stream if stream is None else stream)
 
     def launch_retake(self, qi: int, qo: int, retake: int, stream: int | None = None) -> None:
         """The gated redo of the step q_in -> q_out with the reduced dt."""
@@ -182,7 +184,9 @@ class PatchSolver:
         if cfl and retake and dt_ptr is None and self.fused:
             self.launch_step_cfl(qi, qo)
             self.after_step()
-            self.launch_retake_cfl(qi, qo)
+            # up to two redos, each a gated launch that ends at once unless due
+            self.launch_retake_cfl(qi, qo, last=0)
+            self.launch_retake_cfl(qi, qo, last=1)
             self.cur ^= 1
             return
         dt = dt_ptr if dt_ptr is not None else self.dt.data_ptr()

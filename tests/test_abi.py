@@ -314,7 +314,7 @@ def test_sphere_step_argument_errors(L):
 
     def fused_retake(p, d=fake, r=rt, c=cnt, m=None):
         return lib.swe_patch_retake_cfl(ctypes.byref(p), ctypes.byref(pt), fake, out, fake, d,
-                                        fake, fake, r, c, m, None)
+                                        fake, fake, r, c, m, 1, None)
     for f in (fused, fused_retake):
         assert f(L.params(), d=None) == L.SWE_EINVAL
         assert f(L.params(), r=None) == L.SWE_EINVAL

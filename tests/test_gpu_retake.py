@@ -95,10 +95,15 @@ def test_retake_flags_are_cleared_each_step(gpu):
     s.dt.fill_(too_large_dt(PatchSolver, pb, p, 2.2))
     s.run_async(1)
     torch.cuda.synchronize()
-    assert int(s.retake.item()) == 1  # the first step was redone
+    # the first step was redone, and the redo, within the limit, cleared the flag
+    assert int(s.status[0].item()) & L.STATUS_RETAKEN
+    assert int(s.retake.item()) == 0
+    s.status.zero_()
     s.run_async(1)
     torch.cuda.synchronize()
-    assert int(s.retake.item()) == 0  # the next one stood
+    # the next one stood: no redo, flag clear
+    assert not int(s.status[0].item()) & L.STATUS_RETAKEN
+    assert int(s.retake.item()) == 0
 
 
 @pytest.mark.parametrize("case", ["f64", "f32", "unsplit", "sphere", "f64-large"])
@@ -145,16 +150,19 @@ def test_cfl_rule_fused_into_the_step_equals_the_separate_launches(gpu, case):
         assert np.array_equal(x, y)
 
 
-def test_only_accepted_steps_report_depth_resets(gpu, orc):
-    # serving scenario 45 (372^2, 1000 steps): some steps above the Courant
-    # limit reset depths before the CFL rule redoes them.  The redone steps
-    # report nothing: the fused device loop, the host loop and the batched
-    # loop (swe_batched_advance, as the server runs it) report no reset, as
-    # the reference run does, and end in the reference state bit for bit
+@pytest.mark.parametrize("rid,n", [(45, 372), (86, 668)])
+def test_only_accepted_steps_report_depth_resets(gpu, orc, rid, n):
+    # serving scenarios 45 (372^2) and 86 (668^2), 1000 steps: some steps
+    # above the Courant limit reset depths before the CFL rule redoes them,
+    # and in scenario 86 one redo is still above the limit and is redone
+    # again.  The redone steps report nothing: the fused device loop (up to
+    # two redos), the host loop and the batched loop (swe_batched_advance, as
+    # the server runs it) report no reset, as the reference run does, and end
+    # in the reference state bit for bit
     L, PatchSolver, BatchedSolver, torch = gpu
     from paper_1901_06798_amd.serve import Scenario, ScenarioServer
-    pb = W.scenario(45, n=372, nsteps=1000)
-    print("case scenario 45 accepted-step conditions", flush=True)
+    pb = W.scenario(rid, n=n, nsteps=1000)
+    print(f"case scenario {rid} accepted-step conditions", flush=True)
     g, q, b = oracle_setup(orc, pb)
     r = orc.run(orc.params(), g, q, b, 1000)
     assert r["clamps"] == 0 and r["retakes"] > 0
@@ -166,12 +174,13 @@ def test_only_accepted_steps_report_depth_resets(gpu, orc):
     torch.cuda.synchronize()
     for s in (dev, host):
         f, c = s.flags()
-        assert c == 0 and not f & L.STATUS_NEG_DEPTH, (f, c)
+        assert c == 0 and not f & (L.STATUS_NEG_DEPTH | L.STATUS_CFL_EXCEEDED), (f, c)
         for k, a in enumerate(s.state()):
             assert np.array_equal(a, interior(q)[..., k])
     assert dev.flags()[0] & L.STATUS_RETAKEN
     srv = ScenarioServer(L.params(), max_slots=2, steps_per_round=50)
-    out = srv.serve([Scenario(45, 0.0, pb, 1000), Scenario(3, 0.0, W.scenario(3, n=200), 300)])
+    out = srv.serve([Scenario(rid, 0.0, pb, 1000), Scenario(3, 0.0, W.scenario(3, n=200), 300)])
+    assert not out["status_flags"] & L.STATUS_CFL_EXCEEDED
     got = {sc.rid: sc for sc in out["done"]}
-    assert got[45].result["clamps"] == 0 and not got[45].result["status"] & L.STATUS_NEG_DEPTH
-    assert np.array_equal(got[45].result["eta"], interior(q)[..., 0] + interior(b))
+    assert got[rid].result["clamps"] == 0 and not got[rid].result["status"] & L.STATUS_NEG_DEPTH
+    assert np.array_equal(got[rid].result["eta"], interior(q)[..., 0] + interior(b))
