@@ -693,6 +693,32 @@ int swe_amr_init(const swe_params *p, int32_t ratio, const swe_amr_rect *new_rec
                  const void *q_coarse, int64_t coarse_plane_stride, const void *b_coarse,
                  void *stream);
 
+/* swe_amr_plans: the plans swe_amr_fill and swe_amr_average take for the
+ * n_fine patches of a level (device table `fine`) over the n_coarse patches
+ * of the level below (`coarse`, ratio r), built on the device from the two
+ * rectangle tables (Sec. 3: a finer level's ghost cells come from its own
+ * level or from the level below; the updating process averages the fine
+ * cells onto the coarse cells under them).  Fine patch k writes its ghost
+ * cells, row by row of its frame (two rows, then the four ghost cells of
+ * each interior row, then two rows), to fill_ops[fill_first[k] ..]: a cell
+ * over another fine patch's interior (the first in order) as SWE_AMR_COPY
+ * from that cell, else as SWE_AMR_COARSE from the coarse cell (floor(I / r),
+ * floor(J / r)) with the bilinear stencil documented for swe_amr_fill_op,
+ * each cell looked up in the first coarse patch that holds it; and its
+ * coarse cells (floor(i0 / r) .. floor((i0 + mx) / r) - 1 by the same in j,
+ * row by row) to avg_ops[avg_first[k] ..] (dst in the first coarse patch
+ * that holds the cell, src = the fine cell (r Ic, r Jc), pitch = the fine
+ * pitch).  fill_first, avg_first: device int64 arrays of the caller's
+ * offsets (patch k has (mx + 4)(my + 4) - mx my ghost entries); max_entries
+ * bounds a patch's ghost plus averaging entries.  err: device uint32, OR-ed
+ * with 1 if a ghost cell lies over no cell of either level and 2 if a coarse
+ * cell under a fine patch lies in no coarse patch (those entries then hold
+ * offset 0: the caller must not use the plan). */
+int swe_amr_plans(const swe_amr_rect *fine, int32_t n_fine, const swe_amr_rect *coarse,
+                  int32_t n_coarse, int32_t ratio, int64_t max_entries, swe_amr_fill_op *fill_ops,
+                  const int64_t *fill_first, swe_amr_avg_op *avg_ops, const int64_t *avg_first,
+                  uint32_t *err, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *swe_last_error(void);
 

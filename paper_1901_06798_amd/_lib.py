@@ -130,6 +130,7 @@ def lib():
                                          _P, _P, _P, _P, i64, ctypes.POINTER(swe_launch), _P]
         L.swe_patch_retake_cfl.argtypes = [pp, ctypes.POINTER(swe_patch), _P, _P, _P, _P, _P, _P,
                                            _P, _P, _P, i32, _P]
+        L.swe_amr_plans.argtypes = [_P, i32, _P, i32, i32, i64, _P, _P, _P, _P, _P, _P]
         L.swe_speed_scan_sphere.argtypes = [pp, _P, i32, i32, _P, _P, _P, _P, _P]
         L.swe_mass_sphere.argtypes = [pp, _P, _P, _P, _P, _P]
         L.swe_state_import.argtypes = [pp, _P, i32, i32, i32, _P, _P, i64, i64, _P, _P, _P]
@@ -162,7 +163,8 @@ def lib():
                      "swe_amr_init", "swe_patch_step_sphere", "swe_state_import",
                      "swe_state_export", "swe_batched_step_static", "swe_level_steps",
                      "swe_patch_retake_sphere", "swe_speed_scan_sphere", "swe_mass_sphere",
-                     "swe_batched_advance", "swe_patch_step_cfl", "swe_patch_retake_cfl"):
+                     "swe_batched_advance", "swe_patch_step_cfl", "swe_patch_retake_cfl",
+                     "swe_amr_plans"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -296,6 +298,13 @@ def swe_amr_init(p: swe_params, ratio: int, new_rects: int, n_new: int, max_cell
                               old_plane_stride, coarse_rects, n_coarse, q_coarse,
                               coarse_plane_stride, b_coarse, stream),
            "swe_amr_init")
+
+
+def swe_amr_plans(fine: int, n_fine: int, coarse: int, n_coarse: int, ratio: int,
+                  max_entries: int, fill_ops: int, fill_first: int, avg_ops: int, avg_first: int,
+                  err: int, stream: int = 0) -> None:
+    _check(lib().swe_amr_plans(fine, n_fine, coarse, n_coarse, ratio, max_entries, fill_ops,
+                               fill_first, avg_ops, avg_first, err, stream), "swe_amr_plans")
 
 
 def swe_ghost_fill(p: swe_params, patches: int, n: int, max_mx: int, max_my: int, q: int,

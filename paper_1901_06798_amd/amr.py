@@ -7,10 +7,11 @@ paper's GPU code).
 Each level is one BatchedSolver: its patches live in one pool (two state
 buffers and the bed), and a level step is one swe_batched_step.  Patches of
 level 2 and finer have user boundaries on every side: their ghost cells are
-written by swe_amr_fill before each of their substeps.  The host computes the
-fill and averaging plans once (which cell each ghost cell or covered coarse
-cell reads); a coarse step is then a fixed sequence of launches, with the
-step sizes in device memory, that can be captured into a HIP graph.
+written by swe_amr_fill before each of their substeps.  The fill and averaging
+plans (which cell each ghost cell or covered coarse cell reads) are built on
+the device from the levels' rectangles, once per set of patches; a coarse
+step is then a fixed sequence of launches, with the step sizes in device
+memory, that can be captured into a HIP graph.
 
 Nesting required (not checked cell by cell): every ghost cell of a level-l
 patch (l >= 2) lies over an interior cell of the same level or of level
@@ -143,22 +144,6 @@ def average_plan(fine: _Geo, coarse: _Geo, r: int) -> np.ndarray:
     return np.concatenate(ops) if ops else np.zeros(0, dtype=AVG_DTYPE)
 
 
-def cover_block(geo: _Geo, i0: int, j0: int, nx: int, ny: int, r: int = 1) -> np.ndarray:
-    """Patch of `geo` whose interior holds cell (I // r, J // r), for the cells
-    I in [i0, i0 + nx), J in [j0, j0 + ny) of a level r times finer (-1: none);
-    by rectangle intersection, first patch in order."""
-    out = np.full((ny, nx), -1, dtype=np.int64)
-    for k in range(len(geo.i0)):
-        a = max(i0, geo.i0[k] * r)
-        b = min(i0 + nx, (geo.i0[k] + geo.mx[k]) * r)
-        c = max(j0, geo.j0[k] * r)
-        d = min(j0 + ny, (geo.j0[k] + geo.my[k]) * r)
-        if a < b and c < d:
-            blk = out[c - j0: d - j0, a - i0: b - i0]
-            blk[blk < 0] = k
-    return out
-
-
 class AmrSolver:
     def __init__(self, H: AmrHierarchy, params: L.swe_params | None = None,
                  device: str = "cuda:0", rows=None):
@@ -190,14 +175,16 @@ class AmrSolver:
         self._speeds()
         self.graph = None
 
-    def _level_solver(self, lev: int, ps) -> BatchedSolver:
+    def _level_solver(self, lev: int, ps, fresh: bool = False) -> BatchedSolver:
+        """The level's pool.  fresh: patches made by regridding, whose cells
+        swe_amr_init writes: only their bed is uploaded."""
         bc = self.H.bc if lev == 1 else (BC_USER,) * 4
         d = self.H.dx(lev)
         probs = [Problem(f"l{lev}p{k}", p.h, p.hu, p.hv, p.b_frame[2:-2, 2:-2], d, d, bc,
                          meta={"level": lev}) for k, p in enumerate(ps)]
         bs = BatchedSolver(probs, self.p,
                            sched=L.schedule(seg=64, rows_per_task=self.rows[lev - 1]),
-                           device=self.dev)
+                           device=self.dev, upload=not fresh)
         if lev > 1:  # the bed of the ghost frame (user sides are read from memory)
             for k, p in enumerate(ps):
                 bs._view(bs.b, k, 1)[0][:, : p.mx + 4] = torch.from_numpy(
@@ -205,15 +192,40 @@ class AmrSolver:
         return bs
 
     def _plans(self) -> None:
+        """The ghost-fill and averaging plans of every level above the first,
+        built on the device from the levels' rectangle tables (swe_amr_plans;
+        fill_plan and average_plan build the same on the host)."""
         self.fill_ops, self.avg_ops, self.nfill, self.navg = [None], [], [0], []
+        r = self.r
         for lev in range(1, self.nlev):
-            f = fill_plan(self.geo[lev], self.geo[lev - 1], self.r)
-            a = average_plan(self.geo[lev], self.geo[lev - 1], self.r)
-            # contiguous plans: their bytes go to the device without a copy
-            self.fill_ops.append(torch.from_numpy(f.view(np.uint8)).to(self.dev))
-            self.avg_ops.append(torch.from_numpy(a.view(np.uint8)).to(self.dev))
-            self.nfill.append(f.size)
-            self.navg.append(a.size)
+            fine, coarse = self.geo[lev], self.geo[lev - 1]
+            mx, my = fine.mx.astype(np.int64), fine.my.astype(np.int64)
+            i0, j0 = fine.i0.astype(np.int64), fine.j0.astype(np.int64)
+            ng = (mx + 4) * (my + 4) - mx * my
+            na = ((i0 + mx) // r - i0 // r) * ((j0 + my) // r - j0 // r)
+            ff = np.concatenate([[0], np.cumsum(ng)[:-1]]).astype(np.int64)
+            af = np.concatenate([[0], np.cumsum(na)[:-1]]).astype(np.int64)
+            fill = torch.empty(int(ng.sum()) * FILL_DTYPE.itemsize, dtype=torch.uint8,
+                               device=self.dev)
+            avg = torch.empty(int(na.sum()) * AVG_DTYPE.itemsize, dtype=torch.uint8,
+                              device=self.dev)
+            tf, tc = fine.rects(self.dev), coarse.rects(self.dev)
+            firsts = torch.from_numpy(np.concatenate([ff, af])).to(self.dev)
+            err = torch.zeros(1, dtype=torch.int32, device=self.dev)
+            L.swe_amr_plans(tf.data_ptr(), len(fine.i0), tc.data_ptr(), len(coarse.i0), r,
+                            int((ng + na).max()), fill.data_ptr(), firsts.data_ptr(),
+                            avg.data_ptr(), firsts.data_ptr() + 8 * len(ff), err.data_ptr(),
+                            self.stream)
+            e = int(err.item())  # waits for the plans (and keeps the tables alive until then)
+            if e & 1:
+                raise L.SweError(f"level {lev + 1}: a ghost cell lies over no cell of its level "
+                                 f"or the level below")
+            if e & 2:
+                raise L.SweError(f"level {lev + 1}: a patch is not over the level below")
+            self.fill_ops.append(fill)
+            self.avg_ops.append(avg)
+            self.nfill.append(int(ng.sum()))
+            self.navg.append(int(na.sum()))
 
     # -- regridding --------------------------------------------------------------
     def refine_flags(self, lev: int, tol: float = 5e-3, buffer: int = 2) -> torch.Tensor:
@@ -266,7 +278,7 @@ class AmrSolver:
                 z = np.zeros((my, mx))
                 new_ps.append(AmrPatch(lev, i0, j0, mx, my, z, z, z,
                                        self.H.bed_frame(lev, i0, j0, mx, my)))
-            bs = self._level_solver(lev, new_ps)
+            bs = self._level_solver(lev, new_ps, fresh=True)
             geo = _Geo(new_ps, bs)
             old_bs, old_geo = self.levels[lev - 1], self.geo[lev - 1]
             t3 = time.perf_counter()

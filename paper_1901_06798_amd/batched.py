@@ -22,7 +22,8 @@ from .workloads import Problem
 
 class BatchedSolver:
     def __init__(self, problems, params: L.swe_params | None = None, trefs=None, groups=None,
-                 sched: L.swe_schedule | None = None, device: str = "cuda:0"):
+                 sched: L.swe_schedule | None = None, device: str = "cuda:0",
+                 upload: bool = True):
         if not torch.cuda.is_available():
             raise L.SweError("BatchedSolver needs a GPU (torch.cuda is not available)")
         L.lib()
@@ -72,7 +73,8 @@ class BatchedSolver:
         self.queue = torch.zeros(2, dtype=torch.int32, device=self.dev)
         self.max_mx = max(pb.mx for pb in self.problems)
         self.max_my = max(pb.my for pb in self.problems)
-        self.upload()
+        if upload:  # else the caller writes the pool and the bed itself
+            self.upload()
         self.graph = None
 
     def replan(self, sched: L.swe_schedule) -> None:

@@ -240,6 +240,112 @@ __global__ void __launch_bounds__(256) k_amr_init_rects(FillArgs a, InitArgs g) 
     }
 }
 
+struct PlanArgs {
+    const swe_amr_rect* fine;
+    int nfine;
+    const swe_amr_rect* crs;
+    int ncrs;
+    int ratio;
+    swe_amr_fill_op* fill;
+    const int64_t* fill_first;  // per fine patch: index of its first ghost entry
+    swe_amr_avg_op* avg;
+    const int64_t* avg_first;   // per fine patch: index of its first averaging entry
+    uint32_t* err;              // bit 0: a ghost over no cell; bit 1: a patch not over level l
+};
+
+// The ghost-fill and averaging plans of a level (one block row per fine
+// patch), in the order swe_amr_fill and swe_amr_average document and the
+// host plans use: a patch's ghost cells row by row of its frame, then its
+// coarse cells row by row.  A ghost cell over another patch of its level
+// (the first in order) copies it; else it takes the cell under it and the
+// bilinear stencil of its centre in the level below, each looked up in the
+// first coarse patch that holds it.
+__global__ void __launch_bounds__(256) k_amr_plans(PlanArgs g) {
+    const int k = blockIdx.y;
+    const swe_amr_rect f = g.fine[k];
+    const int r = g.ratio;
+    const int64_t W = f.mx + 4;
+    const int64_t nghost = W * (f.my + 4) - (int64_t)f.mx * f.my;
+    const int ic0 = floor_div(f.i0, r), jc0 = floor_div(f.j0, r);
+    const int ncx = floor_div(f.i0 + f.mx, r) - ic0;
+    const int ncy = floor_div(f.j0 + f.my, r) - jc0;
+    const int64_t navg = (int64_t)ncx * ncy;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nghost + navg;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nghost) {
+            int row, col;
+            if (t < 2 * W) {
+                row = (int)(t / W);
+                col = (int)(t % W);
+            } else if (t < 2 * W + 4 * (int64_t)f.my) {
+                const int64_t u = t - 2 * W;
+                row = 2 + (int)(u / 4);
+                const int m = (int)(u % 4);
+                col = m < 2 ? m : f.mx + m;
+            } else {
+                const int64_t u = t - 2 * W - 4 * (int64_t)f.my;
+                row = f.my + 2 + (int)(u / W);
+                col = (int)(u % W);
+            }
+            const int I = f.i0 + col - 2, J = f.j0 + row - 2;
+            swe_amr_fill_op op;
+            op.dst = f.off + (int64_t)row * f.pitch + col;
+            op.st[0] = op.st[1] = op.st[2] = op.st[3] = -1;
+            op.wx = 0.0;
+            op.wy = 0.0;
+            op.reserved = 0;
+            int same = -1;
+            for (int n = 0; n < g.nfine && same < 0; ++n) {
+                const swe_amr_rect o = g.fine[n];
+                if (n != k && I >= o.i0 && I < o.i0 + o.mx && J >= o.j0 && J < o.j0 + o.my)
+                    same = n;
+            }
+            if (same >= 0) {
+                op.kind = SWE_AMR_COPY;
+                op.src = rect_elem(g.fine[same], I, J);
+            } else {
+                op.kind = SWE_AMR_COARSE;
+                const int Ic = floor_div(I, r), Jc = floor_div(J, r);
+                const int kc = covering(g.crs, g.ncrs, Ic, Jc);
+                if (kc < 0) {
+                    atomicOr(g.err, 1u);
+                    op.src = 0;
+                } else {
+                    op.src = rect_elem(g.crs[kc], Ic, Jc);
+                }
+                const double X = ((double)I + 0.5) / (double)r - 0.5;
+                const double Y = ((double)J + 0.5) / (double)r - 0.5;
+                const double fx = floor(X), fy = floor(Y);
+                const int i0 = (int)fx, j0 = (int)fy;
+                op.wx = X - fx;
+                op.wy = Y - fy;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int Is = i0 + (m & 1), Js = j0 + (m >> 1);
+                    const int ks = covering(g.crs, g.ncrs, Is, Js);
+                    op.st[m] = ks >= 0 ? rect_elem(g.crs[ks], Is, Js) : -1;
+                }
+            }
+            g.fill[g.fill_first[k] + t] = op;
+        } else {
+            const int64_t a = t - nghost;
+            const int Ic = ic0 + (int)(a % ncx), Jc = jc0 + (int)(a / ncx);
+            swe_amr_avg_op op;
+            const int kc = covering(g.crs, g.ncrs, Ic, Jc);
+            if (kc < 0) {
+                atomicOr(g.err, 2u);
+                op.dst = 0;
+            } else {
+                op.dst = rect_elem(g.crs[kc], Ic, Jc);
+            }
+            op.src = rect_elem(f, Ic * r, Jc * r);
+            op.pitch = f.pitch;
+            op.reserved = 0;
+            g.avg[g.avg_first[k] + a] = op;
+        }
+    }
+}
+
 struct AvgArgs {
     const swe_amr_avg_op* ops;
     int64_t nops;
@@ -609,6 +715,33 @@ int swe_amr_init(const swe_params* p, int32_t ratio, const swe_amr_rect* new_rec
     else
         hipLaunchKernelGGL(swe::k_amr_init_rects<float>, grid, dim3(256), 0, st, a, g);
     return check_launch("swe_amr_init");
+}
+
+int swe_amr_plans(const swe_amr_rect* fine, int32_t n_fine, const swe_amr_rect* coarse,
+                  int32_t n_coarse, int32_t ratio, int64_t max_entries, swe_amr_fill_op* fill_ops,
+                  const int64_t* fill_first, swe_amr_avg_op* avg_ops, const int64_t* avg_first,
+                  uint32_t* err, void* stream) {
+    if (ratio < 1 || n_fine < 0 || n_coarse < 0 || max_entries < 0)
+        return afail(SWE_EINVAL, "swe_amr_plans: bad ratio, count or size");
+    if (n_fine == 0 || max_entries == 0) return SWE_OK;
+    if (!fine || !coarse || !fill_ops || !fill_first || !avg_ops || !avg_first || !err)
+        return afail(SWE_EINVAL, "swe_amr_plans: null pointer");
+    if (n_fine > 65535) return afail(SWE_EINVAL, "swe_amr_plans: more than 65535 fine patches");
+    swe::PlanArgs g;
+    g.fine = fine;
+    g.nfine = n_fine;
+    g.crs = coarse;
+    g.ncrs = n_coarse;
+    g.ratio = ratio;
+    g.fill = fill_ops;
+    g.fill_first = fill_first;
+    g.avg = avg_ops;
+    g.avg_first = avg_first;
+    g.err = err;
+    const int64_t bx64 = (max_entries + 255) / 256;
+    const dim3 grid((unsigned)(bx64 < 1024 ? bx64 : 1024), (unsigned)n_fine);
+    hipLaunchKernelGGL(swe::k_amr_plans, grid, dim3(256), 0, static_cast<hipStream_t>(stream), g);
+    return check_launch("swe_amr_plans");
 }
 
 int swe_amr_flag(const swe_params* p, const swe_patch* patches, int32_t n, int32_t max_mx,

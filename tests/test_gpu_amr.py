@@ -236,3 +236,26 @@ def test_bench_hierarchy_matches_the_reference(gpu, precision):
                 worst = max(worst, float(np.abs((h + b) - (want[..., 0] + b))[wet].max()))
     print(f"fp32 deviation, bench hierarchy: max surface difference {worst:.3e} m", flush=True)
     assert worst <= 1e-5
+
+
+def test_device_plans_equal_the_host_plans(gpu):
+    # swe_amr_plans (built on the device from the rectangle tables) against
+    # amr.fill_plan and amr.average_plan (the host plans the CPU tests pin to
+    # the reference coupling), byte for byte, before and after a regrid
+    L, AmrSolver, torch = gpu
+    from paper_1901_06798_amd import amr
+    cases = [W.amr_three_levels(2, bed="shelf", amp=2.0), W.amr_three_levels(4, bed="shelf"),
+             W.amr_nested()]
+    for H in cases:
+        print(f"case device plans ratio={H.ratio} patches={len(H.patches)}", flush=True)
+        s = AmrSolver(H, L.params())
+        for regridded in (False, True):
+            if regridded:
+                s.set_dt(6.0)
+                s.run(2)
+                s.regrid(tol=0.05 if H.ratio != 4 else 0.5)
+            for lev in range(1, s.nlev):
+                f = amr.fill_plan(s.geo[lev], s.geo[lev - 1], s.r)
+                a = amr.average_plan(s.geo[lev], s.geo[lev - 1], s.r)
+                assert np.array_equal(s.fill_ops[lev].cpu().numpy(), f.view(np.uint8)), lev
+                assert np.array_equal(s.avg_ops[lev - 1].cpu().numpy(), a.view(np.uint8)), lev
