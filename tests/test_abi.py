@@ -226,6 +226,17 @@ int main(void) {
     assert init(n_new=0) == L.SWE_OK
     assert init(cells=0) == L.SWE_OK
     assert init(n_new=70000) == L.SWE_EINVAL
+    # swe_amr_plans: ratio >= 1, non-negative counts, every table and output
+    # given when there is work; nothing to plan is no work
+    def plans(ratio=2, n_fine=1, entries=16, fill=fake, err=fake):
+        return lib.swe_amr_plans(fake, n_fine, fake, 1, ratio, entries, fill, fake, fake, fake,
+                                 err, None)
+    assert plans(ratio=0) == L.SWE_EINVAL
+    assert plans(n_fine=-1) == L.SWE_EINVAL
+    assert plans(fill=None) == L.SWE_EINVAL
+    assert plans(err=None) == L.SWE_EINVAL
+    assert plans(n_fine=0) == L.SWE_OK
+    assert plans(entries=0) == L.SWE_OK
 
 
 def test_amr_plans_match_the_hierarchy(L):
