@@ -506,10 +506,16 @@ int swe_batched_retake(const swe_params *p, const swe_patch *patches, const swe_
  * before the first call and left zero: each step's conditions (status bits,
  * depth resets) wait there per group until the CFL rule settles them, so
  * that status and group_status (may be NULL) count accepted steps only (a
- * step the rule redoes reports nothing; its redo reports its own).  Other
- * arguments as swe_batched_step.  For a caller that advances many steps
- * between host decisions (a serving loop's round) this replaces four
- * library calls per step. */
+ * step the rule redoes reports nothing; its redo reports its own).  When a
+ * step is one launch (nsub = 1 and either no items with seg 64 or 32, or
+ * packs with seg 0) and ngroups <= 256, a non-NULL queue (device
+ * uint32_t[2], zero before the first call and left zero) makes the CFL rule
+ * run in the last workgroup of each launch instead of as launches of its
+ * own: its two words count the finished workgroups and say whether a redo
+ * is due, and a redo launch with nothing to redo ends at once.  The results
+ * are bitwise the same either way.  Other arguments as swe_batched_step.
+ * For a caller that advances many steps between host decisions (a serving
+ * loop's round) this replaces four library calls per step. */
 int swe_batched_advance(const swe_params *p, const swe_patch *patches, int32_t npatches,
                         int32_t ngroups, const swe_item *items, int32_t nitems,
                         const swe_task *tasks, const swe_task *plain, int32_t nplain,

@@ -29,6 +29,24 @@
 
 namespace swe {
 
+// The CFL rule of swe_cfl_reduce with the steps' pending conditions, fused
+// into the last workgroup of a step that is one launch (one wave per
+// workgroup).  ctr[0] counts the finished workgroups and is left at 0;
+// ctr[1] says whether the rule flagged a group for a redo, so that a gated
+// redo launch with nothing to redo ends in every workgroup at once.
+constexpr int kTailGroups = 256;
+struct CflTail {
+    uint32_t* ctr;           // NULL: no fused rule
+    int npatches;            // the table's patches
+    int ngroups;             // groups of dt_next, retake_out, group_flags (<= kTailGroups)
+    double* dt_next;         // dt_group, written where the rate is finite and positive
+    uint32_t* retake_out;    // redo flags; NULL: no further redo (a step above the limit stands)
+    uint32_t* status_out;    // (flags, clamps) of the accepted steps
+    uint32_t* gstatus_out;   // per group (flags, clamps); may be NULL
+    uint32_t* group_flags;   // per group flags of the rule; may be NULL
+    double cfl_desired, cfl_max;
+};
+
 struct BatchArgs {
     const swe_patch* patches;
     const swe_item* items;
@@ -47,7 +65,78 @@ struct BatchArgs {
     const uint32_t* retake;  // retake launch: only groups with retake[g] != 0; NULL: all
     int ngroups;             // entries of retake
     int sub;                 // plain launches: the substep this launch runs
+    CflTail t;               // the CFL rule fused into one-launch steps
 };
+
+// Whether a fused redo launch has nothing to redo (wave-uniform): the rule
+// of the launch before wrote ctr[1].
+__device__ __forceinline__ bool tail_idle_redo(const BatchArgs& a) {
+    return a.t.ctr && a.retake &&
+           __hip_atomic_load(&a.t.ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+}
+
+// The last workgroup to finish takes the rate of every patch (its speed
+// maxima over dx and dy, over its substeps), the largest per group, and
+// from it the group's next step size, its redo flag and its flags; the
+// groups' pending conditions join the status where the step stands.  The
+// arithmetic is swe_cfl_reduce's.  Speeds and pending pairs are read with
+// atomic exchanges (the other workgroups wrote them with atomics) and left
+// at 0.
+__device__ __forceinline__ void cfl_tail(const BatchArgs& a, int lane) {
+    const CflTail& t = a.t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(&t.ctr[0], 1u);
+    prev = __builtin_amdgcn_readfirstlane(prev);
+    if (prev + 1 != gridDim.x) return;
+    __shared__ unsigned long long rate[kTailGroups];
+    for (int g = lane; g < t.ngroups; g += kWave) rate[g] = 0ull;
+    __syncthreads();
+    unsigned long long* sm = reinterpret_cast<unsigned long long*>(a.smax);
+    for (int k = lane; k < t.npatches; k += kWave) {
+        const swe_patch& p = a.patches[k];
+        if (p.group < 0 || p.group >= t.ngroups) continue;
+        const double sx = __longlong_as_double(static_cast<long long>(atomicExch(&sm[2 * k], 0ull)));
+        const double sy =
+            __longlong_as_double(static_cast<long long>(atomicExch(&sm[2 * k + 1], 0ull)));
+        const double rx = sx / p.dx, ry = sy / p.dy;
+        double r = rx > ry ? rx : ry;
+        r = r / (double)p.tref;
+        if (isnan(rx) || isnan(ry)) r = rx + ry;
+        atomicMax(&rate[p.group], static_cast<unsigned long long>(__double_as_longlong(r)));
+    }
+    __syncthreads();
+    bool redo = false;
+    for (int g = lane; g < t.ngroups; g += kWave) {
+        const double r = __longlong_as_double(static_cast<long long>(rate[g]));
+        const double dt = t.dt_next[g];
+        uint32_t f = 0;
+        if (isnan(r)) f |= SWE_STATUS_NONFINITE;
+        const bool over = r > 0.0 && dt * r > t.cfl_max;
+        if (over) f |= t.retake_out ? SWE_STATUS_RETAKEN : SWE_STATUS_CFL_EXCEEDED;
+        if (t.retake_out) t.retake_out[g] = over ? 1u : 0u;
+        if (r > 0.0 && isfinite(r)) t.dt_next[g] = t.cfl_desired / r;
+        if (f) {
+            atomicOr(t.status_out, f);
+            if (t.group_flags) atomicOr(&t.group_flags[g], f);
+        }
+        const uint32_t pf = atomicExch(&a.group_status[2 * g], 0u);
+        const uint32_t pc = atomicExch(&a.group_status[2 * g + 1], 0u);
+        const bool stands = !(t.retake_out && over);
+        if (stands) {
+            if (pf) atomicOr(t.status_out, pf);
+            if (pc) atomicAdd(&t.status_out[1], pc);
+            if (t.gstatus_out && pf) atomicOr(&t.gstatus_out[2 * g], pf);
+            if (t.gstatus_out && pc) atomicAdd(&t.gstatus_out[2 * g + 1], pc);
+        }
+        redo = redo || !stands;
+    }
+    const uint32_t any = __any(redo) ? 1u : 0u;
+    if (lane == 0) {
+        atomicExch(&t.ctr[1], any);
+        atomicExch(&t.ctr[0], 0u);
+    }
+}
 
 // The FP32 march fits three waves per SIMD (at most 168 VGPRs) without
 // spilling, which 256-thread workgroups can use; the FP64 one, and the
@@ -169,8 +258,7 @@ __global__ void __launch_bounds__(512, (DEV && !FRIC) ? 3 : 2) k_batched(BatchAr
 // FP64 three), one wave fewer with friction or with two segments per wave
 // (whose tasks are per lane rather than scalar).
 template <bool DEV, int SEG, bool FRIC>
-__global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == kWave ? 0 : 1))
-    k_plain(BatchArgs a) {
+__device__ __forceinline__ void plain_task(const BatchArgs& a) {
     constexpr int kSegPerWave = kWave / SEG;
     const int lane = threadIdx.x & (kWave - 1);
     const int seg_in_wave = lane / SEG;
@@ -228,6 +316,14 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
     if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
 }
 
+template <bool DEV, int SEG, bool FRIC>
+__global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == kWave ? 0 : 1))
+    k_plain(BatchArgs a) {
+    if (tail_idle_redo(a)) return;
+    plain_task<DEV, SEG, FRIC>(a);
+    if (a.t.ctr) cfl_tail(a, threadIdx.x & (kWave - 1));
+}
+
 // Packed tasks (seg = 0): one wave per pack (an entry of `items`), its tasks
 // side by side from lane 0, each lane marching the task whose lanes hold it
 // (lanes past the last task only take part in the cross-lane moves).  The
@@ -236,7 +332,7 @@ __global__ void __launch_bounds__(64, (DEV ? 4 : 3) - (FRIC ? 1 : 0) - (SEG == k
 // suffix maximum within the segment leaves the segment's maximum in its
 // first lane.
 template <bool DEV, bool FRIC>
-__global__ void __launch_bounds__(64, (DEV ? 3 : 2) - (FRIC ? 1 : 0)) k_pack(BatchArgs a) {
+__device__ __forceinline__ void pack_task(const BatchArgs& a) {
     const int lane = threadIdx.x & (kWave - 1);
     const swe_item pk = a.items[blockIdx.x];
     if (a.sub >= pk.substeps) return;
@@ -305,6 +401,13 @@ __global__ void __launch_bounds__(64, (DEV ? 3 : 2) - (FRIC ? 1 : 0)) k_pack(Bat
     if (a.status && r.flags) atomicOr(&a.status[0], r.flags);
     if (a.group_status && run && r.clamps) atomicAdd(&a.group_status[2 * pt.group + 1], r.clamps);
     if (a.group_status && run && r.flags) atomicOr(&a.group_status[2 * pt.group], r.flags);
+}
+
+template <bool DEV, bool FRIC>
+__global__ void __launch_bounds__(64, (DEV ? 3 : 2) - (FRIC ? 1 : 0)) k_pack(BatchArgs a) {
+    if (tail_idle_redo(a)) return;
+    pack_task<DEV, FRIC>(a);
+    if (a.t.ctr) cfl_tail(a, threadIdx.x & (kWave - 1));
 }
 
 template __global__ void k_batched<false, 64, false>(BatchArgs);
@@ -390,6 +493,8 @@ int check_sched(const swe_schedule* s) {
 // swe_step.hip (not part of the ABI)
 extern "C" __attribute__((visibility("hidden"))) int swe_internal_set_error(int code,
                                                                            const char* msg);
+extern "C" __attribute__((visibility("hidden"))) int swe_internal_check_params(
+    const swe_params* p);
 extern "C" __attribute__((visibility("hidden"))) int swe_internal_cfl_reduce_pending(
     const swe_params* p, const swe_patch* patches, int32_t n, int32_t ngroups,
     double* smax_patch, double* dt_group, uint32_t* status, uint32_t* group_flags,
@@ -615,7 +720,8 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
                         const void* pool_b, const double* dt_group, double* smax_patch,
                         uint32_t* status, uint32_t* queue, const swe_schedule* sched,
                         const uint32_t* retake, int32_t ngroups, uint32_t* group_status,
-                        void* stream, bool zero_queue = false, bool pending = false) {
+                        void* stream, bool zero_queue = false, bool pending = false,
+                        const swe::CflTail* tail = nullptr) {
     if (!p) return bfail(SWE_EINVAL, "params is NULL");
     int rc = check_sched(sched);
     if (rc) return rc;
@@ -677,6 +783,7 @@ static int batched_step(const swe_params* p, const swe_patch* patches, const swe
     a.retake = retake;
     a.ngroups = ngroups;
     a.sub = 0;
+    a.t = tail ? *tail : swe::CflTail{};
 
     const bool dev = p->precision == SWE_F32_DEV;
     const bool fric = p->manning_n > 0.0;
@@ -800,6 +907,45 @@ int swe_batched_advance(const swe_params* p, const swe_patch* patches, int32_t n
         return bfail(SWE_EINVAL, "swe_batched_advance: null retake flags, pending pairs, status or pool");
     void* pool[2] = {pool_0, pool_1};
     int cur = first;
+    // a step that is one launch (single-substep plain tasks, or packs with
+    // one substep) carries the CFL rule in its last workgroup, with the
+    // queue's two words as its counters
+    const bool fused = queue && sched && nsub == 1 && ngroups <= swe::kTailGroups &&
+                       (sched->seg == 0 ? nitems > 0 : (nitems == 0 && nplain > 0));
+    if (fused) {
+        int rc = swe_internal_check_params(p);
+        if (rc) return rc;
+        swe::CflTail t{};
+        t.ctr = queue;
+        t.npatches = npatches;
+        t.ngroups = ngroups;
+        t.dt_next = dt_group;
+        t.retake_out = retake;
+        t.status_out = status;
+        t.gstatus_out = group_status;
+        t.group_flags = group_flags;
+        t.cfl_desired = p->cfl_desired;
+        t.cfl_max = p->cfl_max;
+        swe::CflTail last = t;
+        last.retake_out = nullptr;
+        for (int k = 0; k < nsteps; ++k) {
+            // the step, then up to two gated redos, each launch ending with the
+            // rule (the last one flags a step still above the limit)
+            rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub, pool[cur],
+                              pool[1 - cur], pool_work, pool_elems, pool_b, dt_group, smax_patch,
+                              nullptr, queue, sched, nullptr, 0, pending, stream, false, true, &t);
+            if (rc) return rc;
+            for (int redo = 0; redo < 2; ++redo) {
+                rc = batched_step(p, patches, items, nitems, tasks, plain, nplain, nsub,
+                                  pool[cur], pool[1 - cur], pool_work, pool_elems, pool_b,
+                                  dt_group, smax_patch, nullptr, queue, sched, retake, ngroups,
+                                  pending, stream, false, true, redo == 0 ? &t : &last);
+                if (rc) return rc;
+            }
+            cur ^= 1;
+        }
+        return SWE_OK;
+    }
     for (int k = 0; k < nsteps; ++k) {
         // the step, the CFL rule with the retake flags, the gated redo of the
         // flagged groups, and the CFL rule of the redone steps

@@ -1049,6 +1049,12 @@ int swe_cfl_reduce(const swe_params* p, const swe_patch* patches, int32_t n, int
     return check_launch("swe_cfl_reduce");
 }
 
+// The parameter check, for swe_batched_advance's fused CFL rule (not part of
+// the ABI).
+__attribute__((visibility("hidden"))) int swe_internal_check_params(const swe_params* p) {
+    return check_params(p);
+}
+
 // swe_cfl_reduce that also settles the steps' pending conditions (for
 // swe_batched_advance; not part of the ABI).
 __attribute__((visibility("hidden"))) int swe_internal_cfl_reduce_pending(

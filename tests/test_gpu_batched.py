@@ -179,3 +179,49 @@ def test_advance_equals_the_step_by_step_sequence(gpu, seg):
     for k in range(len(probs)):
         for x, y in zip(a.state(k), b.state(k)):
             assert np.array_equal(x, y), k
+
+
+@pytest.mark.parametrize("seg", [64, 32, 0])
+def test_fused_cfl_rule_equals_the_separate_launches(gpu, seg):
+    # one-launch steps (single-substep patches): swe_batched_advance folds the
+    # CFL rule into the step's last workgroup when given the queue words, and
+    # launches the rule separately without them; both give the same states,
+    # step sizes, flags and per-group conditions bit for bit, and leave the
+    # pending pairs and the queue words at zero
+    L, BatchedSolver, PatchSolver, torch = gpu
+    specs, probs, trefs = amr_set(seed=9, counts=(3, 4, 5))
+    groups = [k % 4 for k in range(len(probs))]
+    sched = L.schedule(seg=seg)
+    print(f"case fused batched CFL rule seg={seg}", flush=True)
+    runs = []
+    for fused in (True, False):
+        s = BatchedSolver(probs, L.params(), trefs=[1] * len(probs), groups=groups, sched=sched)
+        assert s.nsub == 1 and (s.nitems == 0) == (seg != 0)
+        s.initial_dt()
+        s.dt.mul_(torch.tensor([1.0, 2.5, 1.0, 1.7], dtype=torch.float64, device=s.dev))
+        pending = torch.zeros(2 * s.ngroups, dtype=torch.int32, device=s.dev)
+        gstat = torch.zeros(2 * s.ngroups, dtype=torch.int32, device=s.dev)
+        s.queue.zero_()
+        for k in range(3):
+            L.swe_batched_advance(
+                s.p, s.table.data_ptr(), s.n, s.ngroups, s.items.data_ptr(), s.nitems,
+                s.tasks.data_ptr(), s.tasks.data_ptr() + L.SWE_TASK_BYTES * (s.ntasks - s.nplain),
+                s.nplain, s.nsub, s.pools[0].data_ptr(), s.pools[1].data_ptr(), s.cur, 0,
+                3 * s.plane, s.b.data_ptr(), s.dt.data_ptr(), s.smax.data_ptr(),
+                s.status.data_ptr(), gstat.data_ptr(), s.group_flags.data_ptr(),
+                s.retake.data_ptr(), pending.data_ptr(), s.queue.data_ptr() if fused else 0,
+                s.sched, 3, s.stream)
+            s.cur = (s.cur + 3) % 2
+            if k == 0:
+                # a group far above the limit again
+                s.dt[3] *= 3.0
+        torch.cuda.synchronize()
+        assert not pending.any() and not s.queue.any() and not s.smax.any()
+        runs.append((s, gstat))
+    (a, ga), (b, gb) = runs
+    assert int(a.status[0].item()) & L.STATUS_RETAKEN
+    assert torch.equal(a.status, b.status) and torch.equal(a.dt, b.dt)
+    assert torch.equal(ga, gb) and torch.equal(a.group_flags, b.group_flags)
+    for k in range(len(probs)):
+        for x, y in zip(a.state(k), b.state(k)):
+            assert np.array_equal(x, y), k
