@@ -119,20 +119,31 @@ def measured_traffic(path: str | None):
         return None
 
 
-def _pmc_mean(run_dir: str, counter: str, kernel_sub: str, workgroup: int | None = None):
+def _pmc_mean(run_dir: str, counter: str, kernel_sub: str, workgroup: int | None = None,
+              first_run: bool = False):
     """Mean of a counter over the dispatches of a kernel; `workgroup` keeps
     only dispatches of that workgroup size (the step kernels' retake launches,
     which end at once unless a step is redone, use 256-thread workgroups, the
-    steps themselves 64)."""
+    steps themselves 64).  first_run: only the kernel's first run of
+    dispatches, up to the first dispatch of another swe kernel of that
+    workgroup size (a run of bench.py with its variants times some kernels on
+    more than one workload, the shelf first)."""
     import csv
     import glob
-    vals = []
+    rows = []
     for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] == counter and kernel_sub in r["Kernel_Name"] and (
+                if r["Counter_Name"] == counter and (
                         workgroup is None or int(r["Workgroup_Size"]) == workgroup):
-                    vals.append(float(r["Counter_Value"]))
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    vals = []
+    for _, name, v in rows:
+        if kernel_sub in name:
+            vals.append(v)
+        elif first_run and vals and "swe::" in name:
+            break
     if not vals:
         raise SystemExit(f"no {counter} samples for {kernel_sub} under {run_dir}")
     return sum(vals) / len(vals), len(vals)
@@ -201,7 +212,7 @@ def make_valu_record(root: str, outdir: str) -> None:
                  f"kernel_source_hash = {kernel_source_hash()}"]
         try:
             for c in SQ_COUNTERS:
-                v, n = _pmc_mean(os.path.join(root, run), c, kern, STEP_WG)
+                v, n = _pmc_mean(os.path.join(root, run), c, kern, STEP_WG, first_run=True)
                 lines.append(f"{c} = {v:.0f}")
         except SystemExit as e:
             print(f"skipping {kern}: {e}")
@@ -874,6 +885,15 @@ def main():
             "achieved_gbs": ra["achieved_gbs"], "hbm_frac": ra["achieved_gbs"] / HBM_PEAK_GBS,
             "flags": ra["flags"],
             "alu": alu_roofline(ra["kernel_ms_avg"], OPCOUNT_ACTIVE, n * n)}
+        log("[bench] FP32 surface-deviation split step on the same sea")
+        torch.cuda.empty_cache()
+        rb = time_patch(pa, L.params(precision=L.F32_DEV), min(args.steps, 200), args.warmup)
+        rb.pop("solver")
+        out["variants"]["fully_active_fp32_dev"] = {
+            "workload": out["variants"]["fully_active_fp64"]["workload"],
+            "cups": rb["cups"], "ms_per_step": rb["ms_per_step"], "kernel_ms_avg": rb["kernel_ms_avg"],
+            "achieved_gbs": rb["achieved_gbs"], "hbm_frac": rb["achieved_gbs"] / HBM_PEAK_GBS,
+            "flags": rb["flags"], "speedup_vs_fp64": rb["cups"] / ra["cups"]}
         del pa
         log("[bench] FP64 split step on a latitude-longitude patch")
         torch.cuda.empty_cache()
