@@ -78,8 +78,8 @@ def log(msg):
 
 # sources of the single-patch step kernels (k_split, k_unsplit) that the
 # counter records describe
-STEP_SOURCES = ("swe_common.hpp", "swe_march.hpp", "swe_math.hpp", "swe_split.hpp",
-                "swe_step.hip", "swe_step_f32.hip", "swe_unsplit.hpp")
+STEP_SOURCES = ("swe_common.hpp", "swe_march.hpp", "swe_math.hpp", "swe_step.hip",
+                "swe_unsplit.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -87,9 +87,9 @@ def kernel_source_hash() -> str:
     record is used only while it carries this hash."""
     import hashlib
 
-    from paper_1901_06798_amd.build import CONTRACT_FLAG, HIPFLAGS
+    from paper_1901_06798_amd.build import HIPFLAGS
     d = os.path.join(ROOT, "paper_1901_06798_amd", "csrc")
-    h = hashlib.sha256(" ".join(HIPFLAGS + [CONTRACT_FLAG]).encode())
+    h = hashlib.sha256(" ".join(HIPFLAGS).encode())
     for name in STEP_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + f.read())
