@@ -178,8 +178,10 @@ class PatchSolver:
                      retake: bool = True) -> None:
         """One step q[cur] -> q[1 - cur]; dt from dt_ptr (device) or self.dt.
         With cfl, the CFL reduction writes the next dt; with retake as well, a
-        step above cfl_max is redone once on the device with the reduced dt
-        (a retaken step still above the limit is flagged CFL_EXCEEDED)."""
+        step above cfl_max is redone on the device with the reduced dt: up to
+        twice when the rule is fused into the launches (the default), once
+        with the separate reduction launches; a last redo still above the
+        limit stands and is flagged CFL_EXCEEDED."""
         qi, qo = self.q[self.cur].data_ptr(), self.q[1 - self.cur].data_ptr()
         if cfl and retake and dt_ptr is None and self.fused:
             self.launch_step_cfl(qi, qo)
