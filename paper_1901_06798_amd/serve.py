@@ -33,6 +33,28 @@ from .solver import _round_up, patch_table
 from .workloads import Problem
 
 
+def admit_in_order(queue: list, try_admit, now: float, max_bypass_s: float) -> list:
+    """Admission of waiting requests (queue in arrival order; try_admit(sc)
+    admits sc if a slot is free and its footprint fits, and says whether it
+    did).  Requests are tried oldest first; one that does not fit is passed
+    over by later ones that do (small grids fill memory that a large one is
+    waiting for), until it has waited longer than max_bypass_s: from then on
+    nothing is admitted ahead of it, so no request waits behind newer ones
+    for longer than that.  max_bypass_s <= 0: strict arrival order.  Removes
+    the admitted requests from queue and returns them."""
+    admitted = []
+    k = 0
+    while k < len(queue):
+        sc = queue[k]
+        if try_admit(sc):
+            admitted.append(queue.pop(k))
+            continue
+        if max_bypass_s <= 0 or now - sc.arrival > max_bypass_s:
+            break
+        k += 1
+    return admitted
+
+
 class PoolAllocator:
     """First-fit allocator of element ranges within one pool; 256-byte aligned."""
 
@@ -116,7 +138,8 @@ class PinnedPool:
 class ScenarioServer:
     def __init__(self, params: L.swe_params | None = None, hbm_budget: int = 64 << 30,
                  max_slots: int = 64, steps_per_round: int = 50, device: str = "cuda:0",
-                 sched: L.swe_schedule | None = None, graphs: bool = False):
+                 sched: L.swe_schedule | None = None, graphs: bool = False,
+                 max_bypass_s: float = 0.0):
         if not torch.cuda.is_available():
             raise L.SweError("ScenarioServer needs a GPU")
         L.lib()
@@ -126,6 +149,11 @@ class ScenarioServer:
         self.esize = 4 if self.p.precision == L.F32_DEV else 8
         self.R = steps_per_round
         self.max_slots = max_slots
+        # a request that does not fit may be passed over by later ones for
+        # this long (admit_in_order); 0: strict arrival order, which gave the
+        # lower p99 on the memory-bound stream (a passed-over large grid then
+        # waits for several smaller ones)
+        self.max_bypass_s = max_bypass_s
         self.sched = sched or L.schedule(seg=64, waves_per_group=4)
         # one plane of the pool holds every scenario's plane; 7 planes in total
         # (2 x 3 state planes + bathymetry)
@@ -482,11 +510,11 @@ class ScenarioServer:
                 sc.reason = (f"needs {self.footprint_bytes(sc.grid)} bytes of HBM, more than "
                              f"the server's budget of {self.budget_bytes()}")
                 rejected.append(sc)
-            # admit in arrival order while slots and memory allow
+            # admit oldest first while slots and memory allow (later requests
+            # pass one that does not fit only with max_bypass_s > 0)
             with mk.range("host: admit"):
-                while queue and self.try_admit(queue[0]):
-                    queue[0].admitted = time.perf_counter() - t0
-                    queue.pop(0)
+                for sc in admit_in_order(queue, self.try_admit, now, self.max_bypass_s):
+                    sc.admitted = time.perf_counter() - t0
             if self.active:
                 steps = min(self.R, min(sc.nsteps - sc.steps_done for sc in self.active))
                 self.round(steps)
