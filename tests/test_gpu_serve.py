@@ -139,3 +139,19 @@ def test_device_built_scenario_matches_host_arrays(gpu):
     b = ScenarioServer(p, max_slots=2).serve([Scenario(0, 0.0, W.scenario(3, n=160), 30)])
     ea, eb = a["done"][0].result["eta"], b["done"][0].result["eta"]
     assert np.abs(ea - eb).max() <= 1e-9
+
+
+def test_steep_coast_scenarios_stay_finite(gpu):
+    # requests 779 (300^2) and 1067 (446^2) of the serving stream run up steep
+    # dry coasts where films of a few millimetres reach hundreds of m/s (in
+    # the reference solver too); the FP32 surface-deviation step diverged on
+    # them when built with contracted multiply-adds.  As built, both finish
+    # their 1000 steps finite, with no step left above the Courant limit
+    L, ScenarioServer, Scenario, PatchSolver, torch = gpu
+    print("case serving FP32, requests 779 and 1067, 1000 steps", flush=True)
+    reqs = [Scenario(rid, 0.0, None, 1000, spec=W.scenario_spec(rid, n=n, nsteps=1000))
+            for rid, n in ((779, 300), (1067, 446))]
+    out = ScenarioServer(L.params(precision=L.F32_DEV), max_slots=2, steps_per_round=50).serve(reqs)
+    assert not out["status_flags"] & (L.STATUS_NONFINITE | L.STATUS_CFL_EXCEEDED)
+    for sc in out["done"]:
+        assert sc.result["status"] == 0 and np.isfinite(sc.result["eta"]).all(), sc.rid
